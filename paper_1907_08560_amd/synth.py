@@ -1,0 +1,159 @@
+"""Seeded synthetic pencils (F, J, G) of the shapes the solver is benchmarked on.
+
+This module only draws inputs: it holds none of the solver's arithmetic, and
+both the HIP path and the CPU oracle consume what it returns.
+
+Recipe (one pencil of order n):
+  * F: m x n, entries i.i.d. (N(0,1) + i N(0,1)) / sqrt(2), m = ceil(ratio_f * n).
+  * J: +1 on the first m_plus rows, -1 on the rest (int8).
+  * G: p x n, G = U diag(s) W^*, with U the first n columns of a p x p Haar
+    unitary, W an n x n Haar unitary (Q of a complex Gaussian matrix with the
+    phases of diag(R) moved into Q, Mezzadri's construction), and
+    s_j = 10**Uniform(log10(s_lo), 0) i.i.d., unsorted.  cond(G^*G) is then
+    at most s_lo**-2.
+  * Draw order inside one pencil: F, s, U, W; all from one numpy PCG64 stream.
+All arrays are complex128 in Fortran (column-major) order.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+@dataclass
+class Pencil:
+    F: np.ndarray   # m x n complex128, Fortran order
+    J: np.ndarray   # m int8, entries +1 / -1
+    G: np.ndarray   # p x n complex128, Fortran order
+    s: np.ndarray   # the singular values used to build G (unsorted)
+    seed: int
+    index: int
+
+    @property
+    def m(self) -> int:
+        return self.F.shape[0]
+
+    @property
+    def n(self) -> int:
+        return self.F.shape[1]
+
+    @property
+    def p(self) -> int:
+        return self.G.shape[0]
+
+    @property
+    def m_plus(self) -> int:
+        return int((self.J > 0).sum())
+
+
+def _gauss(rng: np.random.Generator, rows: int, cols: int) -> np.ndarray:
+    re = rng.standard_normal((rows, cols))
+    im = rng.standard_normal((rows, cols))
+    return (re + 1j * im) / math.sqrt(2.0)
+
+
+def haar_frame(rng: np.random.Generator, rows: int, cols: int) -> np.ndarray:
+    """First `cols` columns of a Haar-distributed rows x rows unitary matrix."""
+    a = _gauss(rng, rows, cols)
+    q, r = np.linalg.qr(a)
+    d = np.diagonal(r)
+    ph = np.where(np.abs(d) > 0, d / np.where(np.abs(d) > 0, np.abs(d), 1.0), 1.0)
+    return q * ph[None, :]
+
+
+def make_pencil(rng: np.random.Generator, n: int, m: int, m_plus: int, p: int,
+                s_lo: float, seed: int = -1, index: int = 0,
+                j_identity: bool = False) -> Pencil:
+    F = _gauss(rng, m, n)
+    if j_identity:
+        m_plus = m
+    J = np.where(np.arange(m) < m_plus, 1, -1).astype(np.int8)
+    s = 10.0 ** rng.uniform(math.log10(s_lo), 0.0, size=n)
+    U = haar_frame(rng, p, n)
+    W = haar_frame(rng, n, n)
+    G = (U * s[None, :]) @ W.conj().T
+    return Pencil(np.asfortranarray(F), J, np.asfortranarray(G), s, seed, index)
+
+
+def pencil_rng(seed: int, batch: int, k: int) -> np.random.Generator:
+    """Generator of pencil k of a batch: SeedSequence(seed).spawn(batch)[k]."""
+    if batch == 1:
+        return np.random.Generator(np.random.PCG64(seed))
+    child = np.random.SeedSequence(seed).spawn(batch)[k]
+    return np.random.Generator(np.random.PCG64(child))
+
+
+def rows_for(n: int, ratio: float) -> int:
+    return int(math.ceil(ratio * n))
+
+
+# The five workloads, seed = 1000 + workload number.
+#   1: n=64, F 96x64, J 72+/24-, G 128x64, s in [1e-4, 1]
+#   2: n=1024, F 1536x1024, J 1152+/384-, G 2048x1024, s in [1e-8, 1]
+#   3: n=4096, F 6144x4096, J 3:1, G 8192x4096, s in [1e-5, 1] (and a J = I run)
+#   4: 64 pencils, n_k ~ U{300..900}, F 1.5n x n, J 3:1, G 2n x n, s in [1e-6, 1]
+#   5: 16 pencils, n_k ~ U{2000..6000}, F 1.5n x n, J 4:1, G 2n x n, s in [1e-6, 1]
+WORKLOADS = {
+    1: dict(batch=1, n=(64, 64), f_ratio=1.5, plus_frac=0.75, g_ratio=2.0, s_lo=1e-4),
+    2: dict(batch=1, n=(1024, 1024), f_ratio=1.5, plus_frac=0.75, g_ratio=2.0, s_lo=1e-8),
+    3: dict(batch=1, n=(4096, 4096), f_ratio=1.5, plus_frac=0.75, g_ratio=2.0, s_lo=1e-5),
+    4: dict(batch=64, n=(300, 900), f_ratio=1.5, plus_frac=0.75, g_ratio=2.0, s_lo=1e-6),
+    5: dict(batch=16, n=(2000, 6000), f_ratio=1.5, plus_frac=0.8, g_ratio=2.0, s_lo=1e-6),
+}
+
+
+def workload_sizes(number: int) -> list[int]:
+    """Pencil orders n_k of a workload (drawn from the workload's own seed)."""
+    w = WORKLOADS[number]
+    lo, hi = w["n"]
+    if lo == hi:
+        return [lo] * w["batch"]
+    rng = np.random.Generator(np.random.PCG64(1000 + number))
+    return [int(v) for v in rng.integers(lo, hi + 1, size=w["batch"])]
+
+
+def workload_pencil(number: int, k: int = 0, j_identity: bool = False,
+                    n_override: int | None = None) -> Pencil:
+    """Pencil k of a workload.  `n_override` shrinks the order (same recipe)."""
+    w = WORKLOADS[number]
+    seed = 1000 + number
+    n = workload_sizes(number)[k] if n_override is None else n_override
+    m = rows_for(n, w["f_ratio"])
+    p = rows_for(n, w["g_ratio"])
+    m_plus = int(round(w["plus_frac"] * m))
+    rng = pencil_rng(seed, w["batch"], k)
+    return make_pencil(rng, n, m, m_plus, p, w["s_lo"], seed=seed, index=k,
+                       j_identity=j_identity)
+
+
+def random_pencil(seed: int, n: int, m: int, m_plus: int, p: int, s_lo: float,
+                  j_identity: bool = False) -> Pencil:
+    """A one-off pencil for tests (same recipe, free sizes)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return make_pencil(rng, n, m, m_plus, p, s_lo, seed=seed, j_identity=j_identity)
+
+
+def random_pairs(seed: int, count: int) -> dict:
+    """Random 2x2 pivot data: a Hermitian [[a, c], [conj(c), b]] and a Hermitian
+    positive definite [[s_a, s_c], [conj(s_c), s_b]], entries over 12 decades.
+
+    s_c = sqrt(s_a s_b) * x * exp(i theta) with x in [0, 1) (one tenth of the
+    draws have x within 1e-6 of 1, one tenth have x = 0); a, b of either sign.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sa = 10.0 ** rng.uniform(-6, 6, size=count)
+    sb = 10.0 ** rng.uniform(-6, 6, size=count)
+    x = rng.uniform(0.0, 1.0, size=count)
+    kind = rng.integers(0, 10, size=count)
+    x = np.where(kind == 0, 1.0 - 10.0 ** rng.uniform(-12, -6, size=count), x)
+    x = np.where(kind == 1, 0.0, x)
+    th = rng.uniform(-math.pi, math.pi, size=count)
+    sc = np.sqrt(sa * sb) * x * np.exp(1j * th)
+    scale_h = 10.0 ** rng.uniform(-6, 6, size=count)
+    a = scale_h * sa * rng.standard_normal(count)
+    b = scale_h * sb * rng.standard_normal(count) * 10.0 ** rng.uniform(-2, 2, size=count)
+    c = scale_h * np.sqrt(sa * sb) * (rng.standard_normal(count)
+                                       + 1j * rng.standard_normal(count))
+    return dict(a=a, b=b, c=c, sa=sa, sb=sb, sc=sc)
