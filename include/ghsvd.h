@@ -1,0 +1,207 @@
+/*
+ * ghsvd.h -- C interface of the MI355X (gfx950) implicit Hari-Zimmermann
+ * generalized hyperbolic SVD solver.
+ *
+ * The method (Singer, Di Napoli, Novakovic, Caklovic, arXiv:1907.08560):
+ * given F (m x n), a signature J = diag(+-1) (m entries) and G (p x n) of full
+ * column rank, the generalized hyperbolic SVD of Section 3, eq. (3.1), yields
+ * the eigenpairs of the Hermitian-definite pencil (H, S) = (F^* J F, G^* G)
+ * by eq. (3.2), without forming H or S and without a Cholesky factorization.
+ * The solver runs the one-time reduction of Section 5 (hyperbolic QR of F
+ * with column pivoting P2, QR of G P2), the one-sided Jacobi-type sweeps of
+ * Section 6 (2x2 step of Section 6.1 on a round-robin ordering; optionally
+ * the Level-2 blocked variant of Section 6.4 with block transforms applied as
+ * matrix-core GEMMs; optionally complex FP32 warm-up sweeps finished in FP64),
+ * and the outputs of Section 6.1.7.
+ *
+ * Conventions for every entry point below:
+ *  - Matrices are column-major (LAPACK).  Complex numbers are interleaved
+ *    (re, im) doubles; "double *F" of an m x n complex matrix with leading
+ *    dimension ldf addresses element (i, j) at F[2 * (i + j * ldf)].
+ *  - Matrix, signature and workspace pointers are DEVICE pointers unless a
+ *    comment says "host".  The caller owns every buffer; the library keeps no
+ *    pointer after a call returns and never modifies inputs.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Work is enqueued on it, and the call returns after the stream has
+ *    drained the work it enqueued, so host outputs (info, counters) are valid
+ *    on return.
+ *  - Return value: 0 success, > 0 warning (outputs valid), < 0 error (device
+ *    outputs undefined).  See ghsvd_status.
+ *  - The library is thread-safe for calls with distinct workspaces; its only
+ *    global state is a mutex-guarded cache of tuned launch parameters.
+ */
+#ifndef GHSVD_H
+#define GHSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GHSVD_OK = 0,
+    GHSVD_NOT_CONVERGED = 1, /* sweep cap reached; outputs are the last iterate          */
+    GHSVD_EINVAL = -1,       /* bad size, leading dimension, NULL pointer or J entry       */
+    GHSVD_ERANK = -2,        /* G numerically rank deficient (or JQR breakdown)           */
+    GHSVD_ENONFINITE = -3,   /* NaN or Inf in the inputs or produced during the sweeps    */
+    GHSVD_ENOMEM = -4,       /* workspace too small (lwork < ghsvd_workspace_size)       */
+    GHSVD_EDEVICE = -5       /* a HIP runtime call failed                                 */
+} ghsvd_status;
+
+enum { GHSVD_FP64 = 0, GHSVD_MIXED = 1 };          /* ghsvd_options.precision */
+enum { GHSVD_POINTWISE = 0, GHSVD_BLOCKED = 1 };   /* ghsvd_options.variant   */
+
+typedef struct {
+    int precision;      /* GHSVD_FP64, or GHSVD_MIXED: complex FP32 warm-up sweeps, then
+                           the FP32 transform applied in FP64 and FP64 sweeps finish      */
+    int variant;        /* GHSVD_POINTWISE (Section 6.3) or GHSVD_BLOCKED (Section 6.4)   */
+    int reduce;         /* 1: reduce to square factors first (Section 5) when m > n or
+                           p > n; 0: sweep the tall factors as given                       */
+    int block_width;    /* blocked variant: block-column width w (8, 16 or 32); 0 = auto   */
+    int waves_per_pair; /* pointwise pair kernel: 64-lane wavefronts per pivot pair
+                           (1, 2, 4, 8 or 16); 0 = auto                                    */
+    int max_sweeps;     /* sweep cap C_max per precision stage; 0 -> 60 (Algorithm 2 uses
+                           ~30 on well-conditioned data; the count grows with cond(S))    */
+    int sort;           /* 1: ascending lambda, X's columns permuted alike; 0: unsorted   */
+    int crit_literal;   /* 0: criterion (6.12) with sqrt(|h_pp||h_qq|); 1: the printed
+                           product form max*eps*sqrt(n)*min                                */
+} ghsvd_options;
+
+typedef struct {
+    int status;
+    int sweeps_fp32;           /* FP32 warm-up sweeps (blocked or pointwise)                */
+    int sweeps_fp64;           /* FP64 sweeps (blocked plus pointwise)                      */
+    int sweeps_blocked;        /* of those, blocked (Level 2) sweeps                        */
+    int n2x2;                  /* 2x2 pivots taken by the hyperbolic QR of F                */
+    int m_r, p_r;              /* row counts of F and G as swept (n after the reduction)    */
+    int n_plus;                /* +1 entries of the signature of the swept F               */
+    long long pairs_visited;   /* pivot pairs visited (outer and inner levels)              */
+    long long pairs_transformed;
+    long long pairs_big;
+} ghsvd_info;
+
+/* Fills *opt with the defaults: FP64, pointwise, reduce = 1, auto widths,
+ * max_sweeps = 60, sort = 1, crit_literal = 0. */
+void ghsvd_default_options(ghsvd_options *opt);
+
+/* Bytes of device workspace ghsvd_solve needs for an m x n F, p x n G.
+ * opt may be NULL (defaults). Returns 0 for invalid sizes. */
+size_t ghsvd_workspace_size(int m, int n, int p, const ghsvd_options *opt);
+
+/*
+ * Solves (F^* J F) X = (G^* G) X diag(lambda), X^* (G^* G) X = I  (eq. (3.2)).
+ *   m, n, p    sizes; require n >= 1, m >= n, p >= n.
+ *   F, ldf     device, m x n complex128, ldf >= m.
+ *   J          device, m int8 entries, each +1 or -1 (else GHSVD_EINVAL).
+ *   G, ldg     device, p x n complex128, ldg >= p, full column rank.
+ *   lambda     device, n doubles out: lambda_j = +-(Sigma_F / Sigma_G)^2_j = h_jj / s_jj,
+ *              the signed squared generalized hyperbolic singular values.
+ *   X, ldx     device, n x n complex128 out, ldx >= n: the S-orthonormal generalized
+ *              eigenvectors (column j belongs to lambda_j).
+ *   work       device workspace of lwork >= ghsvd_workspace_size(m, n, p, opt) bytes,
+ *              256-byte aligned; NULL makes the library allocate and free its own.
+ *   opt        host, may be NULL (defaults).
+ *   info       host, may be NULL; receives counters and the status.
+ * Errors: GHSVD_EINVAL for sizes / ld / NULL / J entries; GHSVD_ERANK when a pivot
+ * pair of G is numerically parallel, a column of G vanishes, or the JQR meets a
+ * zero J-norm; GHSVD_ENONFINITE for NaN/Inf; GHSVD_ENOMEM for a short workspace.
+ */
+int ghsvd_solve(int m, int n, int p, const double *F, int ldf, const int8_t *J,
+                const double *G, int ldg, double *lambda, double *X, int ldx,
+                void *work, size_t lwork, const ghsvd_options *opt, ghsvd_info *info,
+                void *stream);
+
+/* Workspace for ghsvd_solve_batched (host arrays m, n, p of length batch). */
+size_t ghsvd_workspace_size_batched(int batch, const int *m, const int *n, const int *p,
+                                    const ghsvd_options *opt);
+
+/*
+ * Many independent pencils (k-points) of uneven order in one call: one
+ * reduction per pencil, then all pencils' sweeps run together, each launch
+ * covering every still-active pencil; a pencil retires when its own sweep
+ * has no big transformation.  m, n, p, ldf, ldg, ldx: host arrays [batch];
+ * F, J, G, lambda, X: host arrays [batch] of device pointers (same meaning as
+ * ghsvd_solve).  info: host array [batch] (may be NULL).  Returns the worst
+ * per-pencil status (an error if any pencil failed, else a warning if any
+ * pencil hit the sweep cap, else 0).
+ */
+int ghsvd_solve_batched(int batch, const int *m, const int *n, const int *p,
+                        const double *const *F, const int *ldf, const int8_t *const *J,
+                        const double *const *G, const int *ldg, double *const *lambda,
+                        double *const *X, const int *ldx, void *work, size_t lwork,
+                        const ghsvd_options *opt, ghsvd_info *info, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Component entry points: each runs one stage of the path above, so that a
+ * stage can be checked on its own.  Same conventions as ghsvd_solve.
+ * ------------------------------------------------------------------------- */
+
+/*
+ * One-time reduction (Section 5, eq. (5.1)): hyperbolic QR of F with
+ * diagonal plus Bunch-Kaufman partial column pivoting (Section 5.2.1),
+ * hyperbolic Householder reflectors (Theorem 5.1, Section 5.3) and the 2x2
+ * (J, I) URV pivot step; then the Householder QR of G P2 (R_kk =
+ * -e^{i arg x_1} ||x||).  Outputs: Fsq (n x n, ldfs >= n, block upper
+ * triangular, zeros below), Jsq (n int8), Gsq (n x n, ldgs >= n, upper
+ * triangular), perm (n ints: column i of F P2 is column perm[i] of F), all
+ * device; *n2x2 (host) the number of 2x2 pivots.  Then
+ * Fsq^* Jsq Fsq = P2^T F^* J F P2 and Gsq^* Gsq = P2^T G^* G P2.
+ */
+int ghsvd_reduce(int m, int n, int p, const double *F, int ldf, const int8_t *J,
+                 const double *G, int ldg, double *Fsq, int ldfs, int8_t *Jsq,
+                 double *Gsq, int ldgs, int *perm, int *n2x2, void *stream);
+
+/*
+ * The 2x2 step of Section 6.1 for `count` independent pivot pairs (device
+ * arrays): a, b, sa, sb real; c, sc complex (interleaved); tol = eps*sqrt(n).
+ * Z (device, 8 doubles per pair) receives Z' = D0 Z column-major (z11, z21,
+ * z12, z22 as re/im), kind (device int per pair) 0 skipped, 1 small, 2 big,
+ * < 0 error (as ghsvd_status).
+ */
+int ghsvd_pair_params(int count, const double *a, const double *b, const double *c,
+                      const double *sa, const double *sb, const double *sc, double tol,
+                      int crit_literal, double *Z, int *kind, void *stream);
+
+/*
+ * Runs `nsweeps` pointwise FP64 sweeps (or fewer, when a sweep has no big
+ * transformation) in place on F (m x n, rows 0..n_plus-1 carry J = +1, the
+ * rest J = -1), G (p x n) and Z (n x n, caller-initialized, normally I), on
+ * the round-robin ordering of ghsvd_round_robin, waves_per_pair as in
+ * ghsvd_options (0 = auto).  counters (host, 3 * nsweeps long longs) gets
+ * (visited, transformed, big) per sweep; *sweeps_done (host) the sweeps run.
+ */
+int ghsvd_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, double *G, int ldg,
+                 double *Z, int ldz, int nsweeps, int waves_per_pair, int crit_literal,
+                 long long *counters, int *sweeps_done, void *stream);
+
+/*
+ * The round-robin ordering (host): N = n rounded up to even; step s pairs
+ * slot N-1 with s and (s+k) mod (N-1) with (s-k) mod (N-1), k = 1..N/2-1;
+ * each pair as p < q; a pair meeting index n (odd n) is a bye, p = q = -1.
+ * p_out, q_out: host arrays of (N-1) * N/2 ints, step-major.  Returns N-1
+ * (the steps per sweep), or -1 for n < 1.
+ */
+int ghsvd_round_robin(int n, int *p_out, int *q_out);
+
+/*
+ * Kernel timing of the pointwise pair kernel, for measurement harnesses.
+ * ghsvd_profile_enable(every): from now on every `every`-th pair-kernel launch
+ * (per process) is bracketed by two HIP events recorded on the stream the
+ * kernel is launched on; every <= 0 disables it.  ghsvd_profile_read (host
+ * outputs) waits for the recorded events, returns the summed kernel
+ * milliseconds of the timed launches, their count, and the count of all
+ * pair-kernel launches since enabling, then clears the record.
+ */
+void ghsvd_profile_enable(int every);
+int ghsvd_profile_read(double *ms, long long *timed, long long *launches);
+
+/* Human-readable name of a status value (static storage). */
+const char *ghsvd_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GHSVD_H */
