@@ -58,6 +58,9 @@ def main():
     ap.add_argument("--variant", default="pointwise", choices=["pointwise", "blocked"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-every", type=int, default=8)
+    ap.add_argument("--max-sweeps", type=int, default=0)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -66,6 +69,17 @@ def main():
 
     import torch
 
+    if args.copy_probe:
+        # A plain copy of known size: reads and writes copy_probe bytes once.
+        src = torch.ones(args.copy_probe // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 3}), flush=True)
+        return
+
     from paper_1907_08560_amd import ghsvd, synth
 
     dev = torch.device("cuda:0")
@@ -73,7 +87,7 @@ def main():
     F = ghsvd.to_device_fortran(P.F, dev)
     G = ghsvd.to_device_fortran(P.G, dev)
     J = torch.from_numpy(P.J).to(dev)
-    kw = dict(precision=args.precision, variant=args.variant)
+    kw = dict(precision=args.precision, variant=args.variant, max_sweeps=args.max_sweeps)
     opt = ghsvd.options(**kw)
     work = torch.empty(ghsvd.workspace_size(P.m, P.n, P.p, opt), dtype=torch.uint8, device=dev)
     lam = torch.empty(P.n, dtype=torch.float64, device=dev)

@@ -177,6 +177,22 @@ int ghsvd_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, double *G,
                  long long *counters, int *sweeps_done, void *stream);
 
 /*
+ * Runs up to `nsweeps` Level-2 blocked FP64 sweeps (Section 6.4, one inner
+ * sweep per block pivot) in place on F, G, Z (layout as ghsvd_sweeps) with
+ * block width block_width (8 or 16; 0 = auto), stopping after a block sweep
+ * without big inner transformations.  Block b holds columns
+ * [b w, min(b w + w, n)), nb = ceil(n / w) rounded up to even blocks are
+ * paired by ghsvd_round_robin(nb); within a block pair (a, b) the pivot
+ * columns are a's then b's, and the inner sweep visits them in
+ * ghsvd_round_robin(c) order with tol = eps sqrt(c).  counters (host,
+ * 3 * nsweeps) get (visited, transformed, big) inner pairs per block sweep.
+ * Requires n >= 4.
+ */
+int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, double *G, int ldg,
+                       double *Z, int ldz, int block_width, int nsweeps, int crit_literal,
+                       long long *counters, int *sweeps_done, void *stream);
+
+/*
  * The round-robin ordering (host): N = n rounded up to even; step s pairs
  * slot N-1 with s and (s+k) mod (N-1) with (s-k) mod (N-1), k = 1..N/2-1;
  * each pair as p < q; a pair meeting index n (odd n) is a bye, p = q = -1.

@@ -758,3 +758,134 @@ int ora_ghsvd(int m, int n, int p, const cplx *F, int ldf, const signed char *J,
     free(perm);
     return status;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Section 6.4: Level-2 blocked sweeps, Block-Oriented (BO) inner level.     */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Block columns of width w: block b holds columns [b w, min(b w + w, n)); the
+ * number of blocks nb is ceil(n / w) rounded up to even (trailing blocks may
+ * be narrow or empty).  A block step pairs blocks by the round-robin ordering
+ * over nb; for a block pair (a, b) the pivot columns are those of a followed
+ * by those of b (c of them).  The block pivot is shortened by the (J)QR
+ * approach of Section 6.4.2: JQR of F_C under J gives F^ (c x c) with J^ and
+ * P, QR of G_C P gives G^; with the columns put back in the pivot order
+ * (F~ = F^ P^T, G~ = G^ P^T) they satisfy F~^* J^ F~ = F_C^* J F_C and
+ * G~^* G~ = G_C^* G_C.  One inner sweep of Algorithm 2 (BO: C_max = 1, the
+ * round-robin order over c) on (F~, J^, G~) accumulates Z^ (c x c), and, if
+ * it transformed anything, F_C, G_C and Z_C are multiplied by Z^
+ * (Section 6.4.3).  After each block sweep the iteration stops when the
+ * inner sweeps applied no big transformation.  stats as ora_hz_run, counting
+ * inner pivot pairs.  eps is the machine precision of (6.12) with n the
+ * order of the block pivot (tol = eps sqrt(c)).
+ */
+int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J,
+                     cplx *G, int ldg, cplx *Z, int ldz, int w, int max_sweeps,
+                     double eps, int crit_literal, long long *stats)
+{
+    if (m < 1 || n < 2 || p < 1 || ldf < m || ldg < p || ldz < n || w < 1 || max_sweeps < 1)
+        return ORA_EINVAL;
+    for (int i = 0; i < 5; ++i) stats[i] = 0;
+    int nb = (n + w - 1) / w;
+    if (nb % 2) nb += 1;
+    int bsteps = 0;
+    int *bp = malloc(sizeof(int) * (size_t)nb * nb), *bq = malloc(sizeof(int) * (size_t)nb * nb);
+    bsteps = ora_round_robin(nb, bp, bq);
+    const int bslots = nb / 2;
+    const int cmax = 2 * w;
+    if (m < cmax || p < cmax) { free(bp); free(bq); return ORA_EINVAL; }
+    int *cols = malloc(sizeof(int) * (size_t)cmax);
+    cplx *FC = malloc(sizeof(cplx) * (size_t)m * cmax);
+    cplx *GC = malloc(sizeof(cplx) * (size_t)p * cmax);
+    cplx *Ft = malloc(sizeof(cplx) * (size_t)cmax * cmax);
+    cplx *Gt = malloc(sizeof(cplx) * (size_t)cmax * cmax);
+    cplx *Zh = malloc(sizeof(cplx) * (size_t)cmax * cmax);
+    cplx *tmp = malloc(sizeof(cplx) * (size_t)(m > p ? (m > n ? m : n) : (p > n ? p : n)) * cmax);
+    signed char *Jw = malloc((size_t)m);
+    int *perm = malloc(sizeof(int) * (size_t)cmax);
+    int *ip = malloc(sizeof(int) * (size_t)cmax * cmax), *iq = malloc(sizeof(int) * (size_t)cmax * cmax);
+    int status = ORA_NOT_CONVERGED;
+    for (int sweep = 1; sweep <= max_sweeps; ++sweep) {
+        long long tr = 0, big = 0;
+        for (int s = 0; s < bsteps; ++s) {
+            for (int k = 0; k < bslots; ++k) {
+                const int a = bp[s * bslots + k], b = bq[s * bslots + k];
+                if (a < 0) continue;
+                int c = 0;
+                for (int j = a * w; j < a * w + w && j < n; ++j) cols[c++] = j;
+                for (int j = b * w; j < b * w + w && j < n; ++j) cols[c++] = j;
+                if (c < 2) continue;
+                for (int j = 0; j < c; ++j) {
+                    for (int i = 0; i < m; ++i) FC[(size_t)j * m + i] = COL(F, ldf, i, cols[j]);
+                    for (int i = 0; i < p; ++i) GC[(size_t)j * p + i] = COL(G, ldg, i, cols[j]);
+                }
+                /* (J)QR shortening of the block pivot */
+                memcpy(Jw, J, (size_t)m);
+                int n2 = 0;
+                for (int j = 0; j < c; ++j)
+                    for (int i = 0; i < m; ++i) tmp[(size_t)j * m + i] = FC[(size_t)j * m + i];
+                int st = ora_jqr(m, c, tmp, m, Jw, perm, &n2);
+                if (st != ORA_OK) { status = st; goto done; }
+                for (int j = 0; j < c; ++j)
+                    for (int i = 0; i < c; ++i) Ft[(size_t)perm[j] * c + i] = tmp[(size_t)j * m + i];
+                for (int j = 0; j < c; ++j)
+                    for (int i = 0; i < p; ++i) tmp[(size_t)j * p + i] = GC[(size_t)perm[j] * p + i];
+                st = ora_qr(p, c, tmp, p);
+                if (st != ORA_OK) { status = st; goto done; }
+                for (int j = 0; j < c; ++j)
+                    for (int i = 0; i < c; ++i) Gt[(size_t)perm[j] * c + i] = tmp[(size_t)j * p + i];
+                /* one inner sweep (BO), round-robin over the c pivot columns */
+                for (int j = 0; j < c; ++j)
+                    for (int i = 0; i < c; ++i) Zh[(size_t)j * c + i] = (i == j) ? 1.0 : 0.0;
+                const int isteps = ora_round_robin(c, ip, iq);
+                const int islots = (c + (c % 2)) / 2;
+                const double tol = eps * sqrt((double)c);
+                long long itr = 0;
+                for (int is = 0; is < isteps; ++is)
+                    for (int ik = 0; ik < islots; ++ik) {
+                        const int pc = ip[is * islots + ik], qc = iq[is * islots + ik];
+                        if (pc < 0) continue;
+                        const int kind = hz_pair(c, c, c, Ft, c, Jw, Gt, c, Zh, c, pc, qc, tol,
+                                                 crit_literal);
+                        stats[1]++;
+                        if (kind == ORA_ERANK) continue; /* left to the finishing sweeps */
+                        if (kind < 0) { status = kind; goto done; }
+                        if (kind > 0) { tr++; itr++; }
+                        if (kind == 2) big++;
+                    }
+                if (itr == 0) continue;
+                /* F_C <- F_C Z^, G_C <- G_C Z^, Z_C <- Z_C Z^ (Section 6.4.3) */
+                for (int j = 0; j < c; ++j)
+                    for (int i = 0; i < m; ++i) {
+                        cplx acc = 0.0;
+                        for (int l = 0; l < c; ++l) acc += FC[(size_t)l * m + i] * Zh[(size_t)j * c + l];
+                        COL(F, ldf, i, cols[j]) = acc;
+                    }
+                for (int j = 0; j < c; ++j)
+                    for (int i = 0; i < p; ++i) {
+                        cplx acc = 0.0;
+                        for (int l = 0; l < c; ++l) acc += GC[(size_t)l * p + i] * Zh[(size_t)j * c + l];
+                        COL(G, ldg, i, cols[j]) = acc;
+                    }
+                for (int j = 0; j < c; ++j)
+                    for (int i = 0; i < n; ++i) tmp[(size_t)j * n + i] = COL(Z, ldz, i, cols[j]);
+                for (int j = 0; j < c; ++j)
+                    for (int i = 0; i < n; ++i) {
+                        cplx acc = 0.0;
+                        for (int l = 0; l < c; ++l) acc += tmp[(size_t)l * n + i] * Zh[(size_t)j * c + l];
+                        COL(Z, ldz, i, cols[j]) = acc;
+                    }
+            }
+        }
+        stats[0] = sweep;
+        stats[2] += tr;
+        stats[3] += big;
+        stats[4] = big;
+        if (big == 0) { status = ORA_OK; break; }
+    }
+done:
+    free(bp); free(bq); free(cols); free(FC); free(GC); free(Ft); free(Gt); free(Zh); free(tmp);
+    free(Jw); free(perm); free(ip); free(iq);
+    return status;
+}

@@ -62,6 +62,9 @@ class Oracle:
                                 _c_int, _c_int, _c_int, _c_dbl, _c_int, _c_int, _p, _p,
                                 _c_int, _p]
         L.ora_ghsvd.restype = _c_int
+        L.ora_hz_block_run.argtypes = [_c_int, _c_int, _c_int, _p, _c_int, _p, _p, _c_int, _p,
+                                       _c_int, _c_int, _c_int, _c_dbl, _c_int, _p]
+        L.ora_hz_block_run.restype = _c_int
 
     # -- 2x2 step -------------------------------------------------------------
     def pair_params(self, a, b, c, sa, sb, sc, tol, crit_literal=0):
@@ -101,6 +104,21 @@ class Oracle:
                                  p, Z.ctypes.data, n, int(order), int(max_sweeps),
                                  float(eps), int(crit_literal), int(stop_rule),
                                  stats.ctypes.data)
+        return st, F, G, Z, stats
+
+    def hz_block_run(self, F, J, G, Z=None, w=8, max_sweeps=30, eps=EPS64, crit_literal=0):
+        """Level-2 BO block sweeps in place on copies; returns (status, F, G, Z, stats)."""
+        F = np.array(F, dtype=np.complex128, order="F", copy=True)
+        G = np.array(G, dtype=np.complex128, order="F", copy=True)
+        m, n = F.shape
+        p = G.shape[0]
+        Z = (np.eye(n, dtype=np.complex128, order="F") if Z is None
+             else np.array(Z, dtype=np.complex128, order="F", copy=True))
+        J8 = np.ascontiguousarray(J, dtype=np.int8)
+        stats = np.zeros(6, dtype=np.int64)
+        st = self.lib.ora_hz_block_run(m, n, p, F.ctypes.data, m, J8.ctypes.data, G.ctypes.data,
+                                       p, Z.ctypes.data, n, int(w), int(max_sweeps), float(eps),
+                                       int(crit_literal), stats.ctypes.data)
         return st, F, G, Z, stats
 
     def hz_post(self, F, J, G, Z, sort=1):

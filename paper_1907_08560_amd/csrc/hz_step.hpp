@@ -23,8 +23,11 @@ struct Zp {
 // = 1 or not, Section 6.1.7), GHSVD_ERANK (G pair numerically dependent) or
 // GHSVD_ENONFINITE.  Readings: sqrt form of (6.12) unless crit_literal;
 // sigma = +1 at h = 0; the prescaled entries enter (6.4)-(6.12).
+// f32_big = 1 classifies "big" with cos phi and cos psi rounded to FP32 (the
+// FP32 warm-up stage).
 __host__ __device__ inline int hz_step(double a, double b, double2 c, double sa, double sb,
-                                       double2 sc, double tol, int crit_literal, Zp &z) {
+                                       double2 sc, double tol, int crit_literal, Zp &z,
+                                       int f32_big = 0) {
     z.z11 = cmk(1.0, 0.0);
     z.z21 = cmk(0.0, 0.0);
     z.z12 = cmk(0.0, 0.0);
@@ -107,7 +110,10 @@ __host__ __device__ inline int hz_step(double a, double b, double2 c, double sa,
         w12 = cscale(ea, rt);
         w21 = cscale(eb, -rt);
         w22 = cmk(cpsi * rt, 0.0);
-        kind = (cphi == 1.0 && cpsi == 1.0) ? kSmall : kBig;
+        if (f32_big)
+            kind = ((float)cphi == 1.0f && (float)cpsi == 1.0f) ? kSmall : kBig;
+        else
+            kind = (cphi == 1.0 && cpsi == 1.0) ? kSmall : kBig;
     }
     // Z' = D0 Z: row 1 scaled by d_p, row 2 by d_q.
     z.z11 = cscale(w11, dp);

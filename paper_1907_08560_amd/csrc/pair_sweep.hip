@@ -112,7 +112,8 @@ __global__ __launch_bounds__(NT) void k_pair(SweepArgs A, int step) {
     block_sum<8>(v, red);
 
     Zp z;
-    int kind = hz_step(v[0], v[1], cmk(v[2], v[3]), v[4], v[5], cmk(v[6], v[7]), A.tol, A.crit, z);
+    int kind = hz_step(v[0], v[1], cmk(v[2], v[3]), v[4], v[5], cmk(v[6], v[7]), A.tol, A.crit, z,
+                       A.fp32);
     // FP32 stage: a pair that looks dependent in FP32 is left to the FP64 sweeps.
     if (A.fp32 && kind == GHSVD_ERANK) kind = kSkip;
     if (tid == 0) {
@@ -247,6 +248,12 @@ PairGeom choose_pair_geom(int rows, int waves_per_pair) {
     g.nt = nt;
     g.r = (r <= 8) ? r : 0;
     return g;
+}
+
+int enqueue_end_sweep(SweepState *st, unsigned long long *cnt, int nslots, hipStream_t stream) {
+    hipLaunchKernelGGL(k_end_sweep, dim3(1), dim3(256), 0, stream, st, cnt, nslots);
+    GHSVD_HIP(hipGetLastError());
+    return GHSVD_OK;
 }
 
 int enqueue_reset_state(SweepState *st, unsigned long long *slot_cnt, int nslots,

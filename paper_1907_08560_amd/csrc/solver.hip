@@ -159,11 +159,12 @@ int solve_one(const Plan &pl, const PencilWs &w, const double2 *F, long ldf, con
     info.n_plus = nplus;
 
     int status = GHSVD_OK;
+    // Stages: (FP32 warm-up, blocked or pointwise, with its FP64 hand-off) or
+    // (FP64 blocked), then FP64 pointwise sweeps decide convergence.
     if (pl.mixed) {
         rc = run_fp32_stage(pl, w, nplus, o, info, s);
         if (rc < 0) return rc;
-    }
-    if (pl.blocked) {
+    } else if (pl.blocked) {
         rc = run_blocked_fp64(pl, w, nplus, o, info, s);
         if (rc < 0) return rc;
     }

@@ -77,6 +77,9 @@ int run_pointwise_sweeps(SweepArgs a, int max_sweeps, PairGeom g, hipStream_t st
 // bookkeeping) without synchronizing.
 int enqueue_pointwise_sweep(const SweepArgs &a, PairGeom g, hipStream_t stream);
 
+// End-of-sweep bookkeeping over `nslots` per-slot counters (kernel).
+int enqueue_end_sweep(SweepState *st, unsigned long long *cnt, int nslots, hipStream_t stream);
+
 // Zeroes the state and the per-slot counters (kernel, graph-safe).
 int enqueue_reset_state(SweepState *st, unsigned long long *slot_cnt, int nslots,
                         int max_sweeps, hipStream_t stream);

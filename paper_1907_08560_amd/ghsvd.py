@@ -72,6 +72,9 @@ _lib.ghsvd_pair_params.restype = _i
 _lib.ghsvd_sweeps.argtypes = [_i, _i, _i, _p, _i, _i, _p, _i, _p, _i, _i, _i, _i, _p,
                               ctypes.POINTER(_i), _p]
 _lib.ghsvd_sweeps.restype = _i
+_lib.ghsvd_block_sweeps.argtypes = [_i, _i, _i, _p, _i, _i, _p, _i, _p, _i, _i, _i, _i, _p,
+                                    ctypes.POINTER(_i), _p]
+_lib.ghsvd_block_sweeps.restype = _i
 _lib.ghsvd_round_robin.argtypes = [_i, _p, _p]
 _lib.ghsvd_round_robin.restype = _i
 _lib.ghsvd_profile_enable.argtypes = [_i]
@@ -85,7 +88,7 @@ _lib.ghsvd_status_string.restype = ctypes.c_char_p
 EXPORTED = ["ghsvd_default_options", "ghsvd_workspace_size", "ghsvd_solve",
             "ghsvd_workspace_size_batched", "ghsvd_solve_batched", "ghsvd_reduce",
             "ghsvd_pair_params", "ghsvd_sweeps", "ghsvd_round_robin", "ghsvd_status_string",
-            "ghsvd_profile_enable", "ghsvd_profile_read"]
+            "ghsvd_profile_enable", "ghsvd_profile_read", "ghsvd_block_sweeps"]
 
 
 class GhsvdError(RuntimeError):
@@ -240,6 +243,20 @@ def sweeps(F, n_plus: int, G, Z, nsweeps: int, waves_per_pair=0, crit_literal=0,
                            _check_fortran(Z, "Z"), int(nsweeps), int(waves_per_pair),
                            int(crit_literal), cnt.ctypes.data, ctypes.byref(done),
                            _stream_ptr(stream))
+    return rc, done.value, cnt.reshape(nsweeps, 3)
+
+
+def block_sweeps(F, n_plus: int, G, Z, nsweeps: int, block_width=0, crit_literal=0, stream=None):
+    """In-place Level-2 blocked FP64 sweeps; returns (status, sweeps_done, counters (nsweeps, 3))."""
+    m, n = F.shape
+    p = G.shape[0]
+    cnt = np.zeros(3 * nsweeps, dtype=np.int64)
+    done = ctypes.c_int(0)
+    rc = _lib.ghsvd_block_sweeps(m, n, p, F.data_ptr(), _check_fortran(F, "F"), int(n_plus),
+                                 G.data_ptr(), _check_fortran(G, "G"), Z.data_ptr(),
+                                 _check_fortran(Z, "Z"), int(block_width), int(nsweeps),
+                                 int(crit_literal), cnt.ctypes.data, ctypes.byref(done),
+                                 _stream_ptr(stream))
     return rc, done.value, cnt.reshape(nsweeps, 3)
 
 

@@ -1,0 +1,95 @@
+"""GPU parity of the Level-2 blocked variant (Section 6.4) and of the mixed
+FP32 warm-up + FP64 finish, against the CPU oracle, through the C ABI.
+
+The oracle's blocked sweep shortens each block pivot by (J)QR and runs the
+inner sweep one-sidedly; the GPU forms the block pivots with MFMA Grams and
+runs the same 2x2 steps two-sidedly.  Both are the same transformations in
+exact arithmetic, so one block sweep is compared element by element.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1907_08560_amd import ghsvd, synth
+from gpu_util import factor_invariants, host, rel_err, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def small(seed, n, s_lo, ratio_m=1.5, ratio_p=2.0, plus=0.75, j_identity=False):
+    m = int(math.ceil(ratio_m * n))
+    p = int(math.ceil(ratio_p * n))
+    return synth.random_pencil(seed, n, m, int(round(plus * m)), p, s_lo, j_identity=j_identity)
+
+
+@pytest.mark.parametrize("n,w,s_lo", [(96, 8, 1e-3), (96, 16, 1e-3), (70, 16, 1e-2), (41, 8, 1e-2)])
+def test_one_block_sweep_elementwise(oracle, n, w, s_lo):
+    P = small(300 + n + w, n, s_lo)
+    F, J, G = to_dev(P)
+    Z = ghsvd.to_device_fortran(np.eye(n, dtype=np.complex128))
+    rc, done, cnt = ghsvd.block_sweeps(F, P.m_plus, G, Z, 1, block_width=w)
+    st, Fo, Go, Zo, stats = oracle.hz_block_run(P.F, P.J, P.G, w=w, max_sweeps=1)
+    assert done == 1 and rc in (0, 1) and st in (0, 1)
+    assert cnt[0, 0] == stats[1]
+    assert abs(cnt[0, 1] - stats[2]) <= max(2, stats[2] // 100)
+    for A, B in ((host(F), Fo), (host(G), Go), (host(Z), Zo)):
+        colscale = np.linalg.norm(B, axis=0)
+        err = np.max(np.abs(A - B) / colscale[None, :])
+        assert err < 1e-9, err
+
+
+def test_block_sweeps_converge(oracle):
+    P = small(401, 64, 1e-3)
+    F, J, G = to_dev(P)
+    n = P.n
+    Z = ghsvd.to_device_fortran(np.eye(n, dtype=np.complex128))
+    rc, done, cnt = ghsvd.block_sweeps(F, P.m_plus, G, Z, 40, block_width=8)
+    st, Fo, Go, Zo, stats = oracle.hz_block_run(P.F, P.J, P.G, w=8, max_sweeps=40)
+    assert rc == 0 and st == 0
+    assert abs(done - stats[0]) <= 2
+    assert cnt[done - 1, 2] == 0
+
+
+@pytest.mark.parametrize("w", [8, 16])
+def test_blocked_solve_workload_one(oracle, w):
+    P = synth.workload_pencil(1)
+    F, J, G = to_dev(P)
+    lam, X, info = ghsvd.solve(F, J, G, variant="blocked", block_width=w)
+    st, lam_o, X_o, _ = oracle.ghsvd(P.F, P.J, P.G)
+    assert info["status"] == 0 and st == 0
+    assert info["sweeps_blocked"] > 0 and info["sweeps_fp64"] > info["sweeps_blocked"]
+    lam = host(lam)
+    assert rel_err(lam, lam_o) <= 1e-12
+    e_s, e_h, e_d = factor_invariants(P.F, P.J, P.G, lam, host(X))
+    assert e_s < 1e-10 and e_h < 1e-10 and e_d < 1e-10
+
+
+@pytest.mark.parametrize("variant", ["pointwise", "blocked"])
+def test_mixed_solve_workload_one(oracle, variant):
+    P = synth.workload_pencil(1)
+    F, J, G = to_dev(P)
+    lam, X, info = ghsvd.solve(F, J, G, precision="mixed", variant=variant)
+    st, lam_o, X_o, _ = oracle.ghsvd(P.F, P.J, P.G)
+    assert info["status"] == 0 and st == 0
+    # the FP32 stage must have done the bulk of the work: a short FP64 finish
+    assert info["sweeps_fp32"] > 0 and 1 <= info["sweeps_fp64"] <= 8, info
+    lam = host(lam)
+    assert rel_err(lam, lam_o) <= 1e-12
+    e_s, e_h, e_d = factor_invariants(P.F, P.J, P.G, lam, host(X))
+    assert e_s < 1e-10 and e_h < 1e-10 and e_d < 1e-10
+
+
+@pytest.mark.parametrize("n,s_lo,j_identity", [(150, 1e-5, False), (150, 1e-5, True),
+                                                (257, 1e-6, False)])
+def test_mixed_blocked_sizes(oracle, n, s_lo, j_identity):
+    P = small(500 + n, n, s_lo, j_identity=j_identity)
+    F, J, G = to_dev(P)
+    st, lam_o, _, _ = oracle.ghsvd(P.F, P.J, P.G, reduce=True, order=1, max_sweeps=80)
+    assert st == 0
+    bound = 1e-12 if s_lo >= 1e-4 else 1e-10
+    for prec, var in (("fp64", "blocked"), ("mixed", "blocked"), ("mixed", "pointwise")):
+        lam, X, info = ghsvd.solve(F, J, G, precision=prec, variant=var)
+        assert info["status"] == 0, (prec, var, info)
+        assert rel_err(host(lam), lam_o) <= bound, (prec, var, rel_err(host(lam), lam_o))
