@@ -171,13 +171,23 @@ __global__ __launch_bounds__(256) void k_blk_gram(BlkArgs A, int step) {
     }
 }
 
+// One inner sweep over the block pivot (H^, S^) in LDS.  An inner step:
+// (a) one lane per pivot pair computes the FP64 2x2 step; (b) every thread
+// takes one 2x2 block (rows of pair k, columns of pair k') and applies
+// H <- Z_k^* H Z_k', S <- Z_k^* S Z_k', Zs <- Zs Z_k' to it.  The pairs of a
+// step are disjoint, so the blocks are independent and the two-sided update
+// needs a single pass over H and S.  Pair slots whose second column is a bye
+// or padding (>= c) carry the identity; padding entries are zero and stay so.
 template <int PB>
 __global__ __launch_bounds__(256) void k_blk_inner(BlkArgs A, int step) {
+    constexpr int NP = PB / 2;   // pivot pair slots per inner step
+    constexpr int NB = NP * NP;  // 2x2 blocks
     __shared__ double2 H[PB][PB + 1];
     __shared__ double2 S[PB][PB + 1];
     __shared__ double2 Zs[PB][PB + 1];
-    __shared__ double2 zpar[PB / 2][4];
-    __shared__ int kind_s[PB / 2];
+    __shared__ double2 zpar[NP][4];
+    __shared__ int pq_s[NP][2];
+    __shared__ int act_s[NP];
     __shared__ double red[3 * 4];
     if (A.st->done) return;
     const int bpi = blockIdx.x;
@@ -207,65 +217,84 @@ __global__ __launch_bounds__(256) void k_blk_inner(BlkArgs A, int step) {
     const double tol = A.eps * sqrt((double)c);
     double cv = 0.0, ct = 0.0, cbig = 0.0;
     for (int s = 0; s < C - 1; ++s) {
-        if (tid < islots) {
-            int pp, qq;
-            rr_pair(C, s, tid, pp, qq);
-            int kind = kSkip;
-            if (qq < c) {
-                Zp z;
-                kind = hz_step(H[pp][pp].x, H[qq][qq].x, H[pp][qq], S[pp][pp].x, S[qq][qq].x,
-                               S[pp][qq], tol, A.crit, z, A.fp32);
-                cv += 1.0;
-                if (kind == GHSVD_ENONFINITE) atomicCAS(&A.st->err, 0, GHSVD_ENONFINITE);
-                if (kind < 0) kind = kSkip;  // dependent-looking pivot: left to the finish
-                zpar[tid][0] = z.z11;
-                zpar[tid][1] = z.z21;
-                zpar[tid][2] = z.z12;
-                zpar[tid][3] = z.z22;
-                ct += kind > 0 ? 1.0 : 0.0;
-                cbig += kind == kBig ? 1.0 : 0.0;
+        if (tid < NP) {
+            int pp = -1, qq = -1, kind = kSkip;
+            if (tid < islots) {
+                rr_pair(C, s, tid, pp, qq);
+                if (qq < c) {
+                    Zp z;
+                    kind = hz_step_fast(H[pp][pp].x, H[qq][qq].x, H[pp][qq], S[pp][pp].x,
+                                        S[qq][qq].x, S[pp][qq], tol, A.crit, z, A.fp32);
+                    cv += 1.0;
+                    if (kind == GHSVD_ENONFINITE) atomicCAS(&A.st->err, 0, GHSVD_ENONFINITE);
+                    if (kind < 0) kind = kSkip;  // dependent-looking pivot: left to the finish
+                    zpar[tid][0] = z.z11;
+                    zpar[tid][1] = z.z21;
+                    zpar[tid][2] = z.z12;
+                    zpar[tid][3] = z.z22;
+                    ct += kind > 0 ? 1.0 : 0.0;
+                    cbig += kind == kBig ? 1.0 : 0.0;
+                }
             }
-            kind_s[tid] = kind;
+            pq_s[tid][0] = pp;
+            pq_s[tid][1] = qq;
+            act_s[tid] = kind > 0;
         }
         __syncthreads();
-        // columns: M <- M Z' for M in {H, S, Zs}
-        for (int t = tid; t < islots * c; t += 256) {
-            const int k = t / c, i = t % c;
-            if (kind_s[k] <= 0) continue;
-            int pp, qq;
-            rr_pair(C, s, k, pp, qq);
-            const double2 z11 = zpar[k][0], z21 = zpar[k][1], z12 = zpar[k][2], z22 = zpar[k][3];
-            double2 x, y;
-            x = H[i][pp];
-            y = H[i][qq];
-            H[i][pp] = cadd(cmul(x, z11), cmul(y, z21));
-            H[i][qq] = cadd(cmul(x, z12), cmul(y, z22));
-            x = S[i][pp];
-            y = S[i][qq];
-            S[i][pp] = cadd(cmul(x, z11), cmul(y, z21));
-            S[i][qq] = cadd(cmul(x, z12), cmul(y, z22));
-            x = Zs[i][pp];
-            y = Zs[i][qq];
-            Zs[i][pp] = cadd(cmul(x, z11), cmul(y, z21));
-            Zs[i][qq] = cadd(cmul(x, z12), cmul(y, z22));
-        }
-        __syncthreads();
-        // rows: M <- Z'^* M for M in {H, S}
-        for (int t = tid; t < islots * c; t += 256) {
-            const int k = t / c, j = t % c;
-            if (kind_s[k] <= 0) continue;
-            int pp, qq;
-            rr_pair(C, s, k, pp, qq);
-            const double2 z11 = zpar[k][0], z21 = zpar[k][1], z12 = zpar[k][2], z22 = zpar[k][3];
-            double2 x, y;
-            x = H[pp][j];
-            y = H[qq][j];
-            H[pp][j] = cadd(cmulc(z11, x), cmulc(z21, y));
-            H[qq][j] = cadd(cmulc(z12, x), cmulc(z22, y));
-            x = S[pp][j];
-            y = S[qq][j];
-            S[pp][j] = cadd(cmulc(z11, x), cmulc(z21, y));
-            S[qq][j] = cadd(cmulc(z12, x), cmulc(z22, y));
+        for (int blk = tid; blk < NB; blk += 256) {
+            const int kr = blk % NP, kc = blk / NP;  // row pair, column pair
+            const int p1 = pq_s[kr][0], q1 = pq_s[kr][1];
+            const int p2 = pq_s[kc][0], q2 = pq_s[kc][1];
+            const bool ar = act_s[kr], ac = act_s[kc];
+            if (p1 < 0 || p2 < 0 || (!ar && !ac)) continue;  // padding slot or identity
+            // loads first (one LDS round trip), then arithmetic, then stores
+            const double2 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0);
+            double2 zr[4], zc[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                zr[e] = zpar[kr][e];
+                zc[e] = zpar[kc][e];
+            }
+            const double2 h11 = H[p1][p2], h12 = H[p1][q2], h21 = H[q1][p2], h22 = H[q1][q2];
+            const double2 s11 = S[p1][p2], s12 = S[p1][q2], s21 = S[q1][p2], s22 = S[q1][q2];
+            const double2 w11 = Zs[p1][p2], w12 = Zs[p1][q2], w21 = Zs[q1][p2], w22 = Zs[q1][q2];
+            const double2 r11 = ar ? zr[0] : one, r21 = ar ? zr[1] : zero;
+            const double2 r12 = ar ? zr[2] : zero, r22 = ar ? zr[3] : one;
+            const double2 c11 = ac ? zc[0] : one, c21 = ac ? zc[1] : zero;
+            const double2 c12 = ac ? zc[2] : zero, c22 = ac ? zc[3] : one;
+            // M_blk <- R^* M_blk Cz for H and S; Zs_blk <- Zs_blk Cz
+            double2 x11 = cadd(cmul(h11, c11), cmul(h12, c21));
+            double2 x12 = cadd(cmul(h11, c12), cmul(h12, c22));
+            double2 x21 = cadd(cmul(h21, c11), cmul(h22, c21));
+            double2 x22 = cadd(cmul(h21, c12), cmul(h22, c22));
+            const double2 H11 = cadd(cmulc(r11, x11), cmulc(r21, x21));
+            const double2 H12 = cadd(cmulc(r11, x12), cmulc(r21, x22));
+            const double2 H21 = cadd(cmulc(r12, x11), cmulc(r22, x21));
+            const double2 H22 = cadd(cmulc(r12, x12), cmulc(r22, x22));
+            x11 = cadd(cmul(s11, c11), cmul(s12, c21));
+            x12 = cadd(cmul(s11, c12), cmul(s12, c22));
+            x21 = cadd(cmul(s21, c11), cmul(s22, c21));
+            x22 = cadd(cmul(s21, c12), cmul(s22, c22));
+            const double2 S11 = cadd(cmulc(r11, x11), cmulc(r21, x21));
+            const double2 S12 = cadd(cmulc(r11, x12), cmulc(r21, x22));
+            const double2 S21 = cadd(cmulc(r12, x11), cmulc(r22, x21));
+            const double2 S22 = cadd(cmulc(r12, x12), cmulc(r22, x22));
+            const double2 W11 = cadd(cmul(w11, c11), cmul(w12, c21));
+            const double2 W12 = cadd(cmul(w11, c12), cmul(w12, c22));
+            const double2 W21 = cadd(cmul(w21, c11), cmul(w22, c21));
+            const double2 W22 = cadd(cmul(w21, c12), cmul(w22, c22));
+            H[p1][p2] = H11;
+            H[p1][q2] = H12;
+            H[q1][p2] = H21;
+            H[q1][q2] = H22;
+            S[p1][p2] = S11;
+            S[p1][q2] = S12;
+            S[q1][p2] = S21;
+            S[q1][q2] = S22;
+            Zs[p1][p2] = W11;
+            Zs[p1][q2] = W12;
+            Zs[q1][p2] = W21;
+            Zs[q1][q2] = W22;
         }
         __syncthreads();
     }
@@ -581,7 +610,7 @@ static int run_blocked_sweeps(const Plan &pl, const PencilWs &w, int nplus, cons
         inner = k_blk_inner<16>;
         upd = fp32 ? k_blk_update<float, 16> : k_blk_update<double, 16>;
     }
-    int rc = enqueue_reset_state(w.st, bw.cnt, g.nbp, o.max_sweeps, s);
+    int rc = enqueue_reset_state(w.st, bw.cnt, g.nbp, o.max_sweeps, s, fp32);
     if (rc) return rc;
     SweepState hs;
     for (int sw = 0; sw < o.max_sweeps; ++sw) {
@@ -598,6 +627,7 @@ static int run_blocked_sweeps(const Plan &pl, const PencilWs &w, int nplus, cons
     }
     GHSVD_HIP(hipMemcpyAsync(&hs, w.st, sizeof(SweepState), hipMemcpyDeviceToHost, s));
     GHSVD_HIP(hipStreamSynchronize(s));
+    trace_stage(fp32 ? "blocked-fp32" : "blocked-fp64", hs);
     res.sweeps = hs.sweeps;
     res.converged = hs.converged;
     for (int k = 0; k < hs.sweeps && k < kMaxHist; ++k) {

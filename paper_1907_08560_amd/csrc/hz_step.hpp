@@ -14,6 +14,58 @@ namespace ghsvd {
 
 enum : int { kSkip = 0, kSmall = 1, kBig = 2 };
 
+// Arithmetic policies of the 2x2 step.  IeeeMath: correctly rounded division
+// and square root (host and device).  FastMath (device): the hardware
+// reciprocal / reciprocal square root refined by Newton steps (Markstein's
+// formulation), about one ulp, for the latency-bound inner sweeps of the
+// blocked variant; inputs are finite, positive where a root is taken, and
+// far from the overflow and underflow thresholds.
+struct IeeeMath {
+    __host__ __device__ static double div(double a, double b) { return a / b; }
+    __host__ __device__ static double sqrt_(double x) { return sqrt(x); }
+    __host__ __device__ static double rsqrt(double x) { return 1.0 / sqrt(x); }
+    __host__ __device__ static double hypot_(double a, double b) { return hypot(a, b); }
+};
+
+struct FastMath {
+    __device__ static double rcp(double x) {
+        double r = __builtin_amdgcn_rcp(x);
+        double e = fma(-x, r, 1.0);
+        r = fma(r, e, r);
+        e = fma(-x, r, 1.0);
+        return fma(r, e, r);
+    }
+    __device__ static double div(double a, double b) {
+        const double r = rcp(b);
+        const double q = a * r;
+        return fma(fma(-b, q, a), r, q);
+    }
+    // returns (sqrt(x), 1 / sqrt(x)) for x > 0
+    __device__ static void roots(double x, double &s, double &rs) {
+        double y = __builtin_amdgcn_rsq(x);
+        double g = x * y, h = 0.5 * y;
+        double r = fma(-g, h, 0.5);
+        g = fma(g, r, g);
+        h = fma(h, r, h);
+        r = fma(-g, g, x);
+        s = fma(r, h, g);
+        rs = 2.0 * h;
+    }
+    __device__ static double sqrt_(double x) {
+        if (!(x > 0.0)) return x == 0.0 ? 0.0 : sqrt(x);
+        double s, rs;
+        roots(x, s, rs);
+        return s;
+    }
+    __device__ static double rsqrt(double x) {
+        double s, rs;
+        roots(x, s, rs);
+        // one more Newton step on the reciprocal root
+        return fma(rs, 0.5 * fma(-x * rs, rs, 1.0), rs);
+    }
+    __device__ static double hypot_(double a, double b) { return sqrt_(fma(a, a, b * b)); }
+};
+
 struct Zp {
     double2 z11, z21, z12, z22;  // column update: x_p' = x_p z11 + x_q z21, x_q' = x_p z12 + x_q z22
 };
@@ -25,9 +77,10 @@ struct Zp {
 // sigma = +1 at h = 0; the prescaled entries enter (6.4)-(6.12).
 // f32_big = 1 classifies "big" with cos phi and cos psi rounded to FP32 (the
 // FP32 warm-up stage).
-__host__ __device__ inline int hz_step(double a, double b, double2 c, double sa, double sb,
-                                       double2 sc, double tol, int crit_literal, Zp &z,
-                                       int f32_big = 0) {
+template <class M>
+__host__ __device__ inline int hz_step_m(double a, double b, double2 c, double sa, double sb,
+                                         double2 sc, double tol, int crit_literal, Zp &z,
+                                         int f32_big) {
     z.z11 = cmk(1.0, 0.0);
     z.z21 = cmk(0.0, 0.0);
     z.z12 = cmk(0.0, 0.0);
@@ -38,8 +91,8 @@ __host__ __device__ inline int hz_step(double a, double b, double2 c, double sa,
     if (!(sa > 0.0) || !(sb > 0.0)) return GHSVD_ERANK;
 
     // D0 prescaling (Section 6.1.1), applied per pivot pair.
-    const double dp = 1.0 / sqrt(sa);
-    const double dq = 1.0 / sqrt(sb);
+    const double dp = M::rsqrt(sa);
+    const double dq = M::rsqrt(sb);
     const double dpq = dp * dq;
     const double hpp = a * dp * dp;
     const double hqq = b * dq * dq;
@@ -48,21 +101,21 @@ __host__ __device__ inline int hz_step(double a, double b, double2 c, double sa,
 
     if (hpq.x == 0.0 && hpq.y == 0.0 && spq.x == 0.0 && spq.y == 0.0) return kSkip;
 
-    const double habs = sqrt(cnorm2(hpq));
-    const double x = sqrt(cnorm2(spq));
+    const double habs = M::sqrt_(cnorm2(hpq));
+    const double x = M::sqrt_(cnorm2(spq));
     const double ahp = fabs(hpp), ahq = fabs(hqq);
     const double thr = crit_literal ? (fmax(ahp, ahq) * tol) * fmin(ahp, ahq)
-                                    : tol * sqrt(ahp) * sqrt(ahq);
+                                    : tol * M::sqrt_(ahp) * M::sqrt_(ahq);
     if (!(habs >= thr || x >= tol)) return kSkip;
 
     // Step 1: exp(i alpha_1) = s_pq / |s_pq| (1 when s_pq = 0), S1 = diag(1+x, 1-x).
     double2 e1 = cmk(1.0, 0.0);
     if (x > 0.0) {
-        const double rx = 1.0 / x;
+        const double rx = M::div(1.0, x);
         e1 = cscale(spq, rx);
     }
     if (!(x < 1.0)) return GHSVD_ERANK;
-    const double t = sqrt((1.0 - x) * (1.0 + x));
+    const double t = M::sqrt_((1.0 - x) * (1.0 + x));
     if (!(t > 0.0)) return GHSVD_ERANK;
 
     // Step 2: u + i v = conj(e1) h_pq.
@@ -74,9 +127,9 @@ __host__ __device__ inline int hz_step(double a, double b, double2 c, double sa,
     double2 w11, w21, w12, w22;
     if (h == 0.0 && v == 0.0) {
         // Z = R1 D2 (Section 6.1.6).
-        const double s2 = sqrt(0.5);
-        const double d1 = s2 / sqrt(1.0 + x);
-        const double d2 = s2 / sqrt(1.0 - x);
+        const double s2 = 0.70710678118654752440;
+        const double d1 = s2 * M::rsqrt(1.0 + x);
+        const double d2 = s2 * M::rsqrt(1.0 - x);
         w11 = cmk(d1, 0.0);
         w21 = cmk(e1.x * d1, -e1.y * d1);
         w12 = cmk(-e1.x * d2, -e1.y * d2);
@@ -86,26 +139,26 @@ __host__ __device__ inline int hz_step(double a, double b, double2 c, double sa,
         // Step 3 via (6.7) and (6.11), no trigonometric calls.
         const double sigma = (h >= 0.0) ? 1.0 : -1.0;
         const double twov = 2.0 * v;
-        const double r = hypot(h, twov);
-        const double cos_g = fabs(h) / r;
-        const double sin_g = sigma * twov / r;
+        const double r = M::hypot_(h, twov);
+        const double cos_g = M::div(fabs(h), r);
+        const double sin_g = M::div(sigma * twov, r);
         const double num = sigma * (2.0 * u - (hpp + hqq) * x);
         const double den = t * r;
-        const double rho = hypot(num, den);
-        const double cos_2t = den / rho;
-        const double sin_2t = num / rho;
+        const double rho = M::hypot_(num, den);
+        const double cos_2t = M::div(den, rho);
+        const double sin_2t = M::div(num, rho);
         // (6.10)
         const double base = 1.0 + t * cos_g * cos_2t;
-        const double cphi = sqrt(0.5 * (base + x * sin_2t));
-        const double cpsi = sqrt(0.5 * (base - x * sin_2t));
+        const double cphi = M::sqrt_(0.5 * (base + x * sin_2t));
+        const double cpsi = M::sqrt_(0.5 * (base - x * sin_2t));
         const double im = t * sin_g * cos_2t;
         // e^{i alpha} sin(phi) = e1 ((sin2t - x) + i im) / (2 cos psi)
-        const double ka = 0.5 / cpsi;
+        const double ka = M::div(0.5, cpsi);
         const double2 ea = cmul(e1, cmk((sin_2t - x) * ka, im * ka));
         // e^{-i beta} sin(psi) = conj(e1) ((sin2t + x) - i im) / (2 cos phi)
-        const double kb = 0.5 / cphi;
+        const double kb = M::div(0.5, cphi);
         const double2 eb = cmul(cconj(e1), cmk((sin_2t + x) * kb, -im * kb));
-        const double rt = 1.0 / t;
+        const double rt = M::div(1.0, t);
         w11 = cmk(cphi * rt, 0.0);
         w12 = cscale(ea, rt);
         w21 = cscale(eb, -rt);
@@ -116,6 +169,115 @@ __host__ __device__ inline int hz_step(double a, double b, double2 c, double sa,
             kind = (cphi == 1.0 && cpsi == 1.0) ? kSmall : kBig;
     }
     // Z' = D0 Z: row 1 scaled by d_p, row 2 by d_q.
+    z.z11 = cscale(w11, dp);
+    z.z12 = cscale(w12, dp);
+    z.z21 = cscale(w21, dq);
+    z.z22 = cscale(w22, dq);
+    return kind;
+}
+
+__host__ __device__ inline int hz_step(double a, double b, double2 c, double sa, double sb,
+                                       double2 sc, double tol, int crit_literal, Zp &z,
+                                       int f32_big = 0) {
+    return hz_step_m<IeeeMath>(a, b, c, sa, sb, sc, tol, crit_literal, z, f32_big);
+}
+
+// Latency-oriented form of the same 2x2 step for the blocked variant's inner
+// sweeps (device only): every square root that is followed by a division
+// becomes one reciprocal square root (x = x2 / sqrt(x2) = x2 rsqrt(x2)),
+// the criterion (6.12) is compared in squares, and FastMath supplies the
+// reciprocal roots.  "Small" allows cos phi, cos psi within two ulps below
+// one (the roots are accurate to about one ulp, not correctly rounded).
+__device__ inline int hz_step_fast(double a, double b, double2 c, double sa, double sb,
+                                   double2 sc, double tol, int crit_literal, Zp &z,
+                                   int f32_big) {
+    z.z11 = cmk(1.0, 0.0);
+    z.z21 = cmk(0.0, 0.0);
+    z.z12 = cmk(0.0, 0.0);
+    z.z22 = cmk(1.0, 0.0);
+    // Non-finite entries are not screened here: they propagate into the
+    // columns, where the FP64 pointwise sweeps that follow report them.
+    if (!(sa > 0.0) || !(sb > 0.0)) return GHSVD_ERANK;
+    const double dp = FastMath::rsqrt(sa);
+    const double dq = FastMath::rsqrt(sb);
+    const double dpq = dp * dq;
+    const double hpp = a * dp * dp;
+    const double hqq = b * dq * dq;
+    const double2 hpq = cscale(c, dpq);
+    const double2 spq = cscale(sc, dpq);
+    const double h2 = cnorm2(hpq);
+    const double x2 = cnorm2(spq);
+    if (h2 == 0.0 && x2 == 0.0) return kSkip;
+    const double ahp = fabs(hpp), ahq = fabs(hqq);
+    double thr2;
+    if (crit_literal) {
+        const double t1 = (fmax(ahp, ahq) * tol) * fmin(ahp, ahq);
+        thr2 = t1 * t1;
+    } else {
+        thr2 = (tol * tol) * (ahp * ahq);
+    }
+    if (!(h2 >= thr2 || x2 >= tol * tol)) return kSkip;
+    if (!(x2 < 1.0)) return GHSVD_ERANK;
+    double x = 0.0;
+    double2 e1 = cmk(1.0, 0.0);
+    if (x2 > 0.0) {
+        const double rx = FastMath::rsqrt(x2);
+        x = x2 * rx;
+        e1 = cscale(spq, rx);
+    }
+    const double t2 = (1.0 - x) * (1.0 + x);
+    if (!(t2 > 0.0)) return GHSVD_ERANK;
+    const double rt = FastMath::rsqrt(t2);
+    const double t = t2 * rt;
+    const double2 uv = cmulc(e1, hpq);
+    const double u = uv.x, v = uv.y;
+    const double h = hqq - hpp;
+    int kind;
+    double2 w11, w21, w12, w22;
+    if (h == 0.0 && v == 0.0) {
+        const double s2 = 0.70710678118654752440;
+        const double d1 = s2 * FastMath::rsqrt(1.0 + x);
+        const double d2 = s2 * FastMath::rsqrt(1.0 - x);
+        w11 = cmk(d1, 0.0);
+        w21 = cmk(e1.x * d1, -e1.y * d1);
+        w12 = cmk(-e1.x * d2, -e1.y * d2);
+        w22 = cmk(d2, 0.0);
+        kind = kBig;
+    } else {
+        const double sigma = (h >= 0.0) ? 1.0 : -1.0;
+        const double twov = 2.0 * v;
+        const double q2 = fma(h, h, twov * twov);
+        const double ir = FastMath::rsqrt(q2);
+        const double r = q2 * ir;
+        const double cos_g = fabs(h) * ir;
+        const double sin_g = sigma * twov * ir;
+        const double num = sigma * (2.0 * u - (hpp + hqq) * x);
+        const double den = t * r;
+        const double n2 = fma(num, num, den * den);
+        const double irho = FastMath::rsqrt(n2);
+        const double cos_2t = den * irho;
+        const double sin_2t = num * irho;
+        const double base = 1.0 + t * cos_g * cos_2t;
+        const double ap = 0.5 * (base + x * sin_2t);
+        const double am = 0.5 * (base - x * sin_2t);
+        const double iphi = FastMath::rsqrt(ap);
+        const double ipsi = FastMath::rsqrt(am);
+        const double cphi = ap * iphi;
+        const double cpsi = am * ipsi;
+        const double im = t * sin_g * cos_2t;
+        const double ka = 0.5 * ipsi;
+        const double2 ea = cmul(e1, cmk((sin_2t - x) * ka, im * ka));
+        const double kb = 0.5 * iphi;
+        const double2 eb = cmul(cconj(e1), cmk((sin_2t + x) * kb, -im * kb));
+        w11 = cmk(cphi * rt, 0.0);
+        w12 = cscale(ea, rt);
+        w21 = cscale(eb, -rt);
+        w22 = cmk(cpsi * rt, 0.0);
+        if (f32_big)
+            kind = ((float)cphi == 1.0f && (float)cpsi == 1.0f) ? kSmall : kBig;
+        else
+            kind = (cphi >= 1.0 - 0x1p-52 && cpsi >= 1.0 - 0x1p-52) ? kSmall : kBig;
+    }
     z.z11 = cscale(w11, dp);
     z.z12 = cscale(w12, dp);
     z.z21 = cscale(w21, dq);

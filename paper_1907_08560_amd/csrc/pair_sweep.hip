@@ -9,6 +9,8 @@
 // fixed order, computes the FP64 2x2 step of Section 6.1 (every wavefront
 // redundantly, so no broadcast is needed), and applies Z' to the columns
 // still held in registers, then to the two columns of Z.
+#include <cstdio>
+#include <cstdlib>
 #include <mutex>
 #include <utility>
 #include <vector>
@@ -188,13 +190,16 @@ __global__ __launch_bounds__(256) void k_end_sweep(SweepState *st, unsigned long
         } else if (v[2] == 0.0) {
             st->done = 1;
             st->converged = 1;
+        } else if (st->noise_floor && v[2] * 1024.0 <= v[0]) {
+            st->done = 1;
         } else if (sw + 1 >= st->max_sweeps) {
             st->done = 1;
         }
     }
 }
 
-__global__ void k_reset_state(SweepState *st, unsigned long long *cnt, int nslots, int max_sweeps) {
+__global__ void k_reset_state(SweepState *st, unsigned long long *cnt, int nslots, int max_sweeps,
+                              int noise_floor) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     for (int s = t; s < 3 * nslots; s += gridDim.x * blockDim.x) cnt[s] = 0ull;
     if (t == 0) {
@@ -203,6 +208,7 @@ __global__ void k_reset_state(SweepState *st, unsigned long long *cnt, int nslot
         st->err = 0;
         st->converged = 0;
         st->max_sweeps = max_sweeps;
+        st->noise_floor = noise_floor;
     }
 }
 
@@ -257,12 +263,12 @@ int enqueue_end_sweep(SweepState *st, unsigned long long *cnt, int nslots, hipSt
 }
 
 int enqueue_reset_state(SweepState *st, unsigned long long *slot_cnt, int nslots,
-                        int max_sweeps, hipStream_t stream) {
+                        int max_sweeps, hipStream_t stream, int noise_floor) {
     int blocks = (3 * nslots + 255) / 256;
     if (blocks < 1) blocks = 1;
     if (blocks > 1024) blocks = 1024;
     hipLaunchKernelGGL(k_reset_state, dim3(blocks), dim3(256), 0, stream, st, slot_cnt, nslots,
-                       max_sweeps);
+                       max_sweeps, noise_floor);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }
@@ -318,6 +324,13 @@ int enqueue_pointwise_sweep(const SweepArgs &a, PairGeom g, hipStream_t stream) 
     return GHSVD_OK;
 }
 
+void trace_stage(const char *name, const SweepState &hs) {
+    if (!std::getenv("GHSVD_TRACE")) return;
+    for (int k = 0; k < hs.sweeps && k < kMaxHist; ++k)
+        std::fprintf(stderr, "ghsvd %s sweep %d: visited %llu transformed %llu big %llu\n", name,
+                     k + 1, hs.hist[3 * k], hs.hist[3 * k + 1], hs.hist[3 * k + 2]);
+}
+
 int run_pointwise_sweeps(SweepArgs a, int max_sweeps, PairGeom g, hipStream_t stream,
                          SweepResult &res) {
     res = SweepResult{GHSVD_OK, 0, 0, 0, 0, 0};
@@ -325,7 +338,7 @@ int run_pointwise_sweeps(SweepArgs a, int max_sweeps, PairGeom g, hipStream_t st
         res.converged = 1;
         return GHSVD_OK;
     }
-    int rc = enqueue_reset_state(a.st, a.slot_cnt, a.nslots, max_sweeps, stream);
+    int rc = enqueue_reset_state(a.st, a.slot_cnt, a.nslots, max_sweeps, stream, a.fp32);
     if (rc) return rc;
     SweepState hs;
     for (int sw = 0; sw < max_sweeps; ++sw) {
@@ -338,6 +351,7 @@ int run_pointwise_sweeps(SweepArgs a, int max_sweeps, PairGeom g, hipStream_t st
     }
     GHSVD_HIP(hipMemcpyAsync(&hs, a.st, sizeof(SweepState), hipMemcpyDeviceToHost, stream));
     GHSVD_HIP(hipStreamSynchronize(stream));
+    trace_stage(a.fp32 ? "pointwise-fp32" : "pointwise-fp64", hs);
     res.sweeps = hs.sweeps;
     res.converged = hs.converged;
     for (int s = 0; s < hs.sweeps && s < kMaxHist; ++s) {

@@ -20,7 +20,7 @@ struct SweepState {
     int err;         // first error status (0 = none)
     int converged;   // 1: the last sweep had no big transformation
     int max_sweeps;  // cap of the current stage
-    int stage_sweeps_fp32;
+    int noise_floor;  // 1: also stop once a sweep's big count is at most visited / 1024
     int pad[2];
     unsigned long long hist[3 * kMaxHist];  // (visited, transformed, big) per sweep
 };
@@ -80,8 +80,15 @@ int enqueue_pointwise_sweep(const SweepArgs &a, PairGeom g, hipStream_t stream);
 // End-of-sweep bookkeeping over `nslots` per-slot counters (kernel).
 int enqueue_end_sweep(SweepState *st, unsigned long long *cnt, int nslots, hipStream_t stream);
 
+// When the environment variable GHSVD_TRACE is set, prints the per-sweep
+// counters of a finished stage to stderr (one line per sweep).
+void trace_stage(const char *name, const SweepState &hs);
+
 // Zeroes the state and the per-slot counters (kernel, graph-safe).
+// noise_floor = 1 for the FP32 warm-up: stop once the big transformations
+// of a sweep are at most 1/1024 of the visited pairs (the pairs still
+// rotating then are those FP32 cannot resolve; the FP64 sweeps take over).
 int enqueue_reset_state(SweepState *st, unsigned long long *slot_cnt, int nslots,
-                        int max_sweeps, hipStream_t stream);
+                        int max_sweeps, hipStream_t stream, int noise_floor = 0);
 
 }  // namespace ghsvd

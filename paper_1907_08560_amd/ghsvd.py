@@ -15,7 +15,8 @@ import numpy as np
 import torch
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libghsvd.so")
+# GHSVD_LIB selects another build of the same library (e.g. an instrumented one).
+LIB_PATH = os.environ.get("GHSVD_LIB") or os.path.join(_PKG, "libghsvd.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
