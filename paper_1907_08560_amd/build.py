@@ -49,6 +49,10 @@ def _compile(src: str) -> str:
 def build(jobs: int | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
+    keep = {os.path.basename(x).replace(".hip", ".o") for x in srcs}
+    for f in os.listdir(BUILD):  # objects of sources that no longer exist
+        if f.endswith(".o") and f not in keep:
+            os.remove(os.path.join(BUILD, f))
     jobs = jobs or min(len(srcs), max(1, (os.cpu_count() or 4)))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))

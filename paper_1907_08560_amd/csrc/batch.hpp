@@ -1,0 +1,119 @@
+// batch.hpp -- device-side description of the pencils a launch works on.
+//
+// Every sweep and reduction kernel runs over a batch of pencils (one pencil
+// for ghsvd_solve): the host writes one PencilDev per pencil into device
+// memory, plus prefix sums of the workgroups each pencil needs in a given
+// launch; a workgroup finds its pencil by binary search over the prefix sums.
+// Per-pencil iteration state lives in device memory (SweepState, JqrState),
+// so the launches of a step take the same arguments every time (and can be
+// captured into a graph and replayed).
+#pragma once
+
+#include "hz_common.hpp"
+
+namespace ghsvd {
+
+constexpr int kMaxHist = 128;  // sweeps whose counters are kept on the device
+// Default sweep cap per stage.  Algorithm 2 uses about 30 for the paper's
+// well-conditioned data; the sweep count grows with cond(G^*G) (about 11 at
+// 1e2, 29 at 1e16 for n = 256), so the cap leaves room for cond(S) ~ 1e16.
+constexpr int kDefaultMaxSweeps = 60;
+
+// Iteration state of one pencil in one sweep stage.
+struct SweepState {
+    int done;        // 1: converged, capped, or failed
+    int sweeps;      // sweeps completed in the stage
+    int err;         // first error status (0 = none)
+    int converged;   // 1: the last sweep had no big transformation
+    int max_sweeps;  // cap of the stage
+    int noise_floor; // 1: also stop once a sweep's big count is at most visited / 1024
+    int lstep;       // current step within the sweep
+    unsigned fin;    // workgroups of the current step that have finished
+    unsigned long long hist[3 * kMaxHist];  // (visited, transformed, big) per sweep
+};
+
+// State of the hyperbolic QR of one pencil (the k-loop runs on the device).
+struct JqrState {
+    int k;       // first unreduced column (and row)
+    int piv;     // 1 or 2: pivot size chosen for column k
+    int need2;   // Bunch-Kaufman second test required
+    int ii;      // Bunch-Kaufman candidate column
+    int status;  // 0 or an error
+    int n2x2;    // 2x2 pivots taken
+    int pad[2];
+    double lam;  // |h_{k,ii}|
+    double tau[2];
+    double co, si;
+    double2 eph;
+};
+
+struct PencilDev {
+    // sizes
+    int m, n, p;      // input sizes
+    int mr, pr;       // rows of F and G as swept
+    int reduce;       // one-time reduction active
+    int N, nslots;    // pointwise round robin: players (n rounded up to even), slots
+    int w, nb, nbp;   // blocked: block width, block columns (even), block pairs per step
+    int kf, kg;       // blocked: Gram chunks over F rows, over G rows
+    int tf, tg, tz;   // blocked: update tiles over F, G, Z rows
+    int pad0;
+    // caller buffers
+    const double2 *Fin;
+    long ldfin;
+    const int8_t *Jin;
+    const double2 *Gin;
+    long ldgin;
+    double *lambda;
+    double2 *X;
+    long ldx;
+    // reduction scratch
+    double2 *Ft;
+    long ldft;
+    double2 *Gt;
+    long ldgt;
+    JqrState *jst;
+    double *hd;
+    double2 *hc;
+    double *hi;
+    double2 *sbuf;   // 2 m
+    double2 *qv;     // p
+    double *qcoef;
+    int8_t *Jw;
+    int *rowmap;
+    int *perm;
+    // sweep buffers
+    double2 *Fw;
+    long ldf;
+    double2 *Gw;
+    long ldg;
+    double2 *Zw;
+    long ldz;
+    float2 *F32, *G32, *Z32;
+    SweepState *st;
+    unsigned long long *slot_cnt;  // pointwise: 3 per slot
+    // outputs scratch
+    double *lam_tmp, *scale;
+    int *rank;
+    int *small;  // [0] input flags, [1] n_plus, [2] output flags
+    double *gnorm2;
+    // blocked scratch
+    double2 *part;   // [nbp][kf + kg][PB * PB] partial Grams
+    double2 *zh64;   // [nbp][PB * PB]
+    float2 *zh32;
+    int *ntr;        // [nbp]
+    unsigned long long *bcnt;  // [nbp * 3]
+    double2 *tmp;    // hand-off product
+};
+
+// Pencil of workgroup `blk` given prefix sums pre[0..B] (pre[0] = 0).
+__device__ __forceinline__ int find_pencil(const int *pre, int B, int blk) {
+    int lo = 0, hi = B - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= blk) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace ghsvd

@@ -23,6 +23,7 @@
 #include <cmath>
 
 #include "hz_step.hpp"
+#include "reduce.hpp"
 #include "solver.hpp"
 
 namespace ghsvd {
@@ -59,33 +60,6 @@ constexpr int kGramChunk = 256;  // rows of one Gram partial
 constexpr int kGramSub = 64;     // rows staged in LDS at a time
 constexpr int kUpdRows = 64;     // rows of one update tile
 
-struct BlkArgs {
-    void *F;
-    long ldf;
-    int m;
-    int nplus;
-    void *G;
-    long ldg;
-    int p;
-    void *Z;
-    long ldz;
-    int n;
-    int w;    // block width
-    int nb;   // block columns (even)
-    int nbp;  // block pairs per step
-    int kf, kg;          // Gram chunks over F rows, over G rows
-    int tf, tg, tz;      // update tiles over F, G, Z rows
-    double eps;          // machine precision of (6.12) for the inner level
-    int crit;
-    int fp32;
-    double2 *part;       // [nbp][kf + kg][PB * PB] partial Grams
-    double2 *zh64;       // [nbp][PB * PB] accumulated inner transforms
-    float2 *zh32;        // same in FP32 (FP32 stage)
-    int *ntr;            // [nbp] inner transformations of the current step
-    unsigned long long *cnt;  // [nbp * 3] per-slot counters of the block sweep
-    SweepState *st;
-};
-
 __device__ __forceinline__ int blk_width(int n, int w, int b) {
     const int c = n - b * w;
     return c < 0 ? 0 : (c > w ? w : c);
@@ -97,26 +71,34 @@ __device__ __forceinline__ int blk_col(int w, int a, int b, int ca, int cc) {
 }
 
 template <typename T, int PB>
-__global__ __launch_bounds__(256) void k_blk_gram(BlkArgs A, int step) {
+__global__ __launch_bounds__(256) void k_blk_gram(const PencilDev *PD, const int *pre, int B) {
     using C2 = typename Mfma<T>::c2;
     using ACC = typename Mfma<T>::acc;
+    constexpr bool F32 = sizeof(T) == 4;
     constexpr int NTD = PB / 16;          // output tiles per dimension
     constexpr int NT2 = NTD * NTD;        // output tiles
     constexpr int KSPLIT = 4 / NT2;       // waves sharing one output tile
     __shared__ C2 tile[kGramSub][PB + 1];
     __shared__ double2 red[KSPLIT > 1 ? 4 * 256 : 1];
+    const int pk = find_pencil(pre, B, blockIdx.x);
+    const PencilDev &A = PD[pk];
     if (A.st->done) return;
-    const int bpi = blockIdx.x, kc = blockIdx.y;
+    const int local = blockIdx.x - pre[pk];
+    const int KC = A.kf + A.kg;
+    const int bpi = local / KC, kc = local % KC;
     int a, b;
-    rr_pair(A.nb, step, bpi, a, b);
+    rr_pair(A.nb, A.st->lstep, bpi, a, b);
     const int ca = blk_width(A.n, A.w, a), cb = blk_width(A.n, A.w, b);
     const int c = ca + cb;
     if (c < 2) return;
     const bool isF = kc < A.kf;
     const int r0 = (isF ? kc : kc - A.kf) * kGramChunk;
-    const int rows = isF ? A.m : A.p;
+    const int rows = isF ? A.mr : A.pr;
     const long ld = isF ? A.ldf : A.ldg;
-    const C2 *X = reinterpret_cast<const C2 *>(isF ? A.F : A.G);
+    const C2 *X = reinterpret_cast<const C2 *>(
+        isF ? (F32 ? (const void *)A.F32 : (const void *)A.Fw)
+            : (F32 ? (const void *)A.G32 : (const void *)A.Gw));
+    const int nplus = A.small[1];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int t = wv % NT2, ks = wv / NT2;
     const int ti = t % NTD, tj = t / NTD;
@@ -136,7 +118,7 @@ __global__ __launch_bounds__(256) void k_blk_gram(BlkArgs A, int step) {
             const int k = k0 + (lane >> 4);
             const C2 fa = tile[k][ti * 16 + (lane & 15)];
             C2 fb = tile[k][tj * 16 + (lane & 15)];
-            if (isF && s0 + k >= A.nplus) {
+            if (isF && s0 + k >= nplus) {
                 fb.x = -fb.x;
                 fb.y = -fb.y;
             }
@@ -148,7 +130,7 @@ __global__ __launch_bounds__(256) void k_blk_gram(BlkArgs A, int step) {
         }
         __syncthreads();
     }
-    double2 *P = A.part + ((size_t)bpi * (A.kf + A.kg) + kc) * PB * PB;
+    double2 *P = A.part + ((size_t)bpi * KC + kc) * PB * PB;
     if constexpr (KSPLIT > 1) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) red[wv * 256 + r * 64 + lane] = cmk((double)acc_re[r], (double)acc_im[r]);
@@ -156,10 +138,10 @@ __global__ __launch_bounds__(256) void k_blk_gram(BlkArgs A, int step) {
         if (wv == 0) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                double2 s = red[r * 64 + lane];
-                for (int q = 1; q < KSPLIT; ++q) s = cadd(s, red[q * 256 + r * 64 + lane]);
+                double2 sum = red[r * 64 + lane];
+                for (int q = 1; q < KSPLIT; ++q) sum = cadd(sum, red[q * 256 + r * 64 + lane]);
                 const int i = ti * 16 + Mfma<T>::row(lane, r), j = tj * 16 + (lane & 15);
-                P[(size_t)j * PB + i] = s;
+                P[(size_t)j * PB + i] = sum;
             }
         }
     } else {
@@ -178,8 +160,9 @@ __global__ __launch_bounds__(256) void k_blk_gram(BlkArgs A, int step) {
 // step are disjoint, so the blocks are independent and the two-sided update
 // needs a single pass over H and S.  Pair slots whose second column is a bye
 // or padding (>= c) carry the identity; padding entries are zero and stay so.
-template <int PB>
-__global__ __launch_bounds__(256) void k_blk_inner(BlkArgs A, int step) {
+template <int PB, int F32>
+__global__ __launch_bounds__(256) void k_blk_inner(const PencilDev *PD, const int *pre, int B,
+                                                   int crit) {
     constexpr int NP = PB / 2;   // pivot pair slots per inner step
     constexpr int NB = NP * NP;  // 2x2 blocks
     __shared__ double2 H[PB][PB + 1];
@@ -189,11 +172,13 @@ __global__ __launch_bounds__(256) void k_blk_inner(BlkArgs A, int step) {
     __shared__ int pq_s[NP][2];
     __shared__ int act_s[NP];
     __shared__ double red[3 * 4];
+    const int pk = find_pencil(pre, B, blockIdx.x);
+    const PencilDev &A = PD[pk];
     if (A.st->done) return;
-    const int bpi = blockIdx.x;
+    const int bpi = blockIdx.x - pre[pk];
     const int tid = threadIdx.x;
     int a, b;
-    rr_pair(A.nb, step, bpi, a, b);
+    rr_pair(A.nb, A.st->lstep, bpi, a, b);
     const int ca = blk_width(A.n, A.w, a), cb = blk_width(A.n, A.w, b);
     const int c = ca + cb;
     if (c < 2) {
@@ -214,7 +199,7 @@ __global__ __launch_bounds__(256) void k_blk_inner(BlkArgs A, int step) {
     __syncthreads();
     const int C = c + (c & 1);
     const int islots = C / 2;
-    const double tol = A.eps * sqrt((double)c);
+    const double tol = (F32 ? 0x1p-23 : 0x1p-52) * sqrt((double)c);
     double cv = 0.0, ct = 0.0, cbig = 0.0;
     for (int s = 0; s < C - 1; ++s) {
         if (tid < NP) {
@@ -224,7 +209,7 @@ __global__ __launch_bounds__(256) void k_blk_inner(BlkArgs A, int step) {
                 if (qq < c) {
                     Zp z;
                     kind = hz_step_fast(H[pp][pp].x, H[qq][qq].x, H[pp][qq], S[pp][pp].x,
-                                        S[qq][qq].x, S[pp][qq], tol, A.crit, z, A.fp32);
+                                        S[qq][qq].x, S[pp][qq], tol, crit, z, F32);
                     cv += 1.0;
                     if (kind == GHSVD_ENONFINITE) atomicCAS(&A.st->err, 0, GHSVD_ENONFINITE);
                     if (kind < 0) kind = kSkip;  // dependent-looking pivot: left to the finish
@@ -301,7 +286,7 @@ __global__ __launch_bounds__(256) void k_blk_inner(BlkArgs A, int step) {
     double v[3] = {cv, ct, cbig};
     block_sum<3>(v, red);
     double2 *Z64 = A.zh64 + (size_t)bpi * PB * PB;
-    float2 *Z32 = A.zh32 ? A.zh32 + (size_t)bpi * PB * PB : nullptr;
+    float2 *Z32 = F32 ? A.zh32 + (size_t)bpi * PB * PB : nullptr;
     for (int idx = tid; idx < PB * PB; idx += 256) {
         const int i = idx % PB, j = idx / PB;
         const double2 z = Zs[i][j];
@@ -310,7 +295,7 @@ __global__ __launch_bounds__(256) void k_blk_inner(BlkArgs A, int step) {
     }
     if (tid == 0) {
         A.ntr[bpi] = (int)v[1];
-        unsigned long long *cn = A.cnt + 3 * bpi;
+        unsigned long long *cn = A.bcnt + 3 * bpi;
         cn[0] += (unsigned long long)v[0];
         cn[1] += (unsigned long long)v[1];
         cn[2] += (unsigned long long)v[2];
@@ -318,38 +303,36 @@ __global__ __launch_bounds__(256) void k_blk_inner(BlkArgs A, int step) {
 }
 
 template <typename T, int PB>
-__global__ __launch_bounds__(256) void k_blk_update(BlkArgs A, int step) {
+__device__ __forceinline__ void update_tile(const PencilDev &A, int bpi, int t) {
     using C2 = typename Mfma<T>::c2;
     using ACC = typename Mfma<T>::acc;
+    constexpr bool F32 = sizeof(T) == 4;
     constexpr int NTJ = PB / 16;
     constexpr int NTI = kUpdRows / 16;
     constexpr int TILES = NTI * NTJ;
     __shared__ C2 Xs[kUpdRows][PB + 1];
     __shared__ C2 Zh[PB][PB + 1];
-    if (A.st->done) return;
-    const int bpi = blockIdx.x;
     if (A.ntr[bpi] == 0) return;
     int a, b;
-    rr_pair(A.nb, step, bpi, a, b);
+    rr_pair(A.nb, A.st->lstep, bpi, a, b);
     const int ca = blk_width(A.n, A.w, a), cb = blk_width(A.n, A.w, b);
     const int c = ca + cb;
     if (c < 2) return;
-    int t = blockIdx.y;
     C2 *X;
     long ld;
     int rows;
     if (t < A.tf) {
-        X = reinterpret_cast<C2 *>(A.F);
+        X = reinterpret_cast<C2 *>(F32 ? (void *)A.F32 : (void *)A.Fw);
         ld = A.ldf;
-        rows = A.m;
+        rows = A.mr;
     } else if (t < A.tf + A.tg) {
         t -= A.tf;
-        X = reinterpret_cast<C2 *>(A.G);
+        X = reinterpret_cast<C2 *>(F32 ? (void *)A.G32 : (void *)A.Gw);
         ld = A.ldg;
-        rows = A.p;
+        rows = A.pr;
     } else {
         t -= A.tf + A.tg;
-        X = reinterpret_cast<C2 *>(A.Z);
+        X = reinterpret_cast<C2 *>(F32 ? (void *)A.Z32 : (void *)A.Zw);
         ld = A.ldz;
         rows = A.n;
     }
@@ -358,10 +341,10 @@ __global__ __launch_bounds__(256) void k_blk_update(BlkArgs A, int step) {
     for (int idx = tid; idx < PB * PB; idx += 256) {
         const int k = idx % PB, j = idx / PB;
         C2 z;
-        if constexpr (sizeof(T) == 8) {
-            z = A.zh64[(size_t)bpi * PB * PB + idx];
-        } else {
+        if constexpr (F32) {
             z = A.zh32[(size_t)bpi * PB * PB + idx];
+        } else {
+            z = A.zh64[(size_t)bpi * PB * PB + idx];
         }
         Zh[k][j] = z;
     }
@@ -411,6 +394,20 @@ __global__ __launch_bounds__(256) void k_blk_update(BlkArgs A, int step) {
         const int cc = idx / kUpdRows, rr = idx % kUpdRows;
         if (cc < c && r0 + rr < rows) X[(size_t)blk_col(A.w, a, b, ca, cc) * ld + r0 + rr] = Xs[rr][cc];
     }
+}
+
+// F_C <- F_C Z^, G_C <- G_C Z^, Z_C <- Z_C Z^ for one 64-row tile; the last
+// workgroup of a pencil's step advances the pencil's step counter.
+template <typename T, int PB>
+__global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const int *pre, int B) {
+    const int pk = find_pencil(pre, B, blockIdx.x);
+    const PencilDev &A = PD[pk];
+    SweepState *st = A.st;
+    if (st->done) return;
+    const int local = blockIdx.x - pre[pk];
+    const int TT = A.tf + A.tg + A.tz;
+    update_tile<T, PB>(A, local / TT, local % TT);
+    if (last_workgroup(st, (unsigned)(A.nbp * TT))) step_done(st, A.bcnt, A.nbp, A.nb - 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -501,253 +498,133 @@ __global__ __launch_bounds__(256) void k_handoff_gemm(int rows, int n, const dou
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
-struct BlkGeom {
-    int w, PB, nb, nbp, kf, kg, tf, tg, tz;
-};
-
-static BlkGeom blk_geom(int m, int n, int p, int w) {
-    BlkGeom g{};
-    g.w = w;
-    g.PB = 2 * w;
-    g.nb = (n + w - 1) / w;
-    if (g.nb & 1) g.nb += 1;
-    g.nbp = g.nb / 2;
-    g.kf = (m + kGramChunk - 1) / kGramChunk;
-    g.kg = (p + kGramChunk - 1) / kGramChunk;
-    g.tf = (m + kUpdRows - 1) / kUpdRows;
-    g.tg = (p + kUpdRows - 1) / kUpdRows;
-    g.tz = (n + kUpdRows - 1) / kUpdRows;
-    return g;
+void set_block_geometry(PencilDev &d, int w) {
+    d.w = w;
+    d.nb = (d.n + w - 1) / w;
+    if (d.nb & 1) d.nb += 1;
+    d.nbp = d.nb / 2;
+    d.kf = (d.mr + kGramChunk - 1) / kGramChunk;
+    d.kg = (d.pr + kGramChunk - 1) / kGramChunk;
+    d.tf = (d.mr + kUpdRows - 1) / kUpdRows;
+    d.tg = (d.pr + kUpdRows - 1) / kUpdRows;
+    d.tz = (d.n + kUpdRows - 1) / kUpdRows;
 }
 
-int pick_block_width(int n, int requested) {
+int pick_block_width(int max_n, int requested) {
     if (requested == 8 || requested == 16) return requested;
-    return n >= 512 ? 16 : 8;
+    return max_n >= 512 ? 16 : 8;
 }
 
-struct BlkWs {
-    double2 *part;
-    double2 *zh64;
-    float2 *zh32;
-    int *ntr;
-    unsigned long long *cnt;
-    double2 *tmp;  // hand-off product (rows x n)
+void carve_blocked(Carver &c, int mr, int n, int pr, int w, int mixed, PencilDev &d) {
+    PencilDev g{};
+    g.mr = mr;
+    g.n = n;
+    g.pr = pr;
+    set_block_geometry(g, w);
+    const size_t pb2 = (size_t)(2 * w) * (2 * w);
+    d.part = c.take<double2>((size_t)g.nbp * (g.kf + g.kg) * pb2);
+    d.zh64 = c.take<double2>((size_t)g.nbp * pb2);
+    d.zh32 = c.take<float2>((size_t)g.nbp * pb2);
+    d.ntr = c.take<int>(g.nbp);
+    d.bcnt = c.take<unsigned long long>(3 * (size_t)g.nbp);
+    if (mixed) {
+        const long ld = pad_ld(mr > pr ? mr : pr);
+        d.tmp = c.take<double2>((size_t)ld * n);
+    }
+}
+
+size_t blocked_bytes(int mr, int n, int pr, int w, int mixed) {
+    Carver c{nullptr, 0, (size_t)-1};
+    PencilDev d{};
+    carve_blocked(c, mr, n, pr, w, mixed, d);
+    return c.used + 256;
+}
+
+using BlkFn = void (*)(const PencilDev *, const int *, int);
+using BlkInnerFn = void (*)(const PencilDev *, const int *, int, int);
+
+struct BlockedArg {
+    BlkFn gram, upd;
+    BlkInnerFn inner;
+    int crit;
 };
 
-static BlkWs carve_blk(Carver &c, const Plan &pl, int w) {
-    BlkWs b{};
-    const BlkGeom g = blk_geom(pl.mr, pl.n, pl.pr, w);
-    const size_t pb2 = (size_t)g.PB * g.PB;
-    b.part = c.take<double2>((size_t)g.nbp * (g.kf + g.kg) * pb2);
-    b.zh64 = c.take<double2>((size_t)g.nbp * pb2);
-    b.zh32 = c.take<float2>((size_t)g.nbp * pb2);
-    b.ntr = c.take<int>(g.nbp);
-    b.cnt = c.take<unsigned long long>(3 * (size_t)g.nbp);
-    if (pl.mixed) {
-        const long ld = pl.ldf > pl.ldg ? pl.ldf : pl.ldg;
-        b.tmp = c.take<double2>((size_t)ld * pl.n);
+static int blocked_step(const BatchCtx &c, const void *arg, hipStream_t s) {
+    const BlockedArg *a = static_cast<const BlockedArg *>(arg);
+    hipLaunchKernelGGL(a->gram, dim3(c.total(BatchCtx::kGram)), dim3(256), 0, s, c.dev,
+                       c.pre_of(BatchCtx::kGram), c.B);
+    hipLaunchKernelGGL(a->inner, dim3(c.total(BatchCtx::kBp)), dim3(256), 0, s, c.dev,
+                       c.pre_of(BatchCtx::kBp), c.B, a->crit);
+    hipLaunchKernelGGL(a->upd, dim3(c.total(BatchCtx::kUpd)), dim3(256), 0, s, c.dev,
+                       c.pre_of(BatchCtx::kUpd), c.B);
+    GHSVD_HIP(hipGetLastError());
+    return GHSVD_OK;
+}
+
+int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, hipStream_t s,
+                      std::vector<SweepResult> &res) {
+    int w = 0, steps = 1;
+    for (const PencilDev &P : c.host) {
+        if (w == 0) w = P.w;
+        if (P.w != w) return GHSVD_EINVAL;  // one block width per batch
+        if (P.nb - 1 > steps) steps = P.nb - 1;
     }
-    return b;
-}
-
-void carve_blocked(Carver &c, const Plan &pl, PencilWs &w) {
-    // sized for the widest block choice
-    Carver probe{nullptr, 0, (size_t)-1};
-    (void)carve_blk(probe, pl, 16);
-    const size_t need = probe.used;
-    w.blk = c.take<char>(need);
-    w.blk_bytes = need;
-}
-
-static BlkWs blk_ws(const Plan &pl, const PencilWs &w, int width) {
-    Carver c{reinterpret_cast<char *>(w.blk), 0, w.blk_bytes};
-    return carve_blk(c, pl, width);
-}
-
-using BlkFn = void (*)(BlkArgs, int);
-
-static int run_blocked_sweeps(const Plan &pl, const PencilWs &w, int nplus, const ghsvd_options &o,
-                              int fp32, hipStream_t s, SweepResult &res) {
-    res = SweepResult{GHSVD_OK, 0, 0, 0, 0, 0};
-    const int width = pick_block_width(pl.n, o.block_width);
-    const BlkGeom g = blk_geom(pl.mr, pl.n, pl.pr, width);
-    const BlkWs bw = blk_ws(pl, w, width);
-    BlkArgs A{};
-    A.F = fp32 ? (void *)w.F32 : (void *)w.Fw;
-    A.ldf = pl.ldf;
-    A.m = pl.mr;
-    A.nplus = nplus;
-    A.G = fp32 ? (void *)w.G32 : (void *)w.Gw;
-    A.ldg = pl.ldg;
-    A.p = pl.pr;
-    A.Z = fp32 ? (void *)w.Z32 : (void *)w.Zw;
-    A.ldz = pl.ldz;
-    A.n = pl.n;
-    A.w = g.w;
-    A.nb = g.nb;
-    A.nbp = g.nbp;
-    A.kf = g.kf;
-    A.kg = g.kg;
-    A.tf = g.tf;
-    A.tg = g.tg;
-    A.tz = g.tz;
-    A.eps = fp32 ? 0x1p-23 : 0x1p-52;
-    A.crit = o.crit_literal;
-    A.fp32 = fp32;
-    A.part = bw.part;
-    A.zh64 = bw.zh64;
-    A.zh32 = fp32 ? bw.zh32 : nullptr;
-    A.ntr = bw.ntr;
-    A.cnt = bw.cnt;
-    A.st = w.st;
-    BlkFn gram, inner, upd;
-    if (g.PB == 32) {
-        gram = fp32 ? k_blk_gram<float, 32> : k_blk_gram<double, 32>;
-        inner = k_blk_inner<32>;
-        upd = fp32 ? k_blk_update<float, 32> : k_blk_update<double, 32>;
+    if (c.total(BatchCtx::kBp) == 0) {
+        res.assign(c.B, SweepResult{GHSVD_OK, 0, 1, 0, 0, 0});
+        return GHSVD_OK;
+    }
+    BlockedArg a{};
+    a.crit = crit;
+    if (w == 16) {
+        a.gram = fp32 ? k_blk_gram<float, 32> : k_blk_gram<double, 32>;
+        a.inner = fp32 ? k_blk_inner<32, 1> : k_blk_inner<32, 0>;
+        a.upd = fp32 ? k_blk_update<float, 32> : k_blk_update<double, 32>;
+    } else if (w == 8) {
+        a.gram = fp32 ? k_blk_gram<float, 16> : k_blk_gram<double, 16>;
+        a.inner = fp32 ? k_blk_inner<16, 1> : k_blk_inner<16, 0>;
+        a.upd = fp32 ? k_blk_update<float, 16> : k_blk_update<double, 16>;
     } else {
-        gram = fp32 ? k_blk_gram<float, 16> : k_blk_gram<double, 16>;
-        inner = k_blk_inner<16>;
-        upd = fp32 ? k_blk_update<float, 16> : k_blk_update<double, 16>;
+        return GHSVD_EINVAL;
     }
-    int rc = enqueue_reset_state(w.st, bw.cnt, g.nbp, o.max_sweeps, s, fp32);
-    if (rc) return rc;
-    SweepState hs;
-    for (int sw = 0; sw < o.max_sweeps; ++sw) {
-        for (int step = 0; step < g.nb - 1; ++step) {
-            hipLaunchKernelGGL(gram, dim3(g.nbp, g.kf + g.kg), dim3(256), 0, s, A, step);
-            hipLaunchKernelGGL(inner, dim3(g.nbp), dim3(256), 0, s, A, step);
-            hipLaunchKernelGGL(upd, dim3(g.nbp, g.tf + g.tg + g.tz), dim3(256), 0, s, A, step);
-        }
-        GHSVD_HIP(hipGetLastError());
-        if ((rc = enqueue_end_sweep(w.st, bw.cnt, g.nbp, s))) return rc;
-        GHSVD_HIP(hipMemcpyAsync(&hs, w.st, offsetof(SweepState, hist), hipMemcpyDeviceToHost, s));
-        GHSVD_HIP(hipStreamSynchronize(s));
-        if (hs.done) break;
-    }
-    GHSVD_HIP(hipMemcpyAsync(&hs, w.st, sizeof(SweepState), hipMemcpyDeviceToHost, s));
-    GHSVD_HIP(hipStreamSynchronize(s));
-    trace_stage(fp32 ? "blocked-fp32" : "blocked-fp64", hs);
-    res.sweeps = hs.sweeps;
-    res.converged = hs.converged;
-    for (int k = 0; k < hs.sweeps && k < kMaxHist; ++k) {
-        res.visited += (long long)hs.hist[3 * k + 0];
-        res.transformed += (long long)hs.hist[3 * k + 1];
-        res.big += (long long)hs.hist[3 * k + 2];
-    }
-    res.status = hs.err ? hs.err : (hs.converged ? GHSVD_OK : GHSVD_NOT_CONVERGED);
-    return res.status < 0 ? res.status : GHSVD_OK;
+    return drive_stage(c, max_sweeps, fp32, 1, blocked_step, &a, steps,
+                       fp32 ? "blocked-fp32" : "blocked-fp64", s, res);
 }
 
-int run_blocked_fp64(const Plan &pl, const PencilWs &w, int nplus, const ghsvd_options &o,
-                     ghsvd_info &info, hipStream_t s) {
-    if (pl.n < 4) return GHSVD_OK;
-    SweepResult r;
-    const int rc = run_blocked_sweeps(pl, w, nplus, o, 0, s, r);
-    info.sweeps_fp64 += r.sweeps;
-    info.sweeps_blocked += r.sweeps;
-    info.pairs_visited += r.visited;
-    info.pairs_transformed += r.transformed;
-    info.pairs_big += r.big;
-    return rc;
+int to_fp32(const BatchCtx &c, hipStream_t s) {
+    for (const PencilDev &P : c.host) {
+        const int n = P.n;
+        int bx = (P.mr + 255) / 256;
+        if (bx > 16) bx = 16;
+        hipLaunchKernelGGL(k_to_f32, dim3(bx, n), dim3(256), 0, s, P.mr, n, P.Fw, P.ldf, P.F32, P.ldf);
+        bx = (P.pr + 255) / 256;
+        if (bx > 16) bx = 16;
+        hipLaunchKernelGGL(k_to_f32, dim3(bx, n), dim3(256), 0, s, P.pr, n, P.Gw, P.ldg, P.G32, P.ldg);
+        int rc = set_identity(n, P.Z32, P.ldz, 1, s);
+        if (rc) return rc;
+    }
+    GHSVD_HIP(hipGetLastError());
+    return GHSVD_OK;
 }
 
-int run_fp32_stage(const Plan &pl, const PencilWs &w, int nplus, const ghsvd_options &o,
-                   ghsvd_info &info, hipStream_t s) {
-    const int n = pl.n;
-    int bx = (pl.mr + 255) / 256;
-    if (bx > 16) bx = 16;
-    hipLaunchKernelGGL(k_to_f32, dim3(bx, n), dim3(256), 0, s, pl.mr, n, w.Fw, pl.ldf, w.F32, pl.ldf);
-    bx = (pl.pr + 255) / 256;
-    if (bx > 16) bx = 16;
-    hipLaunchKernelGGL(k_to_f32, dim3(bx, n), dim3(256), 0, s, pl.pr, n, w.Gw, pl.ldg, w.G32, pl.ldg);
-    int rc = set_identity(n, w.Z32, pl.ldz, 1, s);
-    if (rc) return rc;
-    SweepResult r{};
-    if (o.variant == GHSVD_BLOCKED && n >= 4) {
-        rc = run_blocked_sweeps(pl, w, nplus, o, 1, s, r);
-        info.sweeps_blocked += r.sweeps;
-    } else {
-        SweepArgs a = sweep_args(pl, w, nplus, o, 1);
-        const int rows = pl.mr > pl.pr ? pl.mr : pl.pr;
-        rc = run_pointwise_sweeps(a, o.max_sweeps, choose_pair_geom(rows, o.waves_per_pair), s, r);
-        if (rc > 0) rc = GHSVD_OK;
+// Hand-off after the FP32 stage: F <- F Z32, G <- G Z32 in FP64, Z <- Z32.
+int fp32_handoff(const BatchCtx &c, hipStream_t s) {
+    for (const PencilDev &P : c.host) {
+        const int n = P.n;
+        const int gy = (n + kGemmT - 1) / kGemmT;
+        hipLaunchKernelGGL(k_handoff_gemm, dim3((P.mr + kGemmT - 1) / kGemmT, gy), dim3(256), 0, s,
+                           P.mr, n, P.Fw, P.ldf, P.Z32, P.ldz, P.tmp, P.ldf);
+        GHSVD_HIP(hipMemcpy2DAsync(P.Fw, P.ldf * sizeof(double2), P.tmp, P.ldf * sizeof(double2),
+                                   P.mr * sizeof(double2), n, hipMemcpyDeviceToDevice, s));
+        hipLaunchKernelGGL(k_handoff_gemm, dim3((P.pr + kGemmT - 1) / kGemmT, gy), dim3(256), 0, s,
+                           P.pr, n, P.Gw, P.ldg, P.Z32, P.ldz, P.tmp, P.ldg);
+        GHSVD_HIP(hipMemcpy2DAsync(P.Gw, P.ldg * sizeof(double2), P.tmp, P.ldg * sizeof(double2),
+                                   P.pr * sizeof(double2), n, hipMemcpyDeviceToDevice, s));
+        int bx = (n + 255) / 256;
+        if (bx > 16) bx = 16;
+        hipLaunchKernelGGL(k_to_f64, dim3(bx, n), dim3(256), 0, s, n, n, P.Z32, P.ldz, P.Zw, P.ldz);
     }
-    info.sweeps_fp32 += r.sweeps;
-    info.pairs_visited += r.visited;
-    info.pairs_transformed += r.transformed;
-    info.pairs_big += r.big;
-    if (rc < 0) return rc;
-    // Hand-off: F <- F Z32, G <- G Z32 in FP64, Z <- Z32.
-    const BlkWs bw = blk_ws(pl, w, pick_block_width(n, o.block_width));
-    const dim3 gz((n + kGemmT - 1) / kGemmT, (n + kGemmT - 1) / kGemmT);
-    hipLaunchKernelGGL(k_handoff_gemm, dim3((pl.mr + kGemmT - 1) / kGemmT, gz.y), dim3(256), 0, s,
-                       pl.mr, n, w.Fw, pl.ldf, w.Z32, pl.ldz, bw.tmp, pl.ldf);
-    GHSVD_HIP(hipMemcpy2DAsync(w.Fw, pl.ldf * sizeof(double2), bw.tmp, pl.ldf * sizeof(double2),
-                               pl.mr * sizeof(double2), n, hipMemcpyDeviceToDevice, s));
-    hipLaunchKernelGGL(k_handoff_gemm, dim3((pl.pr + kGemmT - 1) / kGemmT, gz.y), dim3(256), 0, s,
-                       pl.pr, n, w.Gw, pl.ldg, w.Z32, pl.ldz, bw.tmp, pl.ldg);
-    GHSVD_HIP(hipMemcpy2DAsync(w.Gw, pl.ldg * sizeof(double2), bw.tmp, pl.ldg * sizeof(double2),
-                               pl.pr * sizeof(double2), n, hipMemcpyDeviceToDevice, s));
-    bx = (n + 255) / 256;
-    if (bx > 16) bx = 16;
-    hipLaunchKernelGGL(k_to_f64, dim3(bx, n), dim3(256), 0, s, n, n, w.Z32, pl.ldz, w.Zw, pl.ldz);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }
 
 }  // namespace ghsvd
-
-using namespace ghsvd;
-
-extern "C" int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, double *G,
-                                  int ldg, double *Z, int ldz, int block_width, int nsweeps,
-                                  int crit_literal, long long *counters, int *sweeps_done,
-                                  void *stream) {
-    if (n < 4 || m < 1 || p < 1 || ldf < m || ldg < p || ldz < n || nsweeps < 1 ||
-        nsweeps > kMaxHist || n_plus < 0 || n_plus > m || !F || !G || !Z)
-        return GHSVD_EINVAL;
-    if (block_width != 0 && block_width != 8 && block_width != 16) return GHSVD_EINVAL;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    ghsvd_options o;
-    ghsvd_default_options(&o);
-    o.block_width = block_width;
-    o.max_sweeps = nsweeps;
-    o.crit_literal = crit_literal;
-    o.variant = GHSVD_BLOCKED;
-    Plan pl{};
-    pl.m = m;
-    pl.n = n;
-    pl.p = p;
-    pl.mr = m;
-    pl.pr = p;
-    pl.ldf = ldf;
-    pl.ldg = ldg;
-    pl.ldz = ldz;
-    pl.N = n + (n & 1);
-    pl.blocked = 1;
-    Carver probe{nullptr, 0, (size_t)-1};
-    PencilWs w{};
-    w.st = probe.take<SweepState>(1);
-    carve_blocked(probe, pl, w);
-    void *buf = nullptr;
-    GHSVD_HIP(hipMalloc(&buf, probe.used));
-    Carver c{reinterpret_cast<char *>(buf), 0, probe.used};
-    w.st = c.take<SweepState>(1);
-    carve_blocked(c, pl, w);
-    w.Fw = reinterpret_cast<double2 *>(F);
-    w.Gw = reinterpret_cast<double2 *>(G);
-    w.Zw = reinterpret_cast<double2 *>(Z);
-    SweepResult r;
-    int rc = run_blocked_sweeps(pl, w, n_plus, o, 0, s, r);
-    SweepState hs;
-    if (hipMemcpy(&hs, w.st, sizeof(SweepState), hipMemcpyDeviceToHost) == hipSuccess) {
-        if (counters)
-            for (int k = 0; k < nsweeps; ++k)
-                for (int j = 0; j < 3; ++j)
-                    counters[3 * k + j] = k < hs.sweeps ? (long long)hs.hist[3 * k + j] : 0;
-        if (sweeps_done) *sweeps_done = hs.sweeps;
-    }
-    (void)hipFree(buf);
-    return rc < 0 ? rc : r.status;
-}

@@ -1,14 +1,15 @@
-// pair_sweep.hip -- the pointwise pivot-pair kernel and its sweep driver.
+// pair_sweep.hip -- the pointwise pivot-pair kernel and the sweep-stage driver.
 //
 // One workgroup per pivot pair of a round-robin step (Section 6.3: the pairs
-// of a step are disjoint, so they run concurrently).  A workgroup reads its
-// two columns of F and G once (coalesced: consecutive lanes read consecutive
-// rows of a column-major matrix), forms the six entries of (6.1) with the
-// split signature J = diag(I, -I) (Section 4.5.1 run-length form with one
-// negative block), reduces them over the wavefronts and the workgroup in a
-// fixed order, computes the FP64 2x2 step of Section 6.1 (every wavefront
-// redundantly, so no broadcast is needed), and applies Z' to the columns
-// still held in registers, then to the two columns of Z.
+// of a step are disjoint, so they run concurrently), for every pencil of the
+// batch in the same launch.  A workgroup reads its two columns of F and G
+// once (coalesced: consecutive lanes read consecutive rows of a column-major
+// matrix), forms the six entries of (6.1) with the split signature
+// J = diag(I, -I) (Section 4.5.1 run-length form with one negative block),
+// reduces them over the wavefronts and the workgroup in a fixed order,
+// computes the FP64 2x2 step of Section 6.1 (every wavefront redundantly, so
+// no broadcast is needed), and applies Z' to the columns still held in
+// registers, then to the two columns of Z.
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
@@ -58,27 +59,26 @@ __device__ __forceinline__ void acc_pair(C2 xp, C2 xq, T sg, T &aa, T &bb, T &cr
     ci += sg * (xp.x * xq.y - xp.y * xq.x);
 }
 
+// One pivot pair (p, q) of pencil P: dots, 2x2 step, column updates.
 template <typename T, int NT, int R>
-__global__ __launch_bounds__(NT) void k_pair(SweepArgs A, int step) {
+__device__ __forceinline__ void pair_body(const PencilDev &P, int p, int q, int slot, int crit) {
     using C2 = typename Cplx<T>::type;
-    if (A.st->done) return;
-    const int slot = blockIdx.x;
-    int p, q;
-    rr_pair(A.N, step, slot, p, q);
-    if (q >= A.n) return;  // bye slot of an odd order
+    constexpr bool F32 = sizeof(T) == 4;
     const int tid = threadIdx.x;
-
-    C2 *Fp = reinterpret_cast<C2 *>(A.F) + (size_t)p * A.ldf;
-    C2 *Fq = reinterpret_cast<C2 *>(A.F) + (size_t)q * A.ldf;
-    C2 *Gp = reinterpret_cast<C2 *>(A.G) + (size_t)p * A.ldg;
-    C2 *Gq = reinterpret_cast<C2 *>(A.G) + (size_t)q * A.ldg;
-    C2 *Zp_ = reinterpret_cast<C2 *>(A.Z) + (size_t)p * A.ldz;
-    C2 *Zq = reinterpret_cast<C2 *>(A.Z) + (size_t)q * A.ldz;
+    C2 *F = reinterpret_cast<C2 *>(F32 ? (void *)P.F32 : (void *)P.Fw);
+    C2 *G = reinterpret_cast<C2 *>(F32 ? (void *)P.G32 : (void *)P.Gw);
+    C2 *Z = reinterpret_cast<C2 *>(F32 ? (void *)P.Z32 : (void *)P.Zw);
+    C2 *Fp = F + (size_t)p * P.ldf;
+    C2 *Fq = F + (size_t)q * P.ldf;
+    C2 *Gp = G + (size_t)p * P.ldg;
+    C2 *Gq = G + (size_t)q * P.ldg;
+    C2 *Zp_ = Z + (size_t)p * P.ldz;
+    C2 *Zq = Z + (size_t)q * P.ldz;
+    const int m = P.mr, pr = P.pr, nplus = P.small[1], n = P.n;
 
     constexpr int RR = R > 0 ? R : 1;
     C2 fp[RR], fq[RR], gp[RR], gq[RR];
     T a = 0, b = 0, cr = 0, ci = 0, sa = 0, sb = 0, sr = 0, si = 0;
-    const int m = A.m, pr = A.p, nplus = A.nplus;
     if constexpr (R > 0) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -113,17 +113,18 @@ __global__ __launch_bounds__(NT) void k_pair(SweepArgs A, int step) {
                    (double)sa, (double)sb, (double)sr, (double)si};
     block_sum<8>(v, red);
 
+    const double tol = (F32 ? 0x1p-23 : 0x1p-52) * sqrt((double)n);
     Zp z;
-    int kind = hz_step(v[0], v[1], cmk(v[2], v[3]), v[4], v[5], cmk(v[6], v[7]), A.tol, A.crit, z,
-                       A.fp32);
+    int kind = hz_step(v[0], v[1], cmk(v[2], v[3]), v[4], v[5], cmk(v[6], v[7]), tol, crit, z,
+                       F32 ? 1 : 0);
     // FP32 stage: a pair that looks dependent in FP32 is left to the FP64 sweeps.
-    if (A.fp32 && kind == GHSVD_ERANK) kind = kSkip;
+    if (F32 && kind == GHSVD_ERANK) kind = kSkip;
     if (tid == 0) {
-        unsigned long long *c = A.slot_cnt + 3 * slot;
+        unsigned long long *c = P.slot_cnt + 3 * slot;
         c[0] += 1ull;
         c[1] += (kind > 0) ? 1ull : 0ull;
         c[2] += (kind == kBig) ? 1ull : 0ull;
-        if (kind < 0) atomicCAS(&A.st->err, 0, kind);
+        if (kind < 0) atomicCAS(&P.st->err, 0, kind);
     }
     if (kind <= 0) return;
 
@@ -153,68 +154,56 @@ __global__ __launch_bounds__(NT) void k_pair(SweepArgs A, int step) {
             Gq[i] = upd(xp, xq, z12, z22);
         }
     }
-    for (int i = tid; i < A.n; i += NT) {
+    for (int i = tid; i < n; i += NT) {
         const C2 xp = Zp_[i], xq = Zq[i];
         Zp_[i] = upd(xp, xq, z11, z21);
         Zq[i] = upd(xp, xq, z12, z22);
     }
 }
 
-// End of a sweep: sums the per-slot counters (fixed order), records them,
-// clears them, and sets the convergence flag (Section 6.1.7: stop after a
-// sweep without big transformations; Algorithm 2: stop at the sweep cap).
-__global__ __launch_bounds__(256) void k_end_sweep(SweepState *st, unsigned long long *cnt,
-                                                   int nslots) {
-    __shared__ double red[3 * 4];
+template <typename T, int NT, int R>
+__global__ __launch_bounds__(NT) void k_pair(const PencilDev *PD, const int *pre, int B, int crit) {
+    const int k = find_pencil(pre, B, blockIdx.x);
+    const PencilDev &P = PD[k];
+    SweepState *st = P.st;
     if (st->done) return;
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int s = threadIdx.x; s < nslots; s += blockDim.x) {
-        v[0] += (double)cnt[3 * s + 0];
-        v[1] += (double)cnt[3 * s + 1];
-        v[2] += (double)cnt[3 * s + 2];
-        cnt[3 * s + 0] = 0ull;
-        cnt[3 * s + 1] = 0ull;
-        cnt[3 * s + 2] = 0ull;
-    }
-    block_sum<3>(v, red);
+    const int slot = blockIdx.x - pre[k];
+    int p, q;
+    rr_pair(P.N, st->lstep, slot, p, q);
+    if (q < P.n) pair_body<T, NT, R>(P, p, q, slot, crit);  // else: bye slot of an odd order
+    if (last_workgroup(st, (unsigned)P.nslots)) step_done(st, P.slot_cnt, P.nslots, P.N - 1);
+}
+
+__global__ void k_reset_states(const PencilDev *PD, int B, int max_sweeps, int noise_floor,
+                               int blocked) {
+    const int k = blockIdx.x;
+    if (k >= B) return;
+    const PencilDev &P = PD[k];
+    SweepState *st = P.st;
+    unsigned long long *cnt = blocked ? P.bcnt : P.slot_cnt;
+    const int nc = blocked ? P.nbp : P.nslots;
+    for (int s = threadIdx.x; s < 3 * nc; s += blockDim.x) cnt[s] = 0ull;
     if (threadIdx.x == 0) {
-        const int sw = st->sweeps;
-        if (sw < kMaxHist) {
-            st->hist[3 * sw + 0] = (unsigned long long)v[0];
-            st->hist[3 * sw + 1] = (unsigned long long)v[1];
-            st->hist[3 * sw + 2] = (unsigned long long)v[2];
-        }
-        st->sweeps = sw + 1;
-        if (st->err != 0) {
-            st->done = 1;
-        } else if (v[2] == 0.0) {
-            st->done = 1;
-            st->converged = 1;
-        } else if (st->noise_floor && v[2] * 1024.0 <= v[0]) {
-            st->done = 1;
-        } else if (sw + 1 >= st->max_sweeps) {
-            st->done = 1;
-        }
+        const int skip = blocked ? (P.n < 4 || P.nb < 2) : 0;
+        st->done = skip;
+        st->converged = skip;
+        st->sweeps = 0;
+        st->err = 0;
+        st->max_sweeps = max_sweeps;
+        st->noise_floor = noise_floor;
+        st->lstep = 0;
+        st->fin = 0u;
     }
 }
 
-__global__ void k_reset_state(SweepState *st, unsigned long long *cnt, int nslots, int max_sweeps,
-                              int noise_floor) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int s = t; s < 3 * nslots; s += gridDim.x * blockDim.x) cnt[s] = 0ull;
-    if (t == 0) {
-        st->done = 0;
-        st->sweeps = 0;
-        st->err = 0;
-        st->converged = 0;
-        st->max_sweeps = max_sweeps;
-        st->noise_floor = noise_floor;
-    }
+__global__ void k_gather_done(const PencilDev *PD, int B, int *done) {
+    for (int k = threadIdx.x; k < B; k += blockDim.x) done[k] = PD[k].st->done;
 }
 
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
+using PairFn = void (*)(const PencilDev *, const int *, int, int);
 
 template <typename T>
 static PairFn pick(int nt, int r) {
@@ -256,21 +245,32 @@ PairGeom choose_pair_geom(int rows, int waves_per_pair) {
     return g;
 }
 
-int enqueue_end_sweep(SweepState *st, unsigned long long *cnt, int nslots, hipStream_t stream) {
-    hipLaunchKernelGGL(k_end_sweep, dim3(1), dim3(256), 0, stream, st, cnt, nslots);
-    GHSVD_HIP(hipGetLastError());
+int upload_batch(BatchCtx &c, hipStream_t s) {
+    const int B = c.B;
+    c.pre.assign(BatchCtx::kKinds * (B + 1), 0);
+    c.max_n = 0;
+    c.max_rows = 0;
+    for (int k = 0; k < B; ++k) {
+        const PencilDev &P = c.host[k];
+        const int w[BatchCtx::kKinds] = {P.nslots, P.n, P.nbp * (P.kf + P.kg), P.nbp,
+                                         P.nbp * (P.tf + P.tg + P.tz), 1};
+        for (int t = 0; t < BatchCtx::kKinds; ++t)
+            c.pre[t * (B + 1) + k + 1] = c.pre[t * (B + 1) + k] + w[t];
+        if (P.n > c.max_n) c.max_n = P.n;
+        const int rows = P.mr > P.pr ? P.mr : P.pr;
+        if (rows > c.max_rows) c.max_rows = rows;
+    }
+    GHSVD_HIP(hipMemcpyAsync(c.dev, c.host.data(), sizeof(PencilDev) * B, hipMemcpyHostToDevice, s));
+    GHSVD_HIP(hipMemcpyAsync(c.pre_dev, c.pre.data(), sizeof(int) * c.pre.size(),
+                             hipMemcpyHostToDevice, s));
     return GHSVD_OK;
 }
 
-int enqueue_reset_state(SweepState *st, unsigned long long *slot_cnt, int nslots,
-                        int max_sweeps, hipStream_t stream, int noise_floor) {
-    int blocks = (3 * nslots + 255) / 256;
-    if (blocks < 1) blocks = 1;
-    if (blocks > 1024) blocks = 1024;
-    hipLaunchKernelGGL(k_reset_state, dim3(blocks), dim3(256), 0, stream, st, slot_cnt, nslots,
-                       max_sweeps, noise_floor);
-    GHSVD_HIP(hipGetLastError());
-    return GHSVD_OK;
+void trace_stage(const char *name, int pencil, const SweepState &hs) {
+    if (!std::getenv("GHSVD_TRACE")) return;
+    for (int k = 0; k < hs.sweeps && k < kMaxHist; ++k)
+        std::fprintf(stderr, "ghsvd %s pencil %d sweep %d: visited %llu transformed %llu big %llu\n",
+                     name, pencil, k + 1, hs.hist[3 * k], hs.hist[3 * k + 1], hs.hist[3 * k + 2]);
 }
 
 // Pair-kernel timing for measurement harnesses (see ghsvd_profile_enable).
@@ -293,75 +293,129 @@ static hipEvent_t take_event() {
 }
 }  // namespace prof
 
-void launch_pair_step(PairFn fn, const SweepArgs &a, PairGeom g, int step, hipStream_t stream) {
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    {
-        std::lock_guard<std::mutex> lk(prof::mu);
-        if (prof::every > 0) {
-            if (prof::launches % prof::every == 0) {
-                e0 = prof::take_event();
-                e1 = prof::take_event();
-            }
-            prof::launches++;
-        }
+void prof_before(hipStream_t s, hipEvent_t &e0, hipEvent_t &e1) {
+    e0 = e1 = nullptr;
+    std::lock_guard<std::mutex> lk(prof::mu);
+    if (prof::every <= 0) return;
+    if (prof::launches % prof::every == 0) {
+        e0 = prof::take_event();
+        e1 = prof::take_event();
+        if (e0 && e1) (void)hipEventRecord(e0, s);
     }
-    if (e0 && e1) (void)hipEventRecord(e0, stream);
-    hipLaunchKernelGGL(fn, dim3(a.nslots), dim3(g.nt), 0, stream, a, step);
-    if (e0 && e1) {
-        (void)hipEventRecord(e1, stream);
-        std::lock_guard<std::mutex> lk(prof::mu);
-        prof::pending.emplace_back(e0, e1);
-    }
+    prof::launches++;
 }
 
-int enqueue_pointwise_sweep(const SweepArgs &a, PairGeom g, hipStream_t stream) {
-    PairFn fn = a.fp32 ? pick<float>(g.nt, g.r) : pick<double>(g.nt, g.r);
-    if (!fn) return GHSVD_EINVAL;
-    const int steps = a.N - 1;
-    for (int s = 0; s < steps; ++s) launch_pair_step(fn, a, g, s, stream);
-    hipLaunchKernelGGL(k_end_sweep, dim3(1), dim3(256), 0, stream, a.st, a.slot_cnt, a.nslots);
+void prof_after(hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+    if (!e0 || !e1) return;
+    (void)hipEventRecord(e1, s);
+    std::lock_guard<std::mutex> lk(prof::mu);
+    prof::pending.emplace_back(e0, e1);
+}
+
+static bool prof_active() {
+    std::lock_guard<std::mutex> lk(prof::mu);
+    return prof::every > 0;
+}
+
+// Graph replay of a round of steps; falls back to direct launches when the
+// capture cannot be made (or while kernel timing is on).
+struct RoundGraph {
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    ~RoundGraph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+int drive_stage(const BatchCtx &c, int max_sweeps, int noise_floor, int blocked, StepFn one_step,
+                const void *arg, int steps_per_round, const char *name, hipStream_t s,
+                std::vector<SweepResult> &res) {
+    const int B = c.B;
+    res.assign(B, SweepResult{GHSVD_OK, 0, 0, 0, 0, 0});
+    hipLaunchKernelGGL(k_reset_states, dim3(B), dim3(256), 0, s, c.dev, B, max_sweeps, noise_floor,
+                       blocked);
+    GHSVD_HIP(hipGetLastError());
+    std::vector<int> done(B, 0);
+    RoundGraph rg;
+    const bool use_graph = !prof_active() && !std::getenv("GHSVD_NO_GRAPH") && s != nullptr;
+    if (use_graph) {
+        bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        int rc = GHSVD_OK;
+        if (ok)
+            for (int i = 0; i < steps_per_round && rc == GHSVD_OK; ++i) rc = one_step(c, arg, s);
+        if (ok) ok = hipStreamEndCapture(s, &rg.graph) == hipSuccess && rc == GHSVD_OK;
+        if (ok) ok = hipGraphInstantiate(&rg.exec, rg.graph, nullptr, nullptr, 0) == hipSuccess;
+        if (!ok) {
+            (void)hipGetLastError();
+            if (rg.exec) (void)hipGraphExecDestroy(rg.exec);
+            if (rg.graph) (void)hipGraphDestroy(rg.graph);
+            rg.exec = nullptr;
+            rg.graph = nullptr;
+        }
+    }
+    for (int round = 0; round < max_sweeps; ++round) {
+        if (rg.exec) {
+            GHSVD_HIP(hipGraphLaunch(rg.exec, s));
+        } else {
+            for (int i = 0; i < steps_per_round; ++i) {
+                const int rc = one_step(c, arg, s);
+                if (rc) return rc;
+            }
+        }
+        hipLaunchKernelGGL(k_gather_done, dim3(1), dim3(256), 0, s, c.dev, B, c.done_dev);
+        GHSVD_HIP(hipGetLastError());
+        GHSVD_HIP(hipMemcpyAsync(done.data(), c.done_dev, sizeof(int) * B, hipMemcpyDeviceToHost, s));
+        GHSVD_HIP(hipStreamSynchronize(s));
+        bool all = true;
+        for (int k = 0; k < B; ++k) all = all && done[k];
+        if (all) break;
+    }
+    int worst = GHSVD_OK;
+    for (int k = 0; k < B; ++k) {
+        SweepState hs;
+        GHSVD_HIP(hipMemcpyAsync(&hs, c.host[k].st, sizeof(SweepState), hipMemcpyDeviceToHost, s));
+        GHSVD_HIP(hipStreamSynchronize(s));
+        trace_stage(name, k, hs);
+        SweepResult &r = res[k];
+        r.sweeps = hs.sweeps;
+        r.converged = hs.converged;
+        for (int q = 0; q < hs.sweeps && q < kMaxHist; ++q) {
+            r.visited += (long long)hs.hist[3 * q + 0];
+            r.transformed += (long long)hs.hist[3 * q + 1];
+            r.big += (long long)hs.hist[3 * q + 2];
+        }
+        r.status = hs.err ? hs.err : (hs.converged ? GHSVD_OK : GHSVD_NOT_CONVERGED);
+        if (r.status < 0) worst = r.status;
+    }
+    return worst < 0 ? worst : GHSVD_OK;
+}
+
+struct PointwiseArg {
+    PairFn fn;
+    PairGeom g;
+    int crit;
+};
+
+static int pointwise_step(const BatchCtx &c, const void *arg, hipStream_t s) {
+    const PointwiseArg *a = static_cast<const PointwiseArg *>(arg);
+    hipEvent_t e0, e1;
+    prof_before(s, e0, e1);
+    hipLaunchKernelGGL(a->fn, dim3(c.total(BatchCtx::kSlots)), dim3(a->g.nt), 0, s, c.dev,
+                       c.pre_of(BatchCtx::kSlots), c.B, a->crit);
+    prof_after(s, e0, e1);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }
 
-void trace_stage(const char *name, const SweepState &hs) {
-    if (!std::getenv("GHSVD_TRACE")) return;
-    for (int k = 0; k < hs.sweeps && k < kMaxHist; ++k)
-        std::fprintf(stderr, "ghsvd %s sweep %d: visited %llu transformed %llu big %llu\n", name,
-                     k + 1, hs.hist[3 * k], hs.hist[3 * k + 1], hs.hist[3 * k + 2]);
-}
-
-int run_pointwise_sweeps(SweepArgs a, int max_sweeps, PairGeom g, hipStream_t stream,
-                         SweepResult &res) {
-    res = SweepResult{GHSVD_OK, 0, 0, 0, 0, 0};
-    if (a.n < 2) {
-        res.converged = 1;
-        return GHSVD_OK;
-    }
-    int rc = enqueue_reset_state(a.st, a.slot_cnt, a.nslots, max_sweeps, stream, a.fp32);
-    if (rc) return rc;
-    SweepState hs;
-    for (int sw = 0; sw < max_sweeps; ++sw) {
-        rc = enqueue_pointwise_sweep(a, g, stream);
-        if (rc) return rc;
-        GHSVD_HIP(hipMemcpyAsync(&hs, a.st, offsetof(SweepState, hist), hipMemcpyDeviceToHost,
-                                 stream));
-        GHSVD_HIP(hipStreamSynchronize(stream));
-        if (hs.done) break;
-    }
-    GHSVD_HIP(hipMemcpyAsync(&hs, a.st, sizeof(SweepState), hipMemcpyDeviceToHost, stream));
-    GHSVD_HIP(hipStreamSynchronize(stream));
-    trace_stage(a.fp32 ? "pointwise-fp32" : "pointwise-fp64", hs);
-    res.sweeps = hs.sweeps;
-    res.converged = hs.converged;
-    for (int s = 0; s < hs.sweeps && s < kMaxHist; ++s) {
-        res.visited += (long long)hs.hist[3 * s + 0];
-        res.transformed += (long long)hs.hist[3 * s + 1];
-        res.big += (long long)hs.hist[3 * s + 2];
-    }
-    if (hs.err) res.status = hs.err;
-    else res.status = hs.converged ? GHSVD_OK : GHSVD_NOT_CONVERGED;
-    return res.status;
+int run_pointwise_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, PairGeom g,
+                        hipStream_t s, std::vector<SweepResult> &res) {
+    PointwiseArg a{fp32 ? pick<float>(g.nt, g.r) : pick<double>(g.nt, g.r), g, crit};
+    if (!a.fn) return GHSVD_EINVAL;
+    int steps = 1;
+    for (const PencilDev &P : c.host) steps = P.N - 1 > steps ? P.N - 1 : steps;
+    return drive_stage(c, max_sweeps, fp32, 0, pointwise_step, &a, steps,
+                       fp32 ? "pointwise-fp32" : "pointwise-fp64", s, res);
 }
 
 // ---------------------------------------------------------------------------
@@ -415,54 +469,6 @@ extern "C" int ghsvd_round_robin(int n, int *p_out, int *q_out) {
             q_out[s * slots + k] = q;
         }
     return N - 1;
-}
-
-extern "C" int ghsvd_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, double *G,
-                            int ldg, double *Z, int ldz, int nsweeps, int waves_per_pair,
-                            int crit_literal, long long *counters, int *sweeps_done,
-                            void *stream) {
-    if (n < 1 || m < 1 || p < 1 || ldf < m || ldg < p || ldz < n || nsweeps < 1 || n_plus < 0 ||
-        n_plus > m || !F || !G || !Z)
-        return GHSVD_EINVAL;
-    if (nsweeps > kMaxHist) return GHSVD_EINVAL;
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    const int N = n + (n & 1);
-    SweepState *st = nullptr;
-    unsigned long long *cnt = nullptr;
-    GHSVD_HIP(hipMalloc(&st, sizeof(SweepState)));
-    if (hipMalloc(&cnt, sizeof(unsigned long long) * 3 * (N / 2 + 1)) != hipSuccess) {
-        (void)hipFree(st);
-        return GHSVD_EDEVICE;
-    }
-    SweepArgs a{};
-    a.F = F; a.ldf = ldf; a.m = m; a.nplus = n_plus;
-    a.G = G; a.ldg = ldg; a.p = p;
-    a.Z = Z; a.ldz = ldz; a.n = n;
-    a.N = N; a.nslots = N / 2;
-    a.tol = 0x1p-52 * sqrt((double)n);
-    a.crit = crit_literal;
-    a.fp32 = 0;
-    a.slot_cnt = cnt;
-    a.st = st;
-    const int rows = m > p ? m : p;
-    SweepResult r;
-    int rc = run_pointwise_sweeps(a, nsweeps, choose_pair_geom(rows, waves_per_pair), s, r);
-    if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) {
-        (void)hipFree(st);
-        (void)hipFree(cnt);
-        return rc;
-    }
-    SweepState hs;
-    if (hipMemcpy(&hs, st, sizeof(SweepState), hipMemcpyDeviceToHost) == hipSuccess) {
-        if (counters)
-            for (int k = 0; k < nsweeps; ++k)
-                for (int j = 0; j < 3; ++j)
-                    counters[3 * k + j] = k < hs.sweeps ? (long long)hs.hist[3 * k + j] : 0;
-        if (sweeps_done) *sweeps_done = hs.sweeps;
-    }
-    (void)hipFree(st);
-    (void)hipFree(cnt);
-    return r.status;
 }
 
 extern "C" void ghsvd_profile_enable(int every) {

@@ -10,12 +10,15 @@
 
 namespace ghsvd {
 
-__global__ __launch_bounds__(256) void k_post_cols(int m, int nplus, int p, int n,
+__global__ __launch_bounds__(256) void k_post_cols(int m, int nplus_unused, int p, int n,
                                                    const double2 *F, long ldf, const double2 *G,
                                                    long ldg, const double2 *Z, long ldz,
                                                    const double *gnorm2, double *lam,
-                                                   double *scale, int *flags) {
+                                                   double *scale, int *flags,
+                                                   const int *nplus_dev) {
     __shared__ double red[3 * 256 / kWave];
+    (void)nplus_unused;
+    const int nplus = nplus_dev[0];
     const int j = blockIdx.x;
     const double2 *f = F + (size_t)j * ldf;
     const double2 *g = G + (size_t)j * ldg;
@@ -69,18 +72,20 @@ __global__ void k_post_out(int n, const double2 *Z, long ldz, const double *lam,
     if (blockIdx.x == 0 && threadIdx.x == 0) lambda[col] = lam[j];
 }
 
-int postprocess(int m, int nplus, int p, int n, const double2 *F, long ldf, const double2 *G,
-                long ldg, const double2 *Z, long ldz, const int *perm, const double *gnorm2,
-                int sort, double *lam_tmp, double *scale, int *rank, int *flags, double *lambda,
-                double2 *X, long ldx, hipStream_t stream) {
-    hipLaunchKernelGGL(k_post_cols, dim3(n), dim3(256), 0, stream, m, nplus, p, n, F, ldf, G, ldg,
-                       Z, ldz, gnorm2, lam_tmp, scale, flags);
-    hipLaunchKernelGGL(k_post_rank, dim3((n + 255) / 256), dim3(256), 0, stream, n, lam_tmp, rank,
-                       sort);
+// lambda[rank_j] = h_j / s_j, X(perm[i], rank_j) = Z(i, j) / sqrt(s_j);
+// small[2] |= 1 when G is numerically rank deficient (a vanishing s_j, or
+// ||x_j|| ||G||_F >= 1 / (sqrt(n) eps)), |= 2 for non-finite values.
+int postprocess(const PencilDev &P, int sort, hipStream_t stream) {
+    const int n = P.n;
+    hipLaunchKernelGGL(k_post_cols, dim3(n), dim3(256), 0, stream, P.mr, 0, P.pr, n, P.Fw, P.ldf,
+                       P.Gw, P.ldg, P.Zw, P.ldz, P.gnorm2, P.lam_tmp, P.scale, P.small + 2,
+                       P.small + 1);
+    hipLaunchKernelGGL(k_post_rank, dim3((n + 255) / 256), dim3(256), 0, stream, n, P.lam_tmp,
+                       P.rank, sort);
     int bx = (n + 255) / 256;
     if (bx > 16) bx = 16;
-    hipLaunchKernelGGL(k_post_out, dim3(bx, n), dim3(256), 0, stream, n, Z, ldz, lam_tmp, scale,
-                       rank, perm, lambda, X, ldx);
+    hipLaunchKernelGGL(k_post_out, dim3(bx, n), dim3(256), 0, stream, n, P.Zw, P.ldz, P.lam_tmp,
+                       P.scale, P.rank, P.reduce ? P.perm : nullptr, P.lambda, P.X, P.ldx);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }

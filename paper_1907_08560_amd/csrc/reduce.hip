@@ -61,13 +61,39 @@ __device__ __forceinline__ bool jqr_active(const JqrState *st, int n) {
 
 // hd[j] = J-norm^2 of column j over rows k..m-1 (first iteration only; later
 // iterations get it from the apply kernel).
-__global__ __launch_bounds__(kGridNT) void k_jqr_colnorms(const double2 *A, long lda, int m, int n,
-                                                          const int8_t *J, JqrState *st,
-                                                          double *hd) {
+// Batched launches over columns: workgroup -> (pencil, column j) through the
+// prefix sums of the column counts; single-workgroup phases: one workgroup
+// per pencil.  Each kernel reads the pencil's fields below.
+#define JQR_PENCIL_COL()                                          \
+    const int pk = find_pencil(pre, B, blockIdx.x);                \
+    const PencilDev &P = PD[pk];                                  \
+    if (!P.reduce) return;                                        \
+    double2 *A = P.Ft;                                            \
+    const long lda = P.ldft;                                      \
+    const int m = P.m, n = P.n;                                   \
+    int8_t *J = P.Jw;                                             \
+    JqrState *st = P.jst;                                         \
+    const int j_local = blockIdx.x - pre[pk];                     \
+    (void)J;                                                      \
+    (void)j_local
+#define JQR_PENCIL_ONE()                                          \
+    const PencilDev &P = PD[blockIdx.x];                          \
+    if (!P.reduce) return;                                        \
+    double2 *A = P.Ft;                                            \
+    const long lda = P.ldft;                                      \
+    const int m = P.m, n = P.n;                                   \
+    int8_t *J = P.Jw;                                             \
+    JqrState *st = P.jst;                                         \
+    (void)J;                                                      \
+    (void)m
+
+__global__ __launch_bounds__(kGridNT) void k_jqr_colnorms(const PencilDev *PD, const int *pre, int B) {
     __shared__ double red[kGridNT / kWave];
+    JQR_PENCIL_COL();
+    double *hd = P.hd;
     if (!jqr_active(st, n)) return;
     const int k = st->k;
-    const int j = blockIdx.x;
+    const int j = j_local;
     if (j < k) return;
     const double h = jnorm_block(A + (size_t)j * lda, J, k, m, red);
     if (threadIdx.x == 0) hd[j] = h;
@@ -76,15 +102,16 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_colnorms(const double2 *A, long
 // Every workgroup finds the diagonal pivot jmax = argmax |hd[j]| (j >= k) and
 // workgroup j computes the J-product of column jmax with column j, stored at
 // the position column j takes after the swap k <-> jmax.
-__global__ __launch_bounds__(kGridNT) void k_jqr_cross(const double2 *A, long lda, int m, int n,
-                                                       const int8_t *J, JqrState *st,
-                                                       const double *hd, double2 *hc) {
+__global__ __launch_bounds__(kGridNT) void k_jqr_cross(const PencilDev *PD, const int *pre, int B) {
     __shared__ double red[2 * kGridNT / kWave];
     __shared__ double rv[kGridNT / kWave];
     __shared__ int ri[kGridNT / kWave];
+    JQR_PENCIL_COL();
+    const double *hd = P.hd;
+    double2 *hc = P.hc;
     if (!jqr_active(st, n)) return;
     const int k = st->k;
-    const int j = blockIdx.x;
+    const int j = j_local;
     if (j < k || k == n - 1) return;
     double bv = -1.0;
     int bi = k;
@@ -100,11 +127,13 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_cross(const double2 *A, long ld
 }
 
 // Applies the diagonal pivot swap and the first Bunch-Kaufman test.
-__global__ __launch_bounds__(kOneNT) void k_jqr_decide1(double2 *A, long lda, int m, int n,
-                                                        JqrState *st, double *hd,
-                                                        const double2 *hc, int *perm) {
+__global__ __launch_bounds__(kOneNT) void k_jqr_decide1(const PencilDev *PD) {
     __shared__ double rv[kOneNT / kWave];
     __shared__ int ri[kOneNT / kWave];
+    JQR_PENCIL_ONE();
+    double *hd = P.hd;
+    const double2 *hc = P.hc;
+    int *perm = P.perm;
     if (!jqr_active(st, n)) return;
     const int k = st->k;
     double bv = -1.0;
@@ -140,13 +169,13 @@ __global__ __launch_bounds__(kOneNT) void k_jqr_decide1(double2 *A, long lda, in
 }
 
 // hi[l] = |J-product of the candidate column ii with column l| (l >= k, l != ii).
-__global__ __launch_bounds__(kGridNT) void k_jqr_cross2(const double2 *A, long lda, int m, int n,
-                                                        const int8_t *J, JqrState *st,
-                                                        double *hi) {
+__global__ __launch_bounds__(kGridNT) void k_jqr_cross2(const PencilDev *PD, const int *pre, int B) {
     __shared__ double red[2 * kGridNT / kWave];
+    JQR_PENCIL_COL();
+    double *hi = P.hi;
     if (!jqr_active(st, n) || !st->need2) return;
     const int k = st->k, ii = st->ii;
-    const int l = blockIdx.x;
+    const int l = j_local;
     if (l < k || l == ii) return;
     const double2 d = jdot_block(A + (size_t)ii * lda, A + (size_t)l * lda, J, k, m, red);
     if (threadIdx.x == 0) hi[l] = sqrt(cnorm2(d));
@@ -154,13 +183,15 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_cross2(const double2 *A, long l
 
 // Second Bunch-Kaufman test, the swaps it implies, and for a 2x2 pivot the
 // Jacobi rotation of the pivot J-Gram applied to columns k, k+1.
-__global__ __launch_bounds__(kOneNT) void k_jqr_decide2(double2 *A, long lda, int m, int n,
-                                                        const int8_t *J, JqrState *st, double *hd,
-                                                        const double *hi, int *perm) {
+__global__ __launch_bounds__(kOneNT) void k_jqr_decide2(const PencilDev *PD) {
     __shared__ double red[4 * kOneNT / kWave];
     __shared__ double rv[kOneNT / kWave];
     __shared__ int ri[kOneNT / kWave];
     __shared__ int piv_s, swp_s;
+    JQR_PENCIL_ONE();
+    double *hd = P.hd;
+    const double *hi = P.hi;
+    int *perm = P.perm;
     if (!jqr_active(st, n) || !st->need2) return;
     const int k = st->k, ii = st->ii;
     double sv = -1.0;
@@ -236,12 +267,12 @@ __global__ __launch_bounds__(kOneNT) void k_jqr_decide2(double2 *A, long lda, in
 }
 
 // Builds the hyperbolic reflector for column c = k + which, rows r0 = c..m-1.
-__global__ __launch_bounds__(kOneNT) void k_jqr_reflect(double2 *A, long lda, int m, int n,
-                                                        int8_t *J, JqrState *st, double2 *sbuf,
-                                                        int which) {
+__global__ __launch_bounds__(kOneNT) void k_jqr_reflect(const PencilDev *PD, int which) {
     __shared__ double red[kOneNT / kWave];
     __shared__ double rv[kOneNT / kWave];
     __shared__ int ri[kOneNT / kWave];
+    JQR_PENCIL_ONE();
+    double2 *sbuf = P.sbuf;
     if (!jqr_active(st, n)) return;
     if (which == 1 && st->piv != 2) return;
     const int c = st->k + which;
@@ -302,17 +333,18 @@ __global__ __launch_bounds__(kOneNT) void k_jqr_reflect(double2 *A, long lda, in
 // Applies H(s) = I + tau s s^* J to columns j > c (rows r0..m-1) and, when
 // the next iteration starts after this reflector, leaves the columns'
 // J-norms over rows c+1..m-1 in hd.
-__global__ __launch_bounds__(kGridNT) void k_jqr_apply(double2 *A, long lda, int m, int n,
-                                                       const int8_t *J, JqrState *st,
-                                                       const double2 *sbuf, double *hd,
+__global__ __launch_bounds__(kGridNT) void k_jqr_apply(const PencilDev *PD, const int *pre, int B,
                                                        int which) {
     __shared__ double red[2 * kGridNT / kWave];
+    JQR_PENCIL_COL();
+    const double2 *sbuf = P.sbuf;
+    double *hd = P.hd;
     if (!jqr_active(st, n)) return;
     const int piv = st->piv;
     if (which == 1 && piv != 2) return;
     const int c = st->k + which;
     const int r0 = c;
-    const int j = blockIdx.x;
+    const int j = j_local;
     if (j <= c) return;
     const double2 *s = sbuf + (size_t)which * m;
     double2 *y = A + (size_t)j * lda;
@@ -332,7 +364,8 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_apply(double2 *A, long lda, int
 }
 
 // Finishes a 2x2 pivot (R^* on rows k, k+1 of the pivot block) and advances k.
-__global__ void k_jqr_finish(double2 *A, long lda, int n, JqrState *st) {
+__global__ void k_jqr_finish(const PencilDev *PD) {
+    JQR_PENCIL_ONE();
     if (!jqr_active(st, n)) return;
     if (threadIdx.x != 0) return;
     const int k = st->k;
@@ -352,9 +385,14 @@ __global__ void k_jqr_finish(double2 *A, long lda, int n, JqrState *st) {
     st->k = k + st->piv;
 }
 
-__global__ void k_jqr_init(JqrState *st, int *perm, int n) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int j = t; j < n; j += gridDim.x * blockDim.x) perm[j] = j;
+__global__ void k_jqr_init(const PencilDev *PD) {
+    const PencilDev &P = PD[blockIdx.x];
+    JqrState *st = P.jst;
+    int *perm = P.perm;
+    const int n = P.n;
+    const int t = threadIdx.x;
+    for (int j = t; j < n; j += blockDim.x) perm[j] = j;
+    if (!P.reduce) return;
     if (t == 0) {
         st->k = 0;
         st->piv = 1;
@@ -365,45 +403,18 @@ __global__ void k_jqr_init(JqrState *st, int *perm, int n) {
     }
 }
 
-int run_jqr(int m, int n, double2 *A, long lda, int8_t *J, int *perm, const JqrBufs &b,
-            hipStream_t stream, int *n2x2) {
-    hipLaunchKernelGGL(k_jqr_init, dim3((n + 255) / 256), dim3(256), 0, stream, b.st, perm, n);
-    hipLaunchKernelGGL(k_jqr_colnorms, dim3(n), dim3(kGridNT), 0, stream, A, lda, m, n, J, b.st,
-                       b.hd);
-    // At most n iterations (fewer when 2x2 pivots occur; the extra ones exit at once).
-    for (int it = 0; it < n; ++it) {
-        hipLaunchKernelGGL(k_jqr_cross, dim3(n), dim3(kGridNT), 0, stream, A, lda, m, n, J, b.st,
-                           b.hd, b.hc);
-        hipLaunchKernelGGL(k_jqr_decide1, dim3(1), dim3(kOneNT), 0, stream, A, lda, m, n, b.st,
-                           b.hd, b.hc, perm);
-        hipLaunchKernelGGL(k_jqr_cross2, dim3(n), dim3(kGridNT), 0, stream, A, lda, m, n, J,
-                           b.st, b.hi);
-        hipLaunchKernelGGL(k_jqr_decide2, dim3(1), dim3(kOneNT), 0, stream, A, lda, m, n, J,
-                           b.st, b.hd, b.hi, perm);
-        for (int w = 0; w < 2; ++w) {
-            hipLaunchKernelGGL(k_jqr_reflect, dim3(1), dim3(kOneNT), 0, stream, A, lda, m, n, J,
-                               b.st, b.s, w);
-            hipLaunchKernelGGL(k_jqr_apply, dim3(n), dim3(kGridNT), 0, stream, A, lda, m, n, J,
-                               b.st, b.s, b.hd, w);
-        }
-        hipLaunchKernelGGL(k_jqr_finish, dim3(1), dim3(64), 0, stream, A, lda, n, b.st);
-    }
-    GHSVD_HIP(hipGetLastError());
-    JqrState hs;
-    GHSVD_HIP(hipMemcpyAsync(&hs, b.st, sizeof(JqrState), hipMemcpyDeviceToHost, stream));
-    GHSVD_HIP(hipStreamSynchronize(stream));
-    if (n2x2) *n2x2 = hs.n2x2;
-    if (hs.status) return hs.status;
-    if (hs.k < n) return GHSVD_ERANK;
-    return GHSVD_OK;
-}
-
 // ---------------------------------------------------------------------------
 // Householder QR of G P2.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kOneNT) void k_qr_house(double2 *A, long lda, int p, int k,
-                                                     double2 *v, double *coef) {
+__global__ __launch_bounds__(kOneNT) void k_qr_house(const PencilDev *PD, int k) {
     __shared__ double red[kOneNT / kWave];
+    const PencilDev &P = PD[blockIdx.x];
+    if (!P.reduce || k >= P.n || P.jst->status != 0) return;
+    double2 *A = P.Gt;
+    const long lda = P.ldgt;
+    const int p = P.p;
+    double2 *v = P.qv;
+    double *coef = P.qcoef;
     double2 *x = A + (size_t)k * lda;
     double s[1] = {0.0};
     for (int r = k + threadIdx.x; r < p; r += blockDim.x) s[0] += cnorm2(x[r]);
@@ -428,11 +439,19 @@ __global__ __launch_bounds__(kOneNT) void k_qr_house(double2 *A, long lda, int p
     }
 }
 
-__global__ __launch_bounds__(kGridNT) void k_qr_apply(double2 *A, long lda, int p, int k,
-                                                      const double2 *v, const double *coef) {
+__global__ __launch_bounds__(kGridNT) void k_qr_apply(const PencilDev *PD, const int *pre, int B,
+                                                      int k) {
     __shared__ double red[2 * kGridNT / kWave];
-    const int j = k + 1 + blockIdx.x;
-    const double cf = coef[0];
+    const int pk = find_pencil(pre, B, blockIdx.x);
+    const PencilDev &P = PD[pk];
+    if (!P.reduce || k >= P.n || P.jst->status != 0) return;
+    const int j = blockIdx.x - pre[pk];
+    if (j <= k) return;
+    double2 *A = P.Gt;
+    const long lda = P.ldgt;
+    const int p = P.p;
+    const double2 *v = P.qv;
+    const double cf = P.qcoef[0];
     if (cf == 0.0) return;
     double2 *y = A + (size_t)j * lda;
     double w[2] = {0.0, 0.0};
@@ -444,17 +463,6 @@ __global__ __launch_bounds__(kGridNT) void k_qr_apply(double2 *A, long lda, int 
     block_sum<2>(w, red);
     const double2 tw = cmk(w[0] * cf, w[1] * cf);
     for (int r = k + threadIdx.x; r < p; r += blockDim.x) y[r] = csub(y[r], cmul(v[r], tw));
-}
-
-int run_qr(int p, int n, double2 *A, long lda, double2 *v, double *coef, hipStream_t stream) {
-    for (int k = 0; k < n; ++k) {
-        hipLaunchKernelGGL(k_qr_house, dim3(1), dim3(kOneNT), 0, stream, A, lda, p, k, v, coef);
-        if (k + 1 < n)
-            hipLaunchKernelGGL(k_qr_apply, dim3(n - k - 1), dim3(kGridNT), 0, stream, A, lda, p,
-                               k, v, coef);
-    }
-    GHSVD_HIP(hipGetLastError());
-    return GHSVD_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -598,6 +606,74 @@ int set_identity(int n, void *Z, long ldz, int fp32, hipStream_t stream) {
     if (bx > 16) bx = 16;
     hipLaunchKernelGGL(k_identity, dim3(bx, n), dim3(256), 0, stream, n, Z, ldz, fp32);
     GHSVD_HIP(hipGetLastError());
+    return GHSVD_OK;
+}
+
+__global__ void k_jqr_status(const PencilDev *PD, int B, int *out) {
+    for (int k = threadIdx.x; k < B; k += blockDim.x) {
+        const PencilDev &P = PD[k];
+        if (!P.reduce) {
+            out[2 * k] = 0;
+            out[2 * k + 1] = 0;
+            continue;
+        }
+        const JqrState *st = P.jst;
+        out[2 * k] = st->status ? st->status : (st->k < P.n ? GHSVD_ERANK : 0);
+        out[2 * k + 1] = st->n2x2;
+    }
+}
+
+int run_reduction(const BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
+                  hipStream_t s) {
+    const int B = c.B;
+    status.assign(B, 0);
+    n2x2.assign(B, 0);
+    int any = 0;
+    for (const PencilDev &P : c.host) any |= P.reduce;
+    if (!any) return GHSVD_OK;
+    for (int k = 0; k < B; ++k) {
+        const PencilDev &P = c.host[k];
+        if (!P.reduce) continue;
+        int rc = copy_cols(P.m, P.n, P.Fin, P.ldfin, P.Ft, P.ldft, nullptr, s);
+        if (rc) return rc;
+        GHSVD_HIP(hipMemcpyAsync(P.Jw, P.Jin, (size_t)P.m, hipMemcpyDeviceToDevice, s));
+    }
+    const int *pc = c.pre_of(BatchCtx::kCols);
+    const int tot = c.total(BatchCtx::kCols);
+    hipLaunchKernelGGL(k_jqr_init, dim3(B), dim3(256), 0, s, c.dev);
+    hipLaunchKernelGGL(k_jqr_colnorms, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B);
+    // At most max_n iterations (fewer when 2x2 pivots occur; extra ones exit at once).
+    for (int it = 0; it < c.max_n; ++it) {
+        hipLaunchKernelGGL(k_jqr_cross, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B);
+        hipLaunchKernelGGL(k_jqr_decide1, dim3(B), dim3(kOneNT), 0, s, c.dev);
+        hipLaunchKernelGGL(k_jqr_cross2, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B);
+        hipLaunchKernelGGL(k_jqr_decide2, dim3(B), dim3(kOneNT), 0, s, c.dev);
+        for (int w = 0; w < 2; ++w) {
+            hipLaunchKernelGGL(k_jqr_reflect, dim3(B), dim3(kOneNT), 0, s, c.dev, w);
+            hipLaunchKernelGGL(k_jqr_apply, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, w);
+        }
+        hipLaunchKernelGGL(k_jqr_finish, dim3(B), dim3(64), 0, s, c.dev);
+    }
+    GHSVD_HIP(hipGetLastError());
+    for (int k = 0; k < B; ++k) {
+        const PencilDev &P = c.host[k];
+        if (!P.reduce) continue;
+        int rc = copy_cols(P.p, P.n, P.Gin, P.ldgin, P.Gt, P.ldgt, P.perm, s);
+        if (rc) return rc;
+    }
+    for (int k = 0; k < c.max_n; ++k) {
+        hipLaunchKernelGGL(k_qr_house, dim3(B), dim3(kOneNT), 0, s, c.dev, k);
+        hipLaunchKernelGGL(k_qr_apply, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, k);
+    }
+    GHSVD_HIP(hipGetLastError());
+    std::vector<int> out(2 * B);
+    hipLaunchKernelGGL(k_jqr_status, dim3(1), dim3(256), 0, s, c.dev, B, c.done_dev);
+    GHSVD_HIP(hipMemcpyAsync(out.data(), c.done_dev, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, s));
+    GHSVD_HIP(hipStreamSynchronize(s));
+    for (int k = 0; k < B; ++k) {
+        status[k] = out[2 * k];
+        n2x2[k] = out[2 * k + 1];
+    }
     return GHSVD_OK;
 }
 

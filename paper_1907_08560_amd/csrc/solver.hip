@@ -1,17 +1,24 @@
-// solver.hip -- the C entry points: workspace planning, the reduction, the
-// sweep stages and the outputs for one pencil (ghsvd_solve) and for a batch
-// of uneven pencils (ghsvd_solve_batched, in batched.hip).
-#include <cstdio>
+// solver.hip -- the C entry points.  ghsvd_solve is a batch of one pencil;
+// ghsvd_solve_batched runs all pencils' reductions and sweeps together, each
+// launch covering every pencil still active.
+#include <algorithm>
 #include <cstring>
+#include <vector>
 
-#include "post.hpp"
 #include "reduce.hpp"
 #include "solver.hpp"
 #include "sweep.hpp"
 
 namespace ghsvd {
 
-Plan make_plan(int m, int n, int p, const ghsvd_options &o) {
+void fill_options(const ghsvd_options *opt, ghsvd_options &o) {
+    ghsvd_default_options(&o);
+    if (opt) o = *opt;
+    if (o.max_sweeps <= 0) o.max_sweeps = kDefaultMaxSweeps;
+    if (o.max_sweeps > kMaxHist) o.max_sweeps = kMaxHist;
+}
+
+Plan make_plan(int m, int n, int p, const ghsvd_options &o, int block_width) {
     Plan pl{};
     pl.m = m;
     pl.n = n;
@@ -27,168 +34,322 @@ Plan make_plan(int m, int n, int p, const ghsvd_options &o) {
     pl.N = n + (n & 1);
     pl.mixed = (o.precision == GHSVD_MIXED);
     pl.blocked = (o.variant == GHSVD_BLOCKED);
+    pl.w = block_width;
     return pl;
 }
 
-PencilWs carve(Carver &c, const Plan &pl) {
-    PencilWs w{};
+void carve_pencil(Carver &c, const Plan &pl, PencilDev &d) {
     const int n = pl.n;
+    d.m = pl.m;
+    d.n = n;
+    d.p = pl.p;
+    d.mr = pl.mr;
+    d.pr = pl.pr;
+    d.reduce = pl.reduce;
+    d.N = pl.N;
+    d.nslots = pl.N / 2;
+    d.ldft = pl.ldft;
+    d.ldgt = pl.ldgt;
+    d.ldf = pl.ldf;
+    d.ldg = pl.ldg;
+    d.ldz = pl.ldz;
+    d.jst = c.take<JqrState>(1);
     if (pl.reduce) {
-        w.Ft = c.take<double2>((size_t)pl.ldft * n);
-        w.Gt = c.take<double2>((size_t)pl.ldgt * n);
-        w.jq.st = c.take<JqrState>(1);
-        w.jq.hd = c.take<double>(n);
-        w.jq.hc = c.take<double2>(n);
-        w.jq.hi = c.take<double>(n);
-        w.jq.s = c.take<double2>(2 * (size_t)pl.m);
-        w.qv = c.take<double2>(pl.p);
-        w.qcoef = c.take<double>(1);
+        d.Ft = c.take<double2>((size_t)pl.ldft * n);
+        d.Gt = c.take<double2>((size_t)pl.ldgt * n);
+        d.hd = c.take<double>(n);
+        d.hc = c.take<double2>(n);
+        d.hi = c.take<double>(n);
+        d.sbuf = c.take<double2>(2 * (size_t)pl.m);
+        d.qv = c.take<double2>(pl.p);
+        d.qcoef = c.take<double>(1);
     }
-    w.Jw = c.take<int8_t>(pl.m);
-    w.rowmap = c.take<int>(pl.m > n ? pl.m : n);
-    w.perm = c.take<int>(n);
-    w.Fw = c.take<double2>((size_t)pl.ldf * n);
-    w.Gw = c.take<double2>((size_t)pl.ldg * n);
-    w.Zw = c.take<double2>((size_t)pl.ldz * n);
-    w.st = c.take<SweepState>(1);
-    w.slot_cnt = c.take<unsigned long long>(3 * (size_t)(pl.N / 2 + 1));
-    w.lam_tmp = c.take<double>(n);
-    w.scale = c.take<double>(n);
-    w.rank = c.take<int>(n);
-    w.small = c.take<int>(8);
-    w.gnorm2 = c.take<double>(1);
+    d.Jw = c.take<int8_t>(pl.m);
+    d.rowmap = c.take<int>(pl.m > n ? pl.m : n);
+    d.perm = c.take<int>(n);
+    d.Fw = c.take<double2>((size_t)pl.ldf * n);
+    d.Gw = c.take<double2>((size_t)pl.ldg * n);
+    d.Zw = c.take<double2>((size_t)pl.ldz * n);
+    d.st = c.take<SweepState>(1);
+    d.slot_cnt = c.take<unsigned long long>(3 * (size_t)(pl.N / 2 + 1));
+    d.lam_tmp = c.take<double>(n);
+    d.scale = c.take<double>(n);
+    d.rank = c.take<int>(n);
+    d.small = c.take<int>(8);
+    d.gnorm2 = c.take<double>(1);
     if (pl.mixed) {
-        w.F32 = c.take<float2>((size_t)pl.ldf * n);
-        w.G32 = c.take<float2>((size_t)pl.ldg * n);
-        w.Z32 = c.take<float2>((size_t)pl.ldz * n);
+        d.F32 = c.take<float2>((size_t)pl.ldf * n);
+        d.G32 = c.take<float2>((size_t)pl.ldg * n);
+        d.Z32 = c.take<float2>((size_t)pl.ldz * n);
     }
-    if (pl.blocked || pl.mixed) carve_blocked(c, pl, w);
-    return w;
-}
-
-size_t plan_bytes(const Plan &pl) {
-    Carver c{nullptr, 0, (size_t)-1};
-    (void)carve(c, pl);
-    return align_up(c.used, 256);
-}
-
-__global__ void k_zero_small(int *small, double *gnorm2) {
-    const int t = threadIdx.x;
-    if (t < 8) small[t] = 0;
-    if (t == 0) gnorm2[0] = 0.0;
-}
-
-static void fill_options(const ghsvd_options *opt, ghsvd_options &o) {
-    ghsvd_default_options(&o);
-    if (opt) o = *opt;
-    if (o.max_sweeps <= 0) o.max_sweeps = kDefaultMaxSweeps;
-    if (o.max_sweeps > kMaxHist) o.max_sweeps = kMaxHist;
-}
-
-// Reduction (or plain copies) into the sweep buffers; leaves nplus in small[1].
-int prepare_pencil(const Plan &pl, const PencilWs &w, const double2 *F, long ldf,
-                   const int8_t *J, const double2 *G, long ldg, hipStream_t s, int *n2x2) {
-    const int m = pl.m, n = pl.n, p = pl.p;
-    int rc;
-    *n2x2 = 0;
-    if (pl.reduce) {
-        if ((rc = copy_cols(m, n, F, ldf, w.Ft, pl.ldft, nullptr, s))) return rc;
-        GHSVD_HIP(hipMemcpyAsync(w.Jw, J, (size_t)m, hipMemcpyDeviceToDevice, s));
-        rc = run_jqr(m, n, w.Ft, pl.ldft, w.Jw, w.perm, w.jq, s, n2x2);
-        if (rc) return rc;
-        if ((rc = copy_cols(p, n, G, ldg, w.Gt, pl.ldgt, w.perm, s))) return rc;
-        if ((rc = run_qr(p, n, w.Gt, pl.ldgt, w.qv, w.qcoef, s))) return rc;
-        if ((rc = jsplit(n, n, w.Ft, pl.ldft, w.Jw, w.Fw, pl.ldf, w.rowmap, w.small + 1, s)))
-            return rc;
-        if ((rc = copy_cols(n, n, w.Gt, pl.ldgt, w.Gw, pl.ldg, nullptr, s))) return rc;
+    if (pl.blocked || pl.mixed) {
+        carve_blocked(c, pl.mr, n, pl.pr, pl.w, pl.mixed, d);
+        set_block_geometry(d, pl.w);
     } else {
-        if ((rc = jsplit(m, n, F, ldf, J, w.Fw, pl.ldf, w.rowmap, w.small + 1, s))) return rc;
-        if ((rc = copy_cols(p, n, G, ldg, w.Gw, pl.ldg, nullptr, s))) return rc;
+        d.w = pl.w;
+        d.nb = 0;
+        d.nbp = 0;
     }
-    return set_identity(n, w.Zw, pl.ldz, 0, s);
 }
 
-SweepArgs sweep_args(const Plan &pl, const PencilWs &w, int nplus, const ghsvd_options &o,
-                     int fp32) {
-    SweepArgs a{};
-    a.F = fp32 ? (void *)w.F32 : (void *)w.Fw;
-    a.ldf = pl.ldf;
-    a.m = pl.mr;
-    a.nplus = nplus;
-    a.G = fp32 ? (void *)w.G32 : (void *)w.Gw;
-    a.ldg = pl.ldg;
-    a.p = pl.pr;
-    a.Z = fp32 ? (void *)w.Z32 : (void *)w.Zw;
-    a.ldz = pl.ldz;
-    a.n = pl.n;
-    a.N = pl.N;
-    a.nslots = pl.N / 2;
-    a.tol = (fp32 ? 0x1p-23 : 0x1p-52) * sqrt((double)pl.n);
-    a.crit = o.crit_literal;
-    a.fp32 = fp32;
-    a.slot_cnt = w.slot_cnt;
-    a.st = w.st;
-    return a;
+size_t pencil_bytes(const Plan &pl) {
+    Carver c{nullptr, 0, (size_t)-1};
+    PencilDev d{};
+    carve_pencil(c, pl, d);
+    return align_up(c.used, 256) + 256;
 }
 
-static int worst(int a, int b) {
+size_t batch_bytes(int B) {
+    return align_up(sizeof(PencilDev) * B, 256) +
+           align_up(sizeof(int) * BatchCtx::kKinds * (B + 1), 256) +
+           align_up(sizeof(int) * 2 * (B + 1), 256) + 256;
+}
+
+static void carve_batch(Carver &c, BatchCtx &bc, int B) {
+    bc.dev = c.take<PencilDev>(B);
+    bc.pre_dev = c.take<int>(BatchCtx::kKinds * (B + 1));
+    bc.done_dev = c.take<int>(2 * (B + 1));
+}
+
+__global__ void k_zero_small(const PencilDev *PD, int B) {
+    const int k = blockIdx.x;
+    if (k >= B) return;
+    if (threadIdx.x < 8) PD[k].small[threadIdx.x] = 0;
+    if (threadIdx.x == 0) PD[k].gnorm2[0] = 0.0;
+}
+
+__global__ void k_gather_small(const PencilDev *PD, int B, int idx, int *out) {
+    for (int k = threadIdx.x; k < B; k += blockDim.x) out[k] = PD[k].small[idx];
+}
+
+static int gather_small(const BatchCtx &c, int idx, std::vector<int> &out, hipStream_t s) {
+    out.assign(c.B, 0);
+    hipLaunchKernelGGL(k_gather_small, dim3(1), dim3(256), 0, s, c.dev, c.B, idx, c.done_dev);
+    GHSVD_HIP(hipGetLastError());
+    GHSVD_HIP(hipMemcpyAsync(out.data(), c.done_dev, sizeof(int) * c.B, hipMemcpyDeviceToHost, s));
+    GHSVD_HIP(hipStreamSynchronize(s));
+    return GHSVD_OK;
+}
+
+static int worst_of(int a, int b) {
     if (a < 0 || b < 0) return a < b ? a : b;
     return a > b ? a : b;
 }
 
-int solve_one(const Plan &pl, const PencilWs &w, const double2 *F, long ldf, const int8_t *J,
-              const double2 *G, long ldg, double *lambda, double2 *X, long ldx,
-              const ghsvd_options &o, ghsvd_info &info, hipStream_t s) {
-    const int n = pl.n;
-    int rc;
-    hipLaunchKernelGGL(k_zero_small, dim3(1), dim3(64), 0, s, w.small, w.gnorm2);
-    if ((rc = check_inputs(pl.m, n, pl.p, F, ldf, J, G, ldg, w.small, w.gnorm2, s))) return rc;
-    int hsmall[8];
-    GHSVD_HIP(hipMemcpyAsync(hsmall, w.small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
-    GHSVD_HIP(hipStreamSynchronize(s));
-    if (hsmall[0] & 1) return GHSVD_EINVAL;
-    if (hsmall[0] & 2) return GHSVD_ENONFINITE;
+// Keeps only the pencils whose status is still non-negative.
+static int compact(BatchCtx &c, std::vector<int> &idx, const std::vector<int> &status,
+                   hipStream_t s) {
+    std::vector<PencilDev> keep;
+    std::vector<int> kidx;
+    for (size_t k = 0; k < idx.size(); ++k)
+        if (status[idx[k]] >= 0) {
+            keep.push_back(c.host[k]);
+            kidx.push_back(idx[k]);
+        }
+    if (kidx.size() == idx.size()) return GHSVD_OK;
+    c.host.swap(keep);
+    idx.swap(kidx);
+    c.B = (int)c.host.size();
+    if (c.B == 0) return GHSVD_OK;
+    return upload_batch(c, s);
+}
 
-    rc = prepare_pencil(pl, w, F, ldf, J, G, ldg, s, &info.n2x2);
-    if (rc) return rc;
-    GHSVD_HIP(hipMemcpyAsync(hsmall, w.small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
-    GHSVD_HIP(hipStreamSynchronize(s));
-    const int nplus = hsmall[1];
-    info.m_r = pl.mr;
-    info.p_r = pl.pr;
-    info.n_plus = nplus;
+size_t solve_batch_bytes(const std::vector<PencilIO> &io, const ghsvd_options &o) {
+    int max_n = 0;
+    for (const PencilIO &p : io) max_n = p.n > max_n ? p.n : max_n;
+    const int w = pick_block_width(max_n, o.block_width);
+    size_t total = batch_bytes((int)io.size());
+    for (const PencilIO &p : io) total += pencil_bytes(make_plan(p.m, p.n, p.p, o, w));
+    return total;
+}
 
-    int status = GHSVD_OK;
-    // Stages: (FP32 warm-up, blocked or pointwise, with its FP64 hand-off) or
-    // (FP64 blocked), then FP64 pointwise sweeps decide convergence.
-    if (pl.mixed) {
-        rc = run_fp32_stage(pl, w, nplus, o, info, s);
-        if (rc < 0) return rc;
-    } else if (pl.blocked) {
-        rc = run_blocked_fp64(pl, w, nplus, o, info, s);
-        if (rc < 0) return rc;
+int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *work, size_t lwork,
+                std::vector<ghsvd_info> &info, hipStream_t s) {
+    const int B0 = (int)io.size();
+    info.assign(B0, ghsvd_info{});
+    std::vector<int> status(B0, GHSVD_OK);
+    int max_n = 0;
+    for (const PencilIO &p : io) max_n = p.n > max_n ? p.n : max_n;
+    const int w = pick_block_width(max_n, o.block_width);
+    Carver c{reinterpret_cast<char *>(work), 0, lwork};
+    BatchCtx bc;
+    carve_batch(c, bc, B0);
+    bc.B = B0;
+    bc.host.resize(B0);
+    std::vector<int> idx(B0);
+    for (int k = 0; k < B0; ++k) {
+        const PencilIO &p = io[k];
+        const Plan pl = make_plan(p.m, p.n, p.p, o, w);
+        PencilDev &d = bc.host[k];
+        d = PencilDev{};
+        c.used = align_up(c.used, 256);
+        carve_pencil(c, pl, d);
+        d.Fin = p.F;
+        d.ldfin = p.ldf;
+        d.Jin = p.J;
+        d.Gin = p.G;
+        d.ldgin = p.ldg;
+        d.lambda = p.lambda;
+        d.X = p.X;
+        d.ldx = p.ldx;
+        idx[k] = k;
+        info[k].m_r = pl.mr;
+        info[k].p_r = pl.pr;
     }
-    {
-        SweepArgs a = sweep_args(pl, w, nplus, o, 0);
-        const int rows = pl.mr > pl.pr ? pl.mr : pl.pr;
-        SweepResult r;
-        rc = run_pointwise_sweeps(a, o.max_sweeps, choose_pair_geom(rows, o.waves_per_pair), s, r);
-        info.sweeps_fp64 += r.sweeps;
-        info.pairs_visited += r.visited;
-        info.pairs_transformed += r.transformed;
-        info.pairs_big += r.big;
-        if (rc < 0) return rc;
-        status = worst(status, rc);
-    }
-    rc = postprocess(pl.mr, nplus, pl.pr, n, w.Fw, pl.ldf, w.Gw, pl.ldg, w.Zw, pl.ldz,
-                     pl.reduce ? w.perm : nullptr, w.gnorm2, o.sort, w.lam_tmp, w.scale, w.rank,
-                     w.small + 2, lambda, X, ldx, s);
+    if (!c.ok()) return GHSVD_ENOMEM;
+    int rc = upload_batch(bc, s);
     if (rc) return rc;
-    GHSVD_HIP(hipMemcpyAsync(hsmall, w.small, sizeof(hsmall), hipMemcpyDeviceToHost, s));
+
+    // 1. input checks
+    hipLaunchKernelGGL(k_zero_small, dim3(bc.B), dim3(64), 0, s, bc.dev, bc.B);
+    for (const PencilDev &P : bc.host)
+        if ((rc = check_inputs(P.m, P.n, P.p, P.Fin, P.ldfin, P.Jin, P.Gin, P.ldgin, P.small,
+                               P.gnorm2, s)))
+            return rc;
+    std::vector<int> fl;
+    if ((rc = gather_small(bc, 0, fl, s))) return rc;
+    for (int k = 0; k < bc.B; ++k) {
+        if (fl[k] & 1) status[idx[k]] = GHSVD_EINVAL;
+        else if (fl[k] & 2) status[idx[k]] = GHSVD_ENONFINITE;
+    }
+    if ((rc = compact(bc, idx, status, s))) return rc;
+
+    // 2. one-time reduction (batched), signature split, sweep buffers
+    if (bc.B > 0) {
+        std::vector<int> rst, n2;
+        if ((rc = run_reduction(bc, rst, n2, s))) return rc;
+        for (int k = 0; k < bc.B; ++k) {
+            info[idx[k]].n2x2 = n2[k];
+            if (rst[k]) status[idx[k]] = rst[k];
+        }
+        if ((rc = compact(bc, idx, status, s))) return rc;
+    }
+    for (const PencilDev &P : bc.host) {
+        if (P.reduce) {
+            if ((rc = jsplit(P.n, P.n, P.Ft, P.ldft, P.Jw, P.Fw, P.ldf, P.rowmap, P.small + 1, s)))
+                return rc;
+            if ((rc = copy_cols(P.n, P.n, P.Gt, P.ldgt, P.Gw, P.ldg, nullptr, s))) return rc;
+        } else {
+            if ((rc = jsplit(P.m, P.n, P.Fin, P.ldfin, P.Jin, P.Fw, P.ldf, P.rowmap, P.small + 1, s)))
+                return rc;
+            if ((rc = copy_cols(P.p, P.n, P.Gin, P.ldgin, P.Gw, P.ldg, nullptr, s))) return rc;
+        }
+        if ((rc = set_identity(P.n, P.Zw, P.ldz, 0, s))) return rc;
+    }
+    if (bc.B > 0) {
+        std::vector<int> np;
+        if ((rc = gather_small(bc, 1, np, s))) return rc;
+        for (int k = 0; k < bc.B; ++k) info[idx[k]].n_plus = np[k];
+    }
+
+    // 3. sweep stages: (FP32 warm-up, blocked or pointwise, with its FP64
+    // hand-off) or FP64 blocked, then FP64 pointwise sweeps decide convergence.
+    auto account = [&](const std::vector<SweepResult> &r, int fp32, int blocked) {
+        for (int k = 0; k < bc.B; ++k) {
+            ghsvd_info &inf = info[idx[k]];
+            if (fp32) inf.sweeps_fp32 += r[k].sweeps;
+            else inf.sweeps_fp64 += r[k].sweeps;
+            if (blocked) inf.sweeps_blocked += r[k].sweeps;
+            inf.pairs_visited += r[k].visited;
+            inf.pairs_transformed += r[k].transformed;
+            inf.pairs_big += r[k].big;
+        }
+    };
+    std::vector<SweepResult> res;
+    if (bc.B > 0 && o.precision == GHSVD_MIXED) {
+        if ((rc = to_fp32(bc, s))) return rc;
+        const int blk = o.variant == GHSVD_BLOCKED;
+        if (blk) rc = run_blocked_stage(bc, 1, o.max_sweeps, o.crit_literal, s, res);
+        else rc = run_pointwise_stage(bc, 1, o.max_sweeps, o.crit_literal,
+                                      choose_pair_geom(bc.max_rows, o.waves_per_pair), s, res);
+        if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) return rc;
+        account(res, 1, blk);
+        if ((rc = fp32_handoff(bc, s))) return rc;
+    } else if (bc.B > 0 && o.variant == GHSVD_BLOCKED) {
+        rc = run_blocked_stage(bc, 0, o.max_sweeps, o.crit_literal, s, res);
+        if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) return rc;
+        account(res, 0, 1);
+        for (int k = 0; k < bc.B; ++k)
+            if (res[k].status < 0) status[idx[k]] = res[k].status;
+        if ((rc = compact(bc, idx, status, s))) return rc;
+    }
+    if (bc.B > 0) {
+        rc = run_pointwise_stage(bc, 0, o.max_sweeps, o.crit_literal,
+                                 choose_pair_geom(bc.max_rows, o.waves_per_pair), s, res);
+        if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) return rc;
+        account(res, 0, 0);
+        for (int k = 0; k < bc.B; ++k) status[idx[k]] = res[k].status;
+        if ((rc = compact(bc, idx, status, s))) return rc;
+    }
+
+    // 4. outputs
+    for (const PencilDev &P : bc.host)
+        if ((rc = postprocess(P, o.sort, s))) return rc;
+    if (bc.B > 0) {
+        std::vector<int> of;
+        if ((rc = gather_small(bc, 2, of, s))) return rc;
+        for (int k = 0; k < bc.B; ++k) {
+            if (of[k] & 2) status[idx[k]] = GHSVD_ENONFINITE;
+            else if (of[k] & 1) status[idx[k]] = GHSVD_ERANK;
+        }
+    }
+    int worst = GHSVD_OK;
+    for (int k = 0; k < B0; ++k) {
+        info[k].status = status[k];
+        worst = worst_of(worst, status[k]);
+    }
+    return worst;
+}
+
+// A one-pencil batch whose sweep buffers are the caller's (component entry
+// points).  Owns its scratch allocation.
+struct OwnedBatch {
+    BatchCtx bc;
+    void *buf = nullptr;
+    ~OwnedBatch() {
+        if (buf) (void)hipFree(buf);
+    }
+};
+
+static int make_inplace_batch(OwnedBatch &ob, int m, int n, int p, double *F, int ldf, double *G,
+                              int ldg, double *Z, int ldz, int blocked, int w, hipStream_t s) {
+    ghsvd_options o;
+    fill_options(nullptr, o);
+    o.reduce = 0;
+    o.variant = blocked ? GHSVD_BLOCKED : GHSVD_POINTWISE;
+    Plan pl = make_plan(m, n, p, o, w);
+    const size_t need = batch_bytes(1) + pencil_bytes(pl);
+    GHSVD_HIP(hipMalloc(&ob.buf, need));
+    Carver c{reinterpret_cast<char *>(ob.buf), 0, need};
+    carve_batch(c, ob.bc, 1);
+    ob.bc.B = 1;
+    ob.bc.host.resize(1);
+    PencilDev &d = ob.bc.host[0];
+    d = PencilDev{};
+    c.used = align_up(c.used, 256);
+    carve_pencil(c, pl, d);
+    d.Fw = reinterpret_cast<double2 *>(F);
+    d.ldf = ldf;
+    d.Gw = reinterpret_cast<double2 *>(G);
+    d.ldg = ldg;
+    d.Zw = reinterpret_cast<double2 *>(Z);
+    d.ldz = ldz;
+    return upload_batch(ob.bc, s);
+}
+
+__global__ void k_set_nplus(const PencilDev *PD, int nplus) { PD[0].small[1] = nplus; }
+
+static int copy_counters(const BatchCtx &bc, int nsweeps, long long *counters, int *sweeps_done,
+                         hipStream_t s) {
+    SweepState hs;
+    GHSVD_HIP(hipMemcpyAsync(&hs, bc.host[0].st, sizeof(SweepState), hipMemcpyDeviceToHost, s));
     GHSVD_HIP(hipStreamSynchronize(s));
-    if (hsmall[2] & 2) return GHSVD_ENONFINITE;
-    if (hsmall[2] & 1) return GHSVD_ERANK;
-    return status;
+    if (counters)
+        for (int k = 0; k < nsweeps; ++k)
+            for (int j = 0; j < 3; ++j)
+                counters[3 * k + j] = k < hs.sweeps ? (long long)hs.hist[3 * k + j] : 0;
+    if (sweeps_done) *sweeps_done = hs.sweeps;
+    return GHSVD_OK;
 }
 
 }  // namespace ghsvd
@@ -223,50 +384,131 @@ extern "C" const char *ghsvd_status_string(int status) {
 
 static bool valid_sizes(int m, int n, int p) { return n >= 1 && m >= n && p >= n; }
 
+static bool valid_options(const ghsvd_options &o) {
+    return (o.precision == GHSVD_FP64 || o.precision == GHSVD_MIXED) &&
+           (o.variant == GHSVD_POINTWISE || o.variant == GHSVD_BLOCKED) &&
+           (o.block_width == 0 || o.block_width == 8 || o.block_width == 16) &&
+           o.waves_per_pair >= 0 && o.waves_per_pair <= 16;
+}
+
 extern "C" size_t ghsvd_workspace_size(int m, int n, int p, const ghsvd_options *opt) {
     if (!valid_sizes(m, n, p)) return 0;
     ghsvd_options o;
     fill_options(opt, o);
-    return plan_bytes(make_plan(m, n, p, o));
+    std::vector<PencilIO> io(1);
+    io[0] = PencilIO{m, n, p, nullptr, m, nullptr, nullptr, p, nullptr, nullptr, n};
+    return solve_batch_bytes(io, o);
+}
+
+extern "C" size_t ghsvd_workspace_size_batched(int batch, const int *m, const int *n, const int *p,
+                                               const ghsvd_options *opt) {
+    if (batch < 1 || !m || !n || !p) return 0;
+    ghsvd_options o;
+    fill_options(opt, o);
+    std::vector<PencilIO> io(batch);
+    for (int k = 0; k < batch; ++k) {
+        if (!valid_sizes(m[k], n[k], p[k])) return 0;
+        io[k] = PencilIO{m[k], n[k], p[k], nullptr, m[k], nullptr, nullptr, p[k], nullptr, nullptr, n[k]};
+    }
+    return solve_batch_bytes(io, o);
+}
+
+static int run_with_workspace(const std::vector<PencilIO> &io, const ghsvd_options &o, void *work,
+                              size_t lwork, std::vector<ghsvd_info> &info, hipStream_t s) {
+    const size_t need = solve_batch_bytes(io, o);
+    void *own = nullptr;
+    if (!work) {
+        if (hipMalloc(&own, need) != hipSuccess) return GHSVD_EDEVICE;
+        work = own;
+        lwork = need;
+    }
+    int rc;
+    if (lwork < need) {
+        rc = GHSVD_ENOMEM;
+        info.assign(io.size(), ghsvd_info{});
+        for (auto &i : info) i.status = rc;
+    } else {
+        rc = solve_batch(io, o, work, lwork, info, s);
+        if (rc == GHSVD_EDEVICE || rc == GHSVD_ENOMEM)
+            for (auto &i : info)
+                if (i.status >= 0) i.status = rc;
+    }
+    if (own) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(own);
+    }
+    return rc;
 }
 
 extern "C" int ghsvd_solve(int m, int n, int p, const double *F, int ldf, const int8_t *J,
                            const double *G, int ldg, double *lambda, double *X, int ldx,
                            void *work, size_t lwork, const ghsvd_options *opt, ghsvd_info *info,
                            void *stream) {
-    ghsvd_info inf{};
-    auto finish = [&](int rc) {
-        inf.status = rc;
-        if (info) *info = inf;
-        return rc;
-    };
-    if (!valid_sizes(m, n, p) || ldf < m || ldg < p || ldx < n || !F || !J || !G || !lambda ||
-        !X)
-        return finish(GHSVD_EINVAL);
     ghsvd_options o;
     fill_options(opt, o);
-    if (o.precision != GHSVD_FP64 && o.precision != GHSVD_MIXED) return finish(GHSVD_EINVAL);
-    if (o.variant != GHSVD_POINTWISE && o.variant != GHSVD_BLOCKED) return finish(GHSVD_EINVAL);
-    const Plan pl = make_plan(m, n, p, o);
-    const size_t need = plan_bytes(pl);
-    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    void *own = nullptr;
-    if (!work) {
-        if (hipMalloc(&own, need) != hipSuccess) return finish(GHSVD_EDEVICE);
-        work = own;
-        lwork = need;
+    if (!valid_sizes(m, n, p) || ldf < m || ldg < p || ldx < n || !F || !J || !G || !lambda ||
+        !X || !valid_options(o)) {
+        if (info) {
+            *info = ghsvd_info{};
+            info->status = GHSVD_EINVAL;
+        }
+        return GHSVD_EINVAL;
     }
-    if (lwork < need) return finish(GHSVD_ENOMEM);
-    Carver c{reinterpret_cast<char *>(work), 0, lwork};
-    PencilWs w = carve(c, pl);
-    int rc = solve_one(pl, w, reinterpret_cast<const double2 *>(F), ldf, J,
-                       reinterpret_cast<const double2 *>(G), ldg, lambda,
-                       reinterpret_cast<double2 *>(X), ldx, o, inf, s);
-    if (own) {
-        (void)hipStreamSynchronize(s);
-        (void)hipFree(own);
+    std::vector<PencilIO> io(1);
+    io[0] = PencilIO{m, n, p, reinterpret_cast<const double2 *>(F), ldf, J,
+                     reinterpret_cast<const double2 *>(G), ldg, lambda,
+                     reinterpret_cast<double2 *>(X), ldx};
+    std::vector<ghsvd_info> inf;
+    const int rc = run_with_workspace(io, o, work, lwork, inf, reinterpret_cast<hipStream_t>(stream));
+    if (info) {
+        *info = inf.empty() ? ghsvd_info{} : inf[0];
+        if (inf.empty()) info->status = rc;
     }
-    return finish(rc);
+    return rc;
+}
+
+extern "C" int ghsvd_solve_batched(int batch, const int *m, const int *n, const int *p,
+                                   const double *const *F, const int *ldf, const int8_t *const *J,
+                                   const double *const *G, const int *ldg, double *const *lambda,
+                                   double *const *X, const int *ldx, void *work, size_t lwork,
+                                   const ghsvd_options *opt, ghsvd_info *info, void *stream) {
+    if (batch < 1 || !m || !n || !p || !F || !ldf || !J || !G || !ldg || !lambda || !X || !ldx)
+        return GHSVD_EINVAL;
+    ghsvd_options o;
+    fill_options(opt, o);
+    if (!valid_options(o)) return GHSVD_EINVAL;
+    // The workspace is sized by ghsvd_workspace_size_batched over all pencils;
+    // a pencil with invalid arguments gets GHSVD_EINVAL and no work.
+    std::vector<PencilIO> io;
+    std::vector<int> map;
+    std::vector<int> st(batch, GHSVD_OK);
+    for (int k = 0; k < batch; ++k) {
+        if (!valid_sizes(m[k], n[k], p[k]) || ldf[k] < m[k] || ldg[k] < p[k] || ldx[k] < n[k] ||
+            !F[k] || !J[k] || !G[k] || !lambda[k] || !X[k]) {
+            st[k] = GHSVD_EINVAL;
+            continue;
+        }
+        io.push_back(PencilIO{m[k], n[k], p[k], reinterpret_cast<const double2 *>(F[k]), ldf[k], J[k],
+                              reinterpret_cast<const double2 *>(G[k]), ldg[k], lambda[k],
+                              reinterpret_cast<double2 *>(X[k]), ldx[k]});
+        map.push_back(k);
+    }
+    std::vector<ghsvd_info> inf;
+    int rc = GHSVD_OK;
+    if (!io.empty())
+        rc = run_with_workspace(io, o, work, lwork, inf, reinterpret_cast<hipStream_t>(stream));
+    int worst = (rc == GHSVD_EDEVICE || rc == GHSVD_ENOMEM) ? rc : GHSVD_OK;
+    if (info)
+        for (int k = 0; k < batch; ++k) {
+            info[k] = ghsvd_info{};
+            info[k].status = st[k];
+        }
+    for (size_t q = 0; q < map.size(); ++q) {
+        if (q < inf.size()) st[map[q]] = inf[q].status;
+        if (info && q < inf.size()) info[map[q]] = inf[q];
+    }
+    for (int k = 0; k < batch; ++k) worst = worst_of(worst, st[k]);
+    return worst;
 }
 
 extern "C" int ghsvd_reduce(int m, int n, int p, const double *F, int ldf, const int8_t *J,
@@ -278,39 +520,88 @@ extern "C" int ghsvd_reduce(int m, int n, int p, const double *F, int ldf, const
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     ghsvd_options o;
     fill_options(nullptr, o);
-    o.reduce = 1;
-    Plan pl = make_plan(m, n, p, o);
+    Plan pl = make_plan(m, n, p, o, 8);
     pl.reduce = 1;
-    const size_t need = plan_bytes(pl);
-    void *buf = nullptr;
-    GHSVD_HIP(hipMalloc(&buf, need));
-    Carver c{reinterpret_cast<char *>(buf), 0, need};
-    PencilWs w = carve(c, pl);
-    int rc = GHSVD_OK;
-    hipLaunchKernelGGL(k_zero_small, dim3(1), dim3(64), 0, s, w.small, w.gnorm2);
-    rc = check_inputs(m, n, p, reinterpret_cast<const double2 *>(F), ldf, J,
-                      reinterpret_cast<const double2 *>(G), ldg, w.small, w.gnorm2, s);
-    int hsmall[8] = {0};
-    if (!rc && hipMemcpyAsync(hsmall, w.small, sizeof(hsmall), hipMemcpyDeviceToHost, s) != hipSuccess)
-        rc = GHSVD_EDEVICE;
-    if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = GHSVD_EDEVICE;
-    if (!rc && (hsmall[0] & 1)) rc = GHSVD_EINVAL;
-    if (!rc && (hsmall[0] & 2)) rc = GHSVD_ENONFINITE;
-    int n2 = 0;
-    if (!rc) rc = copy_cols(m, n, reinterpret_cast<const double2 *>(F), ldf, w.Ft, pl.ldft, nullptr, s);
-    if (!rc && hipMemcpyAsync(w.Jw, J, (size_t)m, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        rc = GHSVD_EDEVICE;
-    if (!rc) rc = run_jqr(m, n, w.Ft, pl.ldft, w.Jw, w.perm, w.jq, s, &n2);
-    if (!rc) rc = copy_cols(p, n, reinterpret_cast<const double2 *>(G), ldg, w.Gt, pl.ldgt, w.perm, s);
-    if (!rc) rc = run_qr(p, n, w.Gt, pl.ldgt, w.qv, w.qcoef, s);
-    if (!rc) rc = copy_cols(n, n, w.Ft, pl.ldft, reinterpret_cast<double2 *>(Fsq), ldfs, nullptr, s);
-    if (!rc) rc = copy_cols(n, n, w.Gt, pl.ldgt, reinterpret_cast<double2 *>(Gsq), ldgs, nullptr, s);
-    if (!rc && hipMemcpyAsync(Jsq, w.Jw, (size_t)n, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        rc = GHSVD_EDEVICE;
-    if (!rc && hipMemcpyAsync(perm, w.perm, sizeof(int) * n, hipMemcpyDeviceToDevice, s) != hipSuccess)
-        rc = GHSVD_EDEVICE;
-    if (hipStreamSynchronize(s) != hipSuccess && !rc) rc = GHSVD_EDEVICE;
-    (void)hipFree(buf);
-    if (n2x2) *n2x2 = n2;
-    return rc;
+    pl.mr = n;
+    pl.pr = n;
+    pl.ldf = pad_ld(n);
+    pl.ldg = pad_ld(n);
+    OwnedBatch ob;
+    const size_t need = batch_bytes(1) + pencil_bytes(pl);
+    GHSVD_HIP(hipMalloc(&ob.buf, need));
+    Carver c{reinterpret_cast<char *>(ob.buf), 0, need};
+    carve_batch(c, ob.bc, 1);
+    ob.bc.B = 1;
+    ob.bc.host.resize(1);
+    PencilDev &d = ob.bc.host[0];
+    d = PencilDev{};
+    c.used = align_up(c.used, 256);
+    carve_pencil(c, pl, d);
+    d.Fin = reinterpret_cast<const double2 *>(F);
+    d.ldfin = ldf;
+    d.Jin = J;
+    d.Gin = reinterpret_cast<const double2 *>(G);
+    d.ldgin = ldg;
+    int rc = upload_batch(ob.bc, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_zero_small, dim3(1), dim3(64), 0, s, ob.bc.dev, 1);
+    if ((rc = check_inputs(m, n, p, d.Fin, ldf, J, d.Gin, ldg, d.small, d.gnorm2, s))) return rc;
+    std::vector<int> fl;
+    if ((rc = gather_small(ob.bc, 0, fl, s))) return rc;
+    if (fl[0] & 1) return GHSVD_EINVAL;
+    if (fl[0] & 2) return GHSVD_ENONFINITE;
+    std::vector<int> rst, n2;
+    if ((rc = run_reduction(ob.bc, rst, n2, s))) return rc;
+    if (n2x2) *n2x2 = n2[0];
+    if (rst[0]) return rst[0];
+    if ((rc = copy_cols(n, n, d.Ft, d.ldft, reinterpret_cast<double2 *>(Fsq), ldfs, nullptr, s)))
+        return rc;
+    if ((rc = copy_cols(n, n, d.Gt, d.ldgt, reinterpret_cast<double2 *>(Gsq), ldgs, nullptr, s)))
+        return rc;
+    GHSVD_HIP(hipMemcpyAsync(Jsq, d.Jw, (size_t)n, hipMemcpyDeviceToDevice, s));
+    GHSVD_HIP(hipMemcpyAsync(perm, d.perm, sizeof(int) * n, hipMemcpyDeviceToDevice, s));
+    GHSVD_HIP(hipStreamSynchronize(s));
+    return GHSVD_OK;
+}
+
+extern "C" int ghsvd_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, double *G,
+                            int ldg, double *Z, int ldz, int nsweeps, int waves_per_pair,
+                            int crit_literal, long long *counters, int *sweeps_done,
+                            void *stream) {
+    if (n < 1 || m < 1 || p < 1 || ldf < m || ldg < p || ldz < n || nsweeps < 1 ||
+        nsweeps > kMaxHist || n_plus < 0 || n_plus > m || !F || !G || !Z || waves_per_pair < 0 ||
+        waves_per_pair > 16)
+        return GHSVD_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    OwnedBatch ob;
+    int rc = make_inplace_batch(ob, m, n, p, F, ldf, G, ldg, Z, ldz, 0, 8, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_set_nplus, dim3(1), dim3(1), 0, s, ob.bc.dev, n_plus);
+    std::vector<SweepResult> res;
+    rc = run_pointwise_stage(ob.bc, 0, nsweeps, crit_literal,
+                             choose_pair_geom(m > p ? m : p, waves_per_pair), s, res);
+    if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) return rc;
+    if ((rc = copy_counters(ob.bc, nsweeps, counters, sweeps_done, s))) return rc;
+    return res[0].status;
+}
+
+extern "C" int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, double *G,
+                                  int ldg, double *Z, int ldz, int block_width, int nsweeps,
+                                  int crit_literal, long long *counters, int *sweeps_done,
+                                  void *stream) {
+    if (n < 4 || m < 1 || p < 1 || ldf < m || ldg < p || ldz < n || nsweeps < 1 ||
+        nsweeps > kMaxHist || n_plus < 0 || n_plus > m || !F || !G || !Z)
+        return GHSVD_EINVAL;
+    if (block_width != 0 && block_width != 8 && block_width != 16) return GHSVD_EINVAL;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    OwnedBatch ob;
+    int rc = make_inplace_batch(ob, m, n, p, F, ldf, G, ldg, Z, ldz, 1,
+                                pick_block_width(n, block_width), s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_set_nplus, dim3(1), dim3(1), 0, s, ob.bc.dev, n_plus);
+    std::vector<SweepResult> res;
+    rc = run_blocked_stage(ob.bc, 0, nsweeps, crit_literal, s, res);
+    if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) return rc;
+    if ((rc = copy_counters(ob.bc, nsweeps, counters, sweeps_done, s))) return rc;
+    return res[0].status;
 }

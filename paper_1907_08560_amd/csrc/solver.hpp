@@ -1,60 +1,63 @@
-// solver.hpp -- per-pencil plan and workspace of the solver.
+// solver.hpp -- per-pencil plan, workspace carving and the batch pipeline.
 #pragma once
 
-#include "hz_common.hpp"
-#include "reduce.hpp"
+#include <vector>
+
+#include "batch.hpp"
 #include "sweep.hpp"
 
 namespace ghsvd {
 
+// Host-side plan of one pencil.
 struct Plan {
-    int m, n, p;    // input sizes
-    int reduce;     // run the one-time reduction
-    int mr, pr;     // rows of F and G as swept
-    long ldft, ldgt;  // tall scratch copies
+    int m, n, p;       // input sizes
+    int reduce;        // run the one-time reduction
+    int mr, pr;        // rows of F and G as swept
+    long ldft, ldgt;   // tall scratch copies
     long ldf, ldg, ldz;
-    int N;          // n rounded up to even
-    int mixed;      // FP32 warm-up stage
-    int blocked;    // Level-2 blocked FP64 stage
+    int N;             // n rounded up to even
+    int mixed;         // FP32 warm-up stage
+    int blocked;       // Level-2 blocked stage
+    int w;             // block width (blocked or mixed)
 };
 
-struct BlockedWs;
+Plan make_plan(int m, int n, int p, const ghsvd_options &o, int block_width);
+// Carves one pencil's workspace and fills the sizes and scratch pointers of d
+// (the caller's buffers are set separately).
+void carve_pencil(Carver &c, const Plan &pl, PencilDev &d);
+size_t pencil_bytes(const Plan &pl);
+// Device bytes shared by a batch of B pencils (descriptors, prefix sums, flags).
+size_t batch_bytes(int B);
+int pick_block_width(int max_n, int requested);
+void fill_options(const ghsvd_options *opt, ghsvd_options &o);
 
-struct PencilWs {
-    double2 *Ft, *Gt;
-    JqrBufs jq;
-    double2 *qv;
-    double *qcoef;
-    int8_t *Jw;
-    int *rowmap, *perm;
-    double2 *Fw, *Gw, *Zw;
-    SweepState *st;
-    unsigned long long *slot_cnt;
-    double *lam_tmp, *scale;
-    int *rank;
-    int *small;  // [0] input flags, [1] nplus, [2] output flags
-    double *gnorm2;
-    float2 *F32, *G32, *Z32;
-    // blocked variant scratch
-    void *blk;
-    size_t blk_bytes;
+// One pencil's inputs and outputs (device pointers).
+struct PencilIO {
+    int m, n, p;
+    const double2 *F;
+    long ldf;
+    const int8_t *J;
+    const double2 *G;
+    long ldg;
+    double *lambda;
+    double2 *X;
+    long ldx;
 };
 
-Plan make_plan(int m, int n, int p, const ghsvd_options &o);
-PencilWs carve(Carver &c, const Plan &pl);
-size_t plan_bytes(const Plan &pl);
-SweepArgs sweep_args(const Plan &pl, const PencilWs &w, int nplus, const ghsvd_options &o, int fp32);
-int prepare_pencil(const Plan &pl, const PencilWs &w, const double2 *F, long ldf, const int8_t *J,
-                   const double2 *G, long ldg, hipStream_t s, int *n2x2);
-int solve_one(const Plan &pl, const PencilWs &w, const double2 *F, long ldf, const int8_t *J,
-              const double2 *G, long ldg, double *lambda, double2 *X, long ldx,
-              const ghsvd_options &o, ghsvd_info &info, hipStream_t s);
+// The whole path for a batch: input checks, reduction, sweep stages, outputs.
+// status[k] and info[k] per pencil; returns the worst status.
+int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *work, size_t lwork,
+                std::vector<ghsvd_info> &info, hipStream_t s);
+size_t solve_batch_bytes(const std::vector<PencilIO> &io, const ghsvd_options &o);
 
-// Blocked variant and FP32 warm-up (blocked.hip).
-void carve_blocked(Carver &c, const Plan &pl, PencilWs &w);
-int run_fp32_stage(const Plan &pl, const PencilWs &w, int nplus, const ghsvd_options &o,
-                   ghsvd_info &info, hipStream_t s);
-int run_blocked_fp64(const Plan &pl, const PencilWs &w, int nplus, const ghsvd_options &o,
-                     ghsvd_info &info, hipStream_t s);
+// Blocked and FP32 stages (blocked.hip).
+void set_block_geometry(PencilDev &d, int w);
+size_t blocked_bytes(int mr, int n, int pr, int w, int mixed);
+void carve_blocked(Carver &c, int mr, int n, int pr, int w, int mixed, PencilDev &d);
+int to_fp32(const BatchCtx &c, hipStream_t s);
+int fp32_handoff(const BatchCtx &c, hipStream_t s);
+
+// Outputs (post.hip): lambda, X for one pencil; flags in small[2].
+int postprocess(const PencilDev &P, int sort, hipStream_t s);
 
 }  // namespace ghsvd
