@@ -5,7 +5,7 @@
 // memory, plus prefix sums of the workgroups each pencil needs in a given
 // launch; a workgroup finds its pencil by binary search over the prefix sums.
 // Per-pencil iteration state lives in device memory (SweepState, JqrState),
-// so the launches of a step take the same arguments every time (and can be
+// so a round of launches takes the same arguments every time (and can be
 // captured into a graph and replayed).
 #pragma once
 
@@ -27,8 +27,7 @@ struct SweepState {
     int converged;   // 1: the last sweep had no big transformation
     int max_sweeps;  // cap of the stage
     int noise_floor; // 1: also stop once a sweep's big count is at most visited / 1024
-    int lstep;       // current step within the sweep
-    unsigned fin;    // workgroups of the current step that have finished
+    int pad[2];
     unsigned long long hist[3 * kMaxHist];  // (visited, transformed, big) per sweep
 };
 

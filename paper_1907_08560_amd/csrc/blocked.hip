@@ -71,7 +71,7 @@ __device__ __forceinline__ int blk_col(int w, int a, int b, int ca, int cc) {
 }
 
 template <typename T, int PB>
-__global__ __launch_bounds__(256) void k_blk_gram(const PencilDev *PD, const int *pre, int B) {
+__global__ __launch_bounds__(256) void k_blk_gram(const PencilDev *PD, const int *pre, int B, int step) {
     using C2 = typename Mfma<T>::c2;
     using ACC = typename Mfma<T>::acc;
     constexpr bool F32 = sizeof(T) == 4;
@@ -81,13 +81,13 @@ __global__ __launch_bounds__(256) void k_blk_gram(const PencilDev *PD, const int
     __shared__ C2 tile[kGramSub][PB + 1];
     __shared__ double2 red[KSPLIT > 1 ? 4 * 256 : 1];
     const int pk = find_pencil(pre, B, blockIdx.x);
-    const PencilDev &A = PD[pk];
-    if (A.st->done) return;
+    const PencilDev A = PD[pk];
+    if (step >= A.nb - 1 || A.st->done) return;
     const int local = blockIdx.x - pre[pk];
     const int KC = A.kf + A.kg;
     const int bpi = local / KC, kc = local % KC;
     int a, b;
-    rr_pair(A.nb, A.st->lstep, bpi, a, b);
+    rr_pair(A.nb, step, bpi, a, b);
     const int ca = blk_width(A.n, A.w, a), cb = blk_width(A.n, A.w, b);
     const int c = ca + cb;
     if (c < 2) return;
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(256) void k_blk_gram(const PencilDev *PD, const int
 // or padding (>= c) carry the identity; padding entries are zero and stay so.
 template <int PB, int F32>
 __global__ __launch_bounds__(256) void k_blk_inner(const PencilDev *PD, const int *pre, int B,
-                                                   int crit) {
+                                                   int crit, int step) {
     constexpr int NP = PB / 2;   // pivot pair slots per inner step
     constexpr int NB = NP * NP;  // 2x2 blocks
     __shared__ double2 H[PB][PB + 1];
@@ -173,12 +173,12 @@ __global__ __launch_bounds__(256) void k_blk_inner(const PencilDev *PD, const in
     __shared__ int act_s[NP];
     __shared__ double red[3 * 4];
     const int pk = find_pencil(pre, B, blockIdx.x);
-    const PencilDev &A = PD[pk];
-    if (A.st->done) return;
+    const PencilDev A = PD[pk];
+    if (step >= A.nb - 1 || A.st->done) return;
     const int bpi = blockIdx.x - pre[pk];
     const int tid = threadIdx.x;
     int a, b;
-    rr_pair(A.nb, A.st->lstep, bpi, a, b);
+    rr_pair(A.nb, step, bpi, a, b);
     const int ca = blk_width(A.n, A.w, a), cb = blk_width(A.n, A.w, b);
     const int c = ca + cb;
     if (c < 2) {
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(256) void k_blk_inner(const PencilDev *PD, const in
 }
 
 template <typename T, int PB>
-__device__ __forceinline__ void update_tile(const PencilDev &A, int bpi, int t) {
+__device__ __forceinline__ void update_tile(const PencilDev &A, int step, int bpi, int t) {
     using C2 = typename Mfma<T>::c2;
     using ACC = typename Mfma<T>::acc;
     constexpr bool F32 = sizeof(T) == 4;
@@ -314,7 +314,7 @@ __device__ __forceinline__ void update_tile(const PencilDev &A, int bpi, int t) 
     __shared__ C2 Zh[PB][PB + 1];
     if (A.ntr[bpi] == 0) return;
     int a, b;
-    rr_pair(A.nb, A.st->lstep, bpi, a, b);
+    rr_pair(A.nb, step, bpi, a, b);
     const int ca = blk_width(A.n, A.w, a), cb = blk_width(A.n, A.w, b);
     const int c = ca + cb;
     if (c < 2) return;
@@ -396,18 +396,16 @@ __device__ __forceinline__ void update_tile(const PencilDev &A, int bpi, int t) 
     }
 }
 
-// F_C <- F_C Z^, G_C <- G_C Z^, Z_C <- Z_C Z^ for one 64-row tile; the last
-// workgroup of a pencil's step advances the pencil's step counter.
+// F_C <- F_C Z^, G_C <- G_C Z^, Z_C <- Z_C Z^ for one 64-row tile.
 template <typename T, int PB>
-__global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const int *pre, int B) {
+__global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const int *pre, int B,
+                                                    int step) {
     const int pk = find_pencil(pre, B, blockIdx.x);
-    const PencilDev &A = PD[pk];
-    SweepState *st = A.st;
-    if (st->done) return;
+    const PencilDev A = PD[pk];
+    if (step >= A.nb - 1 || A.st->done) return;
     const int local = blockIdx.x - pre[pk];
     const int TT = A.tf + A.tg + A.tz;
-    update_tile<T, PB>(A, local / TT, local % TT);
-    if (last_workgroup(st, (unsigned)(A.nbp * TT))) step_done(st, A.bcnt, A.nbp, A.nb - 1);
+    update_tile<T, PB>(A, step, local / TT, local % TT);
 }
 
 // ---------------------------------------------------------------------------
@@ -540,8 +538,8 @@ size_t blocked_bytes(int mr, int n, int pr, int w, int mixed) {
     return c.used + 256;
 }
 
-using BlkFn = void (*)(const PencilDev *, const int *, int);
-using BlkInnerFn = void (*)(const PencilDev *, const int *, int, int);
+using BlkFn = void (*)(const PencilDev *, const int *, int, int);
+using BlkInnerFn = void (*)(const PencilDev *, const int *, int, int, int);
 
 struct BlockedArg {
     BlkFn gram, upd;
@@ -549,14 +547,14 @@ struct BlockedArg {
     int crit;
 };
 
-static int blocked_step(const BatchCtx &c, const void *arg, hipStream_t s) {
+static int blocked_step(const BatchCtx &c, const void *arg, int step, hipStream_t s) {
     const BlockedArg *a = static_cast<const BlockedArg *>(arg);
     hipLaunchKernelGGL(a->gram, dim3(c.total(BatchCtx::kGram)), dim3(256), 0, s, c.dev,
-                       c.pre_of(BatchCtx::kGram), c.B);
+                       c.pre_of(BatchCtx::kGram), c.B, step);
     hipLaunchKernelGGL(a->inner, dim3(c.total(BatchCtx::kBp)), dim3(256), 0, s, c.dev,
-                       c.pre_of(BatchCtx::kBp), c.B, a->crit);
+                       c.pre_of(BatchCtx::kBp), c.B, a->crit, step);
     hipLaunchKernelGGL(a->upd, dim3(c.total(BatchCtx::kUpd)), dim3(256), 0, s, c.dev,
-                       c.pre_of(BatchCtx::kUpd), c.B);
+                       c.pre_of(BatchCtx::kUpd), c.B, step);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }

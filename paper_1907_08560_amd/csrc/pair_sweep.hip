@@ -162,23 +162,22 @@ __device__ __forceinline__ void pair_body(const PencilDev &P, int p, int q, int 
 }
 
 template <typename T, int NT, int R>
-__global__ __launch_bounds__(NT) void k_pair(const PencilDev *PD, const int *pre, int B, int crit) {
+__global__ __launch_bounds__(NT) void k_pair(const PencilDev *PD, const int *pre, int B, int crit,
+                                             int step) {
     const int k = find_pencil(pre, B, blockIdx.x);
-    const PencilDev &P = PD[k];
-    SweepState *st = P.st;
-    if (st->done) return;
+    const PencilDev P = PD[k];
+    if (step >= P.N - 1 || P.st->done) return;  // surplus step of a smaller pencil, or finished
     const int slot = blockIdx.x - pre[k];
     int p, q;
-    rr_pair(P.N, st->lstep, slot, p, q);
+    rr_pair(P.N, step, slot, p, q);
     if (q < P.n) pair_body<T, NT, R>(P, p, q, slot, crit);  // else: bye slot of an odd order
-    if (last_workgroup(st, (unsigned)P.nslots)) step_done(st, P.slot_cnt, P.nslots, P.N - 1);
 }
 
 __global__ void k_reset_states(const PencilDev *PD, int B, int max_sweeps, int noise_floor,
                                int blocked) {
     const int k = blockIdx.x;
     if (k >= B) return;
-    const PencilDev &P = PD[k];
+    const PencilDev P = PD[k];
     SweepState *st = P.st;
     unsigned long long *cnt = blocked ? P.bcnt : P.slot_cnt;
     const int nc = blocked ? P.nbp : P.nslots;
@@ -191,8 +190,49 @@ __global__ void k_reset_states(const PencilDev *PD, int B, int max_sweeps, int n
         st->err = 0;
         st->max_sweeps = max_sweeps;
         st->noise_floor = noise_floor;
-        st->lstep = 0;
-        st->fin = 0u;
+    }
+}
+
+// End of a round, one workgroup per pencil still running: sums the per-slot
+// counters of the sweep just finished in a fixed order, clears them, records
+// them, and applies the stopping rules (Section 6.1.7: no big transformation
+// in the sweep; Algorithm 2: the sweep cap; the FP32 stage also stops at its
+// noise floor, a sweep with at most one big transformation per 1024 visits).
+__global__ __launch_bounds__(256) void k_end_round(const PencilDev *PD, int B, int blocked) {
+    __shared__ double red[3 * 256 / kWave];
+    const PencilDev P = PD[blockIdx.x];
+    SweepState *st = P.st;
+    if (st->done) return;
+    unsigned long long *cnt = blocked ? P.bcnt : P.slot_cnt;
+    const int nc = blocked ? P.nbp : P.nslots;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < nc; k += blockDim.x) {
+        v[0] += (double)cnt[3 * k + 0];
+        v[1] += (double)cnt[3 * k + 1];
+        v[2] += (double)cnt[3 * k + 2];
+        cnt[3 * k + 0] = 0ull;
+        cnt[3 * k + 1] = 0ull;
+        cnt[3 * k + 2] = 0ull;
+    }
+    block_sum<3>(v, red);
+    if (threadIdx.x == 0) {
+        const int sw = st->sweeps;
+        if (sw < kMaxHist) {
+            st->hist[3 * sw + 0] = (unsigned long long)v[0];
+            st->hist[3 * sw + 1] = (unsigned long long)v[1];
+            st->hist[3 * sw + 2] = (unsigned long long)v[2];
+        }
+        st->sweeps = sw + 1;
+        if (st->err != 0) {
+            st->done = 1;
+        } else if (v[2] == 0.0) {
+            st->done = 1;
+            st->converged = 1;
+        } else if (st->noise_floor && v[2] * 1024.0 <= v[0]) {
+            st->done = 1;
+        } else if (sw + 1 >= st->max_sweeps) {
+            st->done = 1;
+        }
     }
 }
 
@@ -203,7 +243,7 @@ __global__ void k_gather_done(const PencilDev *PD, int B, int *done) {
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
-using PairFn = void (*)(const PencilDev *, const int *, int, int);
+using PairFn = void (*)(const PencilDev *, const int *, int, int, int);
 
 template <typename T>
 static PairFn pick(int nt, int r) {
@@ -317,56 +357,80 @@ static bool prof_active() {
     return prof::every > 0;
 }
 
-// Graph replay of a round of steps; falls back to direct launches when the
-// capture cannot be made (or while kernel timing is on).
+// A round captured into a graph on an internal stream (graphs cannot be
+// captured on the legacy null stream the caller may pass).
 struct RoundGraph {
+    hipStream_t gs = nullptr;
+    hipEvent_t ev = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraph_t graph = nullptr;
     ~RoundGraph() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (gs) (void)hipStreamDestroy(gs);
+        if (ev) (void)hipEventDestroy(ev);
     }
 };
+
+static int enqueue_round(const BatchCtx &c, StepFn one_step, const void *arg, int steps,
+                         int blocked, hipStream_t s) {
+    for (int i = 0; i < steps; ++i) {
+        const int rc = one_step(c, arg, i, s);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_end_round, dim3(c.B), dim3(256), 0, s, c.dev, c.B, blocked);
+    GHSVD_HIP(hipGetLastError());
+    return GHSVD_OK;
+}
+
+// Captures one round on rg.gs; false (and no graph) when any part fails.
+static bool capture_round(const BatchCtx &c, StepFn one_step, const void *arg, int steps,
+                          int blocked, RoundGraph &rg) {
+    if (hipStreamCreateWithFlags(&rg.gs, hipStreamNonBlocking) != hipSuccess) return false;
+    if (hipEventCreateWithFlags(&rg.ev, hipEventDisableTiming) != hipSuccess) return false;
+    if (hipStreamBeginCapture(rg.gs, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+    const int rc = enqueue_round(c, one_step, arg, steps, blocked, rg.gs);
+    const bool ended = hipStreamEndCapture(rg.gs, &rg.graph) == hipSuccess;
+    if (rc != GHSVD_OK || !ended) return false;
+    return hipGraphInstantiate(&rg.exec, rg.graph, nullptr, nullptr, 0) == hipSuccess;
+}
 
 int drive_stage(const BatchCtx &c, int max_sweeps, int noise_floor, int blocked, StepFn one_step,
                 const void *arg, int steps_per_round, const char *name, hipStream_t s,
                 std::vector<SweepResult> &res) {
     const int B = c.B;
     res.assign(B, SweepResult{GHSVD_OK, 0, 0, 0, 0, 0});
-    hipLaunchKernelGGL(k_reset_states, dim3(B), dim3(256), 0, s, c.dev, B, max_sweeps, noise_floor,
-                       blocked);
+    RoundGraph rg;
+    if (!prof_active() && !std::getenv("GHSVD_NO_GRAPH") &&
+        !capture_round(c, one_step, arg, steps_per_round, blocked, rg)) {
+        (void)hipGetLastError();
+        if (rg.exec) (void)hipGraphExecDestroy(rg.exec);
+        if (rg.graph) (void)hipGraphDestroy(rg.graph);
+        rg.exec = nullptr;
+        rg.graph = nullptr;
+    }
+    // The stage runs on the graph's stream after the caller's prior work.
+    hipStream_t ss = s;
+    if (rg.exec) {
+        GHSVD_HIP(hipEventRecord(rg.ev, s));
+        GHSVD_HIP(hipStreamWaitEvent(rg.gs, rg.ev, 0));
+        ss = rg.gs;
+    }
+    hipLaunchKernelGGL(k_reset_states, dim3(B), dim3(256), 0, ss, c.dev, B, max_sweeps,
+                       noise_floor, blocked);
     GHSVD_HIP(hipGetLastError());
     std::vector<int> done(B, 0);
-    RoundGraph rg;
-    const bool use_graph = !prof_active() && !std::getenv("GHSVD_NO_GRAPH") && s != nullptr;
-    if (use_graph) {
-        bool ok = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) == hipSuccess;
-        int rc = GHSVD_OK;
-        if (ok)
-            for (int i = 0; i < steps_per_round && rc == GHSVD_OK; ++i) rc = one_step(c, arg, s);
-        if (ok) ok = hipStreamEndCapture(s, &rg.graph) == hipSuccess && rc == GHSVD_OK;
-        if (ok) ok = hipGraphInstantiate(&rg.exec, rg.graph, nullptr, nullptr, 0) == hipSuccess;
-        if (!ok) {
-            (void)hipGetLastError();
-            if (rg.exec) (void)hipGraphExecDestroy(rg.exec);
-            if (rg.graph) (void)hipGraphDestroy(rg.graph);
-            rg.exec = nullptr;
-            rg.graph = nullptr;
-        }
-    }
     for (int round = 0; round < max_sweeps; ++round) {
         if (rg.exec) {
-            GHSVD_HIP(hipGraphLaunch(rg.exec, s));
+            GHSVD_HIP(hipGraphLaunch(rg.exec, ss));
         } else {
-            for (int i = 0; i < steps_per_round; ++i) {
-                const int rc = one_step(c, arg, s);
-                if (rc) return rc;
-            }
+            const int rc = enqueue_round(c, one_step, arg, steps_per_round, blocked, ss);
+            if (rc) return rc;
         }
-        hipLaunchKernelGGL(k_gather_done, dim3(1), dim3(256), 0, s, c.dev, B, c.done_dev);
+        hipLaunchKernelGGL(k_gather_done, dim3(1), dim3(256), 0, ss, c.dev, B, c.done_dev);
         GHSVD_HIP(hipGetLastError());
-        GHSVD_HIP(hipMemcpyAsync(done.data(), c.done_dev, sizeof(int) * B, hipMemcpyDeviceToHost, s));
-        GHSVD_HIP(hipStreamSynchronize(s));
+        GHSVD_HIP(hipMemcpyAsync(done.data(), c.done_dev, sizeof(int) * B, hipMemcpyDeviceToHost, ss));
+        GHSVD_HIP(hipStreamSynchronize(ss));
         bool all = true;
         for (int k = 0; k < B; ++k) all = all && done[k];
         if (all) break;
@@ -374,8 +438,8 @@ int drive_stage(const BatchCtx &c, int max_sweeps, int noise_floor, int blocked,
     int worst = GHSVD_OK;
     for (int k = 0; k < B; ++k) {
         SweepState hs;
-        GHSVD_HIP(hipMemcpyAsync(&hs, c.host[k].st, sizeof(SweepState), hipMemcpyDeviceToHost, s));
-        GHSVD_HIP(hipStreamSynchronize(s));
+        GHSVD_HIP(hipMemcpyAsync(&hs, c.host[k].st, sizeof(SweepState), hipMemcpyDeviceToHost, ss));
+        GHSVD_HIP(hipStreamSynchronize(ss));
         trace_stage(name, k, hs);
         SweepResult &r = res[k];
         r.sweeps = hs.sweeps;
@@ -397,12 +461,12 @@ struct PointwiseArg {
     int crit;
 };
 
-static int pointwise_step(const BatchCtx &c, const void *arg, hipStream_t s) {
+static int pointwise_step(const BatchCtx &c, const void *arg, int step, hipStream_t s) {
     const PointwiseArg *a = static_cast<const PointwiseArg *>(arg);
     hipEvent_t e0, e1;
     prof_before(s, e0, e1);
     hipLaunchKernelGGL(a->fn, dim3(c.total(BatchCtx::kSlots)), dim3(a->g.nt), 0, s, c.dev,
-                       c.pre_of(BatchCtx::kSlots), c.B, a->crit);
+                       c.pre_of(BatchCtx::kSlots), c.B, a->crit, step);
     prof_after(s, e0, e1);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;

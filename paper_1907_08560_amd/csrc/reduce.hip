@@ -66,7 +66,7 @@ __device__ __forceinline__ bool jqr_active(const JqrState *st, int n) {
 // per pencil.  Each kernel reads the pencil's fields below.
 #define JQR_PENCIL_COL()                                          \
     const int pk = find_pencil(pre, B, blockIdx.x);                \
-    const PencilDev &P = PD[pk];                                  \
+    const PencilDev P = PD[pk];                                  \
     if (!P.reduce) return;                                        \
     double2 *A = P.Ft;                                            \
     const long lda = P.ldft;                                      \
@@ -77,7 +77,7 @@ __device__ __forceinline__ bool jqr_active(const JqrState *st, int n) {
     (void)J;                                                      \
     (void)j_local
 #define JQR_PENCIL_ONE()                                          \
-    const PencilDev &P = PD[blockIdx.x];                          \
+    const PencilDev P = PD[blockIdx.x];                          \
     if (!P.reduce) return;                                        \
     double2 *A = P.Ft;                                            \
     const long lda = P.ldft;                                      \
@@ -386,7 +386,7 @@ __global__ void k_jqr_finish(const PencilDev *PD) {
 }
 
 __global__ void k_jqr_init(const PencilDev *PD) {
-    const PencilDev &P = PD[blockIdx.x];
+    const PencilDev P = PD[blockIdx.x];
     JqrState *st = P.jst;
     int *perm = P.perm;
     const int n = P.n;
@@ -408,7 +408,7 @@ __global__ void k_jqr_init(const PencilDev *PD) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kOneNT) void k_qr_house(const PencilDev *PD, int k) {
     __shared__ double red[kOneNT / kWave];
-    const PencilDev &P = PD[blockIdx.x];
+    const PencilDev P = PD[blockIdx.x];
     if (!P.reduce || k >= P.n || P.jst->status != 0) return;
     double2 *A = P.Gt;
     const long lda = P.ldgt;
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(kGridNT) void k_qr_apply(const PencilDev *PD, const
                                                       int k) {
     __shared__ double red[2 * kGridNT / kWave];
     const int pk = find_pencil(pre, B, blockIdx.x);
-    const PencilDev &P = PD[pk];
+    const PencilDev P = PD[pk];
     if (!P.reduce || k >= P.n || P.jst->status != 0) return;
     const int j = blockIdx.x - pre[pk];
     if (j <= k) return;
@@ -611,7 +611,7 @@ int set_identity(int n, void *Z, long ldz, int fp32, hipStream_t stream) {
 
 __global__ void k_jqr_status(const PencilDev *PD, int B, int *out) {
     for (int k = threadIdx.x; k < B; k += blockDim.x) {
-        const PencilDev &P = PD[k];
+        const PencilDev P = PD[k];
         if (!P.reduce) {
             out[2 * k] = 0;
             out[2 * k + 1] = 0;

@@ -60,80 +60,16 @@ void prof_before(hipStream_t s, hipEvent_t &e0, hipEvent_t &e1);
 void prof_after(hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 
 // Shared host loop of the stages: resets the per-pencil states (blocked = 1
-// retires pencils too small for blocking at once), then repeats `one_step`
-// (which enqueues one global step for all pencils) in rounds of
-// `steps_per_round` until every pencil is done, and collects the results.
-using StepFn = int (*)(const BatchCtx &, const void *, hipStream_t);
+// retires pencils too small for blocking at once), then runs rounds until
+// every pencil is done.  A round is one sweep of every pencil still running:
+// `one_step(c, arg, i, s)` for i = 0 .. steps_per_round - 1 (it enqueues
+// global step i for all pencils; a pencil with fewer steps per sweep idles
+// in the surplus steps), then the end-of-round kernel, which applies the
+// stopping rules.  The round is captured once into a graph on an internal
+// stream and replayed (unless kernel timing is on or GHSVD_NO_GRAPH is set).
+using StepFn = int (*)(const BatchCtx &, const void *, int, hipStream_t);
 int drive_stage(const BatchCtx &c, int max_sweeps, int noise_floor, int blocked, StepFn one_step,
                 const void *arg, int steps_per_round, const char *name, hipStream_t s,
                 std::vector<SweepResult> &res);
-
-// Last-workgroup protocol of a step: every workgroup of a pencil calls this
-// at its end (all threads); it returns true in exactly one workgroup, the
-// last to finish, which then sees the writes of all the others (the release
-// fence before, and the acquire fence after, the counting atomic).
-__device__ inline bool last_workgroup(SweepState *st, unsigned total) {
-    __shared__ int last_s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(&st->fin, 1u);
-        last_s = (prev + 1u == total) ? 1 : 0;
-        if (last_s) __threadfence();
-    }
-    __syncthreads();
-    return last_s != 0;
-}
-
-// Run by all threads of the last workgroup of a pencil's step: advances the
-// step counter; at the end of a sweep sums the per-slot counters in a fixed
-// order, clears them, records them, and sets the stop flags (Section 6.1.7:
-// no big transformation in the sweep; Algorithm 2: the sweep cap; the FP32
-// noise floor).
-__device__ inline void step_done(SweepState *st, unsigned long long *cnt, int nslots, int steps) {
-    __shared__ int ls_s;
-    __shared__ double red[3 * 16];
-    if (threadIdx.x == 0) ls_s = st->lstep + 1;
-    __syncthreads();
-    const int ls = ls_s;
-    if (ls < steps) {
-        if (threadIdx.x == 0) {
-            st->lstep = ls;
-            st->fin = 0u;
-        }
-        return;
-    }
-    double v[3] = {0.0, 0.0, 0.0};
-    for (int k = threadIdx.x; k < nslots; k += blockDim.x) {
-        v[0] += (double)cnt[3 * k + 0];
-        v[1] += (double)cnt[3 * k + 1];
-        v[2] += (double)cnt[3 * k + 2];
-        cnt[3 * k + 0] = 0ull;
-        cnt[3 * k + 1] = 0ull;
-        cnt[3 * k + 2] = 0ull;
-    }
-    block_sum<3>(v, red);
-    if (threadIdx.x == 0) {
-        const int sw = st->sweeps;
-        if (sw < kMaxHist) {
-            st->hist[3 * sw + 0] = (unsigned long long)v[0];
-            st->hist[3 * sw + 1] = (unsigned long long)v[1];
-            st->hist[3 * sw + 2] = (unsigned long long)v[2];
-        }
-        st->sweeps = sw + 1;
-        if (st->err != 0) {
-            st->done = 1;
-        } else if (v[2] == 0.0) {
-            st->done = 1;
-            st->converged = 1;
-        } else if (st->noise_floor && v[2] * 1024.0 <= v[0]) {
-            st->done = 1;
-        } else if (sw + 1 >= st->max_sweeps) {
-            st->done = 1;
-        }
-        st->lstep = 0;
-        st->fin = 0u;
-    }
-}
 
 }  // namespace ghsvd
