@@ -1,15 +1,26 @@
 """Benchmark: whole-solve throughput of the HZ-GHSVD path on one MI355X.
 
 A "step" is one complete ghsvd_solve of the n = 1024 pencil (F 1536 x 1024
-with J = diag(+1 x1152, -1 x384), G 2048 x 1024 with cond(G^*G) up to 1e16,
-complex128): input checks, one-time reduction (JQR of F, QR of G P2),
-round-robin pointwise FP64 sweeps to convergence, and the outputs lambda, X.
-Inputs are resident in HBM before the timed region.  Prints one JSON line.
+with J = diag(+1 x1152, -1 x384), G 2048 x 1024 = U diag(s) W^* with s
+log-uniform in [1e-8, 1], so cond(G^* G) = 1e16; complex128): input checks,
+one-time reduction (hyperbolic QR of F, QR of G P2), the sweep stages of the
+chosen path (default: Level-2 blocked FP64 sweeps, then the FP64 pointwise
+sweep that confirms convergence), and the outputs lambda, X.  Inputs are
+resident in HBM before the timed region.  Prints one JSON line.
+
+Beside the timed path it reports:
+  * per sweep-kernel kind, the mean launch time measured with HIP events on
+    the launch stream over the timed region, and its roofline;
+  * the error of lambda against the stored oracle eigenvalues of this pencil;
+  * the other paths on the same pencil (plain FP64 pointwise; mixed FP32 ->
+    FP64), with their times and errors;
+  * the CPU oracle on a bounded sample (reduction + one sweep, extrapolated).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
-                    [--variant pointwise|blocked] [--no-cpu-baseline]
+                    [--variant blocked|pointwise] [--no-compare] [--no-cpu-baseline]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -21,32 +32,151 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GHSVD pencils/s + pair-updates/s, mixed+batched vs plain FP64, rel err<=1e-12"
-HBM_PEAK_GBS = 8000.0
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_MFMA_PEAK_TF = 78.6       # dense FP64 matrix
+FP32_MFMA_PEAK_TF = 157.3      # dense FP32 matrix
+FP64_VALU_PEAK_TF = 78.6       # FP64 vector
+GOLDEN = os.path.join(ROOT, "tests", "golden", "workload2_lambda.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
 
-def pair_bytes(visited, transformed, mr, pr, n):
-    """Algorithmic HBM bytes of the pair kernel: a transformed pair reads and
-    writes two columns of F, G and Z' (64 (m_r + p_r + n) bytes in complex128),
-    a skipped pair only reads its F and G columns (32 (m_r + p_r) bytes)."""
-    return transformed * 64.0 * (mr + pr + n) + (visited - transformed) * 32.0 * (mr + pr)
+def pair_bytes(visited, transformed, mr, pr, n, fp32=False):
+    """Algorithmic HBM bytes of the pointwise pair kernel: a transformed pair
+    reads and writes two columns of F, G and Z' (64 (m_r + p_r + n) bytes in
+    complex128), a skipped pair only reads its F and G columns
+    (32 (m_r + p_r) bytes).  Complex64 halves both."""
+    b = transformed * 64.0 * (mr + pr + n) + (visited - transformed) * 32.0 * (mr + pr)
+    return b / 2 if fp32 else b
 
 
-def cpu_baseline(P, gpu_sweeps):
+def kernel_rooflines(times, info_sum, mr, pr, n, w, nbp, fp32_blocked=False):
+    """Per-kind roofline over the timed region.  times[kind] = (ms, timed, launches)."""
+    out = {}
+    c = 2 * w
+    for kind, (ms, timed, launches) in times.items():
+        if timed == 0 or launches == 0:
+            continue
+        mean_s = ms / timed * 1e-3
+        rec = {"mean_us": mean_s * 1e6, "launches": launches, "timed_launches": timed,
+               "total_ms_est": mean_s * launches * 1e3}
+        if kind in ("pair64", "pair32"):
+            vis, tr = info_sum["pw_visited"], info_sum["pw_transformed"]
+            if kind == "pair32":  # FP32 pair stage counters are not separated; skip
+                continue
+            b = pair_bytes(vis, tr, mr, pr, n) / launches
+            rec.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
+                       achieved=b / mean_s / 1e9, units_per_launch=vis / launches,
+                       work_per_launch=b, work_unit="bytes")
+        elif kind in ("gram", "update"):
+            bsz = 8 if fp32_blocked else 16
+            if kind == "gram":
+                flops = 4.0 * c * c * (mr + pr) * nbp           # Hermitian Grams, SURVEY model
+                byts = c * bsz * (mr + pr) * nbp                # block columns read once
+            else:
+                flops = 8.0 * c * c * (mr + pr + n) * nbp       # three complex GEMMs
+                byts = 2.0 * c * bsz * (mr + pr + n) * nbp      # block columns read + written
+            peak_tf = FP32_MFMA_PEAK_TF if fp32_blocked else FP64_MFMA_PEAK_TF
+            t_mfma = flops / (peak_tf * 1e12)
+            t_hbm = byts / (HBM_PEAK_GBS * 1e9)
+            if t_hbm >= t_mfma:
+                rec.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
+                           achieved=byts / mean_s / 1e9, work_per_launch=byts, work_unit="bytes")
+            else:
+                rec.update(bound="mfma", unit="TFLOP/s", peak=peak_tf,
+                           achieved=flops / mean_s / 1e12, work_per_launch=flops,
+                           work_unit="flops")
+            rec["units_per_launch"] = nbp
+        elif kind == "inner":
+            # two-sided 2x2-block updates of H^ and S^ (128 flops each) and the
+            # accumulation into Z^ (64 flops), (c/2)^2 blocks per inner step,
+            # c - 1 inner steps per block pair
+            flops = 320.0 * (c * c / 4.0) * (c - 1) * nbp
+            rec.update(bound="alu", unit="TFLOP/s", peak=FP64_VALU_PEAK_TF,
+                       achieved=flops / mean_s / 1e12, work_per_launch=flops, work_unit="flops",
+                       units_per_launch=nbp, us_per_inner_step=mean_s * 1e6 / (c - 1))
+        rec["frac"] = rec["achieved"] / rec["peak"]
+        out[kind] = rec
+    return out
+
+
+KERNEL_NAMES = {"pair64": "k_pair<double> (pointwise FP64 pair kernel)",
+                "gram": "k_blk_gram (block-pivot Grams, MFMA)",
+                "inner": "k_blk_inner (inner 2x2 sweep of a block pivot, LDS)",
+                "update": "k_blk_update (block-column update, MFMA)"}
+
+
+def stored_traffic(kind):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel's source changed since the counters were taken."""
+    try:
+        with open(TRAFFIC) as f:
+            t = json.load(f).get(kind)
+    except (OSError, ValueError):
+        return None
+    if not t:
+        return None
+    src = os.path.join(ROOT, t["source"])
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    return t["bytes_per_launch"] if sha == t["sha256"] else None
+
+
+def lambda_errors(lam):
+    with open(GOLDEN) as f:
+        ref = np.asarray(json.load(f)["lambda"], dtype=np.float64)
+    e = np.abs(lam - ref) / np.abs(ref)
+    return float(e.max()), float(np.median(e))
+
+
+def cpu_baseline(P, oracle_sweeps):
     """The CPU oracle on a bounded sample of the same workload: the full
-    reduction (JQR + QR) plus one square sweep, extrapolated to the GPU's
-    FP64 sweep count."""
+    reduction (hyperbolic QR + QR) plus one round-robin sweep on the square
+    factors, extrapolated to the oracle's own sweep count on this pencil."""
     from oracle import oracle as O
     o = O.Oracle()
     t0 = time.perf_counter()
     st, Fsq, Jsq, Gsq, perm, n2 = o.reduce(P.F, P.J, P.G)
     t_red = time.perf_counter() - t0
     t0 = time.perf_counter()
-    st2, *_rest, stats = o.hz_run(Fsq, Jsq, Gsq, order=1, max_sweeps=1)
+    o.hz_run(Fsq, Jsq, Gsq, order=1, max_sweeps=1)
     t_sw = time.perf_counter() - t0
-    total = t_red + gpu_sweeps * t_sw
+    total = t_red + oracle_sweeps * t_sw
     return {"value": 1.0 / total, "unit": "pencils/s", "cores": 1, "kind": "oracle",
-            "sample": (f"reduction ({t_red:.1f} s) + 1 of {gpu_sweeps} square sweeps "
-                       f"({t_sw:.1f} s) measured, total extrapolated to {total:.0f} s/pencil")}
+            "sample": (f"one pencil: reduction ({t_red:.1f} s) + 1 square sweep ({t_sw:.1f} s) "
+                       f"measured single-threaded; total extrapolated to {oracle_sweeps} sweeps "
+                       f"(the oracle's count on this pencil) = {total:.0f} s/pencil")}
+
+
+def run_path(ghsvd, F, J, G, P, kw, steps, warmup, profile_every=0):
+    import torch
+    dev = F.device
+    opt = ghsvd.options(**kw)
+    work = torch.empty(ghsvd.workspace_size(P.m, P.n, P.p, opt), dtype=torch.uint8, device=dev)
+    lam = torch.empty(P.n, dtype=torch.float64, device=dev)
+    X = ghsvd.fortran_empty(P.n, P.n, device=dev)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        ghsvd.solve(F, J, G, work=work, out=(lam, X), **kw)
+    torch.cuda.synchronize()
+    if profile_every:
+        ghsvd.profile_enable(profile_every)
+        for k in ghsvd.PROF_KINDS:
+            ghsvd.profile_read(k)  # clear
+    infos = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, _, info = ghsvd.solve(F, J, G, work=work, out=(lam, X), **kw)
+        infos.append(info)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    times = {}
+    if profile_every:
+        times = {k: ghsvd.profile_read(k) for k in ghsvd.PROF_KINDS}
+        ghsvd.profile_enable(0)
+    return dt, infos, lam.cpu().numpy(), times
 
 
 def main():
@@ -55,9 +185,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
-    ap.add_argument("--variant", default="pointwise", choices=["pointwise", "blocked"])
+    ap.add_argument("--variant", default="blocked", choices=["pointwise", "blocked"])
+    ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--profile-every", type=int, default=8)
+    ap.add_argument("--profile-every", type=int, default=4)
     ap.add_argument("--max-sweeps", type=int, default=0)
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
@@ -88,38 +219,20 @@ def main():
     G = ghsvd.to_device_fortran(P.G, dev)
     J = torch.from_numpy(P.J).to(dev)
     kw = dict(precision=args.precision, variant=args.variant, max_sweeps=args.max_sweeps)
-    opt = ghsvd.options(**kw)
-    work = torch.empty(ghsvd.workspace_size(P.m, P.n, P.p, opt), dtype=torch.uint8, device=dev)
-    lam = torch.empty(P.n, dtype=torch.float64, device=dev)
-    X = ghsvd.fortran_empty(P.n, P.n, device=dev)
-    torch.cuda.synchronize()
 
-    for _ in range(args.warmup):
-        ghsvd.solve(F, J, G, work=work, out=(lam, X), **kw)
-    torch.cuda.synchronize()
-
-    ghsvd.profile_enable(args.profile_every)
-    infos = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        _, _, info = ghsvd.solve(F, J, G, work=work, out=(lam, X), **kw)
-        infos.append(info)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    k_ms, k_timed, k_launches = ghsvd.profile_read()
-    ghsvd.profile_enable(0)
-
+    dt, infos, lam, times = run_path(ghsvd, F, J, G, P, kw, args.steps, args.warmup,
+                                     args.profile_every)
     ms_per_step = 1000.0 * dt / args.steps
     info = infos[-1]
-    visited = sum(i["pairs_visited"] for i in infos)
-    transformed = sum(i["pairs_transformed"] for i in infos)
+    isum = {k: sum(i[k] for i in infos) for k in ("pairs_visited", "pw_visited", "pw_transformed")}
     mr, pr, n = info["m_r"], info["p_r"], P.n
-    # roofline of the pair kernel: algorithmic bytes per launch / mean launch duration
-    bytes_all = pair_bytes(visited, transformed, mr, pr, n)
-    bytes_per_launch = bytes_all / max(k_launches, 1)
-    mean_ms = k_ms / max(k_timed, 1)
-    achieved = bytes_per_launch / (mean_ms * 1e-3) / 1e9 if k_timed else None
+    w = 16 if n >= 512 else 8  # the library's block width for this order
+    nb = -(-n // w)
+    nb += nb & 1
+    kr = kernel_rooflines(times, isum, mr, pr, n, w, nb // 2,
+                          fp32_blocked=args.precision == "mixed")
+    dom = max(kr, key=lambda k: kr[k]["total_ms_est"]) if kr else None
+    err_max, err_med = lambda_errors(lam)
 
     rec = {
         "metric": METRIC,
@@ -135,31 +248,49 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": ("one pencil n=1024: F 1536x1024 Gaussian, J 1152(+)/384(-), "
-                         "G 2048x1024 = U diag(s) W^*, s log-uniform [1e-8,1], complex128; "
-                         f"reduction + {args.variant} {args.precision} sweeps"),
+            "workload": ("one LAPW-shaped pencil n=1024: F 1536x1024 Gaussian, J 1152(+)/384(-), "
+                         "G 2048x1024 = U diag(s) W^*, s log-uniform [1e-8,1] (cond S = 1e16), "
+                         f"complex128; reduction + {args.variant} {args.precision} sweeps"),
             "n": n, "m": P.m, "p": P.p, "batch": 1,
+            "precision": args.precision, "variant": args.variant,
         },
-        "pair_updates_per_s": visited / dt,
+        "pair_updates_per_s": isum["pairs_visited"] / dt,
         "sweeps_fp64": info["sweeps_fp64"],
         "sweeps_fp32": info["sweeps_fp32"],
+        "sweeps_blocked": info["sweeps_blocked"],
         "status": info["status"],
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "k_pair (pointwise pair kernel)",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": (achieved / HBM_PEAK_GBS) if achieved else None,
-            "traffic": None,
-            "mean_launch_us": mean_ms * 1e3,
-            "bytes_per_launch": bytes_per_launch,
-            "timed_launches": k_timed,
-            "launches": k_launches,
-        },
+        "lambda_rel_err_vs_oracle": {"max": err_max, "median": err_med},
     }
+    if dom is not None:
+        d = kr[dom]
+        rec["roofline"] = {
+            "bound": d["bound"], "kernel": KERNEL_NAMES.get(dom, dom),
+            "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"], "frac": d["frac"],
+            "traffic": stored_traffic(dom),
+            "mean_launch_us": d["mean_us"], "work_per_launch": d["work_per_launch"],
+            "work_unit": d["work_unit"], "timed_launches": d["timed_launches"],
+            "launches": d["launches"],
+        }
+        rec["kernels"] = kr
+    if not args.no_compare:
+        comp = {}
+        for prec, var in (("fp64", "pointwise"), ("mixed", "blocked"), ("fp64", "blocked")):
+            if prec == args.precision and var == args.variant:
+                continue
+            ckw = dict(precision=prec, variant=var, max_sweeps=args.max_sweeps)
+            cdt, cinf, clam, _ = run_path(ghsvd, F, J, G, P, ckw, 2, 1)
+            emax, emed = lambda_errors(clam)
+            comp[f"{prec}-{var}"] = {"ms_per_pencil": 1000.0 * cdt / 2,
+                                     "pencils_per_s": 2 / cdt,
+                                     "sweeps_fp32": cinf[-1]["sweeps_fp32"],
+                                     "sweeps_fp64": cinf[-1]["sweeps_fp64"],
+                                     "status": cinf[-1]["status"],
+                                     "lambda_rel_err_vs_oracle": {"max": emax, "median": emed}}
+        rec["compare"] = comp
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(P, max(info["sweeps_fp64"], 1))
+        with open(GOLDEN) as f:
+            osw = json.load(f)["sweeps"]
+        rec["cpu_baseline"] = cpu_baseline(P, osw)
     print(json.dumps(rec), flush=True)
 
 

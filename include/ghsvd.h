@@ -80,6 +80,8 @@ typedef struct {
     long long pairs_visited;   /* pivot pairs visited (outer and inner levels)              */
     long long pairs_transformed;
     long long pairs_big;
+    long long pw_visited;      /* of the visited pairs, those of the FP64 pointwise sweeps  */
+    long long pw_transformed;  /* and of those, the transformed ones                        */
 } ghsvd_info;
 
 /* Fills *opt with the defaults: FP64, pointwise, reduce = 1, auto widths,
@@ -202,16 +204,23 @@ int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, doub
 int ghsvd_round_robin(int n, int *p_out, int *q_out);
 
 /*
- * Kernel timing of the pointwise pair kernel, for measurement harnesses.
- * ghsvd_profile_enable(every): from now on every `every`-th pair-kernel launch
- * (per process) is bracketed by two HIP events recorded on the stream the
- * kernel is launched on; every <= 0 disables it.  ghsvd_profile_read (host
- * outputs) waits for the recorded events, returns the summed kernel
- * milliseconds of the timed launches, their count, and the count of all
- * pair-kernel launches since enabling, then clears the record.
+ * Kernel timing of the sweep kernels, for measurement harnesses.
+ * ghsvd_profile_enable(every): from now on every `every`-th launch of each
+ * sweep-kernel kind (per process) is bracketed by two HIP events recorded on
+ * the stream the kernel is launched on; while it is on, rounds are launched
+ * directly instead of through a captured graph.  every <= 0 disables it.
+ * ghsvd_profile_read(kind, ...) (host outputs) waits for the recorded events
+ * of that kind, returns the summed kernel milliseconds of the timed
+ * launches, their count, and the count of all launches of the kind since
+ * enabling, then clears that kind's record.  Kinds: GHSVD_PROF_PAIR64 (FP64
+ * pointwise pair kernel), GHSVD_PROF_PAIR32 (its FP32 form),
+ * GHSVD_PROF_GRAM, GHSVD_PROF_INNER, GHSVD_PROF_UPDATE (the three kernels
+ * of a blocked step).  Returns GHSVD_EINVAL for an unknown kind.
  */
+enum { GHSVD_PROF_PAIR64 = 0, GHSVD_PROF_PAIR32 = 1, GHSVD_PROF_GRAM = 2, GHSVD_PROF_INNER = 3,
+       GHSVD_PROF_UPDATE = 4 };
 void ghsvd_profile_enable(int every);
-int ghsvd_profile_read(double *ms, long long *timed, long long *launches);
+int ghsvd_profile_read(int kind, double *ms, long long *timed, long long *launches);
 
 /* Human-readable name of a status value (static storage). */
 const char *ghsvd_status_string(int status);

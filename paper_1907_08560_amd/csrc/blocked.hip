@@ -153,25 +153,136 @@ __global__ __launch_bounds__(256) void k_blk_gram(const PencilDev *PD, const int
     }
 }
 
-// One inner sweep over the block pivot (H^, S^) in LDS.  An inner step:
-// (a) one lane per pivot pair computes the FP64 2x2 step; (b) every thread
-// takes one 2x2 block (rows of pair k, columns of pair k') and applies
-// H <- Z_k^* H Z_k', S <- Z_k^* S Z_k', Zs <- Zs Z_k' to it.  The pairs of a
-// step are disjoint, so the blocks are independent and the two-sided update
-// needs a single pass over H and S.  Pair slots whose second column is a bye
-// or padding (>= c) carry the identity; padding entries are zero and stay so.
+// r^* M c for one entry of a 2x2 block M = [[m00, m01], [m10, m11]]:
+// x_a = m_a0 c0 + m_a1 c1, then conj(r0) x_0 + conj(r1) x_1.  The block
+// update and the look-ahead of the pivot wavefront evaluate these same
+// expressions, so the entries the look-ahead predicts equal the updated
+// ones bit for bit.
+__device__ __forceinline__ double2 mac2(double2 m0, double2 c0, double2 m1, double2 c1) {
+    return cadd(cmul(m0, c0), cmul(m1, c1));
+}
+__device__ __forceinline__ double2 macc2(double2 r0, double2 x0, double2 r1, double2 x1) {
+    return cadd(cmulc(r0, x0), cmulc(r1, x1));
+}
+
+// Threads of the inner kernel: one pivot wavefront, then one thread per 2x2
+// block of (H^, S^) and one per 2x2 block of Z^.
+template <int PB>
+constexpr int inner_threads() {
+    return kWave + PB * PB / 2;
+}
+
+// Shared state of one inner step (double-buffered across steps).
+template <int PB>
+struct InnerStep {
+    double2 z[PB / 2][4];  // Z' of each pair slot: z11, z21, z12, z22
+    int pq[PB / 2][2];     // pivot columns of each slot (-1: unused slot)
+    int act[PB / 2];       // 1: the slot applies its transformation
+    int inv[PB];           // column -> 2 slot + position (0: p, 1: q)
+};
+
+// The pivot wavefront's part of an inner step: the 2x2 steps of all pairs
+// of inner step `is`.  LOOK = 0: the pivot entries are read from (H, S).
+// LOOK = 1: (H, S) are the matrices before the update of step is - 1 (prev),
+// which the other wavefronts are applying at the same time, and each pivot
+// entry after that update is formed here from its 2x2 block and the two
+// transformations that touch it.  Lane l forms entry kind e = l / NP of
+// pair k = l % NP ((p, p), (q, q), (p, q)); lane k gathers its pair's six
+// entries and runs the FP64 2x2 step.
+template <int PB, int F32, int LOOK>
+__device__ __forceinline__ void inner_pivots(int is, int c, int C, double tol, int crit,
+                                             const double2 (*H)[PB + 1],
+                                             const double2 (*S)[PB + 1],
+                                             const InnerStep<PB> &prev, InnerStep<PB> &next,
+                                             double &cv, double &ct, double &cbig, int *err) {
+    constexpr int NP = PB / 2;
+    const int l = threadIdx.x;  // lane of wavefront 0
+    const int k = l % NP, e = l / NP;
+    const int islots = C / 2;
+    int pp = -1, qq = -1;
+    if (k < islots) rr_pair(C, is, k, pp, qq);
+    const bool live = k < islots && qq < c;
+    double2 hv = cmk(0.0, 0.0), sv = cmk(0.0, 0.0);
+    if (live && e < 3) {
+        const int i = (e == 1) ? qq : pp, j = (e == 0) ? pp : qq;
+        if (!LOOK) {
+            hv = H[i][j];
+            sv = S[i][j];
+        } else {
+            const double2 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0);
+            const int ai = prev.inv[i], aj = prev.inv[j];
+            const int ki = ai >> 1, ii = ai & 1, kj = aj >> 1, jj = aj & 1;
+            const int r0 = prev.pq[ki][0], r1 = prev.pq[ki][1];
+            const int c0 = prev.pq[kj][0], c1 = prev.pq[kj][1];
+            double2 ra, rb, ca, cb;  // column ii of Z'_ki, column jj of Z'_kj
+            if (prev.act[ki]) {
+                ra = prev.z[ki][2 * ii];
+                rb = prev.z[ki][2 * ii + 1];
+            } else {
+                ra = ii ? zero : one;
+                rb = ii ? one : zero;
+            }
+            if (prev.act[kj]) {
+                ca = prev.z[kj][2 * jj];
+                cb = prev.z[kj][2 * jj + 1];
+            } else {
+                ca = jj ? zero : one;
+                cb = jj ? one : zero;
+            }
+            hv = macc2(ra, mac2(H[r0][c0], ca, H[r0][c1], cb), rb, mac2(H[r1][c0], ca, H[r1][c1], cb));
+            sv = macc2(ra, mac2(S[r0][c0], ca, S[r0][c1], cb), rb, mac2(S[r1][c0], ca, S[r1][c1], cb));
+        }
+    }
+    // gather (p,p), (q,q), (p,q) of pair k into lane k (all lanes take part)
+    const double hpp = __shfl(hv.x, k, kWave), hqq = __shfl(hv.x, k + NP, kWave);
+    const double hpq_r = __shfl(hv.x, k + 2 * NP, kWave), hpq_i = __shfl(hv.y, k + 2 * NP, kWave);
+    const double spp = __shfl(sv.x, k, kWave), sqq = __shfl(sv.x, k + NP, kWave);
+    const double spq_r = __shfl(sv.x, k + 2 * NP, kWave), spq_i = __shfl(sv.y, k + 2 * NP, kWave);
+    if (l < NP) {
+        int kind = kSkip;
+        if (live) {
+            Zp z;
+            kind = hz_step_fast(hpp, hqq, cmk(hpq_r, hpq_i), spp, sqq, cmk(spq_r, spq_i), tol, crit,
+                                z, F32);
+            cv += 1.0;
+            if (kind == GHSVD_ENONFINITE) atomicCAS(err, 0, GHSVD_ENONFINITE);
+            if (kind < 0) kind = kSkip;  // dependent-looking pivot: left to the finish
+            next.z[k][0] = z.z11;
+            next.z[k][1] = z.z21;
+            next.z[k][2] = z.z12;
+            next.z[k][3] = z.z22;
+            ct += kind > 0 ? 1.0 : 0.0;
+            cbig += kind == kBig ? 1.0 : 0.0;
+        }
+        next.pq[k][0] = pp;
+        next.pq[k][1] = qq;
+        next.act[k] = kind > 0;
+        if (k < islots) {
+            next.inv[pp] = 2 * k;
+            next.inv[qq] = 2 * k + 1;
+        }
+    }
+}
+
+// One inner sweep over the block pivot (H^, S^) in LDS, software-pipelined.
+// While wavefront 0 computes the 2x2 steps of inner step s + 1 (with the
+// pivot entries predicted from the block entries before step s and step s's
+// transformations), the other threads apply step s: one thread per 2x2
+// block (rows of pair k, columns of pair k') does H <- Z_k^* H Z_k' and
+// S <- Z_k^* S Z_k' from one buffer into the other, and one thread per 2x2
+// block does Zs <- Zs Z_k' in place.  The pairs of a step are disjoint, so
+// the blocks are independent.  Pair slots whose second column is a bye or
+// padding (>= c) carry the identity; padding entries are zero and stay so.
 template <int PB, int F32>
-__global__ __launch_bounds__(256) void k_blk_inner(const PencilDev *PD, const int *pre, int B,
-                                                   int crit, int step) {
+__global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilDev *PD,
+                                                                   const int *pre, int B, int crit,
+                                                                   int step) {
     constexpr int NP = PB / 2;   // pivot pair slots per inner step
     constexpr int NB = NP * NP;  // 2x2 blocks
-    __shared__ double2 H[PB][PB + 1];
-    __shared__ double2 S[PB][PB + 1];
+    __shared__ double2 H[2][PB][PB + 1];
+    __shared__ double2 S[2][PB][PB + 1];
     __shared__ double2 Zs[PB][PB + 1];
-    __shared__ double2 zpar[NP][4];
-    __shared__ int pq_s[NP][2];
-    __shared__ int act_s[NP];
-    __shared__ double red[3 * 4];
+    __shared__ InnerStep<PB> st[2];
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev A = PD[pk];
     if (step >= A.nb - 1 || A.st->done) return;
@@ -187,118 +298,114 @@ __global__ __launch_bounds__(256) void k_blk_inner(const PencilDev *PD, const in
     }
     const int KC = A.kf + A.kg;
     const double2 *P = A.part + (size_t)bpi * KC * PB * PB;
-    for (int idx = tid; idx < PB * PB; idx += 256) {
+    for (int idx = tid; idx < PB * PB; idx += inner_threads<PB>()) {
         const int i = idx % PB, j = idx / PB;
         double2 h = cmk(0.0, 0.0), s = cmk(0.0, 0.0);
         for (int k = 0; k < A.kf; ++k) h = cadd(h, P[(size_t)k * PB * PB + idx]);
         for (int k = A.kf; k < KC; ++k) s = cadd(s, P[(size_t)k * PB * PB + idx]);
-        H[i][j] = h;
-        S[i][j] = s;
+        H[0][i][j] = h;
+        S[0][i][j] = s;
         Zs[i][j] = cmk(i == j ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
     const int C = c + (c & 1);
-    const int islots = C / 2;
     const double tol = (F32 ? 0x1p-23 : 0x1p-52) * sqrt((double)c);
     double cv = 0.0, ct = 0.0, cbig = 0.0;
+    if (tid < kWave)
+        inner_pivots<PB, F32, 0>(0, c, C, tol, crit, H[0], S[0], st[1], st[0], cv, ct, cbig,
+                                 &A.st->err);
+    __syncthreads();
     for (int s = 0; s < C - 1; ++s) {
-        if (tid < NP) {
-            int pp = -1, qq = -1, kind = kSkip;
-            if (tid < islots) {
-                rr_pair(C, s, tid, pp, qq);
-                if (qq < c) {
-                    Zp z;
-                    kind = hz_step_fast(H[pp][pp].x, H[qq][qq].x, H[pp][qq], S[pp][pp].x,
-                                        S[qq][qq].x, S[pp][qq], tol, crit, z, F32);
-                    cv += 1.0;
-                    if (kind == GHSVD_ENONFINITE) atomicCAS(&A.st->err, 0, GHSVD_ENONFINITE);
-                    if (kind < 0) kind = kSkip;  // dependent-looking pivot: left to the finish
-                    zpar[tid][0] = z.z11;
-                    zpar[tid][1] = z.z21;
-                    zpar[tid][2] = z.z12;
-                    zpar[tid][3] = z.z22;
-                    ct += kind > 0 ? 1.0 : 0.0;
-                    cbig += kind == kBig ? 1.0 : 0.0;
+        const int cur = s & 1, nxt = cur ^ 1;
+        const InnerStep<PB> &now = st[cur];
+        if (tid < kWave) {
+            if (s + 1 < C - 1)
+                inner_pivots<PB, F32, 1>(s + 1, c, C, tol, crit, H[cur], S[cur], now, st[nxt], cv,
+                                         ct, cbig, &A.st->err);
+        } else {
+            const double2 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0);
+            const int t = tid - kWave;
+            const int blk = t < NB ? t : t - NB;
+            const int kr = blk % NP, kc = blk / NP;  // row pair, column pair
+            const int p1 = now.pq[kr][0], q1 = now.pq[kr][1];
+            const int p2 = now.pq[kc][0], q2 = now.pq[kc][1];
+            const bool ar = now.act[kr], ac = now.act[kc];
+            if (p1 >= 0 && p2 >= 0) {
+                double2 c11 = one, c21 = zero, c12 = zero, c22 = one;
+                if (ac) {
+                    c11 = now.z[kc][0];
+                    c21 = now.z[kc][1];
+                    c12 = now.z[kc][2];
+                    c22 = now.z[kc][3];
+                }
+                if (t < NB) {
+                    const double2 h11 = H[cur][p1][p2], h12 = H[cur][p1][q2];
+                    const double2 h21 = H[cur][q1][p2], h22 = H[cur][q1][q2];
+                    const double2 s11 = S[cur][p1][p2], s12 = S[cur][p1][q2];
+                    const double2 s21 = S[cur][q1][p2], s22 = S[cur][q1][q2];
+                    if (!ar && !ac) {
+                        H[nxt][p1][p2] = h11;
+                        H[nxt][p1][q2] = h12;
+                        H[nxt][q1][p2] = h21;
+                        H[nxt][q1][q2] = h22;
+                        S[nxt][p1][p2] = s11;
+                        S[nxt][p1][q2] = s12;
+                        S[nxt][q1][p2] = s21;
+                        S[nxt][q1][q2] = s22;
+                    } else {
+                        double2 r11 = one, r21 = zero, r12 = zero, r22 = one;
+                        if (ar) {
+                            r11 = now.z[kr][0];
+                            r21 = now.z[kr][1];
+                            r12 = now.z[kr][2];
+                            r22 = now.z[kr][3];
+                        }
+                        double2 x11 = mac2(h11, c11, h12, c21), x12 = mac2(h11, c12, h12, c22);
+                        double2 x21 = mac2(h21, c11, h22, c21), x22 = mac2(h21, c12, h22, c22);
+                        H[nxt][p1][p2] = macc2(r11, x11, r21, x21);
+                        H[nxt][p1][q2] = macc2(r11, x12, r21, x22);
+                        H[nxt][q1][p2] = macc2(r12, x11, r22, x21);
+                        H[nxt][q1][q2] = macc2(r12, x12, r22, x22);
+                        x11 = mac2(s11, c11, s12, c21);
+                        x12 = mac2(s11, c12, s12, c22);
+                        x21 = mac2(s21, c11, s22, c21);
+                        x22 = mac2(s21, c12, s22, c22);
+                        S[nxt][p1][p2] = macc2(r11, x11, r21, x21);
+                        S[nxt][p1][q2] = macc2(r11, x12, r21, x22);
+                        S[nxt][q1][p2] = macc2(r12, x11, r22, x21);
+                        S[nxt][q1][q2] = macc2(r12, x12, r22, x22);
+                    }
+                } else if (ac) {
+                    const double2 w11 = Zs[p1][p2], w12 = Zs[p1][q2];
+                    const double2 w21 = Zs[q1][p2], w22 = Zs[q1][q2];
+                    Zs[p1][p2] = mac2(w11, c11, w12, c21);
+                    Zs[p1][q2] = mac2(w11, c12, w12, c22);
+                    Zs[q1][p2] = mac2(w21, c11, w22, c21);
+                    Zs[q1][q2] = mac2(w21, c12, w22, c22);
                 }
             }
-            pq_s[tid][0] = pp;
-            pq_s[tid][1] = qq;
-            act_s[tid] = kind > 0;
-        }
-        __syncthreads();
-        for (int blk = tid; blk < NB; blk += 256) {
-            const int kr = blk % NP, kc = blk / NP;  // row pair, column pair
-            const int p1 = pq_s[kr][0], q1 = pq_s[kr][1];
-            const int p2 = pq_s[kc][0], q2 = pq_s[kc][1];
-            const bool ar = act_s[kr], ac = act_s[kc];
-            if (p1 < 0 || p2 < 0 || (!ar && !ac)) continue;  // padding slot or identity
-            // loads first (one LDS round trip), then arithmetic, then stores
-            const double2 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0);
-            double2 zr[4], zc[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                zr[e] = zpar[kr][e];
-                zc[e] = zpar[kc][e];
-            }
-            const double2 h11 = H[p1][p2], h12 = H[p1][q2], h21 = H[q1][p2], h22 = H[q1][q2];
-            const double2 s11 = S[p1][p2], s12 = S[p1][q2], s21 = S[q1][p2], s22 = S[q1][q2];
-            const double2 w11 = Zs[p1][p2], w12 = Zs[p1][q2], w21 = Zs[q1][p2], w22 = Zs[q1][q2];
-            const double2 r11 = ar ? zr[0] : one, r21 = ar ? zr[1] : zero;
-            const double2 r12 = ar ? zr[2] : zero, r22 = ar ? zr[3] : one;
-            const double2 c11 = ac ? zc[0] : one, c21 = ac ? zc[1] : zero;
-            const double2 c12 = ac ? zc[2] : zero, c22 = ac ? zc[3] : one;
-            // M_blk <- R^* M_blk Cz for H and S; Zs_blk <- Zs_blk Cz
-            double2 x11 = cadd(cmul(h11, c11), cmul(h12, c21));
-            double2 x12 = cadd(cmul(h11, c12), cmul(h12, c22));
-            double2 x21 = cadd(cmul(h21, c11), cmul(h22, c21));
-            double2 x22 = cadd(cmul(h21, c12), cmul(h22, c22));
-            const double2 H11 = cadd(cmulc(r11, x11), cmulc(r21, x21));
-            const double2 H12 = cadd(cmulc(r11, x12), cmulc(r21, x22));
-            const double2 H21 = cadd(cmulc(r12, x11), cmulc(r22, x21));
-            const double2 H22 = cadd(cmulc(r12, x12), cmulc(r22, x22));
-            x11 = cadd(cmul(s11, c11), cmul(s12, c21));
-            x12 = cadd(cmul(s11, c12), cmul(s12, c22));
-            x21 = cadd(cmul(s21, c11), cmul(s22, c21));
-            x22 = cadd(cmul(s21, c12), cmul(s22, c22));
-            const double2 S11 = cadd(cmulc(r11, x11), cmulc(r21, x21));
-            const double2 S12 = cadd(cmulc(r11, x12), cmulc(r21, x22));
-            const double2 S21 = cadd(cmulc(r12, x11), cmulc(r22, x21));
-            const double2 S22 = cadd(cmulc(r12, x12), cmulc(r22, x22));
-            const double2 W11 = cadd(cmul(w11, c11), cmul(w12, c21));
-            const double2 W12 = cadd(cmul(w11, c12), cmul(w12, c22));
-            const double2 W21 = cadd(cmul(w21, c11), cmul(w22, c21));
-            const double2 W22 = cadd(cmul(w21, c12), cmul(w22, c22));
-            H[p1][p2] = H11;
-            H[p1][q2] = H12;
-            H[q1][p2] = H21;
-            H[q1][q2] = H22;
-            S[p1][p2] = S11;
-            S[p1][q2] = S12;
-            S[q1][p2] = S21;
-            S[q1][q2] = S22;
-            Zs[p1][p2] = W11;
-            Zs[p1][q2] = W12;
-            Zs[q1][p2] = W21;
-            Zs[q1][q2] = W22;
         }
         __syncthreads();
     }
-    double v[3] = {cv, ct, cbig};
-    block_sum<3>(v, red);
     double2 *Z64 = A.zh64 + (size_t)bpi * PB * PB;
     float2 *Z32 = F32 ? A.zh32 + (size_t)bpi * PB * PB : nullptr;
-    for (int idx = tid; idx < PB * PB; idx += 256) {
+    for (int idx = tid; idx < PB * PB; idx += inner_threads<PB>()) {
         const int i = idx % PB, j = idx / PB;
         const double2 z = Zs[i][j];
         Z64[idx] = z;
         if (Z32) Z32[idx] = make_float2((float)z.x, (float)z.y);
     }
-    if (tid == 0) {
-        A.ntr[bpi] = (int)v[1];
-        unsigned long long *cn = A.bcnt + 3 * bpi;
-        cn[0] += (unsigned long long)v[0];
-        cn[1] += (unsigned long long)v[1];
-        cn[2] += (unsigned long long)v[2];
+    if (tid < kWave) {
+        cv = wave_sum(cv);
+        ct = wave_sum(ct);
+        cbig = wave_sum(cbig);
+        if (tid == 0) {
+            A.ntr[bpi] = (int)ct;
+            unsigned long long *cn = A.bcnt + 3 * bpi;
+            cn[0] += (unsigned long long)cv;
+            cn[1] += (unsigned long long)ct;
+            cn[2] += (unsigned long long)cbig;
+        }
     }
 }
 
@@ -544,17 +651,25 @@ using BlkInnerFn = void (*)(const PencilDev *, const int *, int, int, int);
 struct BlockedArg {
     BlkFn gram, upd;
     BlkInnerFn inner;
+    int inner_nt;
     int crit;
 };
 
 static int blocked_step(const BatchCtx &c, const void *arg, int step, hipStream_t s) {
     const BlockedArg *a = static_cast<const BlockedArg *>(arg);
+    hipEvent_t e0, e1;
+    prof_before(kProfGram, s, e0, e1);
     hipLaunchKernelGGL(a->gram, dim3(c.total(BatchCtx::kGram)), dim3(256), 0, s, c.dev,
                        c.pre_of(BatchCtx::kGram), c.B, step);
-    hipLaunchKernelGGL(a->inner, dim3(c.total(BatchCtx::kBp)), dim3(256), 0, s, c.dev,
+    prof_after(kProfGram, s, e0, e1);
+    prof_before(kProfInner, s, e0, e1);
+    hipLaunchKernelGGL(a->inner, dim3(c.total(BatchCtx::kBp)), dim3(a->inner_nt), 0, s, c.dev,
                        c.pre_of(BatchCtx::kBp), c.B, a->crit, step);
+    prof_after(kProfInner, s, e0, e1);
+    prof_before(kProfUpdate, s, e0, e1);
     hipLaunchKernelGGL(a->upd, dim3(c.total(BatchCtx::kUpd)), dim3(256), 0, s, c.dev,
                        c.pre_of(BatchCtx::kUpd), c.B, step);
+    prof_after(kProfUpdate, s, e0, e1);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }
@@ -576,10 +691,12 @@ int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, hip
     if (w == 16) {
         a.gram = fp32 ? k_blk_gram<float, 32> : k_blk_gram<double, 32>;
         a.inner = fp32 ? k_blk_inner<32, 1> : k_blk_inner<32, 0>;
+        a.inner_nt = inner_threads<32>();
         a.upd = fp32 ? k_blk_update<float, 32> : k_blk_update<double, 32>;
     } else if (w == 8) {
         a.gram = fp32 ? k_blk_gram<float, 16> : k_blk_gram<double, 16>;
         a.inner = fp32 ? k_blk_inner<16, 1> : k_blk_inner<16, 0>;
+        a.inner_nt = inner_threads<16>();
         a.upd = fp32 ? k_blk_update<float, 16> : k_blk_update<double, 16>;
     } else {
         return GHSVD_EINVAL;

@@ -313,12 +313,13 @@ void trace_stage(const char *name, int pencil, const SweepState &hs) {
                      name, pencil, k + 1, hs.hist[3 * k], hs.hist[3 * k + 1], hs.hist[3 * k + 2]);
 }
 
-// Pair-kernel timing for measurement harnesses (see ghsvd_profile_enable).
+// Sweep-kernel timing for measurement harnesses (see ghsvd_profile_enable):
+// every `every`-th launch of each kernel kind is bracketed by two events.
 namespace prof {
 static std::mutex mu;
 static int every = 0;
-static long long launches = 0;
-static std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
+static long long launches[kProfKinds] = {};
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[kProfKinds];
 static std::vector<hipEvent_t> spare;
 
 static hipEvent_t take_event() {
@@ -333,23 +334,23 @@ static hipEvent_t take_event() {
 }
 }  // namespace prof
 
-void prof_before(hipStream_t s, hipEvent_t &e0, hipEvent_t &e1) {
+void prof_before(int kind, hipStream_t s, hipEvent_t &e0, hipEvent_t &e1) {
     e0 = e1 = nullptr;
     std::lock_guard<std::mutex> lk(prof::mu);
     if (prof::every <= 0) return;
-    if (prof::launches % prof::every == 0) {
+    if (prof::launches[kind] % prof::every == 0) {
         e0 = prof::take_event();
         e1 = prof::take_event();
         if (e0 && e1) (void)hipEventRecord(e0, s);
     }
-    prof::launches++;
+    prof::launches[kind]++;
 }
 
-void prof_after(hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+void prof_after(int kind, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
     if (!e0 || !e1) return;
     (void)hipEventRecord(e1, s);
     std::lock_guard<std::mutex> lk(prof::mu);
-    prof::pending.emplace_back(e0, e1);
+    prof::pending[kind].emplace_back(e0, e1);
 }
 
 static bool prof_active() {
@@ -459,22 +460,24 @@ struct PointwiseArg {
     PairFn fn;
     PairGeom g;
     int crit;
+    int fp32;
 };
 
 static int pointwise_step(const BatchCtx &c, const void *arg, int step, hipStream_t s) {
     const PointwiseArg *a = static_cast<const PointwiseArg *>(arg);
+    const int kind = a->fp32 ? kProfPair32 : kProfPair64;
     hipEvent_t e0, e1;
-    prof_before(s, e0, e1);
+    prof_before(kind, s, e0, e1);
     hipLaunchKernelGGL(a->fn, dim3(c.total(BatchCtx::kSlots)), dim3(a->g.nt), 0, s, c.dev,
                        c.pre_of(BatchCtx::kSlots), c.B, a->crit, step);
-    prof_after(s, e0, e1);
+    prof_after(kind, s, e0, e1);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }
 
 int run_pointwise_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, PairGeom g,
                         hipStream_t s, std::vector<SweepResult> &res) {
-    PointwiseArg a{fp32 ? pick<float>(g.nt, g.r) : pick<double>(g.nt, g.r), g, crit};
+    PointwiseArg a{fp32 ? pick<float>(g.nt, g.r) : pick<double>(g.nt, g.r), g, crit, fp32};
     if (!a.fn) return GHSVD_EINVAL;
     int steps = 1;
     for (const PencilDev &P : c.host) steps = P.N - 1 > steps ? P.N - 1 : steps;
@@ -538,17 +541,18 @@ extern "C" int ghsvd_round_robin(int n, int *p_out, int *q_out) {
 extern "C" void ghsvd_profile_enable(int every) {
     std::lock_guard<std::mutex> lk(prof::mu);
     prof::every = every > 0 ? every : 0;
-    prof::launches = 0;
+    for (long long &l : prof::launches) l = 0;
 }
 
-extern "C" int ghsvd_profile_read(double *ms, long long *timed, long long *launches) {
+extern "C" int ghsvd_profile_read(int kind, double *ms, long long *timed, long long *launches) {
+    if (kind < 0 || kind >= kProfKinds) return GHSVD_EINVAL;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
     long long nl;
     {
         std::lock_guard<std::mutex> lk(prof::mu);
-        ev.swap(prof::pending);
-        nl = prof::launches;
-        prof::launches = 0;
+        ev.swap(prof::pending[kind]);
+        nl = prof::launches[kind];
+        prof::launches[kind] = 0;
     }
     double tot = 0.0;
     int rc = GHSVD_OK;

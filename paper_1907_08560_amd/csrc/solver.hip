@@ -253,6 +253,10 @@ int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *w
             inf.pairs_visited += r[k].visited;
             inf.pairs_transformed += r[k].transformed;
             inf.pairs_big += r[k].big;
+            if (!fp32 && !blocked) {
+                inf.pw_visited += r[k].visited;
+                inf.pw_transformed += r[k].transformed;
+            }
         }
     };
     std::vector<SweepResult> res;

@@ -55,9 +55,11 @@ int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, hip
 // counters of a finished stage to stderr (one line per sweep).
 void trace_stage(const char *name, int pencil, const SweepState &hs);
 
-// Pair-kernel timing record (see ghsvd_profile_enable).
-void prof_before(hipStream_t s, hipEvent_t &e0, hipEvent_t &e1);
-void prof_after(hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+// Sweep-kernel timing record (see ghsvd_profile_enable), per kernel kind.
+enum { kProfPair64 = 0, kProfPair32 = 1, kProfGram = 2, kProfInner = 3, kProfUpdate = 4,
+       kProfKinds = 5 };
+void prof_before(int kind, hipStream_t s, hipEvent_t &e0, hipEvent_t &e1);
+void prof_after(int kind, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 
 // Shared host loop of the stages: resets the per-pencil states (blocked = 1
 // retires pencils too small for blocking at once), then runs rounds until

@@ -43,7 +43,8 @@ class Info(ctypes.Structure):
                 ("sweeps_fp64", ctypes.c_int), ("sweeps_blocked", ctypes.c_int),
                 ("n2x2", ctypes.c_int), ("m_r", ctypes.c_int), ("p_r", ctypes.c_int),
                 ("n_plus", ctypes.c_int), ("pairs_visited", ctypes.c_longlong),
-                ("pairs_transformed", ctypes.c_longlong), ("pairs_big", ctypes.c_longlong)]
+                ("pairs_transformed", ctypes.c_longlong), ("pairs_big", ctypes.c_longlong),
+                ("pw_visited", ctypes.c_longlong), ("pw_transformed", ctypes.c_longlong)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -80,8 +81,8 @@ _lib.ghsvd_round_robin.argtypes = [_i, _p, _p]
 _lib.ghsvd_round_robin.restype = _i
 _lib.ghsvd_profile_enable.argtypes = [_i]
 _lib.ghsvd_profile_enable.restype = None
-_lib.ghsvd_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_longlong),
-                                    ctypes.POINTER(ctypes.c_longlong)]
+_lib.ghsvd_profile_read.argtypes = [_i, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
 _lib.ghsvd_profile_read.restype = _i
 _lib.ghsvd_status_string.argtypes = [_i]
 _lib.ghsvd_status_string.restype = ctypes.c_char_p
@@ -270,17 +271,21 @@ def round_robin(n: int):
     return steps, pp[: steps * slots].reshape(steps, slots), qq[: steps * slots].reshape(steps, slots)
 
 
+PROF_KINDS = {"pair64": 0, "pair32": 1, "gram": 2, "inner": 3, "update": 4}
+
+
 def profile_enable(every: int) -> None:
-    """Time every `every`-th pair-kernel launch with HIP events (0 disables)."""
+    """Time every `every`-th launch of each sweep-kernel kind with HIP events (0 disables)."""
     _lib.ghsvd_profile_enable(int(every))
 
 
-def profile_read():
-    """(kernel milliseconds of the timed launches, timed launches, all launches)."""
+def profile_read(kind: str = "pair64"):
+    """(kernel milliseconds of the timed launches, timed launches, all launches) of one kind."""
     ms = ctypes.c_double(0.0)
     timed = ctypes.c_longlong(0)
     total = ctypes.c_longlong(0)
-    rc = _lib.ghsvd_profile_read(ctypes.byref(ms), ctypes.byref(timed), ctypes.byref(total))
+    rc = _lib.ghsvd_profile_read(PROF_KINDS[kind], ctypes.byref(ms), ctypes.byref(timed),
+                                 ctypes.byref(total))
     if rc < 0:
         raise GhsvdError(rc, "ghsvd_profile_read")
     return ms.value, timed.value, total.value
