@@ -59,7 +59,7 @@ typedef struct {
     int variant;        /* GHSVD_POINTWISE (Section 6.3) or GHSVD_BLOCKED (Section 6.4)   */
     int reduce;         /* 1: reduce to square factors first (Section 5) when m > n or
                            p > n; 0: sweep the tall factors as given                       */
-    int block_width;    /* blocked variant: block-column width w (8, 16 or 32); 0 = auto   */
+    int block_width;    /* blocked variant: block-column width w (8 or 16); 0 = auto        */
     int waves_per_pair; /* pointwise pair kernel: 64-lane wavefronts per pivot pair
                            (1, 2, 4, 8 or 16); 0 = auto                                    */
     int max_sweeps;     /* sweep cap C_max per precision stage; 0 -> 60 (Algorithm 2 uses
