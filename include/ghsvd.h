@@ -67,7 +67,16 @@ typedef struct {
     int sort;           /* 1: ascending lambda, X's columns permuted alike; 0: unsorted   */
     int crit_literal;   /* 0: criterion (6.12) with sqrt(|h_pp||h_qq|); 1: the printed
                            product form max*eps*sqrt(n)*min                                */
+    int inner_order;    /* blocked variant, pairs of the one inner sweep per block pivot:
+                           GHSVD_INNER_FULL: all pairs of the 2w pivot columns in round-
+                           robin order (Section 6.4.2, BO); GHSVD_INNER_CROSS (default):
+                           the same at the first block step of a sweep, where every block
+                           appears once, and only the w x w pairs across the two blocks
+                           at the other steps, so each column pair is visited once per
+                           sweep                                                        */
 } ghsvd_options;
+
+enum { GHSVD_INNER_FULL = 0, GHSVD_INNER_CROSS = 1 };  /* ghsvd_options.inner_order */
 
 typedef struct {
     int status;
@@ -85,7 +94,7 @@ typedef struct {
 } ghsvd_info;
 
 /* Fills *opt with the defaults: FP64, pointwise, reduce = 1, auto widths,
- * max_sweeps = 60, sort = 1, crit_literal = 0. */
+ * max_sweeps = 60, sort = 1, crit_literal = 0, inner_order = GHSVD_INNER_CROSS. */
 void ghsvd_default_options(ghsvd_options *opt);
 
 /* Bytes of device workspace ghsvd_solve needs for an m x n F, p x n G.
@@ -186,13 +195,15 @@ int ghsvd_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, double *G,
  * [b w, min(b w + w, n)), nb = ceil(n / w) rounded up to even blocks are
  * paired by ghsvd_round_robin(nb); within a block pair (a, b) the pivot
  * columns are a's then b's, and the inner sweep visits them in
- * ghsvd_round_robin(c) order with tol = eps sqrt(c).  counters (host,
+ * ghsvd_round_robin(c) order with tol = eps sqrt(c); inner_order as in
+ * ghsvd_options (GHSVD_INNER_CROSS: after the first block step of a sweep,
+ * step k pairs column i of block a with column (i + k) mod w of block b).  counters (host,
  * 3 * nsweeps) get (visited, transformed, big) inner pairs per block sweep.
  * Requires n >= 4.
  */
 int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, double *G, int ldg,
-                       double *Z, int ldz, int block_width, int nsweeps, int crit_literal,
-                       long long *counters, int *sweeps_done, void *stream);
+                       double *Z, int ldz, int block_width, int inner_order, int nsweeps,
+                       int crit_literal, long long *counters, int *sweeps_done, void *stream);
 
 /*
  * The round-robin ordering (host): N = n rounded up to even; step s pairs

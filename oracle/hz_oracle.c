@@ -782,7 +782,7 @@ int ora_ghsvd(int m, int n, int p, const cplx *F, int ldf, const signed char *J,
  */
 int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J,
                      cplx *G, int ldg, cplx *Z, int ldz, int w, int max_sweeps,
-                     double eps, int crit_literal, long long *stats)
+                     double eps, int crit_literal, int inner_order, long long *stats)
 {
     if (m < 1 || n < 2 || p < 1 || ldf < m || ldg < p || ldz < n || w < 1 || max_sweeps < 1)
         return ORA_EINVAL;
@@ -835,11 +835,28 @@ int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J
                 if (st != ORA_OK) { status = st; goto done; }
                 for (int j = 0; j < c; ++j)
                     for (int i = 0; i < c; ++i) Gt[(size_t)perm[j] * c + i] = tmp[(size_t)j * p + i];
-                /* one inner sweep (BO), round-robin over the c pivot columns */
+                /* one inner sweep (BO): round-robin over the c pivot columns, or,
+                 * with inner_order = 1 at every block step but the first of the
+                 * sweep, only the w x w pairs across two full blocks: step k
+                 * pairs column i of block a with column (i + k) mod w of block b.
+                 * The first block step meets every block once, so then each
+                 * pair of columns is visited once per sweep. */
                 for (int j = 0; j < c; ++j)
                     for (int i = 0; i < c; ++i) Zh[(size_t)j * c + i] = (i == j) ? 1.0 : 0.0;
-                const int isteps = ora_round_robin(c, ip, iq);
-                const int islots = (c + (c % 2)) / 2;
+                int isteps, islots;
+                const int ca = (a * w + w <= n) ? w : (a * w < n ? n - a * w : 0);
+                if (inner_order == 1 && s > 0 && ca == w && c == 2 * w) {
+                    isteps = w;
+                    islots = w;
+                    for (int is = 0; is < w; ++is)
+                        for (int ik = 0; ik < w; ++ik) {
+                            ip[is * w + ik] = ik;
+                            iq[is * w + ik] = w + (ik + is) % w;
+                        }
+                } else {
+                    isteps = ora_round_robin(c, ip, iq);
+                    islots = (c + (c % 2)) / 2;
+                }
                 const double tol = eps * sqrt((double)c);
                 long long itr = 0;
                 for (int is = 0; is < isteps; ++is)

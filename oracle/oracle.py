@@ -63,7 +63,7 @@ class Oracle:
                                 _c_int, _p]
         L.ora_ghsvd.restype = _c_int
         L.ora_hz_block_run.argtypes = [_c_int, _c_int, _c_int, _p, _c_int, _p, _p, _c_int, _p,
-                                       _c_int, _c_int, _c_int, _c_dbl, _c_int, _p]
+                                       _c_int, _c_int, _c_int, _c_dbl, _c_int, _c_int, _p]
         L.ora_hz_block_run.restype = _c_int
 
     # -- 2x2 step -------------------------------------------------------------
@@ -106,8 +106,10 @@ class Oracle:
                                  stats.ctypes.data)
         return st, F, G, Z, stats
 
-    def hz_block_run(self, F, J, G, Z=None, w=8, max_sweeps=30, eps=EPS64, crit_literal=0):
-        """Level-2 BO block sweeps in place on copies; returns (status, F, G, Z, stats)."""
+    def hz_block_run(self, F, J, G, Z=None, w=8, max_sweeps=30, eps=EPS64, crit_literal=0,
+                     inner_order=0):
+        """Level-2 BO block sweeps in place on copies; returns (status, F, G, Z, stats).
+        inner_order 1: cross-block inner pairs after the first block step of a sweep."""
         F = np.array(F, dtype=np.complex128, order="F", copy=True)
         G = np.array(G, dtype=np.complex128, order="F", copy=True)
         m, n = F.shape
@@ -118,7 +120,7 @@ class Oracle:
         stats = np.zeros(6, dtype=np.int64)
         st = self.lib.ora_hz_block_run(m, n, p, F.ctypes.data, m, J8.ctypes.data, G.ctypes.data,
                                        p, Z.ctypes.data, n, int(w), int(max_sweeps), float(eps),
-                                       int(crit_literal), stats.ctypes.data)
+                                       int(crit_literal), int(inner_order), stats.ctypes.data)
         return st, F, G, Z, stats
 
     def hz_post(self, F, J, G, Z, sort=1):

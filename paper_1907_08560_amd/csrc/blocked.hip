@@ -21,6 +21,7 @@
 // blocked stage: a block sweep whose inner sweeps applied no big
 // transformation (Section 6.1.7).
 #include <cmath>
+#include <cstdlib>
 
 #include "hz_step.hpp"
 #include "reduce.hpp"
@@ -172,13 +173,68 @@ constexpr int inner_threads() {
     return kWave + PB * PB / 2;
 }
 
+// Pair ordering inside a block pivot of c columns (block a's columns first,
+// then block b's).  Round-robin: the circle method of Section 6.3 over C = c
+// rounded up to even, C - 1 steps of C / 2 slots, a pair meeting index c is
+// a bye.  Cross (two full blocks of w columns): step s pairs column k of
+// block a with column (k + s) mod w of block b, w steps of w slots.  Both
+// directions are closed forms, so a slot's columns and a column's slot cost
+// no memory access.
+struct InnerOrder {
+    int cross, C, w;
+    __device__ int steps() const { return cross ? w : C - 1; }
+    __device__ int slots() const { return cross ? w : C / 2; }
+    __device__ void pair(int s, int k, int &p, int &q) const {
+        if (cross) {
+            int j = k + s;
+            if (j >= w) j -= w;
+            p = k;
+            q = w + j;
+        } else {
+            rr_pair(C, s, k, p, q);
+        }
+    }
+    // Slot of column x at step s, and its position in the pair (0: p, 1: q).
+    // Every difference below lies in (-period, 2 period), so a conditional
+    // add or subtract replaces the modulo.
+    __device__ void where(int s, int x, int &slot, int &pos) const {
+        if (cross) {
+            int k = x - w - s;
+            if (k < 0) k += w;
+            slot = x < w ? x : k;
+            pos = x < w ? 0 : 1;
+            return;
+        }
+        const int M = C - 1;
+        int partner;
+        if (x == M) {
+            slot = 0;
+            partner = s;
+        } else if (x == s) {
+            slot = 0;
+            partner = M;
+        } else {
+            int d = x - s;
+            if (d < 0) d += M;
+            if (d <= C / 2 - 1) {
+                slot = d;
+                partner = s - d;
+                if (partner < 0) partner += M;
+            } else {
+                slot = M - d;
+                partner = s + M - d;
+                if (partner >= M) partner -= M;
+            }
+        }
+        pos = x < partner ? 0 : 1;
+    }
+};
+
 // Shared state of one inner step (double-buffered across steps).
 template <int PB>
 struct InnerStep {
     double2 z[PB / 2][4];  // Z' of each pair slot: z11, z21, z12, z22
-    int pq[PB / 2][2];     // pivot columns of each slot (-1: unused slot)
     int act[PB / 2];       // 1: the slot applies its transformation
-    int inv[PB];           // column -> 2 slot + position (0: p, 1: q)
 };
 
 // The pivot wavefront's part of an inner step: the 2x2 steps of all pairs
@@ -190,18 +246,18 @@ struct InnerStep {
 // pair k = l % NP ((p, p), (q, q), (p, q)); lane k gathers its pair's six
 // entries and runs the FP64 2x2 step.
 template <int PB, int F32, int LOOK>
-__device__ __forceinline__ void inner_pivots(int is, int c, int C, double tol, int crit,
-                                             const double2 (*H)[PB + 1],
+__device__ __forceinline__ void inner_pivots(const InnerOrder &ord, int is, int c, double tol,
+                                             int crit, const double2 (*H)[PB + 1],
                                              const double2 (*S)[PB + 1],
                                              const InnerStep<PB> &prev, InnerStep<PB> &next,
                                              double &cv, double &ct, double &cbig, int *err) {
     constexpr int NP = PB / 2;
     const int l = threadIdx.x;  // lane of wavefront 0
     const int k = l % NP, e = l / NP;
-    const int islots = C / 2;
+    const int nsl = ord.slots();
     int pp = -1, qq = -1;
-    if (k < islots) rr_pair(C, is, k, pp, qq);
-    const bool live = k < islots && qq < c;
+    if (k < nsl) ord.pair(is, k, pp, qq);
+    const bool live = k < nsl && qq < c;
     double2 hv = cmk(0.0, 0.0), sv = cmk(0.0, 0.0);
     if (live && e < 3) {
         const int i = (e == 1) ? qq : pp, j = (e == 0) ? pp : qq;
@@ -210,10 +266,11 @@ __device__ __forceinline__ void inner_pivots(int is, int c, int C, double tol, i
             sv = S[i][j];
         } else {
             const double2 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0);
-            const int ai = prev.inv[i], aj = prev.inv[j];
-            const int ki = ai >> 1, ii = ai & 1, kj = aj >> 1, jj = aj & 1;
-            const int r0 = prev.pq[ki][0], r1 = prev.pq[ki][1];
-            const int c0 = prev.pq[kj][0], c1 = prev.pq[kj][1];
+            int ki, ii, kj, jj, r0, r1, c0, c1;
+            ord.where(is - 1, i, ki, ii);
+            ord.where(is - 1, j, kj, jj);
+            ord.pair(is - 1, ki, r0, r1);
+            ord.pair(is - 1, kj, c0, c1);
             double2 ra, rb, ca, cb;  // column ii of Z'_ki, column jj of Z'_kj
             if (prev.act[ki]) {
                 ra = prev.z[ki][2 * ii];
@@ -254,13 +311,7 @@ __device__ __forceinline__ void inner_pivots(int is, int c, int C, double tol, i
             ct += kind > 0 ? 1.0 : 0.0;
             cbig += kind == kBig ? 1.0 : 0.0;
         }
-        next.pq[k][0] = pp;
-        next.pq[k][1] = qq;
         next.act[k] = kind > 0;
-        if (k < islots) {
-            next.inv[pp] = 2 * k;
-            next.inv[qq] = 2 * k + 1;
-        }
     }
 }
 
@@ -273,10 +324,14 @@ __device__ __forceinline__ void inner_pivots(int is, int c, int C, double tol, i
 // block does Zs <- Zs Z_k' in place.  The pairs of a step are disjoint, so
 // the blocks are independent.  Pair slots whose second column is a bye or
 // padding (>= c) carry the identity; padding entries are zero and stay so.
+// cross_mode = 1: block steps after the first of a sweep visit only the w^2
+// pairs across the two blocks (InnerOrder cross); the first block step of a
+// sweep, where every block appears once, visits all pairs, so that each pair
+// of columns is visited once per sweep.
 template <int PB, int F32>
 __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilDev *PD,
                                                                    const int *pre, int B, int crit,
-                                                                   int step) {
+                                                                   int step, int cross_mode) {
     constexpr int NP = PB / 2;   // pivot pair slots per inner step
     constexpr int NB = NP * NP;  // 2x2 blocks
     __shared__ double2 H[2][PB][PB + 1];
@@ -308,29 +363,34 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
         Zs[i][j] = cmk(i == j ? 1.0 : 0.0, 0.0);
     }
     __syncthreads();
-    const int C = c + (c & 1);
+    InnerOrder ord;
+    ord.cross = cross_mode && step > 0 && ca == NP && cb == NP;
+    ord.C = c + (c & 1);
+    ord.w = NP;
+    const int nsteps = ord.steps(), nsl = ord.slots();
     const double tol = (F32 ? 0x1p-23 : 0x1p-52) * sqrt((double)c);
     double cv = 0.0, ct = 0.0, cbig = 0.0;
     if (tid < kWave)
-        inner_pivots<PB, F32, 0>(0, c, C, tol, crit, H[0], S[0], st[1], st[0], cv, ct, cbig,
+        inner_pivots<PB, F32, 0>(ord, 0, c, tol, crit, H[0], S[0], st[1], st[0], cv, ct, cbig,
                                  &A.st->err);
     __syncthreads();
-    for (int s = 0; s < C - 1; ++s) {
+    for (int s = 0; s < nsteps; ++s) {
         const int cur = s & 1, nxt = cur ^ 1;
         const InnerStep<PB> &now = st[cur];
         if (tid < kWave) {
-            if (s + 1 < C - 1)
-                inner_pivots<PB, F32, 1>(s + 1, c, C, tol, crit, H[cur], S[cur], now, st[nxt], cv,
-                                         ct, cbig, &A.st->err);
+            if (s + 1 < nsteps)
+                inner_pivots<PB, F32, 1>(ord, s + 1, c, tol, crit, H[cur], S[cur], now, st[nxt],
+                                         cv, ct, cbig, &A.st->err);
         } else {
             const double2 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0);
             const int t = tid - kWave;
             const int blk = t < NB ? t : t - NB;
             const int kr = blk % NP, kc = blk / NP;  // row pair, column pair
-            const int p1 = now.pq[kr][0], q1 = now.pq[kr][1];
-            const int p2 = now.pq[kc][0], q2 = now.pq[kc][1];
-            const bool ar = now.act[kr], ac = now.act[kc];
-            if (p1 >= 0 && p2 >= 0) {
+            if (kr < nsl && kc < nsl) {
+                int p1, q1, p2, q2;
+                ord.pair(s, kr, p1, q1);
+                ord.pair(s, kc, p2, q2);
+                const bool ar = now.act[kr], ac = now.act[kc];
                 double2 c11 = one, c21 = zero, c12 = zero, c22 = one;
                 if (ac) {
                     c11 = now.z[kc][0];
@@ -646,13 +706,14 @@ size_t blocked_bytes(int mr, int n, int pr, int w, int mixed) {
 }
 
 using BlkFn = void (*)(const PencilDev *, const int *, int, int);
-using BlkInnerFn = void (*)(const PencilDev *, const int *, int, int, int);
+using BlkInnerFn = void (*)(const PencilDev *, const int *, int, int, int, int);
 
 struct BlockedArg {
     BlkFn gram, upd;
     BlkInnerFn inner;
     int inner_nt;
     int crit;
+    int cross;
 };
 
 static int blocked_step(const BatchCtx &c, const void *arg, int step, hipStream_t s) {
@@ -664,7 +725,7 @@ static int blocked_step(const BatchCtx &c, const void *arg, int step, hipStream_
     prof_after(kProfGram, s, e0, e1);
     prof_before(kProfInner, s, e0, e1);
     hipLaunchKernelGGL(a->inner, dim3(c.total(BatchCtx::kBp)), dim3(a->inner_nt), 0, s, c.dev,
-                       c.pre_of(BatchCtx::kBp), c.B, a->crit, step);
+                       c.pre_of(BatchCtx::kBp), c.B, a->crit, step, a->cross);
     prof_after(kProfInner, s, e0, e1);
     prof_before(kProfUpdate, s, e0, e1);
     hipLaunchKernelGGL(a->upd, dim3(c.total(BatchCtx::kUpd)), dim3(256), 0, s, c.dev,
@@ -674,7 +735,8 @@ static int blocked_step(const BatchCtx &c, const void *arg, int step, hipStream_
     return GHSVD_OK;
 }
 
-int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, hipStream_t s,
+int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, int inner_order,
+                      hipStream_t s,
                       std::vector<SweepResult> &res) {
     int w = 0, steps = 1;
     for (const PencilDev &P : c.host) {
@@ -688,6 +750,7 @@ int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, hip
     }
     BlockedArg a{};
     a.crit = crit;
+    a.cross = inner_order == GHSVD_INNER_CROSS;
     if (w == 16) {
         a.gram = fp32 ? k_blk_gram<float, 32> : k_blk_gram<double, 32>;
         a.inner = fp32 ? k_blk_inner<32, 1> : k_blk_inner<32, 0>;

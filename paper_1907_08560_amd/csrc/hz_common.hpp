@@ -126,7 +126,9 @@ struct Carver {
 // rounded up to a multiple of 8 elements (128 bytes for complex128).
 inline int pad_ld(int rows) { return (rows + 7) / 8 * 8; }
 
-// The round-robin ordering: pair of slot k at step s for N (even) players.
+// The round-robin ordering: pair of slot k at step s for N (even) players
+// (0 <= s < N - 1, 0 <= k < N / 2; the sums below stay within one period,
+// so a conditional subtraction replaces the integer modulo).
 __host__ __device__ __forceinline__ void rr_pair(int N, int s, int k, int &p, int &q) {
     int i, j;
     if (k == 0) {
@@ -134,8 +136,10 @@ __host__ __device__ __forceinline__ void rr_pair(int N, int s, int k, int &p, in
         j = s;
     } else {
         const int M = N - 1;
-        i = (s + k) % M;
-        j = (s - k + M) % M;
+        i = s + k;
+        if (i >= M) i -= M;
+        j = s - k;
+        if (j < 0) j += M;
     }
     p = i < j ? i : j;
     q = i < j ? j : i;

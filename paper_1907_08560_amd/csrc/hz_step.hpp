@@ -182,12 +182,17 @@ __host__ __device__ inline int hz_step(double a, double b, double2 c, double sa,
     return hz_step_m<IeeeMath>(a, b, c, sa, sb, sc, tol, crit_literal, z, f32_big);
 }
 
-// Latency-oriented form of the same 2x2 step for the blocked variant's inner
-// sweeps (device only): every square root that is followed by a division
-// becomes one reciprocal square root (x = x2 / sqrt(x2) = x2 rsqrt(x2)),
-// the criterion (6.12) is compared in squares, and FastMath supplies the
-// reciprocal roots.  "Small" allows cos phi, cos psi within two ulps below
-// one (the roots are accurate to about one ulp, not correctly rounded).
+// The 2x2 step for the latency-bound inner sweeps: the same closed form with
+// FastMath roots, arranged so that the dependency chain holds four levels of
+// reciprocal square roots instead of six.  1/sqrt(s_a), 1/sqrt(s_b) and
+// 1/|s_c| are independent; they give x = |s_pq| = |s_c| d_p d_q, the phase
+// e^{i alpha_1} = s_c / |s_c| and with it the pair (u, v) of (6.5), all
+// without a root of x.  t = sqrt(1 - x^2) and r = sqrt(h^2 + 4 v^2) are then
+// independent, rho follows from both, and cos phi, cos psi come last.
+// "Small" (Section 6.1.7) is cos phi, cos psi within 2^-52 of 1, the
+// resolution of a ~1-ulp root; f32_big classifies after rounding to FP32.
+// Non-finite entries are not screened here: they propagate into the columns,
+// where the FP64 pointwise sweeps that follow report them.
 __device__ inline int hz_step_fast(double a, double b, double2 c, double sa, double sb,
                                    double2 sc, double tol, int crit_literal, Zp &z,
                                    int f32_big) {
@@ -195,18 +200,19 @@ __device__ inline int hz_step_fast(double a, double b, double2 c, double sa, dou
     z.z21 = cmk(0.0, 0.0);
     z.z12 = cmk(0.0, 0.0);
     z.z22 = cmk(1.0, 0.0);
-    // Non-finite entries are not screened here: they propagate into the
-    // columns, where the FP64 pointwise sweeps that follow report them.
     if (!(sa > 0.0) || !(sb > 0.0)) return GHSVD_ERANK;
+    const double sc2 = cnorm2(sc);
+    // level 1: three independent reciprocal roots
     const double dp = FastMath::rsqrt(sa);
     const double dq = FastMath::rsqrt(sb);
+    const double rsc = sc2 > 0.0 ? FastMath::rsqrt(sc2) : 0.0;
     const double dpq = dp * dq;
     const double hpp = a * dp * dp;
     const double hqq = b * dq * dq;
     const double2 hpq = cscale(c, dpq);
-    const double2 spq = cscale(sc, dpq);
     const double h2 = cnorm2(hpq);
-    const double x2 = cnorm2(spq);
+    const double x = sc2 * rsc * dpq;  // |s_pq|
+    const double x2 = x * x;
     if (h2 == 0.0 && x2 == 0.0) return kSkip;
     const double ahp = fabs(hpp), ahq = fabs(hqq);
     double thr2;
@@ -217,21 +223,17 @@ __device__ inline int hz_step_fast(double a, double b, double2 c, double sa, dou
         thr2 = (tol * tol) * (ahp * ahq);
     }
     if (!(h2 >= thr2 || x2 >= tol * tol)) return kSkip;
-    if (!(x2 < 1.0)) return GHSVD_ERANK;
-    double x = 0.0;
-    double2 e1 = cmk(1.0, 0.0);
-    if (x2 > 0.0) {
-        const double rx = FastMath::rsqrt(x2);
-        x = x2 * rx;
-        e1 = cscale(spq, rx);
-    }
-    const double t2 = (1.0 - x) * (1.0 + x);
-    if (!(t2 > 0.0)) return GHSVD_ERANK;
-    const double rt = FastMath::rsqrt(t2);
-    const double t = t2 * rt;
+    if (!(x < 1.0)) return GHSVD_ERANK;
+    const double2 e1 = sc2 > 0.0 ? cscale(sc, rsc) : cmk(1.0, 0.0);
+    // u + i v = conj(e1) h_pq
     const double2 uv = cmulc(e1, hpq);
     const double u = uv.x, v = uv.y;
     const double h = hqq - hpp;
+    const double t2 = (1.0 - x) * (1.0 + x);
+    if (!(t2 > 0.0)) return GHSVD_ERANK;
+    // level 2: t and r
+    const double rt = FastMath::rsqrt(t2);
+    const double t = t2 * rt;
     int kind;
     double2 w11, w21, w12, w22;
     if (h == 0.0 && v == 0.0) {
@@ -253,6 +255,7 @@ __device__ inline int hz_step_fast(double a, double b, double2 c, double sa, dou
         const double sin_g = sigma * twov * ir;
         const double num = sigma * (2.0 * u - (hpp + hqq) * x);
         const double den = t * r;
+        // level 3: rho
         const double n2 = fma(num, num, den * den);
         const double irho = FastMath::rsqrt(n2);
         const double cos_2t = den * irho;
@@ -260,6 +263,7 @@ __device__ inline int hz_step_fast(double a, double b, double2 c, double sa, dou
         const double base = 1.0 + t * cos_g * cos_2t;
         const double ap = 0.5 * (base + x * sin_2t);
         const double am = 0.5 * (base - x * sin_2t);
+        // level 4: cos phi, cos psi
         const double iphi = FastMath::rsqrt(ap);
         const double ipsi = FastMath::rsqrt(am);
         const double cphi = ap * iphi;

@@ -242,8 +242,9 @@ int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *w
         for (int k = 0; k < bc.B; ++k) info[idx[k]].n_plus = np[k];
     }
 
-    // 3. sweep stages: (FP32 warm-up, blocked or pointwise, with its FP64
-    // hand-off) or FP64 blocked, then FP64 pointwise sweeps decide convergence.
+    // 3. sweep stages: the FP32 warm-up (blocked or pointwise) with its FP64
+    // hand-off when mixed; FP64 blocked sweeps for the blocked variant; then
+    // FP64 pointwise sweeps, which decide convergence.
     auto account = [&](const std::vector<SweepResult> &r, int fp32, int blocked) {
         for (int k = 0; k < bc.B; ++k) {
             ghsvd_info &inf = info[idx[k]];
@@ -263,14 +264,15 @@ int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *w
     if (bc.B > 0 && o.precision == GHSVD_MIXED) {
         if ((rc = to_fp32(bc, s))) return rc;
         const int blk = o.variant == GHSVD_BLOCKED;
-        if (blk) rc = run_blocked_stage(bc, 1, o.max_sweeps, o.crit_literal, s, res);
+        if (blk) rc = run_blocked_stage(bc, 1, o.max_sweeps, o.crit_literal, o.inner_order, s, res);
         else rc = run_pointwise_stage(bc, 1, o.max_sweeps, o.crit_literal,
                                       choose_pair_geom(bc.max_rows, o.waves_per_pair), s, res);
         if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) return rc;
         account(res, 1, blk);
         if ((rc = fp32_handoff(bc, s))) return rc;
-    } else if (bc.B > 0 && o.variant == GHSVD_BLOCKED) {
-        rc = run_blocked_stage(bc, 0, o.max_sweeps, o.crit_literal, s, res);
+    }
+    if (bc.B > 0 && o.variant == GHSVD_BLOCKED) {
+        rc = run_blocked_stage(bc, 0, o.max_sweeps, o.crit_literal, o.inner_order, s, res);
         if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) return rc;
         account(res, 0, 1);
         for (int k = 0; k < bc.B; ++k)
@@ -371,6 +373,7 @@ extern "C" void ghsvd_default_options(ghsvd_options *opt) {
     opt->max_sweeps = kDefaultMaxSweeps;
     opt->sort = 1;
     opt->crit_literal = 0;
+    opt->inner_order = GHSVD_INNER_CROSS;
 }
 
 extern "C" const char *ghsvd_status_string(int status) {
@@ -590,13 +593,14 @@ extern "C" int ghsvd_sweeps(int m, int n, int p, double *F, int ldf, int n_plus,
 }
 
 extern "C" int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, double *G,
-                                  int ldg, double *Z, int ldz, int block_width, int nsweeps,
-                                  int crit_literal, long long *counters, int *sweeps_done,
-                                  void *stream) {
+                                  int ldg, double *Z, int ldz, int block_width, int inner_order,
+                                  int nsweeps, int crit_literal, long long *counters,
+                                  int *sweeps_done, void *stream) {
     if (n < 4 || m < 1 || p < 1 || ldf < m || ldg < p || ldz < n || nsweeps < 1 ||
         nsweeps > kMaxHist || n_plus < 0 || n_plus > m || !F || !G || !Z)
         return GHSVD_EINVAL;
     if (block_width != 0 && block_width != 8 && block_width != 16) return GHSVD_EINVAL;
+    if (inner_order != GHSVD_INNER_FULL && inner_order != GHSVD_INNER_CROSS) return GHSVD_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     OwnedBatch ob;
     int rc = make_inplace_batch(ob, m, n, p, F, ldf, G, ldg, Z, ldz, 1,
@@ -604,7 +608,7 @@ extern "C" int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n
     if (rc) return rc;
     hipLaunchKernelGGL(k_set_nplus, dim3(1), dim3(1), 0, s, ob.bc.dev, n_plus);
     std::vector<SweepResult> res;
-    rc = run_blocked_stage(ob.bc, 0, nsweeps, crit_literal, s, res);
+    rc = run_blocked_stage(ob.bc, 0, nsweeps, crit_literal, inner_order, s, res);
     if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) return rc;
     if ((rc = copy_counters(ob.bc, nsweeps, counters, sweeps_done, s))) return rc;
     return res[0].status;

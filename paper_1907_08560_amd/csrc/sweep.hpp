@@ -48,7 +48,8 @@ int run_pointwise_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, P
                         hipStream_t s, std::vector<SweepResult> &res);
 
 // Level-2 blocked sweeps (Section 6.4) for every pencil with n >= 4.
-int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, hipStream_t s,
+int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, int inner_order,
+                      hipStream_t s,
                       std::vector<SweepResult> &res);
 
 // When the environment variable GHSVD_TRACE is set, prints the per-sweep

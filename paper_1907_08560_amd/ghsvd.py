@@ -35,7 +35,7 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("variant", ctypes.c_int), ("reduce", ctypes.c_int),
                 ("block_width", ctypes.c_int), ("waves_per_pair", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("sort", ctypes.c_int),
-                ("crit_literal", ctypes.c_int)]
+                ("crit_literal", ctypes.c_int), ("inner_order", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -74,7 +74,7 @@ _lib.ghsvd_pair_params.restype = _i
 _lib.ghsvd_sweeps.argtypes = [_i, _i, _i, _p, _i, _i, _p, _i, _p, _i, _i, _i, _i, _p,
                               ctypes.POINTER(_i), _p]
 _lib.ghsvd_sweeps.restype = _i
-_lib.ghsvd_block_sweeps.argtypes = [_i, _i, _i, _p, _i, _i, _p, _i, _p, _i, _i, _i, _i, _p,
+_lib.ghsvd_block_sweeps.argtypes = [_i, _i, _i, _p, _i, _i, _p, _i, _p, _i, _i, _i, _i, _i, _p,
                                     ctypes.POINTER(_i), _p]
 _lib.ghsvd_block_sweeps.restype = _i
 _lib.ghsvd_round_robin.argtypes = [_i, _p, _p]
@@ -124,8 +124,12 @@ def _stream_ptr(stream) -> int:
     return s.cuda_stream
 
 
+INNER = {"full": 0, "cross": 1}
+
+
 def options(precision="fp64", variant="pointwise", reduce=True, block_width=0,
-            waves_per_pair=0, max_sweeps=0, sort=True, crit_literal=False) -> Options:
+            waves_per_pair=0, max_sweeps=0, sort=True, crit_literal=False,
+            inner_order="cross") -> Options:
     o = Options()
     _lib.ghsvd_default_options(ctypes.byref(o))
     o.precision = {"fp64": FP64, "mixed": MIXED}[precision]
@@ -137,6 +141,7 @@ def options(precision="fp64", variant="pointwise", reduce=True, block_width=0,
         o.max_sweeps = int(max_sweeps)
     o.sort = int(bool(sort))
     o.crit_literal = int(bool(crit_literal))
+    o.inner_order = INNER[inner_order]
     return o
 
 
@@ -248,7 +253,8 @@ def sweeps(F, n_plus: int, G, Z, nsweeps: int, waves_per_pair=0, crit_literal=0,
     return rc, done.value, cnt.reshape(nsweeps, 3)
 
 
-def block_sweeps(F, n_plus: int, G, Z, nsweeps: int, block_width=0, crit_literal=0, stream=None):
+def block_sweeps(F, n_plus: int, G, Z, nsweeps: int, block_width=0, crit_literal=0,
+                 inner_order="cross", stream=None):
     """In-place Level-2 blocked FP64 sweeps; returns (status, sweeps_done, counters (nsweeps, 3))."""
     m, n = F.shape
     p = G.shape[0]
@@ -256,7 +262,8 @@ def block_sweeps(F, n_plus: int, G, Z, nsweeps: int, block_width=0, crit_literal
     done = ctypes.c_int(0)
     rc = _lib.ghsvd_block_sweeps(m, n, p, F.data_ptr(), _check_fortran(F, "F"), int(n_plus),
                                  G.data_ptr(), _check_fortran(G, "G"), Z.data_ptr(),
-                                 _check_fortran(Z, "Z"), int(block_width), int(nsweeps),
+                                 _check_fortran(Z, "Z"), int(block_width), INNER[inner_order],
+                                 int(nsweeps),
                                  int(crit_literal), cnt.ctypes.data, ctypes.byref(done),
                                  _stream_ptr(stream))
     return rc, done.value, cnt.reshape(nsweeps, 3)

@@ -4,7 +4,9 @@ FP32 warm-up + FP64 finish, against the CPU oracle, through the C ABI.
 The oracle's blocked sweep shortens each block pivot by (J)QR and runs the
 inner sweep one-sidedly; the GPU forms the block pivots with MFMA Grams and
 runs the same 2x2 steps two-sidedly.  Both are the same transformations in
-exact arithmetic, so one block sweep is compared element by element.
+exact arithmetic, so one block sweep is compared element by element, for
+both inner orderings (all pivot pairs, Section 6.4.2; or cross-block pairs
+after the first block step of a sweep).
 """
 import math
 
@@ -24,13 +26,18 @@ def small(seed, n, s_lo, ratio_m=1.5, ratio_p=2.0, plus=0.75, j_identity=False):
     return synth.random_pencil(seed, n, m, int(round(plus * m)), p, s_lo, j_identity=j_identity)
 
 
+INNER = {"full": 0, "cross": 1}
+
+
+@pytest.mark.parametrize("inner", ["full", "cross"])
 @pytest.mark.parametrize("n,w,s_lo", [(96, 8, 1e-3), (96, 16, 1e-3), (70, 16, 1e-2), (41, 8, 1e-2)])
-def test_one_block_sweep_elementwise(oracle, n, w, s_lo):
+def test_one_block_sweep_elementwise(oracle, n, w, s_lo, inner):
     P = small(300 + n + w, n, s_lo)
     F, J, G = to_dev(P)
     Z = ghsvd.to_device_fortran(np.eye(n, dtype=np.complex128))
-    rc, done, cnt = ghsvd.block_sweeps(F, P.m_plus, G, Z, 1, block_width=w)
-    st, Fo, Go, Zo, stats = oracle.hz_block_run(P.F, P.J, P.G, w=w, max_sweeps=1)
+    rc, done, cnt = ghsvd.block_sweeps(F, P.m_plus, G, Z, 1, block_width=w, inner_order=inner)
+    st, Fo, Go, Zo, stats = oracle.hz_block_run(P.F, P.J, P.G, w=w, max_sweeps=1,
+                                                inner_order=INNER[inner])
     assert done == 1 and rc in (0, 1) and st in (0, 1)
     assert cnt[0, 0] == stats[1]
     assert abs(cnt[0, 1] - stats[2]) <= max(2, stats[2] // 100)
@@ -40,23 +47,26 @@ def test_one_block_sweep_elementwise(oracle, n, w, s_lo):
         assert err < 1e-9, err
 
 
-def test_block_sweeps_converge(oracle):
+@pytest.mark.parametrize("inner", ["full", "cross"])
+def test_block_sweeps_converge(oracle, inner):
     P = small(401, 64, 1e-3)
     F, J, G = to_dev(P)
     n = P.n
     Z = ghsvd.to_device_fortran(np.eye(n, dtype=np.complex128))
-    rc, done, cnt = ghsvd.block_sweeps(F, P.m_plus, G, Z, 40, block_width=8)
-    st, Fo, Go, Zo, stats = oracle.hz_block_run(P.F, P.J, P.G, w=8, max_sweeps=40)
+    rc, done, cnt = ghsvd.block_sweeps(F, P.m_plus, G, Z, 40, block_width=8, inner_order=inner)
+    st, Fo, Go, Zo, stats = oracle.hz_block_run(P.F, P.J, P.G, w=8, max_sweeps=40,
+                                                inner_order=INNER[inner])
     assert rc == 0 and st == 0
     assert abs(done - stats[0]) <= 2
     assert cnt[done - 1, 2] == 0
 
 
+@pytest.mark.parametrize("inner", ["full", "cross"])
 @pytest.mark.parametrize("w", [8, 16])
-def test_blocked_solve_workload_one(oracle, w):
+def test_blocked_solve_workload_one(oracle, w, inner):
     P = synth.workload_pencil(1)
     F, J, G = to_dev(P)
-    lam, X, info = ghsvd.solve(F, J, G, variant="blocked", block_width=w)
+    lam, X, info = ghsvd.solve(F, J, G, variant="blocked", block_width=w, inner_order=inner)
     st, lam_o, X_o, _ = oracle.ghsvd(P.F, P.J, P.G)
     assert info["status"] == 0 and st == 0
     assert info["sweeps_blocked"] > 0 and info["sweeps_fp64"] > info["sweeps_blocked"]
