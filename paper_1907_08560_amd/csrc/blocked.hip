@@ -58,7 +58,6 @@ struct Mfma<float> {
 };
 
 constexpr int kGramChunk = 256;  // rows of one Gram partial
-constexpr int kGramSub = 64;     // rows staged in LDS at a time
 constexpr int kUpdRows = 64;     // rows of one update tile
 
 __device__ __forceinline__ int blk_width(int n, int w, int b) {
@@ -71,16 +70,28 @@ __device__ __forceinline__ int blk_col(int w, int a, int b, int ca, int cc) {
     return cc < ca ? a * w + cc : b * w + (cc - ca);
 }
 
+// Partial block-pivot Grams over one 256-row chunk of F (J-weighted) or G:
+// P = X_C^* W X_C with X_C the c pivot columns.  Eight wavefronts each take
+// 32 rows and read them straight into the operand layout of the 16x16x4
+// MFMA (lane i + 16 k holds row k of pivot column i, for the column tiles
+// 0..15 and 16..31): the same register is the A operand (conjugated,
+// weighted) of one tile and the B operand of another.  Only the upper tiles
+// of the Hermitian result are formed; the wavefronts' sums are added in LDS
+// in a fixed order, and the lower tile is written as the conjugate
+// transpose.  Padding columns (>= c) and rows past the end read as zero.
+constexpr int kGramWaves = 8;
+
 template <typename T, int PB>
-__global__ __launch_bounds__(256) void k_blk_gram(const PencilDev *PD, const int *pre, int B, int step) {
+__global__ __launch_bounds__(kWave * kGramWaves) void k_blk_gram(const PencilDev *PD,
+                                                                 const int *pre, int B,
+                                                                 int step) {
     using C2 = typename Mfma<T>::c2;
     using ACC = typename Mfma<T>::acc;
     constexpr bool F32 = sizeof(T) == 4;
-    constexpr int NTD = PB / 16;          // output tiles per dimension
-    constexpr int NT2 = NTD * NTD;        // output tiles
-    constexpr int KSPLIT = 4 / NT2;       // waves sharing one output tile
-    __shared__ C2 tile[kGramSub][PB + 1];
-    __shared__ double2 red[KSPLIT > 1 ? 4 * 256 : 1];
+    constexpr int NTD = PB / 16;              // column tiles
+    constexpr int NT = NTD * (NTD + 1) / 2;   // upper output tiles
+    constexpr int RW = kGramChunk / kGramWaves;  // rows per wavefront
+    __shared__ double2 red[kGramWaves][NT][256];
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev A = PD[pk];
     if (step >= A.nb - 1 || A.st->done) return;
@@ -99,58 +110,74 @@ __global__ __launch_bounds__(256) void k_blk_gram(const PencilDev *PD, const int
     const C2 *X = reinterpret_cast<const C2 *>(
         isF ? (F32 ? (const void *)A.F32 : (const void *)A.Fw)
             : (F32 ? (const void *)A.G32 : (const void *)A.Gw));
-    const int nplus = A.small[1];
+    const int nplus = isF ? A.small[1] : rows;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int t = wv % NT2, ks = wv / NT2;
-    const int ti = t % NTD, tj = t / NTD;
-    ACC acc_re = {0, 0, 0, 0}, acc_im = {0, 0, 0, 0};
-    for (int s0 = r0; s0 < r0 + kGramChunk && s0 < rows; s0 += kGramSub) {
-        for (int idx = tid; idx < kGramSub * PB; idx += 256) {
-            const int cc = idx / kGramSub, rr = idx % kGramSub;
+    const int i16 = lane & 15, kq = lane >> 4;
+    const C2 *col[NTD];
+    bool okc[NTD];
+#pragma unroll
+    for (int t = 0; t < NTD; ++t) {
+        const int cc = t * 16 + i16;
+        okc[t] = cc < c;
+        col[t] = X + (okc[t] ? (size_t)blk_col(A.w, a, b, ca, cc) * ld : 0);
+    }
+    ACC acc_re[NT], acc_im[NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+        acc_re[q] = ACC{0, 0, 0, 0};
+        acc_im[q] = ACC{0, 0, 0, 0};
+    }
+    const int rb = r0 + wv * RW + kq;
+    C2 x[RW / 4][NTD];
+#pragma unroll
+    for (int ks = 0; ks < RW / 4; ++ks) {
+        const int r = rb + 4 * ks;
+#pragma unroll
+        for (int t = 0; t < NTD; ++t) {
             C2 v;
             v.x = 0;
             v.y = 0;
-            if (cc < c && s0 + rr < rows) v = X[(size_t)blk_col(A.w, a, b, ca, cc) * ld + s0 + rr];
-            tile[rr][cc] = v;
+            if (okc[t] && r < rows) v = col[t][r];
+            x[ks][t] = v;
         }
-        __syncthreads();
-        constexpr int KW = kGramSub / KSPLIT;
-        for (int k0 = ks * KW; k0 < ks * KW + KW; k0 += 4) {
-            const int k = k0 + (lane >> 4);
-            const C2 fa = tile[k][ti * 16 + (lane & 15)];
-            C2 fb = tile[k][tj * 16 + (lane & 15)];
-            if (isF && s0 + k >= nplus) {
-                fb.x = -fb.x;
-                fb.y = -fb.y;
-            }
-            // conj(fa) * fb
-            acc_re = Mfma<T>::mma(fa.x, fb.x, acc_re);
-            acc_re = Mfma<T>::mma(fa.y, fb.y, acc_re);
-            acc_im = Mfma<T>::mma(fa.x, fb.y, acc_im);
-            acc_im = Mfma<T>::mma(-fa.y, fb.x, acc_im);
-        }
-        __syncthreads();
     }
-    double2 *P = A.part + ((size_t)bpi * KC + kc) * PB * PB;
-    if constexpr (KSPLIT > 1) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) red[wv * 256 + r * 64 + lane] = cmk((double)acc_re[r], (double)acc_im[r]);
-        __syncthreads();
-        if (wv == 0) {
+    for (int ks = 0; ks < RW / 4; ++ks) {
+        const T wgt = (rb + 4 * ks >= nplus) ? T(-1) : T(1);
+        int q = 0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                double2 sum = red[r * 64 + lane];
-                for (int q = 1; q < KSPLIT; ++q) sum = cadd(sum, red[q * 256 + r * 64 + lane]);
-                const int i = ti * 16 + Mfma<T>::row(lane, r), j = tj * 16 + (lane & 15);
-                P[(size_t)j * PB + i] = sum;
+        for (int ti = 0; ti < NTD; ++ti)
+#pragma unroll
+            for (int tj = ti; tj < NTD; ++tj, ++q) {
+                const T ar = wgt * x[ks][ti].x, ai = wgt * x[ks][ti].y;
+                const T br = x[ks][tj].x, bi = x[ks][tj].y;
+                // conj(a) b
+                acc_re[q] = Mfma<T>::mma(ar, br, acc_re[q]);
+                acc_re[q] = Mfma<T>::mma(ai, bi, acc_re[q]);
+                acc_im[q] = Mfma<T>::mma(ar, bi, acc_im[q]);
+                acc_im[q] = Mfma<T>::mma(-ai, br, acc_im[q]);
             }
-        }
-    } else {
+    }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int i = ti * 16 + Mfma<T>::row(lane, r), j = tj * 16 + (lane & 15);
-            P[(size_t)j * PB + i] = cmk((double)acc_re[r], (double)acc_im[r]);
+    for (int q = 0; q < NT; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            red[wv][q][r * 64 + lane] = cmk((double)acc_re[q][r], (double)acc_im[q][r]);
+    __syncthreads();
+    double2 *P = A.part + ((size_t)bpi * KC + kc) * PB * PB;
+    for (int e = tid; e < NT * 256; e += kWave * kGramWaves) {
+        const int q = e / 256, rl = e % 256, r = rl / 64, ln = rl % 64;
+        double2 sum = red[0][q][rl];
+#pragma unroll
+        for (int w2 = 1; w2 < kGramWaves; ++w2) sum = cadd(sum, red[w2][q][rl]);
+        int ti = 0, tj = q;  // upper tile q -> (ti, tj)
+        if (NTD == 2) {
+            ti = q == 2 ? 1 : 0;
+            tj = q == 0 ? 0 : 1;
         }
+        const int i = ti * 16 + Mfma<T>::row(ln, r), j = tj * 16 + (ln & 15);
+        P[(size_t)j * PB + i] = sum;
+        if (ti != tj) P[(size_t)i * PB + j] = cconj(sum);
     }
 }
 
@@ -469,16 +496,31 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
     }
 }
 
+// F_C <- F_C Z^, G_C <- G_C Z^, Z_C <- Z_C Z^ for one 64-row tile of one
+// block pair, in place (Section 6.4.3), skipped when the inner sweep applied
+// no transformation.  Each wavefront owns a 16-row strip and forms its
+// transpose, D = Z^T X^T, with the 16x16x4 MFMA: lane j + 16 k loads row j of
+// pivot column k of the strip (the B operand; 16 lanes read 16 consecutive
+// rows of one column), the A operand Z^[k][i] comes from LDS, and lane l
+// holds D[i][l % 16] = X Z^ at row l % 16, column i, so 16 lanes store 256
+// contiguous bytes of one column.  Every read of the strip precedes its
+// writes within the wavefront, and strips are disjoint.
 template <typename T, int PB>
-__device__ __forceinline__ void update_tile(const PencilDev &A, int step, int bpi, int t) {
+__global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const int *pre, int B,
+                                                    int step) {
     using C2 = typename Mfma<T>::c2;
     using ACC = typename Mfma<T>::acc;
     constexpr bool F32 = sizeof(T) == 4;
-    constexpr int NTJ = PB / 16;
-    constexpr int NTI = kUpdRows / 16;
-    constexpr int TILES = NTI * NTJ;
-    __shared__ C2 Xs[kUpdRows][PB + 1];
-    __shared__ C2 Zh[PB][PB + 1];
+    constexpr int NTD = PB / 16;  // output column tiles
+    constexpr int KS = PB / 4;    // k-steps
+    __shared__ C2 Zl[PB][PB + 1];
+    const int pk = find_pencil(pre, B, blockIdx.x);
+    const PencilDev A = PD[pk];
+    if (step >= A.nb - 1 || A.st->done) return;
+    const int local = blockIdx.x - pre[pk];
+    const int TT = A.tf + A.tg + A.tz;
+    const int bpi = local / TT;
+    int t = local % TT;
     if (A.ntr[bpi] == 0) return;
     int a, b;
     rr_pair(A.nb, step, bpi, a, b);
@@ -503,76 +545,60 @@ __device__ __forceinline__ void update_tile(const PencilDev &A, int step, int bp
         ld = A.ldz;
         rows = A.n;
     }
-    const int r0 = t * kUpdRows;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     for (int idx = tid; idx < PB * PB; idx += 256) {
-        const int k = idx % PB, j = idx / PB;
         C2 z;
         if constexpr (F32) {
             z = A.zh32[(size_t)bpi * PB * PB + idx];
         } else {
             z = A.zh64[(size_t)bpi * PB * PB + idx];
         }
-        Zh[k][j] = z;
+        Zl[idx % PB][idx / PB] = z;
     }
-    for (int idx = tid; idx < kUpdRows * PB; idx += 256) {
-        const int cc = idx / kUpdRows, rr = idx % kUpdRows;
+    const int j = lane & 15, kq = lane >> 4;
+    const int row = t * kUpdRows + wv * 16 + j;
+    const bool okr = row < rows;
+    C2 xb[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int cc = 4 * ks + kq;
         C2 v;
         v.x = 0;
         v.y = 0;
-        if (cc < c && r0 + rr < rows) v = X[(size_t)blk_col(A.w, a, b, ca, cc) * ld + r0 + rr];
-        Xs[rr][cc] = v;
+        if (okr && cc < c) v = X[(size_t)blk_col(A.w, a, b, ca, cc) * ld + row];
+        xb[ks] = v;
     }
     __syncthreads();
-    ACC out_re[(TILES + 3) / 4], out_im[(TILES + 3) / 4];
+    ACC acc_re[NTD], acc_im[NTD];
 #pragma unroll
-    for (int q = 0; q < (TILES + 3) / 4; ++q) {
-        const int tt = wv + 4 * q;
-        out_re[q] = ACC{0, 0, 0, 0};
-        out_im[q] = ACC{0, 0, 0, 0};
-        if (tt >= TILES) continue;
-        const int ti = tt % NTI, tj = tt / NTI;
-        for (int k0 = 0; k0 < PB; k0 += 4) {
-            const int k = k0 + (lane >> 4);
-            const C2 xa = Xs[ti * 16 + (lane & 15)][k];
-            const C2 zb = Zh[k][tj * 16 + (lane & 15)];
-            out_re[q] = Mfma<T>::mma(xa.x, zb.x, out_re[q]);
-            out_re[q] = Mfma<T>::mma(-xa.y, zb.y, out_re[q]);
-            out_im[q] = Mfma<T>::mma(xa.x, zb.y, out_im[q]);
-            out_im[q] = Mfma<T>::mma(xa.y, zb.x, out_im[q]);
+    for (int ti = 0; ti < NTD; ++ti) {
+        acc_re[ti] = ACC{0, 0, 0, 0};
+        acc_im[ti] = ACC{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int ti = 0; ti < NTD; ++ti) {
+            const C2 z = Zl[4 * ks + kq][ti * 16 + j];
+            // (X Z^) = X_re Z_re - X_im Z_im + i (X_re Z_im + X_im Z_re)
+            acc_re[ti] = Mfma<T>::mma(z.x, xb[ks].x, acc_re[ti]);
+            acc_re[ti] = Mfma<T>::mma(-z.y, xb[ks].y, acc_re[ti]);
+            acc_im[ti] = Mfma<T>::mma(z.y, xb[ks].x, acc_im[ti]);
+            acc_im[ti] = Mfma<T>::mma(z.x, xb[ks].y, acc_im[ti]);
         }
-    }
-    __syncthreads();
+    if (!okr) return;
 #pragma unroll
-    for (int q = 0; q < (TILES + 3) / 4; ++q) {
-        const int tt = wv + 4 * q;
-        if (tt >= TILES) continue;
-        const int ti = tt % NTI, tj = tt / NTI;
+    for (int ti = 0; ti < NTD; ++ti)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            C2 v;
-            v.x = out_re[q][r];
-            v.y = out_im[q][r];
-            Xs[ti * 16 + Mfma<T>::row(lane, r)][tj * 16 + (lane & 15)] = v;
+            const int oc = ti * 16 + Mfma<T>::row(lane, r);
+            if (oc < c) {
+                C2 v;
+                v.x = acc_re[ti][r];
+                v.y = acc_im[ti][r];
+                X[(size_t)blk_col(A.w, a, b, ca, oc) * ld + row] = v;
+            }
         }
-    }
-    __syncthreads();
-    for (int idx = tid; idx < kUpdRows * PB; idx += 256) {
-        const int cc = idx / kUpdRows, rr = idx % kUpdRows;
-        if (cc < c && r0 + rr < rows) X[(size_t)blk_col(A.w, a, b, ca, cc) * ld + r0 + rr] = Xs[rr][cc];
-    }
-}
-
-// F_C <- F_C Z^, G_C <- G_C Z^, Z_C <- Z_C Z^ for one 64-row tile.
-template <typename T, int PB>
-__global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const int *pre, int B,
-                                                    int step) {
-    const int pk = find_pencil(pre, B, blockIdx.x);
-    const PencilDev A = PD[pk];
-    if (step >= A.nb - 1 || A.st->done) return;
-    const int local = blockIdx.x - pre[pk];
-    const int TT = A.tf + A.tg + A.tz;
-    update_tile<T, PB>(A, step, local / TT, local % TT);
 }
 
 // ---------------------------------------------------------------------------
@@ -720,7 +746,8 @@ static int blocked_step(const BatchCtx &c, const void *arg, int step, hipStream_
     const BlockedArg *a = static_cast<const BlockedArg *>(arg);
     hipEvent_t e0, e1;
     prof_before(kProfGram, s, e0, e1);
-    hipLaunchKernelGGL(a->gram, dim3(c.total(BatchCtx::kGram)), dim3(256), 0, s, c.dev,
+    hipLaunchKernelGGL(a->gram, dim3(c.total(BatchCtx::kGram)), dim3(kWave * kGramWaves), 0, s,
+                       c.dev,
                        c.pre_of(BatchCtx::kGram), c.B, step);
     prof_after(kProfGram, s, e0, e1);
     prof_before(kProfInner, s, e0, e1);
