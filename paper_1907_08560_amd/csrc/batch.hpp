@@ -54,7 +54,8 @@ struct PencilDev {
     int N, nslots;    // pointwise round robin: players (n rounded up to even), slots
     int w, nb, nbp;   // blocked: block width, block columns (even), block pairs per step
     int kf, kg;       // blocked: Gram chunks over F rows, over G rows
-    int tf, tg, tz;   // blocked: update tiles over F, G, Z rows
+    int tf, tg, tz;   // blocked: 16-row update strips over F, G, Z
+    int tu;           // blocked: update workgroups per block pair
     int pad0;
     // caller buffers
     const double2 *Fin;

@@ -58,7 +58,6 @@ struct Mfma<float> {
 };
 
 constexpr int kGramChunk = 256;  // rows of one Gram partial
-constexpr int kUpdRows = 64;     // rows of one update tile
 
 __device__ __forceinline__ int blk_width(int n, int w, int b) {
     const int c = n - b * w;
@@ -107,19 +106,19 @@ __global__ __launch_bounds__(kWave * kGramWaves) void k_blk_gram(const PencilDev
     const int r0 = (isF ? kc : kc - A.kf) * kGramChunk;
     const int rows = isF ? A.mr : A.pr;
     const long ld = isF ? A.ldf : A.ldg;
-    const C2 *X = reinterpret_cast<const C2 *>(
+    const GPtr<C2> X(reinterpret_cast<const C2 *>(
         isF ? (F32 ? (const void *)A.F32 : (const void *)A.Fw)
-            : (F32 ? (const void *)A.G32 : (const void *)A.Gw));
+            : (F32 ? (const void *)A.G32 : (const void *)A.Gw)));
     const int nplus = isF ? A.small[1] : rows;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int i16 = lane & 15, kq = lane >> 4;
-    const C2 *col[NTD];
+    GPtr<C2> col[NTD];
     bool okc[NTD];
 #pragma unroll
     for (int t = 0; t < NTD; ++t) {
         const int cc = t * 16 + i16;
         okc[t] = cc < c;
-        col[t] = X + (okc[t] ? (size_t)blk_col(A.w, a, b, ca, cc) * ld : 0);
+        col[t] = X + (okc[t] ? (long)blk_col(A.w, a, b, ca, cc) * ld : 0L);
     }
     ACC acc_re[NT], acc_im[NT];
 #pragma unroll
@@ -132,12 +131,16 @@ __global__ __launch_bounds__(kWave * kGramWaves) void k_blk_gram(const PencilDev
 #pragma unroll
     for (int ks = 0; ks < RW / 4; ++ks) {
         const int r = rb + 4 * ks;
+        // every lane loads (a clamped, in-bounds address, so the value is
+        // finite); padding is zeroed by a 0/1 factor, with no branch
+        const bool okr = r < rows;
+        const int rc = okr ? r : rows - 1;
 #pragma unroll
         for (int t = 0; t < NTD; ++t) {
-            C2 v;
-            v.x = 0;
-            v.y = 0;
-            if (okc[t] && r < rows) v = col[t][r];
+            const T msk = (okc[t] && okr) ? T(1) : T(0);
+            C2 v = col[t].ld(rc);
+            v.x *= msk;
+            v.y *= msk;
             x[ks][t] = v;
         }
     }
@@ -164,7 +167,7 @@ __global__ __launch_bounds__(kWave * kGramWaves) void k_blk_gram(const PencilDev
         for (int r = 0; r < 4; ++r)
             red[wv][q][r * 64 + lane] = cmk((double)acc_re[q][r], (double)acc_im[q][r]);
     __syncthreads();
-    double2 *P = A.part + ((size_t)bpi * KC + kc) * PB * PB;
+    const GPtr<double2> P(A.part + ((size_t)bpi * KC + kc) * PB * PB);
     for (int e = tid; e < NT * 256; e += kWave * kGramWaves) {
         const int q = e / 256, rl = e % 256, r = rl / 64, ln = rl % 64;
         double2 sum = red[0][q][rl];
@@ -176,8 +179,8 @@ __global__ __launch_bounds__(kWave * kGramWaves) void k_blk_gram(const PencilDev
             tj = q == 0 ? 0 : 1;
         }
         const int i = ti * 16 + Mfma<T>::row(ln, r), j = tj * 16 + (ln & 15);
-        P[(size_t)j * PB + i] = sum;
-        if (ti != tj) P[(size_t)i * PB + j] = cconj(sum);
+        P.st((long)j * PB + i, sum);
+        if (ti != tj) P.st((long)i * PB + j, cconj(sum));
     }
 }
 
@@ -272,32 +275,66 @@ struct InnerStep {
 // transformations that touch it.  Lane l forms entry kind e = l / NP of
 // pair k = l % NP ((p, p), (q, q), (p, q)); lane k gathers its pair's six
 // entries and runs the FP64 2x2 step.
+// Look-ahead operands of lane l at inner step is (is >= 1), packed as bytes:
+// x = rows r0, r1 and columns c0, c1 of the 2x2 block of step is - 1 that
+// holds the lane's pivot entry; y = that block's row slot ki and position
+// ii, column slot kj and position jj; y = kNoEntry when the lane forms no
+// entry.  Filled once per launch from the closed-form ordering.
+constexpr unsigned kNoEntry = 0xffffffffu;
+
+template <int PB>
+__device__ __forceinline__ uint2 lookahead_entry(const InnerOrder &ord, int is, int l, int c) {
+    constexpr int NP = PB / 2;
+    const int k = l % NP, e = l / NP;
+    int pp = -1, qq = -1;
+    if (k < ord.slots()) ord.pair(is, k, pp, qq);
+    if (!(k < ord.slots() && qq < c && e < 3)) return make_uint2(0u, kNoEntry);
+    const int i = (e == 1) ? qq : pp, j = (e == 0) ? pp : qq;
+    int ki, ii, kj, jj, r0, r1, c0, c1;
+    ord.where(is - 1, i, ki, ii);
+    ord.where(is - 1, j, kj, jj);
+    ord.pair(is - 1, ki, r0, r1);
+    ord.pair(is - 1, kj, c0, c1);
+    return make_uint2((unsigned)r0 | (unsigned)r1 << 8 | (unsigned)c0 << 16 | (unsigned)c1 << 24,
+                      (unsigned)ki | (unsigned)ii << 8 | (unsigned)kj << 16 | (unsigned)jj << 24);
+}
+
 template <int PB, int F32, int LOOK>
 __device__ __forceinline__ void inner_pivots(const InnerOrder &ord, int is, int c, double tol,
                                              int crit, const double2 (*H)[PB + 1],
                                              const double2 (*S)[PB + 1],
                                              const InnerStep<PB> &prev, InnerStep<PB> &next,
-                                             double &cv, double &ct, double &cbig, int *err) {
+                                             const uint2 *tab, double &cv, double &ct,
+                                             double &cbig, int *err) {
     constexpr int NP = PB / 2;
     const int l = threadIdx.x;  // lane of wavefront 0
     const int k = l % NP, e = l / NP;
-    const int nsl = ord.slots();
+    bool live, mine;
+    uint2 te = make_uint2(0u, kNoEntry);
     int pp = -1, qq = -1;
-    if (k < nsl) ord.pair(is, k, pp, qq);
-    const bool live = k < nsl && qq < c;
+    if (LOOK) {
+        // this lane's entry, and whether pair k is live (its (p,p) entry exists)
+        if (l < 3 * NP) te = tab[l];
+        live = __shfl((int)(te.y != kNoEntry), k, kWave) != 0;
+        mine = te.y != kNoEntry;
+    } else {
+        const int nsl = ord.slots();
+        if (k < nsl) ord.pair(is, k, pp, qq);
+        live = k < nsl && qq < c;
+        mine = live && e < 3;
+    }
     double2 hv = cmk(0.0, 0.0), sv = cmk(0.0, 0.0);
-    if (live && e < 3) {
-        const int i = (e == 1) ? qq : pp, j = (e == 0) ? pp : qq;
+    if (mine) {
         if (!LOOK) {
+            const int i = (e == 1) ? qq : pp, j = (e == 0) ? pp : qq;
             hv = H[i][j];
             sv = S[i][j];
         } else {
             const double2 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0);
-            int ki, ii, kj, jj, r0, r1, c0, c1;
-            ord.where(is - 1, i, ki, ii);
-            ord.where(is - 1, j, kj, jj);
-            ord.pair(is - 1, ki, r0, r1);
-            ord.pair(is - 1, kj, c0, c1);
+            const int r0 = te.x & 0xff, r1 = (te.x >> 8) & 0xff;
+            const int c0 = (te.x >> 16) & 0xff, c1 = te.x >> 24;
+            const int ki = te.y & 0xff, ii = (te.y >> 8) & 0xff;
+            const int kj = (te.y >> 16) & 0xff, jj = te.y >> 24;
             double2 ra, rb, ca, cb;  // column ii of Z'_ki, column jj of Z'_kj
             if (prev.act[ki]) {
                 ra = prev.z[ki][2 * ii];
@@ -365,6 +402,7 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
     __shared__ double2 S[2][PB][PB + 1];
     __shared__ double2 Zs[PB][PB + 1];
     __shared__ InnerStep<PB> st[2];
+    __shared__ uint2 tab[PB][3 * NP];  // look-ahead operands per inner step and lane
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev A = PD[pk];
     if (step >= A.nb - 1 || A.st->done) return;
@@ -378,28 +416,34 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
         if (tid == 0) A.ntr[bpi] = 0;
         return;
     }
-    const int KC = A.kf + A.kg;
-    const double2 *P = A.part + (size_t)bpi * KC * PB * PB;
-    for (int idx = tid; idx < PB * PB; idx += inner_threads<PB>()) {
-        const int i = idx % PB, j = idx / PB;
-        double2 h = cmk(0.0, 0.0), s = cmk(0.0, 0.0);
-        for (int k = 0; k < A.kf; ++k) h = cadd(h, P[(size_t)k * PB * PB + idx]);
-        for (int k = A.kf; k < KC; ++k) s = cadd(s, P[(size_t)k * PB * PB + idx]);
-        H[0][i][j] = h;
-        S[0][i][j] = s;
-        Zs[i][j] = cmk(i == j ? 1.0 : 0.0, 0.0);
-    }
-    __syncthreads();
+    // the latency-critical pivot wavefront issues first
+    if (tid < kWave) __builtin_amdgcn_s_setprio(3);
     InnerOrder ord;
     ord.cross = cross_mode && step > 0 && ca == NP && cb == NP;
     ord.C = c + (c & 1);
     ord.w = NP;
     const int nsteps = ord.steps(), nsl = ord.slots();
+    const int KC = A.kf + A.kg;
+    const GPtr<double2> P(A.part + (size_t)bpi * KC * PB * PB);
+    for (int idx = tid; idx < PB * PB; idx += inner_threads<PB>()) {
+        const int i = idx % PB, j = idx / PB;
+        double2 h = cmk(0.0, 0.0), s = cmk(0.0, 0.0);
+        for (int k = 0; k < A.kf; ++k) h = cadd(h, P.ld((long)k * PB * PB + idx));
+        for (int k = A.kf; k < KC; ++k) s = cadd(s, P.ld((long)k * PB * PB + idx));
+        H[0][i][j] = h;
+        S[0][i][j] = s;
+        Zs[i][j] = cmk(i == j ? 1.0 : 0.0, 0.0);
+    }
+    for (int idx = tid; idx < (nsteps - 1) * 3 * NP; idx += inner_threads<PB>()) {
+        const int is = 1 + idx / (3 * NP), l = idx % (3 * NP);
+        tab[is][l] = lookahead_entry<PB>(ord, is, l, c);
+    }
+    __syncthreads();
     const double tol = (F32 ? 0x1p-23 : 0x1p-52) * sqrt((double)c);
     double cv = 0.0, ct = 0.0, cbig = 0.0;
     if (tid < kWave)
-        inner_pivots<PB, F32, 0>(ord, 0, c, tol, crit, H[0], S[0], st[1], st[0], cv, ct, cbig,
-                                 &A.st->err);
+        inner_pivots<PB, F32, 0>(ord, 0, c, tol, crit, H[0], S[0], st[1], st[0], nullptr, cv,
+                                 ct, cbig, &A.st->err);
     __syncthreads();
     for (int s = 0; s < nsteps; ++s) {
         const int cur = s & 1, nxt = cur ^ 1;
@@ -407,7 +451,7 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
         if (tid < kWave) {
             if (s + 1 < nsteps)
                 inner_pivots<PB, F32, 1>(ord, s + 1, c, tol, crit, H[cur], S[cur], now, st[nxt],
-                                         cv, ct, cbig, &A.st->err);
+                                         tab[s + 1], cv, ct, cbig, &A.st->err);
         } else {
             const double2 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0);
             const int t = tid - kWave;
@@ -474,13 +518,13 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
         }
         __syncthreads();
     }
-    double2 *Z64 = A.zh64 + (size_t)bpi * PB * PB;
-    float2 *Z32 = F32 ? A.zh32 + (size_t)bpi * PB * PB : nullptr;
+    const GPtr<double2> Z64(A.zh64 + (size_t)bpi * PB * PB);
+    const GPtr<float2> Z32(F32 ? A.zh32 + (size_t)bpi * PB * PB : A.zh32);
     for (int idx = tid; idx < PB * PB; idx += inner_threads<PB>()) {
         const int i = idx % PB, j = idx / PB;
         const double2 z = Zs[i][j];
-        Z64[idx] = z;
-        if (Z32) Z32[idx] = make_float2((float)z.x, (float)z.y);
+        Z64.st(idx, z);
+        if (F32) Z32.st(idx, make_float2((float)z.x, (float)z.y));
     }
     if (tid < kWave) {
         cv = wave_sum(cv);
@@ -496,15 +540,48 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
     }
 }
 
-// F_C <- F_C Z^, G_C <- G_C Z^, Z_C <- Z_C Z^ for one 64-row tile of one
-// block pair, in place (Section 6.4.3), skipped when the inner sweep applied
-// no transformation.  Each wavefront owns a 16-row strip and forms its
-// transpose, D = Z^T X^T, with the 16x16x4 MFMA: lane j + 16 k loads row j of
-// pivot column k of the strip (the B operand; 16 lanes read 16 consecutive
-// rows of one column), the A operand Z^[k][i] comes from LDS, and lane l
-// holds D[i][l % 16] = X Z^ at row l % 16, column i, so 16 lanes store 256
-// contiguous bytes of one column.  Every read of the strip precedes its
-// writes within the wavefront, and strips are disjoint.
+// F_C <- F_C Z^, G_C <- G_C Z^, Z_C <- Z_C Z^ for one block pair, in place
+// (Section 6.4.3), skipped when the inner sweep applied no transformation.
+// The rows of F, G and Z form 16-row strips (tf + tg + tz of them); a
+// workgroup's four wavefronts take kUpdStrips strips each, interleaved, and
+// load the next strip while the matrix cores work on the current one.  A
+// wavefront forms the strip's transpose, D = Z^T X^T, with the 16x16x4
+// MFMA: lane j + 16 k loads row j of pivot column k (the B operand; 16
+// lanes read 16 consecutive rows of one column), the A operand Z^[k][i]
+// comes from LDS, and lane l holds D[i][l % 16] = (X Z^)[l % 16][i], so 16
+// lanes store 256 contiguous bytes of one column.  Every read of a strip
+// precedes its writes within the wavefront, and strips are disjoint.
+constexpr int kUpdStrips = 3;
+
+// Matrix, leading dimension and row of lane row j of strip st (F, G, Z
+// strips in that order); ok = 0 past the last row or the last strip.
+template <typename C2>
+__device__ __forceinline__ GPtr<C2> strip_of(const PencilDev &A, int st, int j, long &ld, int &row,
+                                            bool &ok) {
+    constexpr bool F32 = sizeof(C2) == 8;
+    C2 *X;
+    int rows;
+    if (st < A.tf) {
+        X = reinterpret_cast<C2 *>(F32 ? (void *)A.F32 : (void *)A.Fw);
+        ld = A.ldf;
+        rows = A.mr;
+    } else if (st < A.tf + A.tg) {
+        st -= A.tf;
+        X = reinterpret_cast<C2 *>(F32 ? (void *)A.G32 : (void *)A.Gw);
+        ld = A.ldg;
+        rows = A.pr;
+    } else {
+        st -= A.tf + A.tg;
+        X = reinterpret_cast<C2 *>(F32 ? (void *)A.Z32 : (void *)A.Zw);
+        ld = A.ldz;
+        rows = A.n;
+    }
+    row = st * 16 + j;
+    ok = row < rows && st < (A.tf + A.tg + A.tz);
+    if (!ok) row = rows - 1;  // an in-bounds address for the unconditional load
+    return GPtr<C2>(X);
+}
+
 template <typename T, int PB>
 __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const int *pre, int B,
                                                     int step) {
@@ -518,87 +595,111 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
     const PencilDev A = PD[pk];
     if (step >= A.nb - 1 || A.st->done) return;
     const int local = blockIdx.x - pre[pk];
-    const int TT = A.tf + A.tg + A.tz;
-    const int bpi = local / TT;
-    int t = local % TT;
+    const int bpi = local / A.tu, g = local % A.tu;
     if (A.ntr[bpi] == 0) return;
     int a, b;
     rr_pair(A.nb, step, bpi, a, b);
     const int ca = blk_width(A.n, A.w, a), cb = blk_width(A.n, A.w, b);
     const int c = ca + cb;
     if (c < 2) return;
-    C2 *X;
-    long ld;
-    int rows;
-    if (t < A.tf) {
-        X = reinterpret_cast<C2 *>(F32 ? (void *)A.F32 : (void *)A.Fw);
-        ld = A.ldf;
-        rows = A.mr;
-    } else if (t < A.tf + A.tg) {
-        t -= A.tf;
-        X = reinterpret_cast<C2 *>(F32 ? (void *)A.G32 : (void *)A.Gw);
-        ld = A.ldg;
-        rows = A.pr;
-    } else {
-        t -= A.tf + A.tg;
-        X = reinterpret_cast<C2 *>(F32 ? (void *)A.Z32 : (void *)A.Zw);
-        ld = A.ldz;
-        rows = A.n;
-    }
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    for (int idx = tid; idx < PB * PB; idx += 256) {
-        C2 z;
-        if constexpr (F32) {
-            z = A.zh32[(size_t)bpi * PB * PB + idx];
-        } else {
-            z = A.zh64[(size_t)bpi * PB * PB + idx];
-        }
-        Zl[idx % PB][idx / PB] = z;
-    }
     const int j = lane & 15, kq = lane >> 4;
-    const int row = t * kUpdRows + wv * 16 + j;
-    const bool okr = row < rows;
-    C2 xb[KS];
+    const int nstrips = A.tf + A.tg + A.tz;
+    // this lane's global columns of the B operand (pivot column 4 ks + kq)
+    long cofs[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const int cc = 4 * ks + kq;
-        C2 v;
-        v.x = 0;
-        v.y = 0;
-        if (okr && cc < c) v = X[(size_t)blk_col(A.w, a, b, ca, cc) * ld + row];
-        xb[ks] = v;
+        cofs[ks] = cc < c ? (long)blk_col(A.w, a, b, ca, cc) : -1;
+    }
+    C2 xb[KS], xn[KS];
+    const int st0 = g * kUpdStrips * 4 + wv;
+    {
+        long ld;
+        int row;
+        bool ok;
+        const GPtr<C2> X = strip_of<C2>(A, st0 < nstrips ? st0 : 0, j, ld, row, ok);
+        ok = ok && st0 < nstrips;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const T msk = (ok && cofs[ks] >= 0) ? T(1) : T(0);
+            C2 v = X.ld((cofs[ks] >= 0 ? cofs[ks] : 0L) * ld + row);
+            v.x *= msk;
+            v.y *= msk;
+            xb[ks] = v;
+        }
+    }
+    for (int idx = tid; idx < PB * PB; idx += 256) {
+        C2 z;
+        if constexpr (F32) {
+            z = GPtr<float2>(A.zh32).ld((long)bpi * PB * PB + idx);
+        } else {
+            z = GPtr<double2>(A.zh64).ld((long)bpi * PB * PB + idx);
+        }
+        Zl[idx % PB][idx / PB] = z;
     }
     __syncthreads();
-    ACC acc_re[NTD], acc_im[NTD];
 #pragma unroll
-    for (int ti = 0; ti < NTD; ++ti) {
-        acc_re[ti] = ACC{0, 0, 0, 0};
-        acc_im[ti] = ACC{0, 0, 0, 0};
-    }
+    for (int it = 0; it < kUpdStrips; ++it) {
+        const int st = st0 + 4 * it;
+        if (it + 1 < kUpdStrips) {
+            long ld;
+            int row;
+            bool ok;
+            const int sn = st + 4;
+            const GPtr<C2> X = strip_of<C2>(A, sn < nstrips ? sn : 0, j, ld, row, ok);
+            ok = ok && sn < nstrips;
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int ti = 0; ti < NTD; ++ti) {
-            const C2 z = Zl[4 * ks + kq][ti * 16 + j];
-            // (X Z^) = X_re Z_re - X_im Z_im + i (X_re Z_im + X_im Z_re)
-            acc_re[ti] = Mfma<T>::mma(z.x, xb[ks].x, acc_re[ti]);
-            acc_re[ti] = Mfma<T>::mma(-z.y, xb[ks].y, acc_re[ti]);
-            acc_im[ti] = Mfma<T>::mma(z.y, xb[ks].x, acc_im[ti]);
-            acc_im[ti] = Mfma<T>::mma(z.x, xb[ks].y, acc_im[ti]);
-        }
-    if (!okr) return;
-#pragma unroll
-    for (int ti = 0; ti < NTD; ++ti)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int oc = ti * 16 + Mfma<T>::row(lane, r);
-            if (oc < c) {
-                C2 v;
-                v.x = acc_re[ti][r];
-                v.y = acc_im[ti][r];
-                X[(size_t)blk_col(A.w, a, b, ca, oc) * ld + row] = v;
+            for (int ks = 0; ks < KS; ++ks) {
+                const T msk = (ok && cofs[ks] >= 0) ? T(1) : T(0);
+                C2 v = X.ld((cofs[ks] >= 0 ? cofs[ks] : 0L) * ld + row);
+                v.x *= msk;
+                v.y *= msk;
+                xn[ks] = v;
             }
         }
+        ACC acc_re[NTD], acc_im[NTD];
+#pragma unroll
+        for (int ti = 0; ti < NTD; ++ti) {
+            acc_re[ti] = ACC{0, 0, 0, 0};
+            acc_im[ti] = ACC{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int ti = 0; ti < NTD; ++ti) {
+                const C2 z = Zl[4 * ks + kq][ti * 16 + j];
+                // (X Z^) = X_re Z_re - X_im Z_im + i (X_re Z_im + X_im Z_re)
+                acc_re[ti] = Mfma<T>::mma(z.x, xb[ks].x, acc_re[ti]);
+                acc_re[ti] = Mfma<T>::mma(-z.y, xb[ks].y, acc_re[ti]);
+                acc_im[ti] = Mfma<T>::mma(z.y, xb[ks].x, acc_im[ti]);
+                acc_im[ti] = Mfma<T>::mma(z.x, xb[ks].y, acc_im[ti]);
+            }
+        if (st < nstrips) {
+            long ld;
+            int row;
+            bool ok;
+            const GPtr<C2> X = strip_of<C2>(A, st, j, ld, row, ok);
+            if (ok) {
+#pragma unroll
+                for (int ti = 0; ti < NTD; ++ti)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int oc = ti * 16 + Mfma<T>::row(lane, r);
+                        if (oc < c) {
+                            C2 v;
+                            v.x = acc_re[ti][r];
+                            v.y = acc_im[ti][r];
+                            X.st((long)blk_col(A.w, a, b, ca, oc) * ld + row, v);
+                        }
+                    }
+            }
+        }
+        if (it + 1 < kUpdStrips) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) xb[ks] = xn[ks];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -696,9 +797,10 @@ void set_block_geometry(PencilDev &d, int w) {
     d.nbp = d.nb / 2;
     d.kf = (d.mr + kGramChunk - 1) / kGramChunk;
     d.kg = (d.pr + kGramChunk - 1) / kGramChunk;
-    d.tf = (d.mr + kUpdRows - 1) / kUpdRows;
-    d.tg = (d.pr + kUpdRows - 1) / kUpdRows;
-    d.tz = (d.n + kUpdRows - 1) / kUpdRows;
+    d.tf = (d.mr + 15) / 16;
+    d.tg = (d.pr + 15) / 16;
+    d.tz = (d.n + 15) / 16;
+    d.tu = (d.tf + d.tg + d.tz + 4 * kUpdStrips - 1) / (4 * kUpdStrips);
 }
 
 int pick_block_width(int max_n, int requested) {

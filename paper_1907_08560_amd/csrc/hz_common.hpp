@@ -126,6 +126,67 @@ struct Carver {
 // rounded up to a multiple of 8 elements (128 bytes for complex128).
 inline int pad_ld(int rows) { return (rows + 7) / 8 * 8; }
 
+// Global-address-space view of a device array.  Kernels reach the matrices
+// through pointers stored in descriptors, whose address space the compiler
+// cannot see, so plain accesses become flat instructions; those also count
+// against the LDS wait counter, which makes every wait for an LDS or
+// cross-lane result wait for outstanding memory loads as well.  Accesses
+// through GPtr are global (vector-memory) instructions.  Elements move as
+// builtin vectors (the HIP vector types only support the generic address
+// space).
+#define GHSVD_GLOBAL __attribute__((address_space(1)))
+typedef double gvec_d2 __attribute__((ext_vector_type(2)));
+typedef float gvec_f2 __attribute__((ext_vector_type(2)));
+template <typename T>
+struct GVec {
+    using type = T;
+};
+template <>
+struct GVec<double2> {
+    using type = gvec_d2;
+};
+template <>
+struct GVec<float2> {
+    using type = gvec_f2;
+};
+__device__ __forceinline__ double2 gv_from(gvec_d2 v) { return make_double2(v.x, v.y); }
+__device__ __forceinline__ float2 gv_from(gvec_f2 v) { return make_float2(v.x, v.y); }
+template <typename T>
+__device__ __forceinline__ T gv_from(T v) {
+    return v;
+}
+__device__ __forceinline__ gvec_d2 gv_to(double2 t) {
+    gvec_d2 v;
+    v.x = t.x;
+    v.y = t.y;
+    return v;
+}
+__device__ __forceinline__ gvec_f2 gv_to(float2 t) {
+    gvec_f2 v;
+    v.x = t.x;
+    v.y = t.y;
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T gv_to(T t) {
+    return t;
+}
+
+template <typename T>
+struct GPtr {
+    using V = typename GVec<T>::type;
+    GHSVD_GLOBAL V *p = nullptr;
+    GPtr() = default;
+    __device__ explicit GPtr(const T *q) : p((GHSVD_GLOBAL V *)(q)) {}
+    __device__ GPtr operator+(long i) const {
+        GPtr r;
+        r.p = p + i;
+        return r;
+    }
+    __device__ T ld(long i) const { return gv_from(p[i]); }
+    __device__ void st(long i, const T &t) const { p[i] = gv_to(t); }
+};
+
 // The round-robin ordering: pair of slot k at step s for N (even) players
 // (0 <= s < N - 1, 0 <= k < N / 2; the sums below stay within one period,
 // so a conditional subtraction replaces the integer modulo).

@@ -65,15 +65,12 @@ __device__ __forceinline__ void pair_body(const PencilDev &P, int p, int q, int 
     using C2 = typename Cplx<T>::type;
     constexpr bool F32 = sizeof(T) == 4;
     const int tid = threadIdx.x;
-    C2 *F = reinterpret_cast<C2 *>(F32 ? (void *)P.F32 : (void *)P.Fw);
-    C2 *G = reinterpret_cast<C2 *>(F32 ? (void *)P.G32 : (void *)P.Gw);
-    C2 *Z = reinterpret_cast<C2 *>(F32 ? (void *)P.Z32 : (void *)P.Zw);
-    C2 *Fp = F + (size_t)p * P.ldf;
-    C2 *Fq = F + (size_t)q * P.ldf;
-    C2 *Gp = G + (size_t)p * P.ldg;
-    C2 *Gq = G + (size_t)q * P.ldg;
-    C2 *Zp_ = Z + (size_t)p * P.ldz;
-    C2 *Zq = Z + (size_t)q * P.ldz;
+    const GPtr<C2> F(reinterpret_cast<C2 *>(F32 ? (void *)P.F32 : (void *)P.Fw));
+    const GPtr<C2> G(reinterpret_cast<C2 *>(F32 ? (void *)P.G32 : (void *)P.Gw));
+    const GPtr<C2> Z(reinterpret_cast<C2 *>(F32 ? (void *)P.Z32 : (void *)P.Zw));
+    const GPtr<C2> Fp = F + (long)p * P.ldf, Fq = F + (long)q * P.ldf;
+    const GPtr<C2> Gp = G + (long)p * P.ldg, Gq = G + (long)q * P.ldg;
+    const GPtr<C2> Zp_ = Z + (long)p * P.ldz, Zq = Z + (long)q * P.ldz;
     const int m = P.mr, pr = P.pr, nplus = P.small[1], n = P.n;
 
     constexpr int RR = R > 0 ? R : 1;
@@ -84,16 +81,16 @@ __device__ __forceinline__ void pair_body(const PencilDev &P, int p, int q, int 
         for (int r = 0; r < R; ++r) {
             const int i = tid + r * NT;
             if (i < m) {
-                fp[r] = Fp[i];
-                fq[r] = Fq[i];
+                fp[r] = Fp.ld(i);
+                fq[r] = Fq.ld(i);
             }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int i = tid + r * NT;
             if (i < pr) {
-                gp[r] = Gp[i];
-                gq[r] = Gq[i];
+                gp[r] = Gp.ld(i);
+                gq[r] = Gq.ld(i);
             }
         }
 #pragma unroll
@@ -104,8 +101,8 @@ __device__ __forceinline__ void pair_body(const PencilDev &P, int p, int q, int 
         }
     } else {
         for (int i = tid; i < m; i += NT)
-            acc_pair<T, C2>(Fp[i], Fq[i], i < nplus ? T(1) : T(-1), a, b, cr, ci);
-        for (int i = tid; i < pr; i += NT) acc_pair<T, C2>(Gp[i], Gq[i], T(1), sa, sb, sr, si);
+            acc_pair<T, C2>(Fp.ld(i), Fq.ld(i), i < nplus ? T(1) : T(-1), a, b, cr, ci);
+        for (int i = tid; i < pr; i += NT) acc_pair<T, C2>(Gp.ld(i), Gq.ld(i), T(1), sa, sb, sr, si);
     }
 
     __shared__ double red[8 * (NT / kWave)];
@@ -134,30 +131,30 @@ __device__ __forceinline__ void pair_body(const PencilDev &P, int p, int q, int 
         for (int r = 0; r < R; ++r) {
             const int i = tid + r * NT;
             if (i < m) {
-                Fp[i] = upd(fp[r], fq[r], z11, z21);
-                Fq[i] = upd(fp[r], fq[r], z12, z22);
+                Fp.st(i, upd(fp[r], fq[r], z11, z21));
+                Fq.st(i, upd(fp[r], fq[r], z12, z22));
             }
             if (i < pr) {
-                Gp[i] = upd(gp[r], gq[r], z11, z21);
-                Gq[i] = upd(gp[r], gq[r], z12, z22);
+                Gp.st(i, upd(gp[r], gq[r], z11, z21));
+                Gq.st(i, upd(gp[r], gq[r], z12, z22));
             }
         }
     } else {
         for (int i = tid; i < m; i += NT) {
-            const C2 xp = Fp[i], xq = Fq[i];
-            Fp[i] = upd(xp, xq, z11, z21);
-            Fq[i] = upd(xp, xq, z12, z22);
+            const C2 xp = Fp.ld(i), xq = Fq.ld(i);
+            Fp.st(i, upd(xp, xq, z11, z21));
+            Fq.st(i, upd(xp, xq, z12, z22));
         }
         for (int i = tid; i < pr; i += NT) {
-            const C2 xp = Gp[i], xq = Gq[i];
-            Gp[i] = upd(xp, xq, z11, z21);
-            Gq[i] = upd(xp, xq, z12, z22);
+            const C2 xp = Gp.ld(i), xq = Gq.ld(i);
+            Gp.st(i, upd(xp, xq, z11, z21));
+            Gq.st(i, upd(xp, xq, z12, z22));
         }
     }
     for (int i = tid; i < n; i += NT) {
-        const C2 xp = Zp_[i], xq = Zq[i];
-        Zp_[i] = upd(xp, xq, z11, z21);
-        Zq[i] = upd(xp, xq, z12, z22);
+        const C2 xp = Zp_.ld(i), xq = Zq.ld(i);
+        Zp_.st(i, upd(xp, xq, z11, z21));
+        Zq.st(i, upd(xp, xq, z12, z22));
     }
 }
 
@@ -293,7 +290,7 @@ int upload_batch(BatchCtx &c, hipStream_t s) {
     for (int k = 0; k < B; ++k) {
         const PencilDev &P = c.host[k];
         const int w[BatchCtx::kKinds] = {P.nslots, P.n, P.nbp * (P.kf + P.kg), P.nbp,
-                                         P.nbp * (P.tf + P.tg + P.tz), 1};
+                                         P.nbp * P.tu, 1};
         for (int t = 0; t < BatchCtx::kKinds; ++t)
             c.pre[t * (B + 1) + k + 1] = c.pre[t * (B + 1) + k] + w[t];
         if (P.n > c.max_n) c.max_n = P.n;
