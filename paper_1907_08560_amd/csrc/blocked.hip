@@ -428,7 +428,10 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
     for (int idx = tid; idx < PB * PB; idx += inner_threads<PB>()) {
         const int i = idx % PB, j = idx / PB;
         double2 h = cmk(0.0, 0.0), s = cmk(0.0, 0.0);
+        // partials summed in chunk order; unrolled so the loads issue together
+#pragma unroll 4
         for (int k = 0; k < A.kf; ++k) h = cadd(h, P.ld((long)k * PB * PB + idx));
+#pragma unroll 4
         for (int k = A.kf; k < KC; ++k) s = cadd(s, P.ld((long)k * PB * PB + idx));
         H[0][i][j] = h;
         S[0][i][j] = s;
@@ -548,7 +551,8 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
 // wavefront forms the strip's transpose, D = Z^T X^T, with the 16x16x4
 // MFMA: lane j + 16 k loads row j of pivot column k (the B operand; 16
 // lanes read 16 consecutive rows of one column), the A operand Z^[k][i]
-// comes from LDS, and lane l holds D[i][l % 16] = (X Z^)[l % 16][i], so 16
+// is staged once through LDS into registers, and lane l holds
+// D[i][l % 16] = (X Z^)[l % 16][i], so 16
 // lanes store 256 contiguous bytes of one column.  Every read of a strip
 // precedes its writes within the wavefront, and strips are disjoint.
 constexpr int kUpdStrips = 3;
@@ -639,6 +643,12 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
         Zl[idx % PB][idx / PB] = z;
     }
     __syncthreads();
+    // the A operands (Z^[4 ks + kq][16 ti + j]) stay in registers for all strips
+    C2 za[KS][NTD];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int ti = 0; ti < NTD; ++ti) za[ks][ti] = Zl[4 * ks + kq][ti * 16 + j];
 #pragma unroll
     for (int it = 0; it < kUpdStrips; ++it) {
         const int st = st0 + 4 * it;
@@ -668,7 +678,7 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
             for (int ti = 0; ti < NTD; ++ti) {
-                const C2 z = Zl[4 * ks + kq][ti * 16 + j];
+                const C2 z = za[ks][ti];
                 // (X Z^) = X_re Z_re - X_im Z_im + i (X_re Z_im + X_im Z_re)
                 acc_re[ti] = Mfma<T>::mma(z.x, xb[ks].x, acc_re[ti]);
                 acc_re[ti] = Mfma<T>::mma(-z.y, xb[ks].y, acc_re[ti]);
