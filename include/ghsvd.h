@@ -28,7 +28,8 @@
  *  - Return value: 0 success, > 0 warning (outputs valid), < 0 error (device
  *    outputs undefined).  See ghsvd_status.
  *  - The library is thread-safe for calls with distinct workspaces; its only
- *    global state is a mutex-guarded cache of tuned launch parameters.
+ *    global state is a mutex-guarded cache of tuned launch parameters
+ *    (ghsvd_autotune).
  */
 #ifndef GHSVD_H
 #define GHSVD_H
@@ -143,6 +144,32 @@ int ghsvd_solve_batched(int batch, const int *m, const int *n, const int *p,
                         const double *const *G, const int *ldg, double *const *lambda,
                         double *const *X, const int *ldx, void *work, size_t lwork,
                         const ghsvd_options *opt, ghsvd_info *info, void *stream);
+
+/*
+ * Launch tuning for a batch shape (not part of the paper's method: it picks
+ * how the same computation is laid onto the GPU).  Runs the one-time
+ * reduction and one FP64 pointwise sweep on the given pencils for each
+ * wavefronts-per-pair candidate (1, 2, 4, 8), and, for opt->variant ==
+ * GHSVD_BLOCKED, one FP64 blocked sweep for each block width (8, 16) with
+ * the best wavefront count; the sweep stages are timed with HIP events.  The
+ * fastest pair is stored for the shape class (variant, precision, and the
+ * base-2 classes of the batch size, the largest n and the largest swept row
+ * count); later solves of that class with block_width = 0 or waves_per_pair
+ * = 0 use it.  Inputs as ghsvd_solve_batched (device F, J, G; not modified);
+ * work/lwork as there (lwork >= ghsvd_workspace_size_batched with
+ * block_width = 0; NULL work allocates).  Outputs (host, each may be NULL):
+ * *block_width, *waves_per_pair, trial_ms[6] (ms of the pointwise trials
+ * for 1, 2, 4, 8 wavefronts, then of the blocked trials for w = 8, 16; -1
+ * when not run).  Results of a solve depend on its launch parameters only
+ * through rounding.
+ */
+int ghsvd_autotune(int batch, const int *m, const int *n, const int *p, const double *const *F,
+                   const int *ldf, const int8_t *const *J, const double *const *G, const int *ldg,
+                   void *work, size_t lwork, const ghsvd_options *opt, int *block_width,
+                   int *waves_per_pair, float *trial_ms, void *stream);
+
+/* Drops every tuned launch parameter. */
+void ghsvd_autotune_clear(void);
 
 /* ---------------------------------------------------------------------------
  * Component entry points: each runs one stage of the path above, so that a

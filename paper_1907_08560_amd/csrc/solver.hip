@@ -3,6 +3,9 @@
 // launch covering every pencil still active.
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "reduce.hpp"
@@ -154,23 +157,90 @@ static int compact(BatchCtx &c, std::vector<int> &idx, const std::vector<int> &s
     return upload_batch(c, s);
 }
 
+// ---------------------------------------------------------------------------
+// Tuned launch parameters.  ghsvd_autotune times trial sweeps and stores the
+// fastest block width and wavefronts per pair for a shape class (variant,
+// precision, and the base-2 size classes of the batch, the largest order and
+// the largest swept row count); solves that leave these options at 0 use the
+// stored values, else fixed rules.  The cache is the library's only global
+// state and is guarded by a mutex.
+// ---------------------------------------------------------------------------
+namespace {
+struct TuneKey {
+    int variant, precision, bcls, ncls, rcls;
+    bool operator<(const TuneKey &o) const {
+        return std::tie(variant, precision, bcls, ncls, rcls) <
+               std::tie(o.variant, o.precision, o.bcls, o.ncls, o.rcls);
+    }
+};
+struct TuneVal {
+    int w, wpp;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+int log2_class(int x) {
+    int c = 0;
+    while ((1 << c) < x && c < 30) ++c;
+    return c;
+}
+
+TuneKey tune_key(const std::vector<PencilIO> &io, const ghsvd_options &o) {
+    int max_n = 0, max_rows = 0;
+    for (const PencilIO &p : io) {
+        const bool red = o.reduce && (p.m > p.n || p.p > p.n);
+        const int rows = red ? p.n : std::max(p.m, p.p);
+        max_n = std::max(max_n, p.n);
+        max_rows = std::max(max_rows, rows);
+    }
+    return TuneKey{o.variant, o.precision, log2_class((int)io.size()), log2_class(max_n),
+                   log2_class(max_rows)};
+}
+}  // namespace
+
+// Block width and wavefronts per pair for this batch: the options when set,
+// else the tuned values for the shape class, else the fixed rules.
+static void resolve_launch(const std::vector<PencilIO> &io, const ghsvd_options &o, int &w,
+                           int &wpp) {
+    int max_n = 0;
+    for (const PencilIO &p : io) max_n = std::max(max_n, p.n);
+    w = o.block_width;
+    wpp = o.waves_per_pair;
+    if (w == 0 || wpp == 0) {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(tune_key(io, o));
+        if (it != g_tune.end()) {
+            if (w == 0) w = it->second.w;
+            if (wpp == 0) wpp = it->second.wpp;
+        }
+    }
+    w = pick_block_width(max_n, w);
+}
+
+// Workspace bytes: with an automatic block width the larger of the widths'
+// needs, so that a later tuned choice always fits.
 size_t solve_batch_bytes(const std::vector<PencilIO> &io, const ghsvd_options &o) {
     int max_n = 0;
     for (const PencilIO &p : io) max_n = p.n > max_n ? p.n : max_n;
-    const int w = pick_block_width(max_n, o.block_width);
     size_t total = batch_bytes((int)io.size());
-    for (const PencilIO &p : io) total += pencil_bytes(make_plan(p.m, p.n, p.p, o, w));
+    for (const PencilIO &p : io) {
+        size_t need = 0;
+        for (int w : {8, 16}) {
+            if (o.block_width != 0 && o.block_width != w) continue;
+            need = std::max(need, pencil_bytes(make_plan(p.m, p.n, p.p, o, w)));
+        }
+        total += need;
+    }
     return total;
 }
 
 int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *work, size_t lwork,
-                std::vector<ghsvd_info> &info, hipStream_t s) {
+                std::vector<ghsvd_info> &info, hipStream_t s, StageClock *clk) {
     const int B0 = (int)io.size();
     info.assign(B0, ghsvd_info{});
     std::vector<int> status(B0, GHSVD_OK);
-    int max_n = 0;
-    for (const PencilIO &p : io) max_n = p.n > max_n ? p.n : max_n;
-    const int w = pick_block_width(max_n, o.block_width);
+    int w, wpp;
+    resolve_launch(io, o, w, wpp);
     Carver c{reinterpret_cast<char *>(work), 0, lwork};
     BatchCtx bc;
     carve_batch(c, bc, B0);
@@ -266,13 +336,30 @@ int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *w
         const int blk = o.variant == GHSVD_BLOCKED;
         if (blk) rc = run_blocked_stage(bc, 1, o.max_sweeps, o.crit_literal, o.inner_order, s, res);
         else rc = run_pointwise_stage(bc, 1, o.max_sweeps, o.crit_literal,
-                                      choose_pair_geom(bc.max_rows, o.waves_per_pair), s, res);
+                                      choose_pair_geom(bc.max_rows, wpp), s, res);
         if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) return rc;
         account(res, 1, blk);
         if ((rc = fp32_handoff(bc, s))) return rc;
     }
+    // events around the FP64 stages when the tuner times them
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    struct EvGuard {
+        hipEvent_t *e;
+        ~EvGuard() {
+            for (int i = 0; i < 4; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
+        }
+    } evg{ev};
+    if (clk)
+        for (int i = 0; i < 4; ++i) GHSVD_HIP(hipEventCreate(&ev[i]));
     if (bc.B > 0 && o.variant == GHSVD_BLOCKED) {
+        if (clk) GHSVD_HIP(hipEventRecord(ev[0], s));
         rc = run_blocked_stage(bc, 0, o.max_sweeps, o.crit_literal, o.inner_order, s, res);
+        if (clk) {
+            GHSVD_HIP(hipEventRecord(ev[1], s));
+            GHSVD_HIP(hipEventSynchronize(ev[1]));
+            GHSVD_HIP(hipEventElapsedTime(&clk->blocked_ms, ev[0], ev[1]));
+        }
         if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) return rc;
         account(res, 0, 1);
         for (int k = 0; k < bc.B; ++k)
@@ -280,8 +367,14 @@ int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *w
         if ((rc = compact(bc, idx, status, s))) return rc;
     }
     if (bc.B > 0) {
+        if (clk) GHSVD_HIP(hipEventRecord(ev[2], s));
         rc = run_pointwise_stage(bc, 0, o.max_sweeps, o.crit_literal,
-                                 choose_pair_geom(bc.max_rows, o.waves_per_pair), s, res);
+                                 choose_pair_geom(bc.max_rows, wpp), s, res);
+        if (clk) {
+            GHSVD_HIP(hipEventRecord(ev[3], s));
+            GHSVD_HIP(hipEventSynchronize(ev[3]));
+            GHSVD_HIP(hipEventElapsedTime(&clk->pointwise_ms, ev[2], ev[3]));
+        }
         if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) return rc;
         account(res, 0, 0);
         for (int k = 0; k < bc.B; ++k) status[idx[k]] = res[k].status;
@@ -289,6 +382,7 @@ int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *w
     }
 
     // 4. outputs
+    if (clk) return GHSVD_OK;  // timing trial: no outputs
     for (const PencilDev &P : bc.host)
         if ((rc = postprocess(P, o.sort, s))) return rc;
     if (bc.B > 0) {
@@ -612,4 +706,104 @@ extern "C" int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n
     if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) return rc;
     if ((rc = copy_counters(ob.bc, nsweeps, counters, sweeps_done, s))) return rc;
     return res[0].status;
+}
+
+extern "C" int ghsvd_autotune(int batch, const int *m, const int *n, const int *p,
+                              const double *const *F, const int *ldf, const int8_t *const *J,
+                              const double *const *G, const int *ldg, void *work, size_t lwork,
+                              const ghsvd_options *opt, int *block_width, int *waves_per_pair,
+                              float *trial_ms, void *stream) {
+    if (batch < 1 || !m || !n || !p || !F || !ldf || !J || !G || !ldg) return GHSVD_EINVAL;
+    ghsvd_options o;
+    fill_options(opt, o);
+    if (!valid_options(o)) return GHSVD_EINVAL;
+    std::vector<PencilIO> io;
+    int max_n = 0;
+    for (int k = 0; k < batch; ++k) {
+        if (!valid_sizes(m[k], n[k], p[k]) || ldf[k] < m[k] || ldg[k] < p[k] || !F[k] || !J[k] ||
+            !G[k])
+            return GHSVD_EINVAL;
+        io.push_back(PencilIO{m[k], n[k], p[k], reinterpret_cast<const double2 *>(F[k]), ldf[k], J[k],
+                              reinterpret_cast<const double2 *>(G[k]), ldg[k], nullptr, nullptr,
+                              n[k]});
+        max_n = std::max(max_n, n[k]);
+    }
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    ghsvd_options ao = o;
+    ao.block_width = 0;
+    const size_t need = solve_batch_bytes(io, ao);
+    void *own = nullptr;
+    if (!work) {
+        if (hipMalloc(&own, need) != hipSuccess) return GHSVD_EDEVICE;
+        work = own;
+        lwork = need;
+    }
+    struct Free {
+        void *p;
+        hipStream_t s;
+        ~Free() {
+            if (p) {
+                (void)hipStreamSynchronize(s);
+                (void)hipFree(p);
+            }
+        }
+    } fr{own, s};
+    if (lwork < need) return GHSVD_ENOMEM;
+    // one FP64 sweep per candidate on these pencils, timed by stage
+    static const int kWpp[4] = {1, 2, 4, 8};
+    static const int kW[2] = {8, 16};
+    float t[6] = {-1, -1, -1, -1, -1, -1};
+    int best_wpp = 0, best_w = pick_block_width(max_n, 0);
+    float best = 0.0f;
+    for (int i = 0; i < 4; ++i) {
+        ghsvd_options to = o;
+        to.precision = GHSVD_FP64;
+        to.variant = GHSVD_POINTWISE;
+        to.waves_per_pair = kWpp[i];
+        to.max_sweeps = 1;
+        StageClock ck;
+        std::vector<ghsvd_info> inf;
+        const int rc = solve_batch(io, to, work, lwork, inf, s, &ck);
+        if (rc < 0) return rc;
+        t[i] = ck.pointwise_ms;
+        if (best_wpp == 0 || t[i] < best) {
+            best = t[i];
+            best_wpp = kWpp[i];
+        }
+    }
+    if (o.variant == GHSVD_BLOCKED) {
+        best = 0.0f;
+        int bw = 0;
+        for (int j = 0; j < 2; ++j) {
+            ghsvd_options to = o;
+            to.precision = GHSVD_FP64;
+            to.block_width = kW[j];
+            to.waves_per_pair = best_wpp;
+            to.max_sweeps = 1;
+            StageClock ck;
+            std::vector<ghsvd_info> inf;
+            const int rc = solve_batch(io, to, work, lwork, inf, s, &ck);
+            if (rc < 0) return rc;
+            t[4 + j] = ck.blocked_ms;
+            if (bw == 0 || t[4 + j] < best) {
+                best = t[4 + j];
+                bw = kW[j];
+            }
+        }
+        best_w = bw;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune[tune_key(io, o)] = TuneVal{best_w, best_wpp};
+    }
+    if (block_width) *block_width = best_w;
+    if (waves_per_pair) *waves_per_pair = best_wpp;
+    if (trial_ms)
+        for (int i = 0; i < 6; ++i) trial_ms[i] = t[i];
+    return GHSVD_OK;
+}
+
+extern "C" void ghsvd_autotune_clear(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune.clear();
 }

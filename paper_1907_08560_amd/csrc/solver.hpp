@@ -44,10 +44,18 @@ struct PencilIO {
     long ldx;
 };
 
+// Timing of the FP64 sweep stages, for the tuner: when passed to solve_batch,
+// the blocked and pointwise FP64 stages are bracketed by events (ms, 0 when
+// the stage did not run) and the outputs are not formed.
+struct StageClock {
+    float blocked_ms = 0.0f;
+    float pointwise_ms = 0.0f;
+};
+
 // The whole path for a batch: input checks, reduction, sweep stages, outputs.
 // status[k] and info[k] per pencil; returns the worst status.
 int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *work, size_t lwork,
-                std::vector<ghsvd_info> &info, hipStream_t s);
+                std::vector<ghsvd_info> &info, hipStream_t s, StageClock *clk = nullptr);
 size_t solve_batch_bytes(const std::vector<PencilIO> &io, const ghsvd_options &o);
 
 // Blocked and FP32 stages (blocked.hip).

@@ -84,13 +84,19 @@ _lib.ghsvd_profile_enable.restype = None
 _lib.ghsvd_profile_read.argtypes = [_i, ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]
 _lib.ghsvd_profile_read.restype = _i
+_lib.ghsvd_autotune.argtypes = [_i, _p, _p, _p, _p, _p, _p, _p, _p, _p, _sz, ctypes.POINTER(Options),
+                                ctypes.POINTER(_i), ctypes.POINTER(_i), _p, _p]
+_lib.ghsvd_autotune.restype = _i
+_lib.ghsvd_autotune_clear.argtypes = []
+_lib.ghsvd_autotune_clear.restype = None
 _lib.ghsvd_status_string.argtypes = [_i]
 _lib.ghsvd_status_string.restype = ctypes.c_char_p
 
 EXPORTED = ["ghsvd_default_options", "ghsvd_workspace_size", "ghsvd_solve",
             "ghsvd_workspace_size_batched", "ghsvd_solve_batched", "ghsvd_reduce",
             "ghsvd_pair_params", "ghsvd_sweeps", "ghsvd_round_robin", "ghsvd_status_string",
-            "ghsvd_profile_enable", "ghsvd_profile_read", "ghsvd_block_sweeps"]
+            "ghsvd_profile_enable", "ghsvd_profile_read", "ghsvd_block_sweeps",
+            "ghsvd_autotune", "ghsvd_autotune_clear"]
 
 
 class GhsvdError(RuntimeError):
@@ -296,3 +302,39 @@ def profile_read(kind: str = "pair64"):
     if rc < 0:
         raise GhsvdError(rc, "ghsvd_profile_read")
     return ms.value, timed.value, total.value
+
+
+def autotune(Fs, Js, Gs, *, stream=None, **kw):
+    """Times trial sweeps on these pencils and stores the fastest launch
+    parameters for their shape class; returns (block_width, waves_per_pair,
+    trial_ms dict)."""
+    opt = options(**kw)
+    b = len(Fs)
+    m = np.array([F.shape[0] for F in Fs], dtype=np.int32)
+    n = np.array([F.shape[1] for F in Fs], dtype=np.int32)
+    p = np.array([G.shape[0] for G in Gs], dtype=np.int32)
+    ldf = np.array([_check_fortran(F, "F") for F in Fs], dtype=np.int32)
+    ldg = np.array([_check_fortran(G, "G") for G in Gs], dtype=np.int32)
+    fp = np.array([F.data_ptr() for F in Fs], dtype=np.uint64)
+    jp = np.array([J.data_ptr() for J in Js], dtype=np.uint64)
+    gp = np.array([G.data_ptr() for G in Gs], dtype=np.uint64)
+    aopt = options(**{**kw, "block_width": 0})
+    need = int(_lib.ghsvd_workspace_size_batched(b, m.ctypes.data, n.ctypes.data, p.ctypes.data,
+                                                  ctypes.byref(aopt)))
+    work = torch.empty(max(need, 1), dtype=torch.uint8, device=Fs[0].device)
+    w = ctypes.c_int(0)
+    wpp = ctypes.c_int(0)
+    t = np.zeros(6, dtype=np.float32)
+    rc = _lib.ghsvd_autotune(b, m.ctypes.data, n.ctypes.data, p.ctypes.data, fp.ctypes.data,
+                             ldf.ctypes.data, jp.ctypes.data, gp.ctypes.data, ldg.ctypes.data,
+                             work.data_ptr(), work.numel(), ctypes.byref(opt), ctypes.byref(w),
+                             ctypes.byref(wpp), t.ctypes.data, _stream_ptr(stream))
+    if rc < 0:
+        raise GhsvdError(rc, "ghsvd_autotune")
+    trials = {f"pointwise_wpp{k}": float(t[i]) for i, k in enumerate((1, 2, 4, 8))}
+    trials.update({f"blocked_w{k}": float(t[4 + i]) for i, k in enumerate((8, 16))})
+    return w.value, wpp.value, trials
+
+
+def autotune_clear() -> None:
+    _lib.ghsvd_autotune_clear()
