@@ -106,6 +106,12 @@ struct PencilDev {
 };
 
 // Pencil of workgroup `blk` given prefix sums pre[0..B] (pre[0] = 0).
+// Index of workgroup blk within its pencil's range of a launch (pencil 0
+// starts at 0, which saves a memory access in the common one-pencil case).
+__device__ __forceinline__ int pencil_local(const int *pre, int pk, int blk) {
+    return pk ? blk - pre[pk] : blk;
+}
+
 __device__ __forceinline__ int find_pencil(const int *pre, int B, int blk) {
     int lo = 0, hi = B - 1;
     while (lo < hi) {

@@ -82,8 +82,8 @@ constexpr int kGramWaves = 8;
 
 template <typename T, int PB>
 __global__ __launch_bounds__(kWave * kGramWaves) void k_blk_gram(const PencilDev *PD,
-                                                                 const int *pre, int B,
-                                                                 int step) {
+                                                                 const int *pre, const int *flag,
+                                                                 int B, int step) {
     using C2 = typename Mfma<T>::c2;
     using ACC = typename Mfma<T>::acc;
     constexpr bool F32 = sizeof(T) == 4;
@@ -93,8 +93,8 @@ __global__ __launch_bounds__(kWave * kGramWaves) void k_blk_gram(const PencilDev
     __shared__ double2 red[kGramWaves][NT][256];
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev A = PD[pk];
-    if (step >= A.nb - 1 || A.st->done) return;
-    const int local = blockIdx.x - pre[pk];
+    if (step >= A.nb - 1 || flag[pk]) return;
+    const int local = pencil_local(pre, pk, blockIdx.x);
     const int KC = A.kf + A.kg;
     const int bpi = local / KC, kc = local % KC;
     int a, b;
@@ -394,8 +394,9 @@ __device__ __forceinline__ void inner_pivots(const InnerOrder &ord, int is, int 
 // of columns is visited once per sweep.
 template <int PB, int F32>
 __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilDev *PD,
-                                                                   const int *pre, int B, int crit,
-                                                                   int step, int cross_mode) {
+                                                                   const int *pre, const int *flag,
+                                                                   int B, int crit, int step,
+                                                                   int cross_mode) {
     constexpr int NP = PB / 2;   // pivot pair slots per inner step
     constexpr int NB = NP * NP;  // 2x2 blocks
     __shared__ double2 H[2][PB][PB + 1];
@@ -405,8 +406,8 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
     __shared__ uint2 tab[PB][3 * NP];  // look-ahead operands per inner step and lane
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev A = PD[pk];
-    if (step >= A.nb - 1 || A.st->done) return;
-    const int bpi = blockIdx.x - pre[pk];
+    if (step >= A.nb - 1 || flag[pk]) return;
+    const int bpi = pencil_local(pre, pk, blockIdx.x);
     const int tid = threadIdx.x;
     int a, b;
     rr_pair(A.nb, step, bpi, a, b);
@@ -587,8 +588,8 @@ __device__ __forceinline__ GPtr<C2> strip_of(const PencilDev &A, int st, int j, 
 }
 
 template <typename T, int PB>
-__global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const int *pre, int B,
-                                                    int step) {
+__global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const int *pre,
+                                                    const int *flag, int B, int step) {
     using C2 = typename Mfma<T>::c2;
     using ACC = typename Mfma<T>::acc;
     constexpr bool F32 = sizeof(T) == 4;
@@ -597,8 +598,8 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
     __shared__ C2 Zl[PB][PB + 1];
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev A = PD[pk];
-    if (step >= A.nb - 1 || A.st->done) return;
-    const int local = blockIdx.x - pre[pk];
+    if (step >= A.nb - 1 || flag[pk]) return;
+    const int local = pencil_local(pre, pk, blockIdx.x);
     const int bpi = local / A.tu, g = local % A.tu;
     if (A.ntr[bpi] == 0) return;
     int a, b;
@@ -843,8 +844,8 @@ size_t blocked_bytes(int mr, int n, int pr, int w, int mixed) {
     return c.used + 256;
 }
 
-using BlkFn = void (*)(const PencilDev *, const int *, int, int);
-using BlkInnerFn = void (*)(const PencilDev *, const int *, int, int, int, int);
+using BlkFn = void (*)(const PencilDev *, const int *, const int *, int, int);
+using BlkInnerFn = void (*)(const PencilDev *, const int *, const int *, int, int, int, int);
 
 struct BlockedArg {
     BlkFn gram, upd;
@@ -860,15 +861,15 @@ static int blocked_step(const BatchCtx &c, const void *arg, int step, hipStream_
     prof_before(kProfGram, s, e0, e1);
     hipLaunchKernelGGL(a->gram, dim3(c.total(BatchCtx::kGram)), dim3(kWave * kGramWaves), 0, s,
                        c.dev,
-                       c.pre_of(BatchCtx::kGram), c.B, step);
+                       c.pre_of(BatchCtx::kGram), c.flag_dev, c.B, step);
     prof_after(kProfGram, s, e0, e1);
     prof_before(kProfInner, s, e0, e1);
     hipLaunchKernelGGL(a->inner, dim3(c.total(BatchCtx::kBp)), dim3(a->inner_nt), 0, s, c.dev,
-                       c.pre_of(BatchCtx::kBp), c.B, a->crit, step, a->cross);
+                       c.pre_of(BatchCtx::kBp), c.flag_dev, c.B, a->crit, step, a->cross);
     prof_after(kProfInner, s, e0, e1);
     prof_before(kProfUpdate, s, e0, e1);
     hipLaunchKernelGGL(a->upd, dim3(c.total(BatchCtx::kUpd)), dim3(256), 0, s, c.dev,
-                       c.pre_of(BatchCtx::kUpd), c.B, step);
+                       c.pre_of(BatchCtx::kUpd), c.flag_dev, c.B, step);
     prof_after(kProfUpdate, s, e0, e1);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;

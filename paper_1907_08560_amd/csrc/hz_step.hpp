@@ -57,11 +57,14 @@ struct FastMath {
         roots(x, s, rs);
         return s;
     }
+    // 1/sqrt(x) for x > 0: the hardware estimate (about 2^-24 relative) and
+    // one third-order correction, y (1 - e)^(-1/2) ~ y (1 + e/2 + 3 e^2/8)
+    // with e = 1 - x y^2, whose truncation error is near 2^-72; the result is
+    // within about one ulp, four dependent operations after the estimate.
     __device__ static double rsqrt(double x) {
-        double s, rs;
-        roots(x, s, rs);
-        // one more Newton step on the reciprocal root
-        return fma(rs, 0.5 * fma(-x * rs, rs, 1.0), rs);
+        const double y = __builtin_amdgcn_rsq(x);
+        const double e = fma(-x * y, y, 1.0);
+        return fma(y * e, fma(e, 0.375, 0.5), y);
     }
     __device__ static double hypot_(double a, double b) { return sqrt_(fma(a, a, b * b)); }
 };

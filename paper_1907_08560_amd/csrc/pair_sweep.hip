@@ -159,19 +159,19 @@ __device__ __forceinline__ void pair_body(const PencilDev &P, int p, int q, int 
 }
 
 template <typename T, int NT, int R>
-__global__ __launch_bounds__(NT) void k_pair(const PencilDev *PD, const int *pre, int B, int crit,
-                                             int step) {
+__global__ __launch_bounds__(NT) void k_pair(const PencilDev *PD, const int *pre, const int *flag,
+                                             int B, int crit, int step) {
     const int k = find_pencil(pre, B, blockIdx.x);
     const PencilDev P = PD[k];
-    if (step >= P.N - 1 || P.st->done) return;  // surplus step of a smaller pencil, or finished
-    const int slot = blockIdx.x - pre[k];
+    if (step >= P.N - 1 || flag[k]) return;  // surplus step of a smaller pencil, or finished
+    const int slot = pencil_local(pre, k, blockIdx.x);
     int p, q;
     rr_pair(P.N, step, slot, p, q);
     if (q < P.n) pair_body<T, NT, R>(P, p, q, slot, crit);  // else: bye slot of an odd order
 }
 
-__global__ void k_reset_states(const PencilDev *PD, int B, int max_sweeps, int noise_floor,
-                               int blocked) {
+__global__ void k_reset_states(const PencilDev *PD, int *flag, int B, int max_sweeps,
+                               int noise_floor, int blocked) {
     const int k = blockIdx.x;
     if (k >= B) return;
     const PencilDev P = PD[k];
@@ -182,6 +182,7 @@ __global__ void k_reset_states(const PencilDev *PD, int B, int max_sweeps, int n
     if (threadIdx.x == 0) {
         const int skip = blocked ? (P.n < 4 || P.nb < 2) : 0;
         st->done = skip;
+        flag[k] = skip;
         st->converged = skip;
         st->sweeps = 0;
         st->err = 0;
@@ -195,7 +196,8 @@ __global__ void k_reset_states(const PencilDev *PD, int B, int max_sweeps, int n
 // them, and applies the stopping rules (Section 6.1.7: no big transformation
 // in the sweep; Algorithm 2: the sweep cap; the FP32 stage also stops at its
 // noise floor, a sweep with at most one big transformation per 1024 visits).
-__global__ __launch_bounds__(256) void k_end_round(const PencilDev *PD, int B, int blocked) {
+__global__ __launch_bounds__(256) void k_end_round(const PencilDev *PD, int *flag, int B,
+                                                   int blocked) {
     __shared__ double red[3 * 256 / kWave];
     const PencilDev P = PD[blockIdx.x];
     SweepState *st = P.st;
@@ -230,17 +232,15 @@ __global__ __launch_bounds__(256) void k_end_round(const PencilDev *PD, int B, i
         } else if (sw + 1 >= st->max_sweeps) {
             st->done = 1;
         }
+        flag[blockIdx.x] = st->done;
     }
 }
 
-__global__ void k_gather_done(const PencilDev *PD, int B, int *done) {
-    for (int k = threadIdx.x; k < B; k += blockDim.x) done[k] = PD[k].st->done;
-}
 
 // ---------------------------------------------------------------------------
 // Host side.
 // ---------------------------------------------------------------------------
-using PairFn = void (*)(const PencilDev *, const int *, int, int, int);
+using PairFn = void (*)(const PencilDev *, const int *, const int *, int, int, int);
 
 template <typename T>
 static PairFn pick(int nt, int r) {
@@ -376,7 +376,7 @@ static int enqueue_round(const BatchCtx &c, StepFn one_step, const void *arg, in
         const int rc = one_step(c, arg, i, s);
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(k_end_round, dim3(c.B), dim3(256), 0, s, c.dev, c.B, blocked);
+    hipLaunchKernelGGL(k_end_round, dim3(c.B), dim3(256), 0, s, c.dev, c.flag_dev, c.B, blocked);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }
@@ -414,7 +414,7 @@ int drive_stage(const BatchCtx &c, int max_sweeps, int noise_floor, int blocked,
         GHSVD_HIP(hipStreamWaitEvent(rg.gs, rg.ev, 0));
         ss = rg.gs;
     }
-    hipLaunchKernelGGL(k_reset_states, dim3(B), dim3(256), 0, ss, c.dev, B, max_sweeps,
+    hipLaunchKernelGGL(k_reset_states, dim3(B), dim3(256), 0, ss, c.dev, c.flag_dev, B, max_sweeps,
                        noise_floor, blocked);
     GHSVD_HIP(hipGetLastError());
     std::vector<int> done(B, 0);
@@ -425,9 +425,7 @@ int drive_stage(const BatchCtx &c, int max_sweeps, int noise_floor, int blocked,
             const int rc = enqueue_round(c, one_step, arg, steps_per_round, blocked, ss);
             if (rc) return rc;
         }
-        hipLaunchKernelGGL(k_gather_done, dim3(1), dim3(256), 0, ss, c.dev, B, c.done_dev);
-        GHSVD_HIP(hipGetLastError());
-        GHSVD_HIP(hipMemcpyAsync(done.data(), c.done_dev, sizeof(int) * B, hipMemcpyDeviceToHost, ss));
+        GHSVD_HIP(hipMemcpyAsync(done.data(), c.flag_dev, sizeof(int) * B, hipMemcpyDeviceToHost, ss));
         GHSVD_HIP(hipStreamSynchronize(ss));
         bool all = true;
         for (int k = 0; k < B; ++k) all = all && done[k];
@@ -466,7 +464,7 @@ static int pointwise_step(const BatchCtx &c, const void *arg, int step, hipStrea
     hipEvent_t e0, e1;
     prof_before(kind, s, e0, e1);
     hipLaunchKernelGGL(a->fn, dim3(c.total(BatchCtx::kSlots)), dim3(a->g.nt), 0, s, c.dev,
-                       c.pre_of(BatchCtx::kSlots), c.B, a->crit, step);
+                       c.pre_of(BatchCtx::kSlots), c.flag_dev, c.B, a->crit, step);
     prof_after(kind, s, e0, e1);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;

@@ -34,7 +34,9 @@ struct BatchCtx {
     const int *pre_of(int kind) const { return pre_dev + kind * (B + 1); }
     int total(int kind) const { return pre[kind * (B + 1) + B]; }
     int max_n = 0, max_rows = 0;
-    int *done_dev = nullptr;        // device [B] stage flags gathered per round
+    int *done_dev = nullptr;        // device [2 (B + 1)] small per-pencil results for the host
+    int *flag_dev = nullptr;        // device [B] 1: the pencil's sweep stage is done (read by
+                                    // every sweep kernel, written at the end of each round)
 };
 
 // Builds the prefix sums and copies descriptors and sums to the device
