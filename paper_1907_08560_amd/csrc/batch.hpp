@@ -32,18 +32,23 @@ struct SweepState {
 };
 
 // State of the hyperbolic QR of one pencil (the k-loop runs on the device).
+// Two copies, by the parity of the step: a step reads one and its last
+// kernel writes the other, so no kernel reads state it may be overwriting.
 struct JqrState {
     int k;       // first unreduced column (and row)
-    int piv;     // 1 or 2: pivot size chosen for column k
-    int need2;   // Bunch-Kaufman second test required
-    int ii;      // Bunch-Kaufman candidate column
     int status;  // 0 or an error
     int n2x2;    // 2x2 pivots taken
-    int pad[2];
+    int pad;
+};
+
+// Decision of the first Bunch-Kaufman test at the current step (written by
+// the second kernel of the step, read by the third).
+struct JqrDecision {
+    int bi;     // diagonal pivot (logical column) swapped to position k
+    int ii;     // candidate column of the second test
+    int need2;  // the second test is required
+    int pad;
     double lam;  // |h_{k,ii}|
-    double tau[2];
-    double co, si;
-    double2 eph;
 };
 
 struct PencilDev {
@@ -71,16 +76,18 @@ struct PencilDev {
     long ldft;
     double2 *Gt;
     long ldgt;
-    JqrState *jst;
-    double *hd;
+    JqrState *jst;    // [2] by step parity
+    JqrDecision *jdec;
+    double *hd;      // J-norm^2 of each physical column over the unreduced rows
     double2 *hc;
     double *hi;
-    double2 *sbuf;   // 2 m
-    double2 *qv;     // p
-    double *qcoef;
-    int8_t *Jw;
+    int *cpb;        // column map after the diagonal-pivot swap of the current step
+    double2 *rblk;   // rows k, k+1 of each pivot column at the end of its step (2 n)
+    int *pblk;       // first row and size of each column's pivot block (2 n)
+    double2 *qdiag;  // R_kk of the QR of G P2 (n)
+    int8_t *Jw;       // [2 m] by step parity during the reduction; J_sq in the first copy after
     int *rowmap;
-    int *perm;
+    int *perm;        // column map P2 (logical column j is physical column perm[j] of Ft)
     // sweep buffers
     double2 *Fw;
     long ldf;

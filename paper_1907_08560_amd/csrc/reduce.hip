@@ -55,414 +55,624 @@ __device__ __forceinline__ void swap_cols_block(double2 *A, long lda, int m, int
     }
 }
 
-__device__ __forceinline__ bool jqr_active(const JqrState *st, int n) {
-    return st->status == 0 && st->k < n;
+__device__ __forceinline__ bool jqr_active(const JqrState &st, int n) {
+    return st.status == 0 && st.k < n;
 }
 
-// hd[j] = J-norm^2 of column j over rows k..m-1 (first iteration only; later
-// iterations get it from the apply kernel).
-// Batched launches over columns: workgroup -> (pencil, column j) through the
-// prefix sums of the column counts; single-workgroup phases: one workgroup
-// per pencil.  Each kernel reads the pencil's fields below.
+// Batched launches over columns: workgroup -> (pencil, logical column j)
+// through the prefix sums of the column counts.  Columns never move: logical
+// column l of the factorization is physical column perm[l] of Ft (the map
+// is P2), and a step's two swaps only change the map.  State, signature and
+// map are read from the copies of the step's parity `par`.
 #define JQR_PENCIL_COL()                                          \
     const int pk = find_pencil(pre, B, blockIdx.x);                \
     const PencilDev P = PD[pk];                                  \
     if (!P.reduce) return;                                        \
-    double2 *A = P.Ft;                                            \
+    const double2 *A = P.Ft;                                      \
     const long lda = P.ldft;                                      \
     const int m = P.m, n = P.n;                                   \
-    int8_t *J = P.Jw;                                             \
-    JqrState *st = P.jst;                                         \
-    const int j_local = blockIdx.x - pre[pk];                     \
+    const JqrState st = P.jst[par];                               \
+    const int8_t *J = P.Jw + (size_t)par * m;                     \
+    const int j_local = pencil_local(pre, pk, blockIdx.x);        \
     (void)J;                                                      \
     (void)j_local
-#define JQR_PENCIL_ONE()                                          \
-    const PencilDev P = PD[blockIdx.x];                          \
-    if (!P.reduce) return;                                        \
-    double2 *A = P.Ft;                                            \
-    const long lda = P.ldft;                                      \
-    const int m = P.m, n = P.n;                                   \
-    int8_t *J = P.Jw;                                             \
-    JqrState *st = P.jst;                                         \
-    (void)J;                                                      \
-    (void)m
 
-__global__ __launch_bounds__(kGridNT) void k_jqr_colnorms(const PencilDev *PD, const int *pre, int B) {
-    __shared__ double red[kGridNT / kWave];
-    JQR_PENCIL_COL();
-    double *hd = P.hd;
-    if (!jqr_active(st, n)) return;
-    const int k = st->k;
-    const int j = j_local;
-    if (j < k) return;
-    const double h = jnorm_block(A + (size_t)j * lda, J, k, m, red);
-    if (threadIdx.x == 0) hd[j] = h;
+__device__ __forceinline__ const double2 *jcol(const double2 *A, long lda, int c) {
+    return A + (size_t)c * lda;
 }
 
-// Every workgroup finds the diagonal pivot jmax = argmax |hd[j]| (j >= k) and
-// workgroup j computes the J-product of column jmax with column j, stored at
-// the position column j takes after the swap k <-> jmax.
-__global__ __launch_bounds__(kGridNT) void k_jqr_cross(const PencilDev *PD, const int *pre, int B) {
+// Diagonal pivot of step k: the logical column i >= k with the largest
+// |J-norm^2| (the first one on ties), the same in every workgroup.
+__device__ __forceinline__ int jqr_diag_pivot(const double *hd, const int *cp, int k, int n,
+                                              double *rv, int *ri) {
+    double bv = -1.0;
+    int bi = k;
+    for (int i = k + threadIdx.x; i < n; i += blockDim.x) {
+        const double v = fabs(hd[cp[i]]);
+        if (v > bv || (v == bv && i < bi)) {
+            bv = v;
+            bi = i;
+        }
+    }
+    block_argmax(bv, bi, rv, ri);
+    return bi;
+}
+
+// hd[c] = J-norm^2 of every column over rows 0..m-1 (before the first step).
+__global__ __launch_bounds__(kGridNT) void k_jqr_colnorms(const PencilDev *PD, const int *pre, int B,
+                                                          int par) {
+    __shared__ double red[kGridNT / kWave];
+    JQR_PENCIL_COL();
+    if (!jqr_active(st, n)) return;
+    const int c = P.perm[j_local];
+    const double h = jnorm_block(jcol(A, lda, c), J, st.k, m, red);
+    if (threadIdx.x == 0) P.hd[c] = h;
+}
+
+// Step, first kernel: every workgroup finds the diagonal pivot bi, and the
+// workgroup of logical column j computes the J-product of column bi with
+// column j (rows k..m-1), stored at the position column j takes after the
+// swap k <-> bi.
+__global__ __launch_bounds__(kGridNT) void k_jqr_cross(const PencilDev *PD, const int *pre, int B,
+                                                       int par) {
     __shared__ double red[2 * kGridNT / kWave];
     __shared__ double rv[kGridNT / kWave];
     __shared__ int ri[kGridNT / kWave];
     JQR_PENCIL_COL();
-    const double *hd = P.hd;
-    double2 *hc = P.hc;
     if (!jqr_active(st, n)) return;
-    const int k = st->k;
-    const int j = j_local;
+    const int k = st.k, j = j_local;
     if (j < k || k == n - 1) return;
-    double bv = -1.0;
-    int bi = k;
-    for (int i = k + threadIdx.x; i < n; i += blockDim.x) {
-        const double v = fabs(hd[i]);
-        if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
-    }
-    block_argmax(bv, bi, rv, ri);
+    const int *cp = P.perm;
+    const int bi = jqr_diag_pivot(P.hd, cp, k, n, rv, ri);
     if (j == bi) return;
-    const double2 d = jdot_block(A + (size_t)bi * lda, A + (size_t)j * lda, J, k, m, red);
+    const double2 d = jdot_block(jcol(A, lda, cp[bi]), jcol(A, lda, cp[j]), J, k, m, red);
     const int pos = (j == k) ? bi : j;
-    if (threadIdx.x == 0) hc[pos] = d;
+    if (threadIdx.x == 0) P.hc[pos] = d;
 }
 
-// Applies the diagonal pivot swap and the first Bunch-Kaufman test.
-__global__ __launch_bounds__(kOneNT) void k_jqr_decide1(const PencilDev *PD) {
-    __shared__ double rv[kOneNT / kWave];
-    __shared__ int ri[kOneNT / kWave];
-    JQR_PENCIL_ONE();
-    double *hd = P.hd;
-    const double2 *hc = P.hc;
-    int *perm = P.perm;
+// Step, second kernel: every workgroup takes the diagonal pivot swap and the
+// first Bunch-Kaufman test (Section 5.2.1, alpha = (1 + sqrt(17)) / 8) from
+// the first kernel's results; the workgroup of column k records them.  When
+// the second test is needed, workgroup l computes |J-product| of the
+// candidate column ii with column l (post-swap positions).
+__global__ __launch_bounds__(kGridNT) void k_jqr_cross2(const PencilDev *PD, const int *pre, int B,
+                                                        int par) {
+    __shared__ double red[2 * kGridNT / kWave];
+    __shared__ double rv[kGridNT / kWave];
+    __shared__ int ri[kGridNT / kWave];
+    JQR_PENCIL_COL();
     if (!jqr_active(st, n)) return;
-    const int k = st->k;
-    double bv = -1.0;
-    int bi = k;
-    for (int i = k + threadIdx.x; i < n; i += blockDim.x) {
-        const double v = fabs(hd[i]);
-        if (v > bv || (v == bv && i < bi)) { bv = v; bi = i; }
-    }
-    block_argmax(bv, bi, rv, ri);
-    swap_cols_block(A, lda, m, k, bi);
-    // candidate ii = argmax_{j > k} |h_kj| (hc already in post-swap positions)
+    const int k = st.k, j = j_local;
+    if (j < k) return;
+    const int *cp = P.perm;
+    const int bi = jqr_diag_pivot(P.hd, cp, k, n, rv, ri);
+    // candidate ii = argmax_{i > k} |h_ki| (hc holds post-swap positions)
     double cv = -1.0;
     int ci = k + 1;
     for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) {
-        const double v = sqrt(cnorm2(hc[i]));
-        if (v > cv || (v == cv && i < ci)) { cv = v; ci = i; }
+        const double v = sqrt(cnorm2(P.hc[i]));
+        if (v > cv || (v == cv && i < ci)) {
+            cv = v;
+            ci = i;
+        }
     }
     block_argmax(cv, ci, rv, ri);
-    if (threadIdx.x == 0) {
-        if (bi != k) {
-            const int t = perm[k]; perm[k] = perm[bi]; perm[bi] = t;
-            const double h = hd[k]; hd[k] = hd[bi]; hd[bi] = h;
-        }
-        const double alpha = (1.0 + sqrt(17.0)) / 8.0;
-        st->piv = 1;
-        st->need2 = 0;
-        if (k < n - 1) {
-            st->ii = ci;
-            st->lam = cv;
-            if (!(fabs(hd[k]) >= alpha * cv)) st->need2 = 1;
+    const double alpha = (1.0 + sqrt(17.0)) / 8.0;
+    const int cpk = cp[bi];  // physical column at position k after the swap
+    const int need2 = (k < n - 1) && !(fabs(P.hd[cpk]) >= alpha * cv);
+    auto cp1 = [&](int l) { return l == k ? cp[bi] : (l == bi ? cp[k] : cp[l]); };
+    if (j == k) {
+        for (int l = threadIdx.x; l < n; l += blockDim.x) P.cpb[l] = cp1(l);
+        if (threadIdx.x == 0) {
+            JqrDecision d;
+            d.bi = bi;
+            d.ii = ci;
+            d.need2 = need2;
+            d.pad = 0;
+            d.lam = cv;
+            *P.jdec = d;
         }
     }
+    if (!need2 || j == ci) return;
+    const double2 d = jdot_block(jcol(A, lda, cp1(ci)), jcol(A, lda, cp1(j)), J, k, m, red);
+    if (threadIdx.x == 0) P.hi[j] = sqrt(cnorm2(d));
 }
 
-// hi[l] = |J-product of the candidate column ii with column l| (l >= k, l != ii).
-__global__ __launch_bounds__(kGridNT) void k_jqr_cross2(const PencilDev *PD, const int *pre, int B) {
-    __shared__ double red[2 * kGridNT / kWave];
-    JQR_PENCIL_COL();
-    double *hi = P.hi;
-    if (!jqr_active(st, n) || !st->need2) return;
-    const int k = st->k, ii = st->ii;
-    const int l = j_local;
-    if (l < k || l == ii) return;
-    const double2 d = jdot_block(A + (size_t)ii * lda, A + (size_t)l * lda, J, k, m, red);
-    if (threadIdx.x == 0) hi[l] = sqrt(cnorm2(d));
-}
-
-// Second Bunch-Kaufman test, the swaps it implies, and for a 2x2 pivot the
-// Jacobi rotation of the pivot J-Gram applied to columns k, k+1.
-__global__ __launch_bounds__(kOneNT) void k_jqr_decide2(const PencilDev *PD) {
-    __shared__ double red[4 * kOneNT / kWave];
-    __shared__ double rv[kOneNT / kWave];
-    __shared__ int ri[kOneNT / kWave];
-    __shared__ int piv_s, swp_s;
-    JQR_PENCIL_ONE();
-    double *hd = P.hd;
-    const double *hi = P.hi;
-    int *perm = P.perm;
-    if (!jqr_active(st, n) || !st->need2) return;
-    const int k = st->k, ii = st->ii;
-    double sv = -1.0;
-    int si = k;
-    for (int l = k + threadIdx.x; l < n; l += blockDim.x) {
-        if (l == ii) continue;
-        const double v = hi[l];
-        if (v > sv || (v == sv && l < si)) { sv = v; si = l; }
+// A column read through the row swaps of the step: rows a0 <-> b0, then
+// a1 <-> b1 (either may be the identity).  Rows named by a swap are staged
+// in LDS before the column is rewritten in place (sv[0..3] = rows a0, b0,
+// a1, b1 of the column as stored).
+struct SwapView {
+    int a0, b0, a1, b1;
+    __device__ int src(int r) const {
+        // the row whose stored value lands at r after both swaps
+        int q = r;
+        if (q == a1) q = b1;
+        else if (q == b1) q = a1;
+        if (q == a0) q = b0;
+        else if (q == b0) q = a0;
+        return q;
     }
-    block_argmax(sv, si, rv, ri);
-    if (threadIdx.x == 0) {
+    __device__ int src0(int r) const {
+        if (r == a0) return b0;
+        if (r == b0) return a0;
+        return r;
+    }
+};
+
+__device__ __forceinline__ double2 sv_load(const double2 *x, const double2 *stash, const SwapView &v,
+                                           int q) {
+    if (q == v.a0) return stash[0];
+    if (q == v.b0) return stash[1];
+    if (q == v.a1) return stash[2];
+    if (q == v.b1) return stash[3];
+    return x[q];
+}
+
+// Step, third kernel.  Every workgroup takes the second Bunch-Kaufman test,
+// the pivot (1x1: the hyperbolic reflector of the pivot column, Theorem 5.1,
+// with a matching-sign row swapped to the front when needed; 2x2: the
+// Jacobi rotation of the pivot J-Gram, one reflector per pivot column and
+// R^* on the pivot rows), all from the pivot columns as stored; then the
+// workgroup of each trailing column applies the reflector(s) to its column
+// in place and leaves its J-norm^2 over the rows still to reduce in hd.
+// The workgroup of column k writes the next state, map and signature, and
+// the pivot rows; the pivot columns themselves are not rewritten (the final
+// extraction takes their rows from rblk and zeros below them).
+__global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const int *pre, int B,
+                                                      int par) {
+    extern __shared__ int8_t Jl[];  // signature with this step's row swaps
+    __shared__ double red[4 * kGridNT / kWave];
+    __shared__ double rv[kGridNT / kWave];
+    __shared__ int ri[kGridNT / kWave];
+    __shared__ double2 stash[4];
+    const int pk = find_pencil(pre, B, blockIdx.x);
+    const PencilDev P = PD[pk];
+    if (!P.reduce) return;
+    double2 *A = P.Ft;
+    const long lda = P.ldft;
+    const int m = P.m, n = P.n;
+    const JqrState cur = P.jst[par];
+    JqrState *nxt = P.jst + (par ^ 1);
+    const int8_t *Jc = P.Jw + (size_t)par * m;
+    int8_t *Jn = P.Jw + (size_t)(par ^ 1) * m;
+    const int j = pencil_local(pre, pk, blockIdx.x);
+    const int tid = threadIdx.x;
+    if (!jqr_active(cur, n)) {
+        if (j == 0) {  // carry the state to the next parity
+            for (int r = tid; r < m; r += blockDim.x) Jn[r] = Jc[r];
+            if (tid == 0) *nxt = cur;
+        }
+        return;
+    }
+    const int k = cur.k;
+    if (j < k) return;
+    const bool desig = j == k;
+    const JqrDecision dec = *P.jdec;
+    const int *cpb = P.cpb;
+    // second Bunch-Kaufman test
+    int piv = 1, swp = -1;
+    const int ii = dec.ii;
+    if (dec.need2) {
+        double sv = -1.0;
+        int si = k;
+        for (int l = k + tid; l < n; l += blockDim.x) {
+            if (l == ii) continue;
+            const double v = P.hi[l];
+            if (v > sv || (v == sv && l < si)) {
+                sv = v;
+                si = l;
+            }
+        }
+        block_argmax(sv, si, rv, ri);
         const double alpha = (1.0 + sqrt(17.0)) / 8.0;
-        const double lam = st->lam;
-        int piv = 1, swp = -1;
-        if (fabs(hd[k]) * sv >= alpha * lam * lam) {
+        const double lam = dec.lam;
+        if (fabs(P.hd[cpb[k]]) * sv >= alpha * lam * lam) {
             piv = 1;
-        } else if (fabs(hd[ii]) >= alpha * sv) {
+        } else if (fabs(P.hd[cpb[ii]]) >= alpha * sv) {
             piv = 1;
             swp = k;
         } else {
             piv = 2;
             if (ii != k + 1) swp = k + 1;
         }
+    }
+    auto cp2 = [&](int l) {
+        int q = l;
         if (swp >= 0) {
-            const int t = perm[swp]; perm[swp] = perm[ii]; perm[ii] = t;
-            const double h = hd[swp]; hd[swp] = hd[ii]; hd[ii] = h;
+            if (l == swp) q = ii;
+            else if (l == ii) q = swp;
         }
-        piv_s = piv;
-        swp_s = swp;
-        st->piv = piv;
-    }
+        return cpb[q];
+    };
+    if (j > k && j < k + piv) return;  // the second column of a 2x2 pivot
+    for (int r = k + tid; r < m; r += blockDim.x) Jl[r] = Jc[r];
     __syncthreads();
-    if (swp_s >= 0) swap_cols_block(A, lda, m, swp_s, ii);
-    if (piv_s != 2) return;
-    __syncthreads();
-    // 2x2 pivot: J-Gram of columns k, k+1 over rows k..m-1.
-    double2 *x = A + (size_t)k * lda;
-    double2 *y = A + (size_t)(k + 1) * lda;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int r = k + threadIdx.x; r < m; r += blockDim.x) {
-        const double s = jsign(J, r);
-        const double2 a = x[r], b = y[r];
-        v[0] += s * cnorm2(a);
-        v[1] += s * cnorm2(b);
-        v[2] += s * (a.x * b.x + a.y * b.y);
-        v[3] += s * (a.x * b.y - a.y * b.x);
-    }
-    block_sum<4>(v, red);
-    const double h11 = v[0], h22 = v[1];
-    const double ah = sqrt(v[2] * v[2] + v[3] * v[3]);
+    const double2 *xa = jcol(A, lda, cp2(k));
+    const double2 *xb = piv == 2 ? jcol(A, lda, cp2(k + 1)) : xa;
+    int status = 0;
+    // ---- the pivot, evaluated in every workgroup ----
+    // 2x2: rotation of the pivot J-Gram over rows k..m-1
     double co = 1.0, sn = 0.0;
-    double2 e = cmk(1.0, 0.0);
-    if (ah > 0.0) {
-        e = cmk(v[2] / ah, v[3] / ah);
-        const double tt = (h22 - h11) / (2.0 * ah);
-        const double tn = (tt >= 0.0 ? 1.0 : -1.0) / (fabs(tt) + sqrt(1.0 + tt * tt));
-        co = 1.0 / sqrt(1.0 + tn * tn);
-        sn = tn * co;
+    double2 eph = cmk(1.0, 0.0);
+    if (piv == 2) {
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int r = k + tid; r < m; r += blockDim.x) {
+            const double s = (double)Jl[r];
+            const double2 a = xa[r], b = xb[r];
+            v[0] += s * cnorm2(a);
+            v[1] += s * cnorm2(b);
+            v[2] += s * (a.x * b.x + a.y * b.y);
+            v[3] += s * (a.x * b.y - a.y * b.x);
+        }
+        block_sum<4>(v, red);
+        const double h11 = v[0], h22 = v[1];
+        const double ah = sqrt(v[2] * v[2] + v[3] * v[3]);
+        if (ah > 0.0) {
+            eph = cmk(v[2] / ah, v[3] / ah);
+            const double tt = (h22 - h11) / (2.0 * ah);
+            const double tn = (tt >= 0.0 ? 1.0 : -1.0) / (fabs(tt) + sqrt(1.0 + tt * tt));
+            co = 1.0 / sqrt(1.0 + tn * tn);
+            sn = tn * co;
+        }
     }
-    // [x, y] <- [x, y] R, R = [[co, e sn], [-conj(e) sn, co]]
-    for (int r = k + threadIdx.x; r < m; r += blockDim.x) {
-        const double2 a = x[r], b = y[r];
-        const double2 ecb = cmulc(e, b);  // conj(e) * b
-        const double2 eb = cmul(e, a);
-        x[r] = csub(cscale(a, co), cscale(ecb, sn));
-        y[r] = cadd(cscale(eb, sn), cscale(b, co));
+    // rotated pivot columns at a stored row q (piv == 1: the column itself)
+    auto pa = [&](int q) {
+        const double2 a = xa[q];
+        if (piv != 2) return a;
+        const double2 b = xb[q];
+        return csub(cscale(a, co), cscale(cmulc(eph, b), sn));
+    };
+    auto pb = [&](int q) {
+        const double2 a = xa[q], b = xb[q];
+        return cadd(cscale(cmul(eph, a), sn), cscale(b, co));
+    };
+    // reflector 0 on the first pivot column, rows k..m-1
+    SwapView sw{k, k, k, k};
+    double h0;
+    {
+        double v[1] = {0.0};
+        for (int r = k + tid; r < m; r += blockDim.x) v[0] += (double)Jl[r] * cnorm2(pa(r));
+        block_sum<1>(v, red);
+        h0 = v[0];
     }
-    if (threadIdx.x == 0) {
-        st->co = co;
-        st->si = sn;
-        st->eph = e;
-    }
-}
-
-// Builds the hyperbolic reflector for column c = k + which, rows r0 = c..m-1.
-__global__ __launch_bounds__(kOneNT) void k_jqr_reflect(const PencilDev *PD, int which) {
-    __shared__ double red[kOneNT / kWave];
-    __shared__ double rv[kOneNT / kWave];
-    __shared__ int ri[kOneNT / kWave];
-    JQR_PENCIL_ONE();
-    double2 *sbuf = P.sbuf;
-    if (!jqr_active(st, n)) return;
-    if (which == 1 && st->piv != 2) return;
-    const int c = st->k + which;
-    const int r0 = c;
-    double2 *x = A + (size_t)c * lda;
-    const double h = jnorm_block(x, J, r0, m, red);
-    if (!isfinite(h) || h == 0.0) {
-        if (threadIdx.x == 0) st->status = isfinite(h) ? GHSVD_ERANK : GHSVD_ENONFINITE;
-        return;
-    }
-    const int8_t sg = h > 0.0 ? 1 : -1;
-    if (J[r0] != sg) {
-        // the matching-sign row with the largest |f_i| comes to the front
+    if (!isfinite(h0) || h0 == 0.0) status = isfinite(h0) ? GHSVD_ERANK : GHSVD_ENONFINITE;
+    int8_t sg0 = h0 > 0.0 ? 1 : -1;
+    if (status == 0 && Jl[k] != sg0) {
         double bv = -1.0;
         int bi = -1;
-        for (int r = r0 + threadIdx.x; r < m; r += blockDim.x) {
-            if (J[r] == sg) {
-                const double v = cnorm2(x[r]);
-                if (v > bv || (v == bv && (bi < 0 || r < bi))) { bv = v; bi = r; }
+        for (int r = k + tid; r < m; r += blockDim.x) {
+            if (Jl[r] == sg0) {
+                const double v = cnorm2(pa(r));
+                if (v > bv || (v == bv && (bi < 0 || r < bi))) {
+                    bv = v;
+                    bi = r;
+                }
             }
         }
         if (bi < 0) bi = 0x7fffffff;
         block_argmax(bv, bi, rv, ri);
-        if (bi < r0 || bi >= m) {
-            if (threadIdx.x == 0) st->status = GHSVD_ERANK;
-            return;
+        if (bi < k || bi >= m) status = GHSVD_ERANK;
+        else sw.b0 = bi;
+    }
+    double2 s0k = cmk(0.0, 0.0), r0k = cmk(0.0, 0.0);
+    double tau0 = 0.0;
+    if (status == 0) {
+        if (sw.b0 != k) {
+            __syncthreads();
+            if (tid == 0) {
+                Jl[sw.b0] = Jl[k];
+                Jl[k] = sg0;
+            }
+            __syncthreads();
         }
-        for (int j = threadIdx.x; j < n; j += blockDim.x) {
-            double2 *col = A + (size_t)j * lda;
-            const double2 t = col[r0];
-            col[r0] = col[bi];
-            col[bi] = t;
+        const double2 f11 = pa(sw.b0);
+        const double af = sqrt(cnorm2(f11));
+        const double2 e = af > 0.0 ? cmk(f11.x / af, f11.y / af) : cmk(1.0, 0.0);
+        const double rr = sqrt(fabs(h0));
+        s0k = cscale(e, af + rr);
+        r0k = cscale(e, -rr);
+        tau0 = -1.0 / (h0 + rr * af * (double)sg0);
+    }
+    // s0 at row r >= k (rows of the swapped view)
+    auto s0 = [&](int r) { return r == k ? s0k : pa(sw.src0(r)); };
+    // 2x2: reflector 0 applied to the second pivot column, then reflector 1
+    double2 w0b = cmk(0.0, 0.0), s1k = cmk(0.0, 0.0), r1k = cmk(0.0, 0.0), ybk = cmk(0.0, 0.0);
+    double tau1 = 0.0;
+    auto pb1 = [&](int r) {  // second pivot column after reflector 0, row r >= k
+        return cadd(pb(sw.src0(r)), cmul(s0(r), cscale(w0b, tau0)));
+    };
+    if (piv == 2 && status == 0) {
+        {
+            double v[2] = {0.0, 0.0};
+            for (int r = k + tid; r < m; r += blockDim.x) {
+                const double s = (double)Jl[r];
+                const double2 a = s0(r), b = pb(sw.src0(r));
+                v[0] += s * (a.x * b.x + a.y * b.y);
+                v[1] += s * (a.x * b.y - a.y * b.x);
+            }
+            block_sum<2>(v, red);
+            w0b = cmk(v[0], v[1]);
         }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            J[bi] = J[r0];
-            J[r0] = sg;
+        double h1;
+        {
+            double v[1] = {0.0};
+            for (int r = k + 1 + tid; r < m; r += blockDim.x) v[0] += (double)Jl[r] * cnorm2(pb1(r));
+            block_sum<1>(v, red);
+            h1 = v[0];
         }
+        if (!isfinite(h1) || h1 == 0.0) status = isfinite(h1) ? GHSVD_ERANK : GHSVD_ENONFINITE;
+        const int8_t sg1 = h1 > 0.0 ? 1 : -1;
+        sw.a1 = sw.b1 = k + 1;
+        if (status == 0 && Jl[k + 1] != sg1) {
+            double bv = -1.0;
+            int bi = -1;
+            for (int r = k + 1 + tid; r < m; r += blockDim.x) {
+                if (Jl[r] == sg1) {
+                    const double v = cnorm2(pb1(r));
+                    if (v > bv || (v == bv && (bi < 0 || r < bi))) {
+                        bv = v;
+                        bi = r;
+                    }
+                }
+            }
+            if (bi < 0) bi = 0x7fffffff;
+            block_argmax(bv, bi, rv, ri);
+            if (bi < k + 1 || bi >= m) status = GHSVD_ERANK;
+            else sw.b1 = bi;
+        }
+        if (status == 0) {
+            if (sw.b1 != k + 1) {
+                __syncthreads();
+                if (tid == 0) {
+                    Jl[sw.b1] = Jl[k + 1];
+                    Jl[k + 1] = sg1;
+                }
+                __syncthreads();
+            }
+            const double2 f11 = pb1(sw.b1);
+            const double af = sqrt(cnorm2(f11));
+            const double2 e = af > 0.0 ? cmk(f11.x / af, f11.y / af) : cmk(1.0, 0.0);
+            const double rr = sqrt(fabs(h1));
+            s1k = cscale(e, af + rr);
+            r1k = cscale(e, -rr);
+            tau1 = -1.0 / (h1 + rr * af * (double)sg1);
+            ybk = pb1(k);
+        }
+    }
+    if (status != 0) {
+        if (desig) {
+            for (int r = tid; r < m; r += blockDim.x) Jn[r] = Jc[r];
+            if (tid == 0) {
+                JqrState t = cur;
+                t.status = status;
+                *nxt = t;
+            }
+        }
+        return;
+    }
+    auto s1 = [&](int r) {  // reflector 1 at row r >= k + 1
+        if (r == k + 1) return s1k;
+        const int q = (r == sw.b1) ? k + 1 : r;  // rows k+1 <-> b1 of the view
+        return pb1(q);
+    };
+    if (desig) {
+        // next state, map, signature, pivot rows
+        for (int l = tid; l < n; l += blockDim.x) P.perm[l] = cp2(l);
+        for (int r = tid; r < m; r += blockDim.x) Jn[r] = r < k ? Jc[r] : Jl[r];
+        if (tid == 0) {
+            if (piv == 1) {
+                P.rblk[2 * k] = r0k;
+                P.rblk[2 * k + 1] = cmk(0.0, 0.0);
+                P.pblk[2 * k] = k;
+                P.pblk[2 * k + 1] = 1;
+            } else {
+                // rows k, k+1 of the two pivot columns, then R^* (2x2 URV step)
+                const double2 xk = r0k, xk1 = cmk(0.0, 0.0), yk = ybk, yk1 = r1k;
+                const double2 a0 = xk, b0 = yk, a1 = xk1, b1 = yk1;
+                P.rblk[2 * k] = cadd(cscale(a0, co), cscale(cmulc(eph, b0), sn));
+                P.rblk[2 * (k + 1)] = csub(cscale(b0, co), cscale(cmul(eph, a0), sn));
+                P.rblk[2 * k + 1] = cadd(cscale(a1, co), cscale(cmulc(eph, b1), sn));
+                P.rblk[2 * (k + 1) + 1] = csub(cscale(b1, co), cscale(cmul(eph, a1), sn));
+                P.pblk[2 * k] = k;
+                P.pblk[2 * k + 1] = 2;
+                P.pblk[2 * (k + 1)] = k;
+                P.pblk[2 * (k + 1) + 1] = 2;
+            }
+            JqrState t = cur;
+            t.k = k + piv;
+            t.n2x2 = cur.n2x2 + (piv == 2 ? 1 : 0);
+            *nxt = t;
+        }
+        return;
+    }
+    // ---- a trailing column: apply the reflector(s) in place ----
+    double2 *y = A + (size_t)cp2(j) * lda;
+    if (tid == 0) {
+        stash[0] = y[sw.a0];
+        stash[1] = y[sw.b0];
+        stash[2] = y[sw.a1];
+        stash[3] = y[sw.b1];
     }
     __syncthreads();
-    const double2 f11 = x[r0];
-    __syncthreads();  // every wavefront has read f_11 before it is overwritten
-    const double af = sqrt(cnorm2(f11));
-    const double2 e = af > 0.0 ? cmk(f11.x / af, f11.y / af) : cmk(1.0, 0.0);
-    const double rr = sqrt(fabs(h));
-    double2 *s = sbuf + (size_t)which * m;
-    for (int r = r0 + 1 + threadIdx.x; r < m; r += blockDim.x) {
-        s[r] = x[r];
-        x[r] = cmk(0.0, 0.0);
-    }
-    if (threadIdx.x == 0) {
-        s[r0] = cscale(e, af + rr);
-        x[r0] = cscale(e, -rr);  // -c_1
-        st->tau[which] = -1.0 / (h + rr * af * (double)sg);
-    }
-}
-
-// Applies H(s) = I + tau s s^* J to columns j > c (rows r0..m-1) and, when
-// the next iteration starts after this reflector, leaves the columns'
-// J-norms over rows c+1..m-1 in hd.
-__global__ __launch_bounds__(kGridNT) void k_jqr_apply(const PencilDev *PD, const int *pre, int B,
-                                                       int which) {
-    __shared__ double red[2 * kGridNT / kWave];
-    JQR_PENCIL_COL();
-    const double2 *sbuf = P.sbuf;
-    double *hd = P.hd;
-    if (!jqr_active(st, n)) return;
-    const int piv = st->piv;
-    if (which == 1 && piv != 2) return;
-    const int c = st->k + which;
-    const int r0 = c;
-    const int j = j_local;
-    if (j <= c) return;
-    const double2 *s = sbuf + (size_t)which * m;
-    double2 *y = A + (size_t)j * lda;
-    const double2 w = jdot_block(s, y, J, r0, m, red);
-    const double2 tw = cscale(w, st->tau[which]);
-    const bool last = (which == 1) || (piv == 1);
-    double v[1] = {0.0};
-    for (int r = r0 + threadIdx.x; r < m; r += blockDim.x) {
-        const double2 nv = cadd(y[r], cmul(s[r], tw));
-        y[r] = nv;
-        if (r > r0) v[0] += jsign(J, r) * cnorm2(nv);
-    }
-    if (last) {
-        block_sum<1>(v, red);
-        if (threadIdx.x == 0) hd[j] = v[0];
-    }
-}
-
-// Finishes a 2x2 pivot (R^* on rows k, k+1 of the pivot block) and advances k.
-__global__ void k_jqr_finish(const PencilDev *PD) {
-    JQR_PENCIL_ONE();
-    if (!jqr_active(st, n)) return;
-    if (threadIdx.x != 0) return;
-    const int k = st->k;
-    if (st->piv == 2) {
-        const double co = st->co, sn = st->si;
-        const double2 e = st->eph;
-        double2 *x = A + (size_t)k * lda;
-        double2 *y = A + (size_t)(k + 1) * lda;
-        for (int r = k; r < k + 2; ++r) {
-            const double2 a = x[r], b = y[r];
-            // [x, y] <- [x, y] R^*, R^* = [[co, -e sn], [conj(e) sn, co]]
-            x[r] = cadd(cscale(a, co), cscale(cmulc(e, b), sn));
-            y[r] = csub(cscale(b, co), cscale(cmul(e, a), sn));
+    // y0 at stored row q through the stash (rows named by a swap)
+    auto y0 = [&](int q) { return sv_load(y, stash, sw, q); };
+    // Jl holds both row swaps; the first reflector's dot takes J with the
+    // first swap only (undo the second one, rows k+1 <-> b1)
+    auto j0 = [&](int r) {
+        const int q = (r == sw.b1) ? sw.a1 : (r == sw.a1 ? sw.b1 : r);
+        return (double)Jl[q];
+    };
+    double2 tw0;
+    {
+        double v[2] = {0.0, 0.0};
+        for (int r = k + tid; r < m; r += blockDim.x) {
+            const double s = j0(r);
+            const double2 a = s0(r), b = y0(sw.src0(r));
+            v[0] += s * (a.x * b.x + a.y * b.y);
+            v[1] += s * (a.x * b.y - a.y * b.x);
         }
-        st->n2x2 += 1;
+        block_sum<2>(v, red);
+        tw0 = cscale(cmk(v[0], v[1]), tau0);
     }
-    st->k = k + st->piv;
+    auto y1 = [&](int r) { return cadd(y0(sw.src0(r)), cmul(s0(r), tw0)); };  // r >= k
+    if (piv == 1) {
+        double v[1] = {0.0};
+        for (int r = k + tid; r < m; r += blockDim.x) {
+            const double2 nv = y1(r);
+            if (r > k) v[0] += (double)Jl[r] * cnorm2(nv);
+            y[r] = nv;
+        }
+        block_sum<1>(v, red);
+        if (tid == 0) P.hd[cp2(j)] = v[0];
+        return;
+    }
+    double2 tw1;
+    {
+        double v[2] = {0.0, 0.0};
+        for (int r = k + 1 + tid; r < m; r += blockDim.x) {
+            const double s = (double)Jl[r];
+            const int q = (r == sw.b1) ? k + 1 : (r == k + 1 ? sw.b1 : r);
+            const double2 a = s1(r), b = y1(q);
+            v[0] += s * (a.x * b.x + a.y * b.y);
+            v[1] += s * (a.x * b.y - a.y * b.x);
+        }
+        block_sum<2>(v, red);
+        tw1 = cscale(cmk(v[0], v[1]), tau1);
+    }
+    double v[1] = {0.0};
+    for (int r = k + tid; r < m; r += blockDim.x) {
+        double2 nv;
+        if (r == k) {
+            nv = y1(k);
+        } else {
+            const int q = (r == sw.b1) ? k + 1 : (r == k + 1 ? sw.b1 : r);
+            nv = cadd(y1(q), cmul(s1(r), tw1));
+            if (r > k + 1) v[0] += (double)Jl[r] * cnorm2(nv);
+        }
+        y[r] = nv;
+    }
+    block_sum<1>(v, red);
+    if (tid == 0) P.hd[cp2(j)] = v[0];
 }
 
 __global__ void k_jqr_init(const PencilDev *PD) {
     const PencilDev P = PD[blockIdx.x];
-    JqrState *st = P.jst;
     int *perm = P.perm;
     const int n = P.n;
     const int t = threadIdx.x;
     for (int j = t; j < n; j += blockDim.x) perm[j] = j;
     if (!P.reduce) return;
-    if (t == 0) {
-        st->k = 0;
-        st->piv = 1;
-        st->need2 = 0;
-        st->ii = 0;
-        st->status = 0;
-        st->n2x2 = 0;
+    // until a column's pivot step records its block, the extraction reads
+    // no recorded rows for it
+    for (int j = t; j < n; j += blockDim.x) {
+        P.pblk[2 * j] = n;
+        P.pblk[2 * j + 1] = 0;
     }
+    if (t == 0) {
+        JqrState s;
+        s.k = 0;
+        s.status = 0;
+        s.n2x2 = 0;
+        s.pad = 0;
+        P.jst[0] = s;
+    }
+}
+
+// After the last step: the state and signature of the final parity move to
+// the first copies (J_sq is the first n entries of Jw).
+__global__ void k_jqr_settle(const PencilDev *PD, int par) {
+    const PencilDev P = PD[blockIdx.x];
+    if (!P.reduce || par == 0) return;
+    for (int r = threadIdx.x; r < P.m; r += blockDim.x) P.Jw[r] = P.Jw[P.m + r];
+    if (threadIdx.x == 0) P.jst[0] = P.jst[1];
+}
+
+// F_sq from the factored columns: logical column j, row r < n is Ft(r,
+// perm[j]) above the column's pivot block, the recorded pivot rows inside
+// it, and zero below; rowmap (may be NULL) moves row r to rowmap[r].
+__global__ void k_jqr_extract(int n, const double2 *Ft, long ldft, const int *perm,
+                              const double2 *rblk, const int *pblk, const int *rowmap,
+                              double2 *dst, long ldd) {
+    const int j = blockIdx.y;
+    const double2 *s = Ft + (size_t)perm[j] * ldft;
+    const int kb = pblk[2 * j], bs = pblk[2 * j + 1];
+    double2 *d = dst + (size_t)j * ldd;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        double2 v;
+        if (r < kb) v = s[r];
+        else if (r < kb + bs) v = rblk[2 * j + (r - kb)];
+        else v = cmk(0.0, 0.0);
+        d[rowmap ? rowmap[r] : r] = v;
+    }
+}
+
+int jqr_extract(const PencilDev &P, double2 *dst, long ldd, const int *rowmap, hipStream_t s) {
+    int bx = (P.n + 255) / 256;
+    if (bx > 16) bx = 16;
+    hipLaunchKernelGGL(k_jqr_extract, dim3(bx, P.n), dim3(256), 0, s, P.n, P.Ft, P.ldft, P.perm,
+                       P.rblk, P.pblk, rowmap, dst, ldd);
+    GHSVD_HIP(hipGetLastError());
+    return GHSVD_OK;
 }
 
 // ---------------------------------------------------------------------------
 // Householder QR of G P2.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kOneNT) void k_qr_house(const PencilDev *PD, int k) {
-    __shared__ double red[kOneNT / kWave];
-    const PencilDev P = PD[blockIdx.x];
-    if (!P.reduce || k >= P.n || P.jst->status != 0) return;
+// One column step k, every trailing column in one launch: each workgroup
+// forms the reflector H = I - v v^* / (||x|| (||x|| + |x_1|)) of column k
+// (rows k..p-1; v = x + e^{i arg x_1} ||x|| e_1) from the column as stored,
+// which no workgroup rewrites during the step, and applies it to its own
+// column j > k; the workgroup of column k records R_kk = -e^{i arg x_1} ||x||.
+__global__ __launch_bounds__(kGridNT) void k_qr_step(const PencilDev *PD, const int *pre, int B,
+                                                     int k) {
+    __shared__ double red[2 * kGridNT / kWave];
+    const int pk = find_pencil(pre, B, blockIdx.x);
+    const PencilDev P = PD[pk];
+    if (!P.reduce || k >= P.n || P.jst[0].status != 0) return;
+    const int j = pencil_local(pre, pk, blockIdx.x);
+    if (j < k) return;
     double2 *A = P.Gt;
     const long lda = P.ldgt;
     const int p = P.p;
-    double2 *v = P.qv;
-    double *coef = P.qcoef;
-    double2 *x = A + (size_t)k * lda;
+    const double2 *x = A + (size_t)k * lda;
     double s[1] = {0.0};
     for (int r = k + threadIdx.x; r < p; r += blockDim.x) s[0] += cnorm2(x[r]);
     block_sum<1>(s, red);
     const double nrm = sqrt(s[0]);
-    if (nrm == 0.0) {
-        if (threadIdx.x == 0) coef[0] = 0.0;
-        return;
-    }
     const double2 x1 = x[k];
-    __syncthreads();  // every wavefront has read x_1 before it is overwritten
     const double ax1 = sqrt(cnorm2(x1));
     const double2 ph = ax1 > 0.0 ? cmk(x1.x / ax1, x1.y / ax1) : cmk(1.0, 0.0);
-    for (int r = k + 1 + threadIdx.x; r < p; r += blockDim.x) {
-        v[r] = x[r];
-        x[r] = cmk(0.0, 0.0);
+    if (j == k) {
+        if (threadIdx.x == 0) P.qdiag[k] = nrm == 0.0 ? x1 : cscale(ph, -nrm);
+        return;
     }
-    if (threadIdx.x == 0) {
-        v[k] = cscale(ph, ax1 + nrm);
-        x[k] = cscale(ph, -nrm);
-        coef[0] = 1.0 / (nrm * (nrm + ax1));  // 2 / (v^* v)
-    }
-}
-
-__global__ __launch_bounds__(kGridNT) void k_qr_apply(const PencilDev *PD, const int *pre, int B,
-                                                      int k) {
-    __shared__ double red[2 * kGridNT / kWave];
-    const int pk = find_pencil(pre, B, blockIdx.x);
-    const PencilDev P = PD[pk];
-    if (!P.reduce || k >= P.n || P.jst->status != 0) return;
-    const int j = blockIdx.x - pre[pk];
-    if (j <= k) return;
-    double2 *A = P.Gt;
-    const long lda = P.ldgt;
-    const int p = P.p;
-    const double2 *v = P.qv;
-    const double cf = P.qcoef[0];
-    if (cf == 0.0) return;
+    if (nrm == 0.0) return;
+    const double cf = 1.0 / (nrm * (nrm + ax1));  // 2 / (v^* v)
+    const double2 vk = cscale(ph, ax1 + nrm);
     double2 *y = A + (size_t)j * lda;
     double w[2] = {0.0, 0.0};
     for (int r = k + threadIdx.x; r < p; r += blockDim.x) {
-        const double2 a = v[r], b = y[r];
+        const double2 a = r == k ? vk : x[r], b = y[r];
         w[0] += a.x * b.x + a.y * b.y;
         w[1] += a.x * b.y - a.y * b.x;
     }
     block_sum<2>(w, red);
     const double2 tw = cmk(w[0] * cf, w[1] * cf);
-    for (int r = k + threadIdx.x; r < p; r += blockDim.x) y[r] = csub(y[r], cmul(v[r], tw));
+    for (int r = k + threadIdx.x; r < p; r += blockDim.x) {
+        const double2 a = r == k ? vk : x[r];
+        y[r] = csub(y[r], cmul(a, tw));
+    }
+}
+
+// After the last step: R's diagonal in place and zeros below it.
+__global__ void k_qr_settle(const PencilDev *PD) {
+    const PencilDev P = PD[blockIdx.z];
+    const int j = blockIdx.y;
+    if (!P.reduce || j >= P.n || P.jst[0].status != 0) return;
+    double2 *x = P.Gt + (size_t)j * P.ldgt;
+    for (int r = j + blockIdx.x * blockDim.x + threadIdx.x; r < P.p; r += gridDim.x * blockDim.x)
+        x[r] = r == j ? P.qdiag[j] : cmk(0.0, 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -542,6 +752,12 @@ __global__ void k_jsplit_copy(int rows, const double2 *src, long lds, double2 *d
         d[rowmap[r]] = s[r];
 }
 
+int jsplit_map(int rows, const int8_t *J, int *rowmap, int *nplus_dev, hipStream_t stream) {
+    hipLaunchKernelGGL(k_jsplit_map, dim3(1), dim3(kOneNT), 0, stream, rows, J, rowmap, nplus_dev);
+    GHSVD_HIP(hipGetLastError());
+    return GHSVD_OK;
+}
+
 int jsplit(int rows, int n, const double2 *src, long lds, const int8_t *J, double2 *dst, long ldd,
            int *rowmap, int *nplus_dev, hipStream_t stream) {
     hipLaunchKernelGGL(k_jsplit_map, dim3(1), dim3(kOneNT), 0, stream, rows, J, rowmap, nplus_dev);
@@ -617,9 +833,9 @@ __global__ void k_jqr_status(const PencilDev *PD, int B, int *out) {
             out[2 * k + 1] = 0;
             continue;
         }
-        const JqrState *st = P.jst;
-        out[2 * k] = st->status ? st->status : (st->k < P.n ? GHSVD_ERANK : 0);
-        out[2 * k + 1] = st->n2x2;
+        const JqrState st = P.jst[0];
+        out[2 * k] = st.status ? st.status : (st.k < P.n ? GHSVD_ERANK : 0);
+        out[2 * k + 1] = st.n2x2;
     }
 }
 
@@ -640,20 +856,20 @@ int run_reduction(const BatchCtx &c, std::vector<int> &status, std::vector<int> 
     }
     const int *pc = c.pre_of(BatchCtx::kCols);
     const int tot = c.total(BatchCtx::kCols);
+    int max_m = 0;
+    for (const PencilDev &P : c.host) max_m = P.m > max_m ? P.m : max_m;
+    const size_t jl_bytes = align_up((size_t)max_m, 16);
     hipLaunchKernelGGL(k_jqr_init, dim3(B), dim3(256), 0, s, c.dev);
-    hipLaunchKernelGGL(k_jqr_colnorms, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B);
-    // At most max_n iterations (fewer when 2x2 pivots occur; extra ones exit at once).
+    hipLaunchKernelGGL(k_jqr_colnorms, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, 0);
+    // At most max_n steps (fewer when 2x2 pivots occur; extra ones only carry
+    // the state to the next parity).  Three launches per step.
     for (int it = 0; it < c.max_n; ++it) {
-        hipLaunchKernelGGL(k_jqr_cross, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B);
-        hipLaunchKernelGGL(k_jqr_decide1, dim3(B), dim3(kOneNT), 0, s, c.dev);
-        hipLaunchKernelGGL(k_jqr_cross2, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B);
-        hipLaunchKernelGGL(k_jqr_decide2, dim3(B), dim3(kOneNT), 0, s, c.dev);
-        for (int w = 0; w < 2; ++w) {
-            hipLaunchKernelGGL(k_jqr_reflect, dim3(B), dim3(kOneNT), 0, s, c.dev, w);
-            hipLaunchKernelGGL(k_jqr_apply, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, w);
-        }
-        hipLaunchKernelGGL(k_jqr_finish, dim3(B), dim3(64), 0, s, c.dev);
+        const int par = it & 1;
+        hipLaunchKernelGGL(k_jqr_cross, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, par);
+        hipLaunchKernelGGL(k_jqr_cross2, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, par);
+        hipLaunchKernelGGL(k_jqr_step, dim3(tot), dim3(kGridNT), jl_bytes, s, c.dev, pc, B, par);
     }
+    hipLaunchKernelGGL(k_jqr_settle, dim3(B), dim3(256), 0, s, c.dev, c.max_n & 1);
     GHSVD_HIP(hipGetLastError());
     for (int k = 0; k < B; ++k) {
         const PencilDev &P = c.host[k];
@@ -661,9 +877,12 @@ int run_reduction(const BatchCtx &c, std::vector<int> &status, std::vector<int> 
         int rc = copy_cols(P.p, P.n, P.Gin, P.ldgin, P.Gt, P.ldgt, P.perm, s);
         if (rc) return rc;
     }
-    for (int k = 0; k < c.max_n; ++k) {
-        hipLaunchKernelGGL(k_qr_house, dim3(B), dim3(kOneNT), 0, s, c.dev, k);
-        hipLaunchKernelGGL(k_qr_apply, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, k);
+    for (int k = 0; k < c.max_n; ++k)
+        hipLaunchKernelGGL(k_qr_step, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, k);
+    {
+        int bx = (c.max_rows + 255) / 256;
+        if (bx > 8) bx = 8;
+        hipLaunchKernelGGL(k_qr_settle, dim3(bx, c.max_n, B), dim3(256), 0, s, c.dev);
     }
     GHSVD_HIP(hipGetLastError());
     std::vector<int> out(2 * B);

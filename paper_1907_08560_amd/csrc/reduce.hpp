@@ -30,6 +30,13 @@ int jsplit(int rows, int n, const double2 *src, long lds, const int8_t *J, doubl
 int check_inputs(int m, int n, int p, const double2 *F, long ldf, const int8_t *J,
                  const double2 *G, long ldg, int *flags, double *gnorm2, hipStream_t stream);
 
+// Row map of the split alone (rowmap, *nplus_dev), for jqr_extract.
+int jsplit_map(int rows, const int8_t *J, int *rowmap, int *nplus_dev, hipStream_t stream);
+
+// F_sq (n x n, columns in the order of P2) of a reduced pencil from its
+// factored columns into dst (ld ldd), rows moved by rowmap (NULL: in place).
+int jqr_extract(const PencilDev &P, double2 *dst, long ldd, const int *rowmap, hipStream_t stream);
+
 // Identity matrix n x n (ld) of complex128 or complex64.
 int set_identity(int n, void *Z, long ldz, int fp32, hipStream_t stream);
 

@@ -56,18 +56,20 @@ void carve_pencil(Carver &c, const Plan &pl, PencilDev &d) {
     d.ldf = pl.ldf;
     d.ldg = pl.ldg;
     d.ldz = pl.ldz;
-    d.jst = c.take<JqrState>(1);
+    d.jst = c.take<JqrState>(2);
     if (pl.reduce) {
         d.Ft = c.take<double2>((size_t)pl.ldft * n);
         d.Gt = c.take<double2>((size_t)pl.ldgt * n);
+        d.jdec = c.take<JqrDecision>(1);
         d.hd = c.take<double>(n);
         d.hc = c.take<double2>(n);
         d.hi = c.take<double>(n);
-        d.sbuf = c.take<double2>(2 * (size_t)pl.m);
-        d.qv = c.take<double2>(pl.p);
-        d.qcoef = c.take<double>(1);
+        d.cpb = c.take<int>(n);
+        d.rblk = c.take<double2>(2 * (size_t)n);
+        d.pblk = c.take<int>(2 * (size_t)n);
+        d.qdiag = c.take<double2>(n);
     }
-    d.Jw = c.take<int8_t>(pl.m);
+    d.Jw = c.take<int8_t>(2 * (size_t)pl.m);
     d.rowmap = c.take<int>(pl.m > n ? pl.m : n);
     d.perm = c.take<int>(n);
     d.Fw = c.take<double2>((size_t)pl.ldf * n);
@@ -297,8 +299,8 @@ int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *w
     }
     for (const PencilDev &P : bc.host) {
         if (P.reduce) {
-            if ((rc = jsplit(P.n, P.n, P.Ft, P.ldft, P.Jw, P.Fw, P.ldf, P.rowmap, P.small + 1, s)))
-                return rc;
+            if ((rc = jsplit_map(P.n, P.Jw, P.rowmap, P.small + 1, s))) return rc;
+            if ((rc = jqr_extract(P, P.Fw, P.ldf, P.rowmap, s))) return rc;
             if ((rc = copy_cols(P.n, P.n, P.Gt, P.ldgt, P.Gw, P.ldg, nullptr, s))) return rc;
         } else {
             if ((rc = jsplit(P.m, P.n, P.Fin, P.ldfin, P.Jin, P.Fw, P.ldf, P.rowmap, P.small + 1, s)))
@@ -656,8 +658,7 @@ extern "C" int ghsvd_reduce(int m, int n, int p, const double *F, int ldf, const
     if ((rc = run_reduction(ob.bc, rst, n2, s))) return rc;
     if (n2x2) *n2x2 = n2[0];
     if (rst[0]) return rst[0];
-    if ((rc = copy_cols(n, n, d.Ft, d.ldft, reinterpret_cast<double2 *>(Fsq), ldfs, nullptr, s)))
-        return rc;
+    if ((rc = jqr_extract(d, reinterpret_cast<double2 *>(Fsq), ldfs, nullptr, s))) return rc;
     if ((rc = copy_cols(n, n, d.Gt, d.ldgt, reinterpret_cast<double2 *>(Gsq), ldgs, nullptr, s)))
         return rc;
     GHSVD_HIP(hipMemcpyAsync(Jsq, d.Jw, (size_t)n, hipMemcpyDeviceToDevice, s));
