@@ -170,8 +170,8 @@ __global__ __launch_bounds__(NT) void k_pair(const PencilDev *PD, const int *pre
     if (q < P.n) pair_body<T, NT, R>(P, p, q, slot, crit);  // else: bye slot of an odd order
 }
 
-__global__ void k_reset_states(const PencilDev *PD, int *flag, int B, int max_sweeps,
-                               int noise_floor, int blocked) {
+__global__ void k_reset_states(const PencilDev *PD, int *flag, const int *presolved, int B,
+                               int max_sweeps, int noise_floor, int blocked) {
     const int k = blockIdx.x;
     if (k >= B) return;
     const PencilDev P = PD[k];
@@ -180,7 +180,7 @@ __global__ void k_reset_states(const PencilDev *PD, int *flag, int B, int max_sw
     const int nc = blocked ? P.nbp : P.nslots;
     for (int s = threadIdx.x; s < 3 * nc; s += blockDim.x) cnt[s] = 0ull;
     if (threadIdx.x == 0) {
-        const int skip = blocked ? (P.n < 4 || P.nb < 2) : 0;
+        const int skip = (blocked ? (P.n < 4 || P.nb < 2) : 0) || (presolved && presolved[k]);
         st->done = skip;
         flag[k] = skip;
         st->converged = skip;
@@ -395,7 +395,7 @@ static bool capture_round(const BatchCtx &c, StepFn one_step, const void *arg, i
 
 int drive_stage(const BatchCtx &c, int max_sweeps, int noise_floor, int blocked, StepFn one_step,
                 const void *arg, int steps_per_round, const char *name, hipStream_t s,
-                std::vector<SweepResult> &res) {
+                std::vector<SweepResult> &res, const std::vector<int> *presolved) {
     const int B = c.B;
     res.assign(B, SweepResult{GHSVD_OK, 0, 0, 0, 0, 0});
     RoundGraph rg;
@@ -414,11 +414,19 @@ int drive_stage(const BatchCtx &c, int max_sweeps, int noise_floor, int blocked,
         GHSVD_HIP(hipStreamWaitEvent(rg.gs, rg.ev, 0));
         ss = rg.gs;
     }
-    hipLaunchKernelGGL(k_reset_states, dim3(B), dim3(256), 0, ss, c.dev, c.flag_dev, B, max_sweeps,
-                       noise_floor, blocked);
+    const int *pre_dev = nullptr;
+    if (presolved) {
+        GHSVD_HIP(hipMemcpyAsync(c.done_dev, presolved->data(), sizeof(int) * B,
+                                 hipMemcpyHostToDevice, ss));
+        pre_dev = c.done_dev;
+    }
+    hipLaunchKernelGGL(k_reset_states, dim3(B), dim3(256), 0, ss, c.dev, c.flag_dev, pre_dev, B,
+                       max_sweeps, noise_floor, blocked);
     GHSVD_HIP(hipGetLastError());
     std::vector<int> done(B, 0);
-    for (int round = 0; round < max_sweeps; ++round) {
+    bool all_pre = presolved != nullptr;
+    for (int k = 0; k < B && all_pre; ++k) all_pre = (*presolved)[k] != 0;
+    for (int round = 0; round < max_sweeps && !all_pre; ++round) {
         if (rg.exec) {
             GHSVD_HIP(hipGraphLaunch(rg.exec, ss));
         } else {
@@ -471,13 +479,14 @@ static int pointwise_step(const BatchCtx &c, const void *arg, int step, hipStrea
 }
 
 int run_pointwise_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, PairGeom g,
-                        hipStream_t s, std::vector<SweepResult> &res) {
+                        hipStream_t s, std::vector<SweepResult> &res,
+                        const std::vector<int> *presolved) {
     PointwiseArg a{fp32 ? pick<float>(g.nt, g.r) : pick<double>(g.nt, g.r), g, crit, fp32};
     if (!a.fn) return GHSVD_EINVAL;
     int steps = 1;
     for (const PencilDev &P : c.host) steps = P.N - 1 > steps ? P.N - 1 : steps;
     return drive_stage(c, max_sweeps, fp32, 0, pointwise_step, &a, steps,
-                       fp32 ? "pointwise-fp32" : "pointwise-fp64", s, res);
+                       fp32 ? "pointwise-fp32" : "pointwise-fp64", s, res, presolved);
 }
 
 // ---------------------------------------------------------------------------

@@ -317,7 +317,8 @@ int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *w
 
     // 3. sweep stages: the FP32 warm-up (blocked or pointwise) with its FP64
     // hand-off when mixed; FP64 blocked sweeps for the blocked variant; then
-    // FP64 pointwise sweeps, which decide convergence.
+    // FP64 pointwise sweeps for every pencil the blocked stage did not
+    // finish.
     auto account = [&](const std::vector<SweepResult> &r, int fp32, int blocked) {
         for (int k = 0; k < bc.B; ++k) {
             ghsvd_info &inf = info[idx[k]];
@@ -334,6 +335,7 @@ int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *w
         }
     };
     std::vector<SweepResult> res;
+    std::vector<int> presolved;
     if (bc.B > 0 && o.precision == GHSVD_MIXED) {
         if ((rc = to_fp32(bc, s))) return rc;
         const int blk = o.variant == GHSVD_BLOCKED;
@@ -367,12 +369,23 @@ int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *w
         account(res, 0, 1);
         for (int k = 0; k < bc.B; ++k)
             if (res[k].status < 0) status[idx[k]] = res[k].status;
+        // A blocked sweep visits every column pair, so one without a big
+        // transformation meets the stopping rule (Section 6.1.7): those
+        // pencils are done; the rest (sweep cap, or no blocked sweep) go on
+        // with pointwise FP64 sweeps.
+        // (compaction keeps the pencils with status >= 0, in order)
+        presolved.clear();
+        for (int k = 0; k < bc.B; ++k)
+            if (status[idx[k]] >= 0)
+                presolved.push_back(res[k].status == GHSVD_OK && res[k].converged &&
+                                    res[k].sweeps > 0);
         if ((rc = compact(bc, idx, status, s))) return rc;
     }
     if (bc.B > 0) {
         if (clk) GHSVD_HIP(hipEventRecord(ev[2], s));
         rc = run_pointwise_stage(bc, 0, o.max_sweeps, o.crit_literal,
-                                 choose_pair_geom(bc.max_rows, wpp), s, res);
+                                 choose_pair_geom(bc.max_rows, wpp), s, res,
+                                 presolved.empty() ? nullptr : &presolved);
         if (clk) {
             GHSVD_HIP(hipEventRecord(ev[3], s));
             GHSVD_HIP(hipEventSynchronize(ev[3]));

@@ -46,8 +46,10 @@ int upload_batch(BatchCtx &c, hipStream_t s);
 // Pointwise sweeps (Algorithm 2 on the round-robin ordering) for every
 // pencil of the batch until each converges or hits max_sweeps.  fp32: the
 // complex64 copies F32/G32/Z32 (warm-up stage, noise-floor stop).
+// presolved (host, may be NULL): pencils marked 1 start the stage converged.
 int run_pointwise_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, PairGeom g,
-                        hipStream_t s, std::vector<SweepResult> &res);
+                        hipStream_t s, std::vector<SweepResult> &res,
+                        const std::vector<int> *presolved = nullptr);
 
 // Level-2 blocked sweeps (Section 6.4) for every pencil with n >= 4.
 int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, int inner_order,
@@ -75,6 +77,6 @@ void prof_after(int kind, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 using StepFn = int (*)(const BatchCtx &, const void *, int, hipStream_t);
 int drive_stage(const BatchCtx &c, int max_sweeps, int noise_floor, int blocked, StepFn one_step,
                 const void *arg, int steps_per_round, const char *name, hipStream_t s,
-                std::vector<SweepResult> &res);
+                std::vector<SweepResult> &res, const std::vector<int> *presolved = nullptr);
 
 }  // namespace ghsvd

@@ -69,7 +69,9 @@ def test_blocked_solve_workload_one(oracle, w, inner):
     lam, X, info = ghsvd.solve(F, J, G, variant="blocked", block_width=w, inner_order=inner)
     st, lam_o, X_o, _ = oracle.ghsvd(P.F, P.J, P.G)
     assert info["status"] == 0 and st == 0
-    assert info["sweeps_blocked"] > 0 and info["sweeps_fp64"] > info["sweeps_blocked"]
+    # a blocked sweep visits every column pair, so a converged blocked stage
+    # needs no confirming pointwise sweep
+    assert info["sweeps_blocked"] > 0 and info["sweeps_fp64"] >= info["sweeps_blocked"]
     lam = host(lam)
     assert rel_err(lam, lam_o) <= 1e-12
     e_s, e_h, e_d = factor_invariants(P.F, P.J, P.G, lam, host(X))
