@@ -95,6 +95,7 @@ def kernel_rooflines(times, info_sum, mr, pr, n, w, nbp, fp32_blocked=False):
                        achieved=flops / mean_s / 1e12, work_per_launch=flops, work_unit="flops",
                        units_per_launch=nbp, us_per_inner_step=mean_s * 1e6 / (c - 1))
         rec["frac"] = rec["achieved"] / rec["peak"]
+        rec["traffic"] = stored_traffic(kind)
         out[kind] = rec
     return out
 
@@ -106,8 +107,9 @@ KERNEL_NAMES = {"pair64": "k_pair<double> (pointwise FP64 pair kernel)",
 
 
 def stored_traffic(kind):
-    """HBM bytes per launch from the committed counter summary, or None when
-    the kernel's source changed since the counters were taken."""
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, each scaled by what the counter reads for a plain copy), or
+    None when a source of the kernel changed since the counters were taken."""
     try:
         with open(TRAFFIC) as f:
             t = json.load(f).get(kind)
@@ -115,12 +117,14 @@ def stored_traffic(kind):
         return None
     if not t:
         return None
-    src = os.path.join(ROOT, t["source"])
+    h = hashlib.sha256()
     try:
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        for src in t["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
     except OSError:
         return None
-    return t["bytes_per_launch"] if sha == t["sha256"] else None
+    return t["bytes_per_launch"] if h.hexdigest() == t["sha256"] else None
 
 
 def lambda_errors(lam):
