@@ -234,6 +234,104 @@ def batched_workload(args, ghsvd, synth, torch, dev):
     print(json.dumps(rec), flush=True)
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def prime(ghsvd, synth, torch, dev, kw):
+    """One small untimed solve on the path, so that the timed runs start warm."""
+    P = synth.workload_pencil(1)
+    ghsvd.solve(ghsvd.to_device_fortran(P.F, dev), torch.from_numpy(P.J).to(dev),
+                ghsvd.to_device_fortran(P.G, dev), check=False, **kw)
+    torch.cuda.synchronize()
+
+
+def time_paths(args, ghsvd, synth, torch, dev, pencils, paths_wanted):
+    """Times each (precision, variant) path on a list of (F, J, G) device
+    pencils in one batched call per step; returns per-path records and lambdas."""
+    Fs = [q[0] for q in pencils]
+    Js = [q[1] for q in pencils]
+    Gs = [q[2] for q in pencils]
+    paths, lams = {}, {}
+    for prec, var in paths_wanted:
+        kw = dict(precision=prec, variant=var, max_sweeps=args.max_sweeps)
+        prime(ghsvd, synth, torch, dev, kw)
+        for _ in range(args.warmup):
+            ghsvd.solve_batched(Fs, Js, Gs, **kw)
+        torch.cuda.synchronize()
+        log(f"timing {prec}-{var}")
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            lam, X, infos, rc = ghsvd.solve_batched(Fs, Js, Gs, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        key = f"{prec}-{var}"
+        lams[key] = [l.cpu().numpy() for l in lam]
+        del X
+        paths[key] = {
+            "pencils_per_s": len(Fs) * args.steps / dt, "ms_per_batch": 1000.0 * dt / args.steps,
+            "status": rc, "max_sweeps_fp64": max(i["sweeps_fp64"] for i in infos),
+            "max_sweeps_fp32": max(i["sweeps_fp32"] for i in infos),
+            "pair_updates_per_s": sum(i["pairs_visited"] for i in infos) * args.steps / dt}
+        log(f"{key}: {paths[key]['ms_per_batch']:.1f} ms, status {rc}")
+    ref = lams.get("fp64-blocked")
+    if ref is not None:
+        for key in lams:
+            if key != "fp64-blocked":
+                paths[key]["max_rel_diff_vs_fp64_blocked"] = max(
+                    float(np.max(np.abs(a - b) / np.abs(b))) for a, b in zip(lams[key], ref))
+    return paths
+
+
+def large_workload(args, ghsvd, synth, torch, dev):
+    """Workload 3 (one n=4096 pencil, F 6144 x 4096 with a 3:1 signature, G
+    8192 x 4096 with s log-uniform in [1e-5, 1], plus the same pencil under
+    J = I) or workload 5 (16 pencils, n_k uniform in [2000, 6000], F 1.5 n_k x
+    n_k with a 4:1 signature, G 2 n_k x n_k, s in [1e-6, 1]) on the blocked
+    paths (and the pointwise FP64 path for workload 3).  Workload 5's Haar QRs
+    run on the device (same draws as the host recipe)."""
+    W = args.workload
+    sizes = synth.workload_sizes(W)
+    pencils = []
+    for k in range(len(sizes)):
+        if W == 3:
+            P = synth.workload_pencil(3, k)
+            pencils.append((ghsvd.to_device_fortran(P.F, dev), torch.from_numpy(P.J).to(dev),
+                            ghsvd.to_device_fortran(P.G, dev)))
+        else:
+            F, J, G, _ = synth.workload_pencil_device(5, k, dev)
+            pencils.append((F, J, G))
+        log(f"pencil {k}: n={sizes[k]} built")
+    torch.cuda.synchronize()
+    want = [("fp64", "blocked"), ("mixed", "blocked")]
+    if W == 3 and not args.no_compare:
+        want.append(("fp64", "pointwise"))
+    paths = time_paths(args, ghsvd, synth, torch, dev, pencils, want)
+    extra = {}
+    if W == 3:
+        ones = [(F, torch.ones_like(J), G) for F, J, G in pencils]
+        extra["j_identity"] = time_paths(args, ghsvd, synth, torch, dev, ones,
+                                         [("fp64", "blocked"), ("mixed", "blocked")])
+    best = max(paths, key=lambda k: paths[k]["pencils_per_s"])
+    desc = {3: ("one pencil n=4096: F 6144x4096 Gaussian, J 4608(+)/1536(-), G 8192x4096 = "
+                "U diag(s) W^*, s log-uniform [1e-5,1] (cond S = 1e10), complex128; plus the "
+                "same pencil under J = I"),
+            5: ("16 pencils, n_k uniform in [2000,6000], F ceil(1.5 n_k) x n_k Gaussian, J 4:1, "
+                "G 2 n_k x n_k = U diag(s) W^*, s log-uniform [1e-6,1], complex128, one batched "
+                "call")}[W]
+    rec = {
+        "metric": METRIC, "value": paths[best]["pencils_per_s"], "unit": "pencils/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": paths[best]["ms_per_batch"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if best.startswith("fp64") else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": f"{desc}; best path {best}", "batch": len(sizes),
+                   "n_min": int(min(sizes)), "n_max": int(max(sizes))},
+        "paths": paths, **extra,
+    }
+    print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -245,8 +343,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-every", type=int, default=4)
     ap.add_argument("--max-sweeps", type=int, default=0)
-    ap.add_argument("--workload", type=int, default=2, choices=[2, 4],
-                    help="2: the single n=1024 pencil (default); 4: the batch of 64 pencils")
+    ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4, 5],
+                    help="2: the single n=1024 pencil (default); 3: one n=4096 pencil; "
+                         "4: the batch of 64 pencils; 5: the batch of 16 large pencils")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -273,6 +372,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.workload == 4:
         batched_workload(args, ghsvd, synth, torch, dev)
+        return
+    if args.workload in (3, 5):
+        large_workload(args, ghsvd, synth, torch, dev)
         return
     P = synth.workload_pencil(2)
     F = ghsvd.to_device_fortran(P.F, dev)

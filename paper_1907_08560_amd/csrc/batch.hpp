@@ -26,8 +26,9 @@ struct SweepState {
     int err;         // first error status (0 = none)
     int converged;   // 1: the last sweep had no big transformation
     int max_sweeps;  // cap of the stage
-    int noise_floor; // 1: also stop once a sweep's big count is at most visited / 1024
-    int pad[2];
+    int noise_floor; // 1: also stop at the noise floor (FP32 stage, see k_end_round)
+    int pad;
+    unsigned int prev_big;  // big count of the previous sweep (noise-floor plateau)
     unsigned long long hist[3 * kMaxHist];  // (visited, transformed, big) per sweep
 };
 

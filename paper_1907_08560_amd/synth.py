@@ -77,6 +77,51 @@ def make_pencil(rng: np.random.Generator, n: int, m: int, m_plus: int, p: int,
     return Pencil(np.asfortranarray(F), J, np.asfortranarray(G), s, seed, index)
 
 
+def make_pencil_device(rng: np.random.Generator, n: int, m: int, m_plus: int, p: int,
+                       s_lo: float, device, j_identity: bool = False):
+    """The recipe of `make_pencil` with the same draws in the same order, but
+    the two Haar QRs and the product G = U diag(s) W^* run on `device` (torch),
+    which keeps large batches cheap to build.  The Gaussian draws and s are
+    identical; U, W and G differ from `make_pencil`'s by rounding only.
+    Returns (F, J, G, s): column-major complex128 / int8 device tensors, s numpy."""
+    import torch
+
+    def frame(a):
+        q, r = torch.linalg.qr(torch.from_numpy(a).to(device))
+        d = torch.diagonal(r)
+        ad = d.abs()
+        ph = torch.where(ad > 0, d / torch.where(ad > 0, ad, torch.ones_like(ad)),
+                         torch.ones_like(d))
+        return q * ph[None, :]
+
+    def fortran(t):
+        return t.t().contiguous().t()
+
+    F = _gauss(rng, m, n)
+    if j_identity:
+        m_plus = m
+    J = np.where(np.arange(m) < m_plus, 1, -1).astype(np.int8)
+    s = 10.0 ** rng.uniform(math.log10(s_lo), 0.0, size=n)
+    U = frame(_gauss(rng, p, n))
+    W = frame(_gauss(rng, n, n))
+    st = torch.from_numpy(s).to(device=device, dtype=torch.complex128)
+    G = (U * st[None, :]) @ W.conj().t().contiguous()
+    Fd = fortran(torch.from_numpy(F).to(device))
+    return Fd, torch.from_numpy(J).to(device), fortran(G), s
+
+
+def workload_pencil_device(number: int, k: int, device, j_identity: bool = False):
+    """Pencil k of a workload, built by `make_pencil_device`."""
+    w = WORKLOADS[number]
+    seed = 1000 + number
+    n = workload_sizes(number)[k]
+    m = rows_for(n, w["f_ratio"])
+    p = rows_for(n, w["g_ratio"])
+    m_plus = int(round(w["plus_frac"] * m))
+    return make_pencil_device(pencil_rng(seed, w["batch"], k), n, m, m_plus, p, w["s_lo"],
+                              device, j_identity=j_identity)
+
+
 def pencil_rng(seed: int, batch: int, k: int) -> np.random.Generator:
     """Generator of pencil k of a batch: SeedSequence(seed).spawn(batch)[k]."""
     if batch == 1:

@@ -32,3 +32,20 @@ def test_batched_sizes():
 def test_j_identity():
     P = synth.workload_pencil(3, j_identity=True, n_override=40)
     assert np.all(P.J == 1)
+
+
+def test_device_builder_matches_host_recipe():
+    """The torch-side builder draws the same numbers in the same order; its QRs
+    and product only change G by rounding."""
+    import torch
+    P = synth.random_pencil(7, 40, 60, 45, 80, 1e-6)
+    rng = np.random.Generator(np.random.PCG64(7))
+    F, J, G, s = synth.make_pencil_device(rng, 40, 60, 45, 80, 1e-6, "cpu")
+    assert F.stride(0) == 1 and G.stride(0) == 1
+    assert np.array_equal(F.numpy(), P.F)
+    assert np.array_equal(J.numpy(), P.J)
+    assert np.array_equal(s, P.s)
+    assert np.abs(G.numpy() - P.G).max() <= 1e-13 * np.abs(P.G).max()
+    sv = np.linalg.svd(G.numpy(), compute_uv=False)
+    assert np.allclose(np.sort(sv), np.sort(P.s), rtol=1e-10, atol=0)
+    assert torch.is_tensor(G) and G.dtype == torch.complex128
