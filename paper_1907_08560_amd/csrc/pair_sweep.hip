@@ -432,6 +432,7 @@ int drive_stage(const BatchCtx &c, int max_sweeps, int noise_floor, int blocked,
                        max_sweeps, noise_floor, blocked);
     GHSVD_HIP(hipGetLastError());
     std::vector<int> done(B, 0);
+    const bool trace = std::getenv("GHSVD_TRACE") != nullptr;
     bool all_pre = presolved != nullptr;
     for (int k = 0; k < B && all_pre; ++k) all_pre = (*presolved)[k] != 0;
     for (int round = 0; round < max_sweeps && !all_pre; ++round) {
@@ -444,7 +445,14 @@ int drive_stage(const BatchCtx &c, int max_sweeps, int noise_floor, int blocked,
         GHSVD_HIP(hipMemcpyAsync(done.data(), c.flag_dev, sizeof(int) * B, hipMemcpyDeviceToHost, ss));
         GHSVD_HIP(hipStreamSynchronize(ss));
         bool all = true;
-        for (int k = 0; k < B; ++k) all = all && done[k];
+        int ndone = 0;
+        for (int k = 0; k < B; ++k) {
+            all = all && done[k];
+            ndone += done[k] != 0;
+        }
+        if (trace)
+            std::fprintf(stderr, "ghsvd %s round %d: %d of %d pencils done\n", name, round + 1,
+                         ndone, B);
         if (all) break;
     }
     int worst = GHSVD_OK;
