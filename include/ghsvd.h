@@ -180,12 +180,17 @@ void ghsvd_autotune_clear(void);
  * One-time reduction (Section 5, eq. (5.1)): hyperbolic QR of F with
  * diagonal plus Bunch-Kaufman partial column pivoting (Section 5.2.1),
  * hyperbolic Householder reflectors (Theorem 5.1, Section 5.3) and the 2x2
- * (J, I) URV pivot step; then the Householder QR of G P2 (R_kk =
- * -e^{i arg x_1} ||x||).  Outputs: Fsq (n x n, ldfs >= n, block upper
- * triangular, zeros below), Jsq (n int8), Gsq (n x n, ldgs >= n, upper
- * triangular), perm (n ints: column i of F P2 is column perm[i] of F), all
- * device; *n2x2 (host) the number of 2x2 pivots.  Then
- * Fsq^* Jsq Fsq = P2^T F^* J F P2 and Gsq^* Gsq = P2^T G^* G P2.
+ * (J, I) URV pivot step; then the Householder QR of G without pivoting
+ * (R_kk = -e^{i arg x_1} ||x||), whose triangular factor R_G is returned
+ * with its columns permuted by P2: Gsq = R_G P2.  The iteration sees G
+ * only through G^*G, for which this factor and the triangular factor of
+ * G P2 (Section 5) are equivalent; the unpivoted QR does not wait for the
+ * pivot decisions and runs beside the hyperbolic QR.  Outputs: Fsq (n x n,
+ * ldfs >= n, block upper triangular, zeros below), Jsq (n int8), Gsq (n x n,
+ * ldgs >= n; Gsq[:, perm^-1] is upper triangular), perm (n ints: column i of
+ * F P2 is column perm[i] of F), all device; *n2x2 (host) the number of 2x2
+ * pivots.  Then Fsq^* Jsq Fsq = P2^T F^* J F P2 and
+ * Gsq^* Gsq = P2^T G^* G P2.
  */
 int ghsvd_reduce(int m, int n, int p, const double *F, int ldf, const int8_t *J,
                  const double *G, int ldg, double *Fsq, int ldfs, int8_t *Jsq,

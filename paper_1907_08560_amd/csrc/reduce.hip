@@ -6,7 +6,11 @@
 // Section 5.3 (Theorem 5.1, generator s = f + c_1 e_1 with arg c_1 = arg f_11,
 // a matching-sign row swapped to the front when needed), 2x2 pivots by the
 // (J, I) URV step (Jacobi rotation of the pivot J-Gram, two reflectors, R^*).
-// G: Householder QR of G P2 (the "TSQR" step; Q is not formed).
+// G: Householder QR of G without pivoting (Q is not formed); the caller
+// permutes the triangular factor's columns by P2.  The iteration sees G only
+// through G^*G, and R_G P2 has the Gram of the triangular factor of G P2, so
+// the QR needs no pivot decision: its column steps ride in the hyperbolic
+// QR's step launches as extra workgroups.
 //
 // The k-loop of the JQR is sequential; each iteration is a fixed sequence of
 // kernels that read the iteration's state from device memory (pivot size,
@@ -219,13 +223,21 @@ __device__ __forceinline__ double2 sv_load(const double2 *x, const double2 *stas
 // The workgroup of column k writes the next state, map and signature, and
 // the pivot rows; the pivot columns themselves are not rewritten (the final
 // extraction takes their rows from rblk and zeros below them).
+__device__ __forceinline__ void qr_step_body(const PencilDev *PD, const int *pre, int B, int k,
+                                             int bid, double *red);
+
+// Workgroups tot.. of the launch run column step qk of G's QR instead.
 __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const int *pre, int B,
-                                                      int par) {
+                                                      int par, int tot, int qk) {
     extern __shared__ int8_t Jl[];  // signature with this step's row swaps
     __shared__ double red[4 * kGridNT / kWave];
     __shared__ double rv[kGridNT / kWave];
     __shared__ int ri[kGridNT / kWave];
     __shared__ double2 stash[4];
+    if ((int)blockIdx.x >= tot) {
+        qr_step_body(PD, pre, B, qk, (int)blockIdx.x - tot, red);
+        return;
+    }
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev P = PD[pk];
     if (!P.reduce) return;
@@ -617,20 +629,19 @@ int jqr_extract(const PencilDev &P, double2 *dst, long ldd, const int *rowmap, h
 }
 
 // ---------------------------------------------------------------------------
-// Householder QR of G P2.
+// Householder QR of G.
 // ---------------------------------------------------------------------------
 // One column step k, every trailing column in one launch: each workgroup
 // forms the reflector H = I - v v^* / (||x|| (||x|| + |x_1|)) of column k
 // (rows k..p-1; v = x + e^{i arg x_1} ||x|| e_1) from the column as stored,
 // which no workgroup rewrites during the step, and applies it to its own
 // column j > k; the workgroup of column k records R_kk = -e^{i arg x_1} ||x||.
-__global__ __launch_bounds__(kGridNT) void k_qr_step(const PencilDev *PD, const int *pre, int B,
-                                                     int k) {
-    __shared__ double red[2 * kGridNT / kWave];
-    const int pk = find_pencil(pre, B, blockIdx.x);
+__device__ __forceinline__ void qr_step_body(const PencilDev *PD, const int *pre, int B, int k,
+                                             int bid, double *red) {
+    const int pk = find_pencil(pre, B, bid);
     const PencilDev P = PD[pk];
-    if (!P.reduce || k >= P.n || P.jst[0].status != 0) return;
-    const int j = pencil_local(pre, pk, blockIdx.x);
+    if (!P.reduce || k >= P.n) return;
+    const int j = pencil_local(pre, pk, bid);
     if (j < k) return;
     double2 *A = P.Gt;
     const long lda = P.ldgt;
@@ -669,7 +680,7 @@ __global__ __launch_bounds__(kGridNT) void k_qr_step(const PencilDev *PD, const 
 __global__ void k_qr_settle(const PencilDev *PD) {
     const PencilDev P = PD[blockIdx.z];
     const int j = blockIdx.y;
-    if (!P.reduce || j >= P.n || P.jst[0].status != 0) return;
+    if (!P.reduce || j >= P.n) return;
     double2 *x = P.Gt + (size_t)j * P.ldgt;
     for (int r = j + blockIdx.x * blockDim.x + threadIdx.x; r < P.p; r += gridDim.x * blockDim.x)
         x[r] = r == j ? P.qdiag[j] : cmk(0.0, 0.0);
@@ -839,6 +850,21 @@ __global__ void k_jqr_status(const PencilDev *PD, int B, int *out) {
     }
 }
 
+// After G's last column step: R's diagonal and the zeros below it.
+static int qr_end(const BatchCtx &c, hipStream_t s) {
+    int bx = (c.max_rows + 255) / 256;
+    if (bx > 8) bx = 8;
+    hipLaunchKernelGGL(k_qr_settle, dim3(bx, c.max_n, c.B), dim3(256), 0, s, c.dev);
+    GHSVD_HIP(hipGetLastError());
+    return GHSVD_OK;
+}
+
+// Section 5: the hyperbolic QR of F with its pivoting, and the QR of G.  The
+// iteration sees G only through G^*G, so any square G_sq with G_sq^* G_sq =
+// P2^T G^* G P2 serves: the triangular factor of G's unpivoted QR with its
+// columns permuted by P2 afterwards (the caller gathers the columns of Gt by
+// the permutation).  That QR needs no pivot decision; its column step it
+// runs in the hyperbolic QR's step launch of iteration it.
 int run_reduction(const BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
                   hipStream_t s) {
     const int B = c.B;
@@ -852,6 +878,7 @@ int run_reduction(const BatchCtx &c, std::vector<int> &status, std::vector<int> 
         if (!P.reduce) continue;
         int rc = copy_cols(P.m, P.n, P.Fin, P.ldfin, P.Ft, P.ldft, nullptr, s);
         if (rc) return rc;
+        if ((rc = copy_cols(P.p, P.n, P.Gin, P.ldgin, P.Gt, P.ldgt, nullptr, s))) return rc;
         GHSVD_HIP(hipMemcpyAsync(P.Jw, P.Jin, (size_t)P.m, hipMemcpyDeviceToDevice, s));
     }
     const int *pc = c.pre_of(BatchCtx::kCols);
@@ -862,29 +889,19 @@ int run_reduction(const BatchCtx &c, std::vector<int> &status, std::vector<int> 
     hipLaunchKernelGGL(k_jqr_init, dim3(B), dim3(256), 0, s, c.dev);
     hipLaunchKernelGGL(k_jqr_colnorms, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, 0);
     // At most max_n steps (fewer when 2x2 pivots occur; extra ones only carry
-    // the state to the next parity).  Three launches per step.
+    // the state to the next parity).  Three launches per step; the third
+    // also carries G's column step it.
     for (int it = 0; it < c.max_n; ++it) {
         const int par = it & 1;
         hipLaunchKernelGGL(k_jqr_cross, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, par);
         hipLaunchKernelGGL(k_jqr_cross2, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, par);
-        hipLaunchKernelGGL(k_jqr_step, dim3(tot), dim3(kGridNT), jl_bytes, s, c.dev, pc, B, par);
+        hipLaunchKernelGGL(k_jqr_step, dim3(2 * tot), dim3(kGridNT), jl_bytes, s, c.dev, pc, B,
+                           par, tot, it);
     }
     hipLaunchKernelGGL(k_jqr_settle, dim3(B), dim3(256), 0, s, c.dev, c.max_n & 1);
     GHSVD_HIP(hipGetLastError());
-    for (int k = 0; k < B; ++k) {
-        const PencilDev &P = c.host[k];
-        if (!P.reduce) continue;
-        int rc = copy_cols(P.p, P.n, P.Gin, P.ldgin, P.Gt, P.ldgt, P.perm, s);
-        if (rc) return rc;
-    }
-    for (int k = 0; k < c.max_n; ++k)
-        hipLaunchKernelGGL(k_qr_step, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, k);
-    {
-        int bx = (c.max_rows + 255) / 256;
-        if (bx > 8) bx = 8;
-        hipLaunchKernelGGL(k_qr_settle, dim3(bx, c.max_n, B), dim3(256), 0, s, c.dev);
-    }
-    GHSVD_HIP(hipGetLastError());
+    int rc = qr_end(c, s);
+    if (rc) return rc;
     std::vector<int> out(2 * B);
     hipLaunchKernelGGL(k_jqr_status, dim3(1), dim3(256), 0, s, c.dev, B, c.done_dev);
     GHSVD_HIP(hipMemcpyAsync(out.data(), c.done_dev, sizeof(int) * 2 * B, hipMemcpyDeviceToHost, s));

@@ -301,7 +301,7 @@ int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *w
         if (P.reduce) {
             if ((rc = jsplit_map(P.n, P.Jw, P.rowmap, P.small + 1, s))) return rc;
             if ((rc = jqr_extract(P, P.Fw, P.ldf, P.rowmap, s))) return rc;
-            if ((rc = copy_cols(P.n, P.n, P.Gt, P.ldgt, P.Gw, P.ldg, nullptr, s))) return rc;
+            if ((rc = copy_cols(P.n, P.n, P.Gt, P.ldgt, P.Gw, P.ldg, P.perm, s))) return rc;
         } else {
             if ((rc = jsplit(P.m, P.n, P.Fin, P.ldfin, P.Jin, P.Fw, P.ldf, P.rowmap, P.small + 1, s)))
                 return rc;
@@ -672,7 +672,7 @@ extern "C" int ghsvd_reduce(int m, int n, int p, const double *F, int ldf, const
     if (n2x2) *n2x2 = n2[0];
     if (rst[0]) return rst[0];
     if ((rc = jqr_extract(d, reinterpret_cast<double2 *>(Fsq), ldfs, nullptr, s))) return rc;
-    if ((rc = copy_cols(n, n, d.Gt, d.ldgt, reinterpret_cast<double2 *>(Gsq), ldgs, nullptr, s)))
+    if ((rc = copy_cols(n, n, d.Gt, d.ldgt, reinterpret_cast<double2 *>(Gsq), ldgs, d.perm, s)))
         return rc;
     GHSVD_HIP(hipMemcpyAsync(Jsq, d.Jw, (size_t)n, hipMemcpyDeviceToDevice, s));
     GHSVD_HIP(hipMemcpyAsync(perm, d.perm, sizeof(int) * n, hipMemcpyDeviceToDevice, s));

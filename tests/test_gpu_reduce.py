@@ -25,16 +25,24 @@ def test_reduce_elementwise(oracle, number, n_override):
     assert np.array_equal(host(perm), perm_o)
     assert np.array_equal(host(Jsq), Jo)
     assert n2 == n2o
-    for A, B in ((host(Fsq), Fo), (host(Gsq), Go)):
+    # G's factor: the oracle's Householder QR of G (unpivoted), columns
+    # permuted by P2; its Gram equals that of the oracle's QR of G P2.
+    st_g, Rg = oracle.qr(np.asfortranarray(P.G))
+    assert st_g == 0
+    for A, B in ((host(Fsq), Fo), (host(Gsq), Rg[:, perm_o])):
         colscale = np.linalg.norm(B, axis=0)
         err = np.max(np.abs(A - B) / colscale[None, :])
         assert err < 1e-10, err
+    Gs = host(Gsq)
+    SG = Go.conj().T @ Go
+    assert np.abs(Gs.conj().T @ Gs - SG).max() < 1e-12 * np.abs(SG).max()
     # invariants of the square factors against the tall ones
     Fs = host(Fsq)
     H = P.F.conj().T @ (P.J[:, None] * P.F)
     Hp = H[np.ix_(perm_o, perm_o)]
     assert np.abs(Fs.conj().T @ (host(Jsq)[:, None] * Fs) - Hp).max() < 1e-11 * np.abs(H).max()
-    assert np.array_equal(np.tril(host(Gsq), -1), np.zeros((P.n, P.n)))
+    inv = np.argsort(perm_o)
+    assert np.array_equal(np.tril(Gs[:, inv], -1), np.zeros((P.n, P.n)))
 
 
 def test_reduce_isotropic_2x2():
