@@ -272,8 +272,8 @@ struct InnerStep {
 // LOOK = 1: (H, S) are the matrices before the update of step is - 1 (prev),
 // which the other wavefronts are applying at the same time, and each pivot
 // entry after that update is formed here from its 2x2 block and the two
-// transformations that touch it.  Lane l forms entry kind e = l / NP of
-// pair k = l % NP ((p, p), (q, q), (p, q)); lane k gathers its pair's six
+// transformations that touch it.  Lane l forms entry kind e = l / 16 of
+// pair k = l % 16 ((p, p), (q, q), (p, q)); lane k gathers its pair's six
 // entries and runs the FP64 2x2 step.
 // Look-ahead operands of lane l at inner step is (is >= 1), packed as bytes:
 // x = rows r0, r1 and columns c0, c1 of the 2x2 block of step is - 1 that
@@ -281,11 +281,29 @@ struct InnerStep {
 // ii, column slot kj and position jj; y = kNoEntry when the lane forms no
 // entry.  Filled once per launch from the closed-form ordering.
 constexpr unsigned kNoEntry = 0xffffffffu;
+// Lane of entry kind e of pair slot k in the pivot wavefront: k + 16 e, so
+// that lane k reaches the other two kinds with the 16- and 32-lane swaps.
+constexpr int kEntryStride = 16;
+constexpr int kEntryLanes = 3 * kEntryStride;
+
+// v from lane l + 16 (l < 16) and from lane l + 32 (l < 32).  Both sides of
+// each swap are v, so the swap's second result is the shifted copy.
+__device__ __forceinline__ double lane_plus16(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[1], (int)a[1]);
+}
+__device__ __forceinline__ double lane_plus32(double v) {
+    const unsigned lo = (unsigned)__double2loint(v), hi = (unsigned)__double2hiint(v);
+    const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    return __hiloint2double((int)b[1], (int)a[1]);
+}
 
 template <int PB>
 __device__ __forceinline__ uint2 lookahead_entry(const InnerOrder &ord, int is, int l, int c) {
-    constexpr int NP = PB / 2;
-    const int k = l % NP, e = l / NP;
+    const int k = l % kEntryStride, e = l / kEntryStride;
     int pp = -1, qq = -1;
     if (k < ord.slots()) ord.pair(is, k, pp, qq);
     if (!(k < ord.slots() && qq < c && e < 3)) return make_uint2(0u, kNoEntry);
@@ -299,24 +317,26 @@ __device__ __forceinline__ uint2 lookahead_entry(const InnerOrder &ord, int is, 
                       (unsigned)ki | (unsigned)ii << 8 | (unsigned)kj << 16 | (unsigned)jj << 24);
 }
 
+// te: this lane's look-ahead operands for step `is` (LOOK = 1), read from
+// the table by the caller one step ahead.
 template <int PB, int F32, int LOOK>
 __device__ __forceinline__ void inner_pivots(const InnerOrder &ord, int is, int c, double tol,
                                              int crit, const double2 (*H)[PB + 1],
                                              const double2 (*S)[PB + 1],
                                              const InnerStep<PB> &prev, InnerStep<PB> &next,
-                                             const uint2 *tab, double &cv, double &ct,
-                                             double &cbig, int *err) {
+                                             uint2 te, double &cv, double &ct, double &cbig,
+                                             int *err) {
     constexpr int NP = PB / 2;
+    static_assert(NP <= kEntryStride, "one lane per pair slot and entry kind");
     const int l = threadIdx.x;  // lane of wavefront 0
-    const int k = l % NP, e = l / NP;
+    const int k = l % kEntryStride, e = l / kEntryStride;
     bool live, mine;
-    uint2 te = make_uint2(0u, kNoEntry);
     int pp = -1, qq = -1;
     if (LOOK) {
-        // this lane's entry, and whether pair k is live (its (p,p) entry exists)
-        if (l < 3 * NP) te = tab[l];
-        live = __shfl((int)(te.y != kNoEntry), k, kWave) != 0;
+        // this lane's entry; for lanes k < NP, whether pair k is live (its
+        // (p,p) entry, formed by the lane itself, exists)
         mine = te.y != kNoEntry;
+        live = mine;
     } else {
         const int nsl = ord.slots();
         if (k < nsl) ord.pair(is, k, pp, qq);
@@ -335,30 +355,25 @@ __device__ __forceinline__ void inner_pivots(const InnerOrder &ord, int is, int 
             const int c0 = (te.x >> 16) & 0xff, c1 = te.x >> 24;
             const int ki = te.y & 0xff, ii = (te.y >> 8) & 0xff;
             const int kj = (te.y >> 16) & 0xff, jj = te.y >> 24;
-            double2 ra, rb, ca, cb;  // column ii of Z'_ki, column jj of Z'_kj
-            if (prev.act[ki]) {
-                ra = prev.z[ki][2 * ii];
-                rb = prev.z[ki][2 * ii + 1];
-            } else {
-                ra = ii ? zero : one;
-                rb = ii ? one : zero;
-            }
-            if (prev.act[kj]) {
-                ca = prev.z[kj][2 * jj];
-                cb = prev.z[kj][2 * jj + 1];
-            } else {
-                ca = jj ? zero : one;
-                cb = jj ? one : zero;
-            }
-            hv = macc2(ra, mac2(H[r0][c0], ca, H[r0][c1], cb), rb, mac2(H[r1][c0], ca, H[r1][c1], cb));
-            sv = macc2(ra, mac2(S[r0][c0], ca, S[r0][c1], cb), rb, mac2(S[r1][c0], ca, S[r1][c1], cb));
+            // every operand is read at once (one LDS round trip); the
+            // identity replaces an inactive slot's transformation by select
+            const int ai = prev.act[ki], aj = prev.act[kj];
+            const double2 za = prev.z[ki][2 * ii], zb = prev.z[ki][2 * ii + 1];
+            const double2 zc = prev.z[kj][2 * jj], zd = prev.z[kj][2 * jj + 1];
+            const double2 h00 = H[r0][c0], h01 = H[r0][c1], h10 = H[r1][c0], h11 = H[r1][c1];
+            const double2 s00 = S[r0][c0], s01 = S[r0][c1], s10 = S[r1][c0], s11 = S[r1][c1];
+            // column ii of Z'_ki, column jj of Z'_kj
+            const double2 ra = ai ? za : (ii ? zero : one), rb = ai ? zb : (ii ? one : zero);
+            const double2 ca = aj ? zc : (jj ? zero : one), cb = aj ? zd : (jj ? one : zero);
+            hv = macc2(ra, mac2(h00, ca, h01, cb), rb, mac2(h10, ca, h11, cb));
+            sv = macc2(ra, mac2(s00, ca, s01, cb), rb, mac2(s10, ca, s11, cb));
         }
     }
     // gather (p,p), (q,q), (p,q) of pair k into lane k (all lanes take part)
-    const double hpp = __shfl(hv.x, k, kWave), hqq = __shfl(hv.x, k + NP, kWave);
-    const double hpq_r = __shfl(hv.x, k + 2 * NP, kWave), hpq_i = __shfl(hv.y, k + 2 * NP, kWave);
-    const double spp = __shfl(sv.x, k, kWave), sqq = __shfl(sv.x, k + NP, kWave);
-    const double spq_r = __shfl(sv.x, k + 2 * NP, kWave), spq_i = __shfl(sv.y, k + 2 * NP, kWave);
+    const double hpp = hv.x, hqq = lane_plus16(hv.x);
+    const double hpq_r = lane_plus32(hv.x), hpq_i = lane_plus32(hv.y);
+    const double spp = sv.x, sqq = lane_plus16(sv.x);
+    const double spq_r = lane_plus32(sv.x), spq_i = lane_plus32(sv.y);
     if (l < NP) {
         int kind = kSkip;
         if (live) {
@@ -403,7 +418,7 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
     __shared__ double2 S[2][PB][PB + 1];
     __shared__ double2 Zs[PB][PB + 1];
     __shared__ InnerStep<PB> st[2];
-    __shared__ uint2 tab[PB][3 * NP];  // look-ahead operands per inner step and lane
+    __shared__ uint2 tab[PB][kEntryLanes];  // look-ahead operands per inner step and lane
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev A = PD[pk];
     if (step >= A.nb - 1 || flag[pk]) return;
@@ -438,24 +453,31 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
         S[0][i][j] = s;
         Zs[i][j] = cmk(i == j ? 1.0 : 0.0, 0.0);
     }
-    for (int idx = tid; idx < (nsteps - 1) * 3 * NP; idx += inner_threads<PB>()) {
-        const int is = 1 + idx / (3 * NP), l = idx % (3 * NP);
+    for (int idx = tid; idx < (nsteps - 1) * kEntryLanes; idx += inner_threads<PB>()) {
+        const int is = 1 + idx / kEntryLanes, l = idx % kEntryLanes;
         tab[is][l] = lookahead_entry<PB>(ord, is, l, c);
     }
     __syncthreads();
     const double tol = (F32 ? 0x1p-23 : 0x1p-52) * sqrt((double)c);
     double cv = 0.0, ct = 0.0, cbig = 0.0;
-    if (tid < kWave)
-        inner_pivots<PB, F32, 0>(ord, 0, c, tol, crit, H[0], S[0], st[1], st[0], nullptr, cv,
-                                 ct, cbig, &A.st->err);
+    // look-ahead operands of the next inner step, read one step ahead
+    uint2 te = make_uint2(0u, kNoEntry);
+    if (tid < kWave) {
+        if (nsteps > 1 && tid < kEntryLanes) te = tab[1][tid];
+        inner_pivots<PB, F32, 0>(ord, 0, c, tol, crit, H[0], S[0], st[1], st[0], te, cv, ct,
+                                 cbig, &A.st->err);
+    }
     __syncthreads();
     for (int s = 0; s < nsteps; ++s) {
         const int cur = s & 1, nxt = cur ^ 1;
         const InnerStep<PB> &now = st[cur];
         if (tid < kWave) {
-            if (s + 1 < nsteps)
+            if (s + 1 < nsteps) {
                 inner_pivots<PB, F32, 1>(ord, s + 1, c, tol, crit, H[cur], S[cur], now, st[nxt],
-                                         tab[s + 1], cv, ct, cbig, &A.st->err);
+                                         te, cv, ct, cbig, &A.st->err);
+                te = (s + 2 < nsteps && tid < kEntryLanes) ? tab[s + 2][tid]
+                                                            : make_uint2(0u, kNoEntry);
+            }
         } else {
             const double2 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0);
             const int t = tid - kWave;
