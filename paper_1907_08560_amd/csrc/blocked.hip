@@ -109,7 +109,7 @@ __global__ __launch_bounds__(kWave * kGramWaves) void k_blk_gram(const PencilDev
     const GPtr<C2> X(reinterpret_cast<const C2 *>(
         isF ? (F32 ? (const void *)A.F32 : (const void *)A.Fw)
             : (F32 ? (const void *)A.G32 : (const void *)A.Gw)));
-    const int nplus = isF ? A.small[1] : rows;
+    const int nplus = isF ? GPtr<int>(A.small).ld(1) : rows;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int i16 = lane & 15, kq = lane >> 4;
     GPtr<C2> col[NTD];
@@ -130,30 +130,32 @@ __global__ __launch_bounds__(kWave * kGramWaves) void k_blk_gram(const PencilDev
     C2 x[RW / 4][NTD];
 #pragma unroll
     for (int ks = 0; ks < RW / 4; ++ks) {
-        const int r = rb + 4 * ks;
         // every lane loads (a clamped, in-bounds address, so the value is
-        // finite); padding is zeroed by a 0/1 factor, with no branch
-        const bool okr = r < rows;
-        const int rc = okr ? r : rows - 1;
+        // finite); padding is zeroed by a 0/1 factor where it is used
+        const int r = rb + 4 * ks;
+        const int rc = r < rows ? r : rows - 1;
 #pragma unroll
-        for (int t = 0; t < NTD; ++t) {
-            const T msk = (okc[t] && okr) ? T(1) : T(0);
-            C2 v = col[t].ld(rc);
-            v.x *= msk;
-            v.y *= msk;
-            x[ks][t] = v;
-        }
+        for (int t = 0; t < NTD; ++t) x[ks][t] = col[t].ld(rc);
     }
+    // all loads are in flight before the first product: the products of
+    // the first rows start as their loads complete, while the rest arrive
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ks = 0; ks < RW / 4; ++ks) {
-        const T wgt = (rb + 4 * ks >= nplus) ? T(-1) : T(1);
+        const int r = rb + 4 * ks;
+        const bool okr = r < rows;
+        const T wgt = (r >= nplus) ? T(-1) : T(1);
+        T mb[NTD];
+#pragma unroll
+        for (int t = 0; t < NTD; ++t) mb[t] = (okc[t] && okr) ? T(1) : T(0);
         int q = 0;
 #pragma unroll
         for (int ti = 0; ti < NTD; ++ti)
 #pragma unroll
             for (int tj = ti; tj < NTD; ++tj, ++q) {
-                const T ar = wgt * x[ks][ti].x, ai = wgt * x[ks][ti].y;
-                const T br = x[ks][tj].x, bi = x[ks][tj].y;
+                const T fa = wgt * mb[ti];
+                const T ar = fa * x[ks][ti].x, ai = fa * x[ks][ti].y;
+                const T br = mb[tj] * x[ks][tj].x, bi = mb[tj] * x[ks][tj].y;
                 // conj(a) b
                 acc_re[q] = Mfma<T>::mma(ar, br, acc_re[q]);
                 acc_re[q] = Mfma<T>::mma(ai, bi, acc_re[q]);
@@ -429,7 +431,7 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
     const int ca = blk_width(A.n, A.w, a), cb = blk_width(A.n, A.w, b);
     const int c = ca + cb;
     if (c < 2) {
-        if (tid == 0) A.ntr[bpi] = 0;
+        if (tid == 0) GPtr<int>(A.ntr).st(bpi, 0);
         return;
     }
     // the latency-critical pivot wavefront issues first
@@ -557,11 +559,11 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
         ct = wave_sum(ct);
         cbig = wave_sum(cbig);
         if (tid == 0) {
-            A.ntr[bpi] = (int)ct;
-            unsigned long long *cn = A.bcnt + 3 * bpi;
-            cn[0] += (unsigned long long)cv;
-            cn[1] += (unsigned long long)ct;
-            cn[2] += (unsigned long long)cbig;
+            GPtr<int>(A.ntr).st(bpi, (int)ct);
+            const GPtr<unsigned long long> cn = GPtr<unsigned long long>(A.bcnt) + 3 * bpi;
+            cn.st(0, cn.ld(0) + (unsigned long long)cv);
+            cn.st(1, cn.ld(1) + (unsigned long long)ct);
+            cn.st(2, cn.ld(2) + (unsigned long long)cbig);
         }
     }
 }
@@ -623,7 +625,7 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
     if (step >= A.nb - 1 || flag[pk]) return;
     const int local = pencil_local(pre, pk, blockIdx.x);
     const int bpi = local / A.tu, g = local % A.tu;
-    if (A.ntr[bpi] == 0) return;
+    if (GPtr<int>(A.ntr).ld(bpi) == 0) return;
     int a, b;
     rr_pair(A.nb, step, bpi, a, b);
     const int ca = blk_width(A.n, A.w, a), cb = blk_width(A.n, A.w, b);
