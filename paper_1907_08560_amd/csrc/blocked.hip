@@ -619,7 +619,6 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
     constexpr bool F32 = sizeof(T) == 4;
     constexpr int NTD = PB / 16;  // output column tiles
     constexpr int KS = PB / 4;    // k-steps
-    __shared__ C2 Zl[PB][PB + 1];
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev A = PD[pk];
     if (step >= A.nb - 1 || flag[pk]) return;
@@ -641,6 +640,23 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
         const int cc = 4 * ks + kq;
         cofs[ks] = cc < c ? (long)blk_col(A.w, a, b, ca, cc) : -1;
     }
+    // the A operands Z^[4 ks + kq][16 ti + j] (Z^ column-major, PB x PB),
+    // read straight into registers, where they stay for all strips
+    C2 za[KS][NTD];
+    {
+        const long zb = (long)bpi * PB * PB;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int ti = 0; ti < NTD; ++ti) {
+                const long e = zb + (4 * ks + kq) + (long)PB * (ti * 16 + j);
+                if constexpr (F32) {
+                    za[ks][ti] = GPtr<float2>(A.zh32).ld(e);
+                } else {
+                    za[ks][ti] = GPtr<double2>(A.zh64).ld(e);
+                }
+            }
+    }
     C2 xb[KS], xn[KS];
     const int st0 = g * kUpdStrips * 4 + wv;
     {
@@ -658,22 +674,6 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
             xb[ks] = v;
         }
     }
-    for (int idx = tid; idx < PB * PB; idx += 256) {
-        C2 z;
-        if constexpr (F32) {
-            z = GPtr<float2>(A.zh32).ld((long)bpi * PB * PB + idx);
-        } else {
-            z = GPtr<double2>(A.zh64).ld((long)bpi * PB * PB + idx);
-        }
-        Zl[idx % PB][idx / PB] = z;
-    }
-    __syncthreads();
-    // the A operands (Z^[4 ks + kq][16 ti + j]) stay in registers for all strips
-    C2 za[KS][NTD];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int ti = 0; ti < NTD; ++ti) za[ks][ti] = Zl[4 * ks + kq][ti * 16 + j];
 #pragma unroll
     for (int it = 0; it < kUpdStrips; ++it) {
         const int st = st0 + 4 * it;
