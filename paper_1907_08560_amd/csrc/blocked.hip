@@ -575,12 +575,12 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
 // load the next strip while the matrix cores work on the current one.  A
 // wavefront forms the strip's transpose, D = Z^T X^T, with the 16x16x4
 // MFMA: lane j + 16 k loads row j of pivot column k (the B operand; 16
-// lanes read 16 consecutive rows of one column), the A operand Z^[k][i]
-// is staged once through LDS into registers, and lane l holds
+// lanes read 16 consecutive rows of one column), the A operands Z^[k][i]
+// are read once straight into registers, and lane l holds
 // D[i][l % 16] = (X Z^)[l % 16][i], so 16
 // lanes store 256 contiguous bytes of one column.  Every read of a strip
 // precedes its writes within the wavefront, and strips are disjoint.
-constexpr int kUpdStrips = 3;
+constexpr int kUpdStrips = 6;
 
 // Matrix, leading dimension and row of lane row j of strip st (F, G, Z
 // strips in that order); ok = 0 past the last row or the last strip.
