@@ -105,3 +105,18 @@ def test_mixed_blocked_sizes(oracle, n, s_lo, j_identity):
         lam, X, info = ghsvd.solve(F, J, G, precision=prec, variant=var)
         assert info["status"] == 0, (prec, var, info)
         assert rel_err(host(lam), lam_o) <= bound, (prec, var, rel_err(host(lam), lam_o))
+
+
+def test_mixed_fp32_stage_stops_before_cap_indefinite():
+    """With an indefinite J, FP32 rounding in the J-Grams keeps a floor of big
+    transformations; the FP32 stage must stop at that plateau (well before
+    its sweep cap) and the FP64 stage must still reach the FP64 result."""
+    P = synth.workload_pencil(3, n_override=1024)
+    F, J, G = to_dev(P)
+    lam64, _, i64 = ghsvd.solve(F, J, G, precision="fp64", variant="blocked")
+    lam, X, info = ghsvd.solve(F, J, G, precision="mixed", variant="blocked")
+    assert i64["status"] == 0 and info["status"] == 0, (i64, info)
+    assert 0 < info["sweeps_fp32"] < 40, info
+    assert rel_err(host(lam), host(lam64)) <= 1e-10
+    e_s, e_h, e_d = factor_invariants(P.F, P.J, P.G, host(lam), host(X))
+    assert e_s < 1e-9 and e_h < 1e-9 and e_d < 1e-9
