@@ -49,6 +49,11 @@ def pair_bytes(visited, transformed, mr, pr, n, fp32=False):
     return b / 2 if fp32 else b
 
 
+def block_width_for(n):
+    """The block width the library picks for a pencil of order n."""
+    return 16 if n >= 512 else 8
+
+
 def kernel_rooflines(times, info_sum, mr, pr, n, w, nbp, fp32_blocked=False):
     """Per-kind roofline over the timed region.  times[kind] = (ms, timed, launches)."""
     out = {}
@@ -199,7 +204,8 @@ def batched_workload(args, ghsvd, synth, torch, dev):
     paths = {}
     lams = {}
     for prec, var in (("fp64", "blocked"), ("mixed", "blocked"), ("fp64", "pointwise")):
-        kw = dict(precision=prec, variant=var, max_sweeps=args.max_sweeps)
+        kw = dict(precision=prec, variant=var, max_sweeps=args.max_sweeps,
+                  block_width=args.block_width)
         for _ in range(args.warmup):
             ghsvd.solve_batched(Fs, Js, Gs, **kw)
         torch.cuda.synchronize()
@@ -254,7 +260,8 @@ def time_paths(args, ghsvd, synth, torch, dev, pencils, paths_wanted):
     Gs = [q[2] for q in pencils]
     paths, lams = {}, {}
     for prec, var in paths_wanted:
-        kw = dict(precision=prec, variant=var, max_sweeps=args.max_sweeps)
+        kw = dict(precision=prec, variant=var, max_sweeps=args.max_sweeps,
+                  block_width=args.block_width)
         prime(ghsvd, synth, torch, dev, kw)
         for _ in range(args.warmup):
             ghsvd.solve_batched(Fs, Js, Gs, **kw)
@@ -343,6 +350,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-every", type=int, default=4)
     ap.add_argument("--max-sweeps", type=int, default=0)
+    ap.add_argument("--block-width", type=int, default=0, choices=[0, 8, 16, 32],
+                    help="blocked variant's block width (0: the library's choice)")
     ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4, 5],
                     help="2: the single n=1024 pencil (default); 3: one n=4096 pencil; "
                          "4: the batch of 64 pencils; 5: the batch of 16 large pencils")
@@ -380,7 +389,8 @@ def main():
     F = ghsvd.to_device_fortran(P.F, dev)
     G = ghsvd.to_device_fortran(P.G, dev)
     J = torch.from_numpy(P.J).to(dev)
-    kw = dict(precision=args.precision, variant=args.variant, max_sweeps=args.max_sweeps)
+    kw = dict(precision=args.precision, variant=args.variant, max_sweeps=args.max_sweeps,
+              block_width=args.block_width)
 
     dt, infos, lam, times = run_path(ghsvd, F, J, G, P, kw, args.steps, args.warmup,
                                      args.profile_every)
@@ -388,7 +398,7 @@ def main():
     info = infos[-1]
     isum = {k: sum(i[k] for i in infos) for k in ("pairs_visited", "pw_visited", "pw_transformed")}
     mr, pr, n = info["m_r"], info["p_r"], P.n
-    w = 16 if n >= 512 else 8  # the library's block width for this order
+    w = args.block_width or block_width_for(n)
     nb = -(-n // w)
     nb += nb & 1
     kr = kernel_rooflines(times, isum, mr, pr, n, w, nb // 2,
@@ -439,7 +449,8 @@ def main():
         for prec, var in (("fp64", "pointwise"), ("mixed", "blocked"), ("fp64", "blocked")):
             if prec == args.precision and var == args.variant:
                 continue
-            ckw = dict(precision=prec, variant=var, max_sweeps=args.max_sweeps)
+            ckw = dict(precision=prec, variant=var, max_sweeps=args.max_sweeps,
+                       block_width=args.block_width)
             cdt, cinf, clam, _ = run_path(ghsvd, F, J, G, P, ckw, 2, 1)
             emax, emed = lambda_errors(clam)
             comp[f"{prec}-{var}"] = {"ms_per_pencil": 1000.0 * cdt / 2,

@@ -60,7 +60,7 @@ typedef struct {
     int variant;        /* GHSVD_POINTWISE (Section 6.3) or GHSVD_BLOCKED (Section 6.4)   */
     int reduce;         /* 1: reduce to square factors first (Section 5) when m > n or
                            p > n; 0: sweep the tall factors as given                       */
-    int block_width;    /* blocked variant: block-column width w (8 or 16); 0 = auto        */
+    int block_width;    /* blocked variant: block-column width w (8, 16 or 32); 0 = auto    */
     int waves_per_pair; /* pointwise pair kernel: 64-lane wavefronts per pivot pair
                            (1, 2, 4, 8 or 16); 0 = auto                                    */
     int max_sweeps;     /* sweep cap C_max per precision stage; 0 -> 60 (Algorithm 2 uses
@@ -150,7 +150,7 @@ int ghsvd_solve_batched(int batch, const int *m, const int *n, const int *p,
  * how the same computation is laid onto the GPU).  Runs the one-time
  * reduction and one FP64 pointwise sweep on the given pencils for each
  * wavefronts-per-pair candidate (1, 2, 4, 8), and, for opt->variant ==
- * GHSVD_BLOCKED, one FP64 blocked sweep for each block width (8, 16) with
+ * GHSVD_BLOCKED, one FP64 blocked sweep for each block width (8, 16, 32) with
  * the best wavefront count; the sweep stages are timed with HIP events.  The
  * fastest pair is stored for the shape class (variant, precision, and the
  * base-2 classes of the batch size, the largest n and the largest swept row
@@ -158,8 +158,8 @@ int ghsvd_solve_batched(int batch, const int *m, const int *n, const int *p,
  * = 0 use it.  Inputs as ghsvd_solve_batched (device F, J, G; not modified);
  * work/lwork as there (lwork >= ghsvd_workspace_size_batched with
  * block_width = 0; NULL work allocates).  Outputs (host, each may be NULL):
- * *block_width, *waves_per_pair, trial_ms[6] (ms of the pointwise trials
- * for 1, 2, 4, 8 wavefronts, then of the blocked trials for w = 8, 16; -1
+ * *block_width, *waves_per_pair, trial_ms[7] (ms of the pointwise trials
+ * for 1, 2, 4, 8 wavefronts, then of the blocked trials for w = 8, 16, 32; -1
  * when not run).  Results of a solve depend on its launch parameters only
  * through rounding.
  */
@@ -222,7 +222,7 @@ int ghsvd_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, double *G,
 /*
  * Runs up to `nsweeps` Level-2 blocked FP64 sweeps (Section 6.4, one inner
  * sweep per block pivot) in place on F, G, Z (layout as ghsvd_sweeps) with
- * block width block_width (8 or 16; 0 = auto), stopping after a block sweep
+ * block width block_width (8, 16 or 32; 0 = auto), stopping after a block sweep
  * without big inner transformations.  Block b holds columns
  * [b w, min(b w + w, n)), nb = ceil(n / w) rounded up to even blocks are
  * paired by ghsvd_round_robin(nb); within a block pair (a, b) the pivot

@@ -108,6 +108,7 @@ struct PencilDev {
     double2 *part;   // [nbp][kf + kg][PB * PB] partial Grams
     double2 *zh64;   // [nbp][PB * PB]
     float2 *zh32;
+    double2 *gp;     // w = 32: [nbp][2][64 * 65 / 2] block-pivot Grams H^, S^, packed upper
     int *ntr;        // [nbp]
     unsigned long long *bcnt;  // [nbp * 3]
     double2 *tmp;    // hand-off product

@@ -186,6 +186,162 @@ __global__ __launch_bounds__(kWave * kGramWaves) void k_blk_gram(const PencilDev
     }
 }
 
+// ---------------------------------------------------------------------------
+// Block width 32: 64 pivot columns per block pair.
+// ---------------------------------------------------------------------------
+// Partial Grams over 128-row chunks.  The chunk is staged through LDS in two
+// 64-row halves (the second half's loads are in flight while the first half
+// is multiplied); wavefront t forms the upper 16x16 tile t of the 4x4 tile
+// grid over all rows of the chunk, so no reduction across wavefronts is
+// needed.  Tiles are written in the MFMA result layout; k_blk_gsum64 adds
+// the chunks.  Padding columns (>= c) and rows past the end read as zero.
+constexpr int kG64Chunk = 128;
+constexpr int kG64Half = 64;
+constexpr int kG64Tiles = 10;
+constexpr int kG64Packed = 64 * 65 / 2;  // packed upper triangle of 64 x 64
+
+// Upper tile t of the 4x4 grid: (0,0) (0,1) (0,2) (0,3) (1,1) (1,2) (1,3)
+// (2,2) (2,3) (3,3).
+__device__ __forceinline__ void tile_of(int t, int &ti, int &tj) {
+    ti = t < 4 ? 0 : (t < 7 ? 1 : (t < 9 ? 2 : 3));
+    const int first = ti == 0 ? 0 : (ti == 1 ? 4 : (ti == 2 ? 7 : 9));
+    tj = ti + (t - first);
+}
+
+// Packed upper triangle, column by column: entry (i, j), i <= j.
+__device__ __forceinline__ int pk_idx(int i, int j) { return ((j * (j + 1)) >> 1) + i; }
+
+template <typename T>
+__global__ __launch_bounds__(kWave * kG64Tiles) void k_blk_gram64(const PencilDev *PD,
+                                                                 const int *pre, const int *flag,
+                                                                 int B, int step) {
+    using C2 = typename Mfma<T>::c2;
+    using ACC = typename Mfma<T>::acc;
+    constexpr bool F32 = sizeof(T) == 4;
+    constexpr int PB = 64;
+    constexpr int NT = kWave * kG64Tiles;
+    constexpr int PER = (kG64Half * PB + NT - 1) / NT;  // staged elements per thread
+    __shared__ C2 Xs[2][kG64Half][PB + 1];
+    const int pk = find_pencil(pre, B, blockIdx.x);
+    const PencilDev A = PD[pk];
+    if (step >= A.nb - 1 || flag[pk]) return;
+    const int local = pencil_local(pre, pk, blockIdx.x);
+    const int KC = A.kf + A.kg;
+    const int bpi = local / KC, kc = local % KC;
+    int a, b;
+    rr_pair(A.nb, step, bpi, a, b);
+    const int ca = blk_width(A.n, A.w, a), cb = blk_width(A.n, A.w, b);
+    const int c = ca + cb;
+    if (c < 2) return;
+    const bool isF = kc < A.kf;
+    const int r0 = (isF ? kc : kc - A.kf) * kG64Chunk;
+    const int rows = isF ? A.mr : A.pr;
+    const long ld = isF ? A.ldf : A.ldg;
+    const GPtr<C2> X(reinterpret_cast<const C2 *>(
+        isF ? (F32 ? (const void *)A.F32 : (const void *)A.Fw)
+            : (F32 ? (const void *)A.G32 : (const void *)A.Gw)));
+    const int nplus = isF ? GPtr<int>(A.small).ld(1) : rows;
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // element u of this thread in a half: column cc = e / 64, row e % 64
+    C2 v[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = tid + u * NT, cc = e / kG64Half, r = r0 + e % kG64Half;
+        const int rc = r < rows ? r : rows - 1;
+        const long col = cc < c ? (long)blk_col(A.w, a, b, ca, cc) : 0L;
+        v[u] = X.ld(col * ld + rc);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = tid + u * NT, cc = e / kG64Half, rl = e % kG64Half;
+        if (e < kG64Half * PB) {
+            const T m = (cc < c && r0 + rl < rows) ? T(1) : T(0);
+            C2 x = v[u];
+            x.x *= m;
+            x.y *= m;
+            Xs[0][rl][cc] = x;
+        }
+    }
+    __syncthreads();
+    // the second half's loads, in flight during the first half's products
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = tid + u * NT, cc = e / kG64Half, r = r0 + kG64Half + e % kG64Half;
+        const int rc = r < rows ? r : rows - 1;
+        const long col = cc < c ? (long)blk_col(A.w, a, b, ca, cc) : 0L;
+        v[u] = X.ld(col * ld + rc);
+    }
+    int ti, tj;
+    tile_of(wv, ti, tj);
+    const int i16 = lane & 15, kq = lane >> 4;
+    ACC acc_re = ACC{0, 0, 0, 0}, acc_im = ACC{0, 0, 0, 0};
+#pragma unroll 4
+    for (int ks = 0; ks < kG64Half / 4; ++ks) {
+        const int rl = 4 * ks + kq;
+        const T wgt = (r0 + rl >= nplus) ? T(-1) : T(1);
+        const C2 xa = Xs[0][rl][ti * 16 + i16], xb = Xs[0][rl][tj * 16 + i16];
+        const T ar = wgt * xa.x, ai = wgt * xa.y;
+        // conj(a) b
+        acc_re = Mfma<T>::mma(ar, xb.x, acc_re);
+        acc_re = Mfma<T>::mma(ai, xb.y, acc_re);
+        acc_im = Mfma<T>::mma(ar, xb.y, acc_im);
+        acc_im = Mfma<T>::mma(-ai, xb.x, acc_im);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int e = tid + u * NT, cc = e / kG64Half, rl = e % kG64Half;
+        if (e < kG64Half * PB) {
+            const T m = (cc < c && r0 + kG64Half + rl < rows) ? T(1) : T(0);
+            C2 x = v[u];
+            x.x *= m;
+            x.y *= m;
+            Xs[1][rl][cc] = x;
+        }
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int ks = 0; ks < kG64Half / 4; ++ks) {
+        const int rl = 4 * ks + kq;
+        const T wgt = (r0 + kG64Half + rl >= nplus) ? T(-1) : T(1);
+        const C2 xa = Xs[1][rl][ti * 16 + i16], xb = Xs[1][rl][tj * 16 + i16];
+        const T ar = wgt * xa.x, ai = wgt * xa.y;
+        acc_re = Mfma<T>::mma(ar, xb.x, acc_re);
+        acc_re = Mfma<T>::mma(ai, xb.y, acc_re);
+        acc_im = Mfma<T>::mma(ar, xb.y, acc_im);
+        acc_im = Mfma<T>::mma(-ai, xb.x, acc_im);
+    }
+    const GPtr<double2> P(A.part + (((size_t)bpi * KC + kc) * kG64Tiles + wv) * 256);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) P.st(r * 64 + lane, cmk((double)acc_re[r], (double)acc_im[r]));
+}
+
+// Adds the chunk partials of upper tile t (blockIdx.y % 10) of H^ (chunks
+// over F) or S^ (over G, blockIdx.y >= 10) of one block pair in chunk order,
+// and writes the tile's entries on and above the diagonal, packed, for the
+// inner sweep.
+template <typename T>
+__global__ __launch_bounds__(256) void k_blk_gsum64(const PencilDev *PD, const int *pre,
+                                                    const int *flag, int B, int step) {
+    const int pk = find_pencil(pre, B, blockIdx.x);
+    const PencilDev A = PD[pk];
+    if (step >= A.nb - 1 || flag[pk]) return;
+    const int bpi = pencil_local(pre, pk, blockIdx.x);
+    int a, b;
+    rr_pair(A.nb, step, bpi, a, b);
+    if (blk_width(A.n, A.w, a) + blk_width(A.n, A.w, b) < 2) return;
+    const int mat = blockIdx.y / kG64Tiles, t = blockIdx.y % kG64Tiles;
+    const int KC = A.kf + A.kg;
+    const int k0 = mat ? A.kf : 0, k1 = mat ? KC : A.kf;
+    const int e = threadIdx.x, r = e / 64, ln = e % 64;
+    const GPtr<double2> P(A.part);
+    double2 sum = cmk(0.0, 0.0);
+    for (int k = k0; k < k1; ++k) sum = cadd(sum, P.ld((((long)bpi * KC + k) * kG64Tiles + t) * 256 + e));
+    int ti, tj;
+    tile_of(t, ti, tj);
+    const int i = ti * 16 + Mfma<T>::row(ln, r), j = tj * 16 + (ln & 15);
+    if (i <= j) GPtr<double2>(A.gp).st(((long)bpi * 2 + mat) * kG64Packed + pk_idx(i, j), sum);
+}
+
 // r^* M c for one entry of a 2x2 block M = [[m00, m01], [m10, m11]]:
 // x_a = m_a0 c0 + m_a1 c1, then conj(r0) x_0 + conj(r1) x_1.  The block
 // update and the look-ahead of the pivot wavefront evaluate these same
@@ -568,6 +724,307 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
     }
 }
 
+// Inner sweep for 64 pivot columns.  (H^, S^) are kept in LDS as packed
+// upper triangles, single-buffered and updated in place; Z^ is a full 64 x 64
+// LDS array (column-major).  An inner step runs in two phases separated by a
+// barrier: every thread first reads what the step needs (the pivot
+// wavefront its look-ahead operands for the next step, each block thread its
+// 2x2 blocks), then the block threads write their updated blocks while the
+// pivot wavefront computes the next step's 2x2 steps and the Z^ threads
+// update Z^.  Threads: the pivot wavefront (lanes 0-31 form the (p,p) and
+// (p,q) entries of pair k = lane and run its 2x2 step, lanes 32-63 form the
+// (q,q) entries), one thread per unordered pair of pair slots {kr <= kc}
+// (528; it forms Z_kr^* M Z_kc and stores the entries on or above the
+// diagonal, conjugated where the block lies below it), and 432 threads for
+// row segments of Z^ (row i, slot k), which also build the next-but-one
+// step's look-ahead table.  The look-ahead forms each entry in the
+// orientation of the thread that stores it (rows from the smaller slot,
+// conjugated after), so the two agree bit for bit.
+constexpr int kI64Threads = 1024;
+constexpr int kI64Blocks = 32 * 33 / 2;
+constexpr int kI64ZThreads = kI64Threads - kWave - kI64Blocks;
+
+__device__ __forceinline__ double2 hget(const double2 *M, int i, int j) {
+    return i <= j ? M[pk_idx(i, j)] : cconj(M[pk_idx(j, i)]);
+}
+
+// Look-ahead operands of entry kind e ((p,p), (q,q), (p,q)) of pair slot k
+// at inner step is >= 1, packed as for lookahead_entry; bit 1 of the byte
+// of ii marks an entry formed transposed and conjugated after.
+__device__ __forceinline__ uint2 lookahead64(const InnerOrder &ord, int is, int k, int e, int c) {
+    int pp = -1, qq = -1;
+    if (k < ord.slots()) ord.pair(is, k, pp, qq);
+    if (!(k < ord.slots() && qq < c)) return make_uint2(0u, kNoEntry);
+    int i = (e == 1) ? qq : pp, j = (e == 0) ? pp : qq;
+    int ki, ii, kj, jj;
+    ord.where(is - 1, i, ki, ii);
+    ord.where(is - 1, j, kj, jj);
+    int cj = 0;
+    if (ki > kj) {
+        int t = ki;
+        ki = kj;
+        kj = t;
+        t = ii;
+        ii = jj;
+        jj = t;
+        cj = 1;
+    }
+    int r0, r1, c0, c1;
+    ord.pair(is - 1, ki, r0, r1);
+    ord.pair(is - 1, kj, c0, c1);
+    return make_uint2((unsigned)r0 | (unsigned)r1 << 8 | (unsigned)c0 << 16 | (unsigned)c1 << 24,
+                      (unsigned)ki | (unsigned)(ii | cj << 1) << 8 | (unsigned)kj << 16 |
+                          (unsigned)jj << 24);
+}
+
+// One look-ahead entry: r^* M c over the 2x2 block of the previous step
+// (same expressions as the block update), from the packed matrix.
+__device__ __forceinline__ double2 lookahead_value(const double2 *M, uint2 te,
+                                                   const InnerStep<64> &prev) {
+    const double2 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0);
+    const int r0 = te.x & 0xff, r1 = (te.x >> 8) & 0xff;
+    const int c0 = (te.x >> 16) & 0xff, c1 = te.x >> 24;
+    const int ki = te.y & 0xff, iib = (te.y >> 8) & 0xff;
+    const int kj = (te.y >> 16) & 0xff, jj = te.y >> 24;
+    const int ii = iib & 1;
+    const int ai = prev.act[ki], aj = prev.act[kj];
+    const double2 za = prev.z[ki][2 * ii], zb = prev.z[ki][2 * ii + 1];
+    const double2 zc = prev.z[kj][2 * jj], zd = prev.z[kj][2 * jj + 1];
+    const double2 h00 = hget(M, r0, c0), h01 = hget(M, r0, c1);
+    const double2 h10 = hget(M, r1, c0), h11 = hget(M, r1, c1);
+    const double2 ra = ai ? za : (ii ? zero : one), rb = ai ? zb : (ii ? one : zero);
+    const double2 ca = aj ? zc : (jj ? zero : one), cb = aj ? zd : (jj ? one : zero);
+    const double2 v = macc2(ra, mac2(h00, ca, h01, cb), rb, mac2(h10, ca, h11, cb));
+    return (iib & 2) ? cconj(v) : v;
+}
+
+template <int F32>
+__global__ __launch_bounds__(kI64Threads) void k_blk_inner64(const PencilDev *PD, const int *pre,
+                                                            const int *flag, int B, int crit,
+                                                            int step, int cross_mode) {
+    constexpr int PB = 64, NP = 32;
+    __shared__ double2 H[kG64Packed];
+    __shared__ double2 S[kG64Packed];
+    __shared__ double2 Zs[PB][PB + 1];  // Zs[column][row]
+    __shared__ InnerStep<PB> st[2];
+    __shared__ uint2 tab[2][3 * NP];     // look-ahead operands, by step parity
+    const int pk = find_pencil(pre, B, blockIdx.x);
+    const PencilDev A = PD[pk];
+    if (step >= A.nb - 1 || flag[pk]) return;
+    const int bpi = pencil_local(pre, pk, blockIdx.x);
+    const int tid = threadIdx.x;
+    int a, b;
+    rr_pair(A.nb, step, bpi, a, b);
+    const int ca = blk_width(A.n, A.w, a), cb = blk_width(A.n, A.w, b);
+    const int c = ca + cb;
+    if (c < 2) {
+        if (tid == 0) GPtr<int>(A.ntr).st(bpi, 0);
+        return;
+    }
+    if (tid < kWave) __builtin_amdgcn_s_setprio(3);
+    InnerOrder ord;
+    ord.cross = cross_mode && step > 0 && ca == NP && cb == NP;
+    ord.C = c + (c & 1);
+    ord.w = NP;
+    const int nsteps = ord.steps(), nsl = ord.slots();
+    // this thread's block slots (block threads) or Z^ lane (Z^ threads)
+    const int tb = tid - kWave, tz = tb - kI64Blocks;
+    int kr = 0, kc = 0;
+    if (tb >= 0 && tb < kI64Blocks) {
+        kc = (int)((sqrtf(8.0f * (float)tb + 1.0f) - 1.0f) * 0.5f);
+        while ((kc + 1) * (kc + 2) / 2 <= tb) ++kc;
+        while (kc * (kc + 1) / 2 > tb) --kc;
+        kr = tb - kc * (kc + 1) / 2;
+    }
+    {
+        const GPtr<double2> G(A.gp + (size_t)bpi * 2 * kG64Packed);
+        for (int idx = tid; idx < kG64Packed; idx += kI64Threads) {
+            H[idx] = G.ld(idx);
+            S[idx] = G.ld(kG64Packed + idx);
+        }
+        for (int idx = tid; idx < PB * PB; idx += kI64Threads) {
+            const int col = idx / PB, row = idx % PB;
+            Zs[col][row] = cmk(row == col ? 1.0 : 0.0, 0.0);
+        }
+        if (nsteps > 1 && tid < 3 * NP)
+            tab[1][tid] = lookahead64(ord, 1, tid % NP, tid / NP, c);
+    }
+    __syncthreads();
+    const double tol = (F32 ? 0x1p-23 : 0x1p-52) * sqrt((double)c);
+    double cv = 0.0, ct = 0.0, cbig = 0.0;
+    // the 2x2 steps of inner step 0 from the entries as stored
+    if (tid < NP) {
+        const int k = tid;
+        int pp = -1, qq = -1;
+        if (k < nsl) ord.pair(0, k, pp, qq);
+        int kind = kSkip;
+        if (k < nsl && qq < c) {
+            const double2 hpq = hget(H, pp, qq), spq = hget(S, pp, qq);
+            Zp z;
+            kind = hz_step_fast(H[pk_idx(pp, pp)].x, H[pk_idx(qq, qq)].x, hpq, S[pk_idx(pp, pp)].x,
+                                S[pk_idx(qq, qq)].x, spq, tol, crit, z, F32);
+            cv += 1.0;
+            if (kind == GHSVD_ENONFINITE) atomicCAS(&A.st->err, 0, GHSVD_ENONFINITE);
+            if (kind < 0) kind = kSkip;
+            st[0].z[k][0] = z.z11;
+            st[0].z[k][1] = z.z21;
+            st[0].z[k][2] = z.z12;
+            st[0].z[k][3] = z.z22;
+            ct += kind > 0 ? 1.0 : 0.0;
+            cbig += kind == kBig ? 1.0 : 0.0;
+        }
+        st[0].act[k] = kind > 0;
+    }
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+        const int cur = s & 1, nxt = cur ^ 1;
+        const InnerStep<PB> &now = st[cur];
+        // ---- phase 1: reads ----
+        double2 hv0 = cmk(0.0, 0.0), sv0 = hv0, hv2 = hv0, sv2 = hv0;
+        bool mine0 = false, mine2 = false;
+        double2 bh[4], bs[4];
+        int p1 = 0, q1 = 0, p2 = 0, q2 = 0;
+        bool blk = false;
+        if (tid < kWave) {
+            if (s + 1 < nsteps) {
+                const uint2 te0 = tab[(s + 1) & 1][tid];  // (p,p) for lanes < 32, (q,q) above
+                mine0 = te0.y != kNoEntry;
+                if (mine0) {
+                    hv0 = lookahead_value(H, te0, now);
+                    sv0 = lookahead_value(S, te0, now);
+                }
+                if (tid < NP) {
+                    const uint2 te2 = tab[(s + 1) & 1][2 * NP + tid];  // (p,q)
+                    mine2 = te2.y != kNoEntry;
+                    if (mine2) {
+                        hv2 = lookahead_value(H, te2, now);
+                        sv2 = lookahead_value(S, te2, now);
+                    }
+                }
+            }
+        } else if (tb < kI64Blocks) {
+            blk = kr < nsl && kc < nsl && (now.act[kr] || now.act[kc]);
+            if (blk) {
+                ord.pair(s, kr, p1, q1);
+                ord.pair(s, kc, p2, q2);
+                bh[0] = hget(H, p1, p2);
+                bh[1] = hget(H, p1, q2);
+                bh[2] = hget(H, q1, p2);
+                bh[3] = hget(H, q1, q2);
+                bs[0] = hget(S, p1, p2);
+                bs[1] = hget(S, p1, q2);
+                bs[2] = hget(S, q1, p2);
+                bs[3] = hget(S, q1, q2);
+            }
+        }
+        __syncthreads();
+        // ---- phase 2: writes ----
+        if (tid < kWave) {
+            if (s + 1 < nsteps) {
+                // gather (q,q) of pair k from lane k + 32 (every lane takes part)
+                const double hqq = lane_plus32(hv0.x), sqq = lane_plus32(sv0.x);
+                if (tid < NP) {
+                    const int k = tid;
+                    int kind = kSkip;
+                    if (mine0 && mine2) {
+                        Zp z;
+                        kind = hz_step_fast(hv0.x, hqq, hv2, sv0.x, sqq, sv2, tol, crit, z, F32);
+                        cv += 1.0;
+                        if (kind == GHSVD_ENONFINITE) atomicCAS(&A.st->err, 0, GHSVD_ENONFINITE);
+                        if (kind < 0) kind = kSkip;
+                        st[nxt].z[k][0] = z.z11;
+                        st[nxt].z[k][1] = z.z21;
+                        st[nxt].z[k][2] = z.z12;
+                        st[nxt].z[k][3] = z.z22;
+                        ct += kind > 0 ? 1.0 : 0.0;
+                        cbig += kind == kBig ? 1.0 : 0.0;
+                    }
+                    st[nxt].act[k] = kind > 0;
+                }
+            }
+        } else if (tb < kI64Blocks) {
+            if (blk) {
+                const double2 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0);
+                const bool ar = now.act[kr], ac = now.act[kc];
+                double2 r11 = one, r21 = zero, r12 = zero, r22 = one;
+                double2 c11 = one, c21 = zero, c12 = zero, c22 = one;
+                if (ar) {
+                    r11 = now.z[kr][0];
+                    r21 = now.z[kr][1];
+                    r12 = now.z[kr][2];
+                    r22 = now.z[kr][3];
+                }
+                if (ac) {
+                    c11 = now.z[kc][0];
+                    c21 = now.z[kc][1];
+                    c12 = now.z[kc][2];
+                    c22 = now.z[kc][3];
+                }
+                double2 *M = H;
+                double2 *m = bh;
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    const double2 x11 = mac2(m[0], c11, m[1], c21), x12 = mac2(m[0], c12, m[1], c22);
+                    const double2 x21 = mac2(m[2], c11, m[3], c21), x22 = mac2(m[2], c12, m[3], c22);
+                    const double2 n11 = macc2(r11, x11, r21, x21), n12 = macc2(r11, x12, r21, x22);
+                    const double2 n21 = macc2(r12, x11, r22, x21), n22 = macc2(r12, x12, r22, x22);
+                    if (kr == kc) {
+                        // the diagonal block: (p,p), (q,q) and one of (p,q), (q,p)
+                        M[pk_idx(p1, p1)] = n11;
+                        M[pk_idx(q1, q1)] = n22;
+                        if (p1 < q1) M[pk_idx(p1, q1)] = n12;
+                        else M[pk_idx(q1, p1)] = n21;
+                    } else {
+                        if (p1 <= p2) M[pk_idx(p1, p2)] = n11; else M[pk_idx(p2, p1)] = cconj(n11);
+                        if (p1 <= q2) M[pk_idx(p1, q2)] = n12; else M[pk_idx(q2, p1)] = cconj(n12);
+                        if (q1 <= p2) M[pk_idx(q1, p2)] = n21; else M[pk_idx(p2, q1)] = cconj(n21);
+                        if (q1 <= q2) M[pk_idx(q1, q2)] = n22; else M[pk_idx(q2, q1)] = cconj(n22);
+                    }
+                    M = S;
+                    m = bs;
+                }
+            }
+        } else {
+            // Z^ <- Z^ Z_k on the columns of each active slot k, row by row
+            for (int u = tz; u < PB * NP; u += kI64ZThreads) {
+                const int row = u % PB, k = u / PB;
+                if (k < nsl && now.act[k]) {
+                    int pp, qq;
+                    ord.pair(s, k, pp, qq);
+                    const double2 c11 = now.z[k][0], c21 = now.z[k][1];
+                    const double2 c12 = now.z[k][2], c22 = now.z[k][3];
+                    const double2 w1 = Zs[pp][row], w2 = Zs[qq][row];
+                    Zs[pp][row] = mac2(w1, c11, w2, c21);
+                    Zs[qq][row] = mac2(w1, c12, w2, c22);
+                }
+            }
+            if (s + 2 < nsteps && tz < 3 * NP)
+                tab[s & 1][tz] = lookahead64(ord, s + 2, tz % NP, tz / NP, c);
+        }
+        __syncthreads();
+    }
+    const GPtr<double2> Z64(A.zh64 + (size_t)bpi * PB * PB);
+    const GPtr<float2> Z32(F32 ? A.zh32 + (size_t)bpi * PB * PB : A.zh32);
+    for (int idx = tid; idx < PB * PB; idx += kI64Threads) {
+        const int i = idx % PB, j = idx / PB;
+        const double2 z = Zs[j][i];
+        Z64.st(idx, z);
+        if (F32) Z32.st(idx, make_float2((float)z.x, (float)z.y));
+    }
+    if (tid < kWave) {
+        cv = wave_sum(cv);
+        ct = wave_sum(ct);
+        cbig = wave_sum(cbig);
+        if (tid == 0) {
+            GPtr<int>(A.ntr).st(bpi, (int)ct);
+            const GPtr<unsigned long long> cn = GPtr<unsigned long long>(A.bcnt) + 3 * bpi;
+            cn.st(0, cn.ld(0) + (unsigned long long)cv);
+            cn.st(1, cn.ld(1) + (unsigned long long)ct);
+            cn.st(2, cn.ld(2) + (unsigned long long)cbig);
+        }
+    }
+}
+
 // F_C <- F_C Z^, G_C <- G_C Z^, Z_C <- Z_C Z^ for one block pair, in place
 // (Section 6.4.3), skipped when the inner sweep applied no transformation.
 // The rows of F, G and Z form 16-row strips (tf + tg + tz of them); a
@@ -581,6 +1038,10 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
 // lanes store 256 contiguous bytes of one column.  Every read of a strip
 // precedes its writes within the wavefront, and strips are disjoint.
 constexpr int kUpdStrips = 6;
+// Strips per wavefront of the update: the 64-column form does four times the
+// products per strip, and takes fewer strips so that a 1024-column pencil
+// still spreads over every CU.
+__host__ __device__ constexpr int upd_strips(int w) { return w == 32 ? 3 : kUpdStrips; }
 
 // Matrix, leading dimension and row of lane row j of strip st (F, G, Z
 // strips in that order); ok = 0 past the last row or the last strip.
@@ -619,6 +1080,10 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
     constexpr bool F32 = sizeof(T) == 4;
     constexpr int NTD = PB / 16;  // output column tiles
     constexpr int KS = PB / 4;    // k-steps
+    constexpr int NS = upd_strips(PB / 2);  // strips per wavefront
+    // 64 columns: Z^ is staged in LDS (its operands do not fit in registers)
+    constexpr bool ZL = PB > 32;
+    __shared__ C2 Zl[ZL ? PB : 1][ZL ? PB + 1 : 1];
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev A = PD[pk];
     if (step >= A.nb - 1 || flag[pk]) return;
@@ -640,10 +1105,21 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
         const int cc = 4 * ks + kq;
         cofs[ks] = cc < c ? (long)blk_col(A.w, a, b, ca, cc) : -1;
     }
-    // the A operands Z^[4 ks + kq][16 ti + j] (Z^ column-major, PB x PB),
-    // read straight into registers, where they stay for all strips
-    C2 za[KS][NTD];
-    {
+    // the A operands Z^[4 ks + kq][16 ti + j] (Z^ column-major, PB x PB):
+    // read straight into registers, where they stay for all strips (32
+    // columns), or staged once in LDS (64 columns)
+    C2 za[ZL ? 1 : KS][NTD];
+    if constexpr (ZL) {
+        for (int idx = tid; idx < PB * PB; idx += 256) {
+            const long e = (long)bpi * PB * PB + idx;
+            if constexpr (F32) {
+                Zl[idx % PB][idx / PB] = GPtr<float2>(A.zh32).ld(e);
+            } else {
+                Zl[idx % PB][idx / PB] = GPtr<double2>(A.zh64).ld(e);
+            }
+        }
+        __syncthreads();
+    } else {
         const long zb = (long)bpi * PB * PB;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks)
@@ -658,7 +1134,7 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
             }
     }
     C2 xb[KS], xn[KS];
-    const int st0 = g * kUpdStrips * 4 + wv;
+    const int st0 = g * NS * 4 + wv;
     {
         long ld;
         int row;
@@ -675,9 +1151,9 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
         }
     }
 #pragma unroll
-    for (int it = 0; it < kUpdStrips; ++it) {
+    for (int it = 0; it < NS; ++it) {
         const int st = st0 + 4 * it;
-        if (it + 1 < kUpdStrips) {
+        if (it + 1 < NS) {
             long ld;
             int row;
             bool ok;
@@ -703,7 +1179,12 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
         for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
             for (int ti = 0; ti < NTD; ++ti) {
-                const C2 z = za[ks][ti];
+                C2 z;
+                if constexpr (ZL) {
+                    z = Zl[4 * ks + kq][ti * 16 + j];
+                } else {
+                    z = za[ks][ti];
+                }
                 // (X Z^) = X_re Z_re - X_im Z_im + i (X_re Z_im + X_im Z_re)
                 acc_re[ti] = Mfma<T>::mma(z.x, xb[ks].x, acc_re[ti]);
                 acc_re[ti] = Mfma<T>::mma(-z.y, xb[ks].y, acc_re[ti]);
@@ -730,7 +1211,7 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
                     }
             }
         }
-        if (it + 1 < kUpdStrips) {
+        if (it + 1 < NS) {
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) xb[ks] = xn[ks];
         }
@@ -830,16 +1311,17 @@ void set_block_geometry(PencilDev &d, int w) {
     d.nb = (d.n + w - 1) / w;
     if (d.nb & 1) d.nb += 1;
     d.nbp = d.nb / 2;
-    d.kf = (d.mr + kGramChunk - 1) / kGramChunk;
-    d.kg = (d.pr + kGramChunk - 1) / kGramChunk;
+    const int chunk = w == 32 ? kG64Chunk : kGramChunk;
+    d.kf = (d.mr + chunk - 1) / chunk;
+    d.kg = (d.pr + chunk - 1) / chunk;
     d.tf = (d.mr + 15) / 16;
     d.tg = (d.pr + 15) / 16;
     d.tz = (d.n + 15) / 16;
-    d.tu = (d.tf + d.tg + d.tz + 4 * kUpdStrips - 1) / (4 * kUpdStrips);
+    d.tu = (d.tf + d.tg + d.tz + 4 * upd_strips(w) - 1) / (4 * upd_strips(w));
 }
 
 int pick_block_width(int max_n, int requested) {
-    if (requested == 8 || requested == 16) return requested;
+    if (requested == 8 || requested == 16 || requested == 32) return requested;
     return max_n >= 512 ? 16 : 8;
 }
 
@@ -853,6 +1335,7 @@ void carve_blocked(Carver &c, int mr, int n, int pr, int w, int mixed, PencilDev
     d.part = c.take<double2>((size_t)g.nbp * (g.kf + g.kg) * pb2);
     d.zh64 = c.take<double2>((size_t)g.nbp * pb2);
     d.zh32 = c.take<float2>((size_t)g.nbp * pb2);
+    d.gp = w == 32 ? c.take<double2>((size_t)g.nbp * 2 * kG64Packed) : nullptr;
     d.ntr = c.take<int>(g.nbp);
     d.bcnt = c.take<unsigned long long>(3 * (size_t)g.nbp);
     if (mixed) {
@@ -872,7 +1355,7 @@ using BlkFn = void (*)(const PencilDev *, const int *, const int *, int, int);
 using BlkInnerFn = void (*)(const PencilDev *, const int *, const int *, int, int, int, int);
 
 struct BlockedArg {
-    BlkFn gram, upd;
+    BlkFn gram, gsum, upd;  // gsum: chunk sums of the 64-column Grams (else null)
     BlkInnerFn inner;
     int inner_nt;
     int crit;
@@ -883,9 +1366,12 @@ static int blocked_step(const BatchCtx &c, const void *arg, int step, hipStream_
     const BlockedArg *a = static_cast<const BlockedArg *>(arg);
     hipEvent_t e0, e1;
     prof_before(kProfGram, s, e0, e1);
-    hipLaunchKernelGGL(a->gram, dim3(c.total(BatchCtx::kGram)), dim3(kWave * kGramWaves), 0, s,
-                       c.dev,
+    hipLaunchKernelGGL(a->gram, dim3(c.total(BatchCtx::kGram)),
+                       dim3(a->gsum ? kWave * kG64Tiles : kWave * kGramWaves), 0, s, c.dev,
                        c.pre_of(BatchCtx::kGram), c.flag_dev, c.B, step);
+    if (a->gsum)
+        hipLaunchKernelGGL(a->gsum, dim3(c.total(BatchCtx::kBp), 2 * kG64Tiles), dim3(256), 0, s,
+                           c.dev, c.pre_of(BatchCtx::kBp), c.flag_dev, c.B, step);
     prof_after(kProfGram, s, e0, e1);
     prof_before(kProfInner, s, e0, e1);
     hipLaunchKernelGGL(a->inner, dim3(c.total(BatchCtx::kBp)), dim3(a->inner_nt), 0, s, c.dev,
@@ -915,7 +1401,13 @@ int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, int
     BlockedArg a{};
     a.crit = crit;
     a.cross = inner_order == GHSVD_INNER_CROSS;
-    if (w == 16) {
+    if (w == 32) {
+        a.gram = fp32 ? k_blk_gram64<float> : k_blk_gram64<double>;
+        a.gsum = fp32 ? k_blk_gsum64<float> : k_blk_gsum64<double>;
+        a.inner = fp32 ? k_blk_inner64<1> : k_blk_inner64<0>;
+        a.inner_nt = kI64Threads;
+        a.upd = fp32 ? k_blk_update<float, 64> : k_blk_update<double, 64>;
+    } else if (w == 16) {
         a.gram = fp32 ? k_blk_gram<float, 32> : k_blk_gram<double, 32>;
         a.inner = fp32 ? k_blk_inner<32, 1> : k_blk_inner<32, 0>;
         a.inner_nt = inner_threads<32>();

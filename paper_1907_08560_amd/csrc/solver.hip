@@ -228,7 +228,7 @@ size_t solve_batch_bytes(const std::vector<PencilIO> &io, const ghsvd_options &o
     size_t total = batch_bytes((int)io.size());
     for (const PencilIO &p : io) {
         size_t need = 0;
-        for (int w : {8, 16}) {
+        for (int w : {8, 16, 32}) {
             if (o.block_width != 0 && o.block_width != w) continue;
             need = std::max(need, pencil_bytes(make_plan(p.m, p.n, p.p, o, w)));
         }
@@ -504,7 +504,8 @@ static bool valid_sizes(int m, int n, int p) { return n >= 1 && m >= n && p >= n
 static bool valid_options(const ghsvd_options &o) {
     return (o.precision == GHSVD_FP64 || o.precision == GHSVD_MIXED) &&
            (o.variant == GHSVD_POINTWISE || o.variant == GHSVD_BLOCKED) &&
-           (o.block_width == 0 || o.block_width == 8 || o.block_width == 16) &&
+           (o.block_width == 0 || o.block_width == 8 || o.block_width == 16 ||
+            o.block_width == 32) &&
            o.waves_per_pair >= 0 && o.waves_per_pair <= 16;
 }
 
@@ -708,7 +709,8 @@ extern "C" int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n
     if (n < 4 || m < 1 || p < 1 || ldf < m || ldg < p || ldz < n || nsweeps < 1 ||
         nsweeps > kMaxHist || n_plus < 0 || n_plus > m || !F || !G || !Z)
         return GHSVD_EINVAL;
-    if (block_width != 0 && block_width != 8 && block_width != 16) return GHSVD_EINVAL;
+    if (block_width != 0 && block_width != 8 && block_width != 16 && block_width != 32)
+        return GHSVD_EINVAL;
     if (inner_order != GHSVD_INNER_FULL && inner_order != GHSVD_INNER_CROSS) return GHSVD_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     OwnedBatch ob;
@@ -766,8 +768,8 @@ extern "C" int ghsvd_autotune(int batch, const int *m, const int *n, const int *
     if (lwork < need) return GHSVD_ENOMEM;
     // one FP64 sweep per candidate on these pencils, timed by stage
     static const int kWpp[4] = {1, 2, 4, 8};
-    static const int kW[2] = {8, 16};
-    float t[6] = {-1, -1, -1, -1, -1, -1};
+    static const int kW[3] = {8, 16, 32};
+    float t[7] = {-1, -1, -1, -1, -1, -1, -1};
     int best_wpp = 0, best_w = pick_block_width(max_n, 0);
     float best = 0.0f;
     for (int i = 0; i < 4; ++i) {
@@ -789,7 +791,7 @@ extern "C" int ghsvd_autotune(int batch, const int *m, const int *n, const int *
     if (o.variant == GHSVD_BLOCKED) {
         best = 0.0f;
         int bw = 0;
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < 3; ++j) {
             ghsvd_options to = o;
             to.precision = GHSVD_FP64;
             to.block_width = kW[j];
@@ -814,7 +816,7 @@ extern "C" int ghsvd_autotune(int batch, const int *m, const int *n, const int *
     if (block_width) *block_width = best_w;
     if (waves_per_pair) *waves_per_pair = best_wpp;
     if (trial_ms)
-        for (int i = 0; i < 6; ++i) trial_ms[i] = t[i];
+        for (int i = 0; i < 7; ++i) trial_ms[i] = t[i];
     return GHSVD_OK;
 }
 

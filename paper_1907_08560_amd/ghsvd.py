@@ -324,7 +324,7 @@ def autotune(Fs, Js, Gs, *, stream=None, **kw):
     work = torch.empty(max(need, 1), dtype=torch.uint8, device=Fs[0].device)
     w = ctypes.c_int(0)
     wpp = ctypes.c_int(0)
-    t = np.zeros(6, dtype=np.float32)
+    t = np.zeros(7, dtype=np.float32)
     rc = _lib.ghsvd_autotune(b, m.ctypes.data, n.ctypes.data, p.ctypes.data, fp.ctypes.data,
                              ldf.ctypes.data, jp.ctypes.data, gp.ctypes.data, ldg.ctypes.data,
                              work.data_ptr(), work.numel(), ctypes.byref(opt), ctypes.byref(w),
@@ -332,7 +332,7 @@ def autotune(Fs, Js, Gs, *, stream=None, **kw):
     if rc < 0:
         raise GhsvdError(rc, "ghsvd_autotune")
     trials = {f"pointwise_wpp{k}": float(t[i]) for i, k in enumerate((1, 2, 4, 8))}
-    trials.update({f"blocked_w{k}": float(t[4 + i]) for i, k in enumerate((8, 16))})
+    trials.update({f"blocked_w{k}": float(t[4 + i]) for i, k in enumerate((8, 16, 32))})
     return w.value, wpp.value, trials
 
 

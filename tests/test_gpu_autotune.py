@@ -26,7 +26,7 @@ def test_autotune_then_solve(oracle, variant):
     assert all(trials[f"pointwise_wpp{k}"] > 0 for k in (1, 2, 4, 8))
     if variant == "blocked":
         assert w in (8, 16)
-        assert trials["blocked_w8"] > 0 and trials["blocked_w16"] > 0
+        assert trials["blocked_w8"] > 0 and trials["blocked_w16"] > 0 and trials["blocked_w32"] > 0
     lam_a, X_a, inf_a, rc = ghsvd.solve_batched(Fs, Js, Gs, variant=variant)
     assert rc == 0
     lam_e, X_e, inf_e, rc = ghsvd.solve_batched(Fs, Js, Gs, variant=variant, block_width=w,

@@ -30,7 +30,8 @@ INNER = {"full": 0, "cross": 1}
 
 
 @pytest.mark.parametrize("inner", ["full", "cross"])
-@pytest.mark.parametrize("n,w,s_lo", [(96, 8, 1e-3), (96, 16, 1e-3), (70, 16, 1e-2), (41, 8, 1e-2)])
+@pytest.mark.parametrize("n,w,s_lo", [(96, 8, 1e-3), (96, 16, 1e-3), (70, 16, 1e-2), (41, 8, 1e-2),
+                                       (192, 32, 1e-3), (150, 32, 1e-2)])
 def test_one_block_sweep_elementwise(oracle, n, w, s_lo, inner):
     P = small(300 + n + w, n, s_lo)
     F, J, G = to_dev(P)
@@ -62,7 +63,7 @@ def test_block_sweeps_converge(oracle, inner):
 
 
 @pytest.mark.parametrize("inner", ["full", "cross"])
-@pytest.mark.parametrize("w", [8, 16])
+@pytest.mark.parametrize("w", [8, 16, 32])
 def test_blocked_solve_workload_one(oracle, w, inner):
     P = synth.workload_pencil(1)
     F, J, G = to_dev(P)
