@@ -426,13 +426,12 @@ struct InnerStep {
 };
 
 // The pivot wavefront's part of an inner step: the 2x2 steps of all pairs
-// of inner step `is`.  LOOK = 0: the pivot entries are read from (H, S).
-// LOOK = 1: (H, S) are the matrices before the update of step is - 1 (prev),
-// which the other wavefronts are applying at the same time, and each pivot
-// entry after that update is formed here from its 2x2 block and the two
-// transformations that touch it.  Lane l forms entry kind e = l / 16 of
-// pair k = l % 16 ((p, p), (q, q), (p, q)); lane k gathers its pair's six
-// entries and runs the FP64 2x2 step.
+// of inner step `is`.  (H, S) are the matrices before the update of step
+// is - 1 (prev), which the other wavefronts are applying at the same time,
+// and each pivot entry after that update is formed here from its 2x2 block
+// and the two transformations that touch it.  Lane l forms entry kind
+// e = l / 16 of pair k = l % 16 ((p, p), (q, q), (p, q)); lane k gathers its
+// pair's six entries and runs the FP64 2x2 step.
 // Look-ahead operands of lane l at inner step is (is >= 1), packed as bytes:
 // x = rows r0, r1 and columns c0, c1 of the 2x2 block of step is - 1 that
 // holds the lane's pivot entry; y = that block's row slot ki and position
@@ -475,59 +474,15 @@ __device__ __forceinline__ uint2 lookahead_entry(const InnerOrder &ord, int is, 
                       (unsigned)ki | (unsigned)ii << 8 | (unsigned)kj << 16 | (unsigned)jj << 24);
 }
 
-// te: this lane's look-ahead operands for step `is` (LOOK = 1), read from
-// the table by the caller one step ahead.
-template <int PB, int F32, int LOOK>
-__device__ __forceinline__ void inner_pivots(const InnerOrder &ord, int is, int c, double tol,
-                                             int crit, const double2 (*H)[PB + 1],
-                                             const double2 (*S)[PB + 1],
-                                             const InnerStep<PB> &prev, InnerStep<PB> &next,
-                                             uint2 te, double &cv, double &ct, double &cbig,
-                                             int *err) {
+// Lane l of the pivot wavefront holds entry kind l / 16 of pair slot
+// l % 16 (hv, sv); lane k < NP gathers its pair's (p,p), (q,q), (p,q) and
+// runs the FP64 2x2 step (all lanes take part in the gather).
+template <int PB, int F32>
+__device__ __forceinline__ void pivot_finish(bool live, double2 hv, double2 sv, double tol, int crit,
+                                             InnerStep<PB> &next, double &cv, double &ct,
+                                             double &cbig, int *err) {
     constexpr int NP = PB / 2;
-    static_assert(NP <= kEntryStride, "one lane per pair slot and entry kind");
-    const int l = threadIdx.x;  // lane of wavefront 0
-    const int k = l % kEntryStride, e = l / kEntryStride;
-    bool live, mine;
-    int pp = -1, qq = -1;
-    if (LOOK) {
-        // this lane's entry; for lanes k < NP, whether pair k is live (its
-        // (p,p) entry, formed by the lane itself, exists)
-        mine = te.y != kNoEntry;
-        live = mine;
-    } else {
-        const int nsl = ord.slots();
-        if (k < nsl) ord.pair(is, k, pp, qq);
-        live = k < nsl && qq < c;
-        mine = live && e < 3;
-    }
-    double2 hv = cmk(0.0, 0.0), sv = cmk(0.0, 0.0);
-    if (mine) {
-        if (!LOOK) {
-            const int i = (e == 1) ? qq : pp, j = (e == 0) ? pp : qq;
-            hv = H[i][j];
-            sv = S[i][j];
-        } else {
-            const double2 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0);
-            const int r0 = te.x & 0xff, r1 = (te.x >> 8) & 0xff;
-            const int c0 = (te.x >> 16) & 0xff, c1 = te.x >> 24;
-            const int ki = te.y & 0xff, ii = (te.y >> 8) & 0xff;
-            const int kj = (te.y >> 16) & 0xff, jj = te.y >> 24;
-            // every operand is read at once (one LDS round trip); the
-            // identity replaces an inactive slot's transformation by select
-            const int ai = prev.act[ki], aj = prev.act[kj];
-            const double2 za = prev.z[ki][2 * ii], zb = prev.z[ki][2 * ii + 1];
-            const double2 zc = prev.z[kj][2 * jj], zd = prev.z[kj][2 * jj + 1];
-            const double2 h00 = H[r0][c0], h01 = H[r0][c1], h10 = H[r1][c0], h11 = H[r1][c1];
-            const double2 s00 = S[r0][c0], s01 = S[r0][c1], s10 = S[r1][c0], s11 = S[r1][c1];
-            // column ii of Z'_ki, column jj of Z'_kj
-            const double2 ra = ai ? za : (ii ? zero : one), rb = ai ? zb : (ii ? one : zero);
-            const double2 ca = aj ? zc : (jj ? zero : one), cb = aj ? zd : (jj ? one : zero);
-            hv = macc2(ra, mac2(h00, ca, h01, cb), rb, mac2(h10, ca, h11, cb));
-            sv = macc2(ra, mac2(s00, ca, s01, cb), rb, mac2(s10, ca, s11, cb));
-        }
-    }
-    // gather (p,p), (q,q), (p,q) of pair k into lane k (all lanes take part)
+    const int l = threadIdx.x, k = l % kEntryStride;
     const double hpp = hv.x, hqq = lane_plus16(hv.x);
     const double hpq_r = lane_plus32(hv.x), hpq_i = lane_plus32(hv.y);
     const double spp = sv.x, sqq = lane_plus16(sv.x);
@@ -550,6 +505,44 @@ __device__ __forceinline__ void inner_pivots(const InnerOrder &ord, int is, int 
         }
         next.act[k] = kind > 0;
     }
+}
+
+// The pivot wavefront's part of inner step `is` >= 1: each lane forms its
+// look-ahead entry (te: its operands, read from the table by the caller one
+// step ahead) from the block entries before step is - 1 and that step's
+// transformations, then the pairs' 2x2 steps run.
+template <int PB, int F32>
+__device__ __forceinline__ void inner_pivots(double tol, int crit, const double2 (*H)[PB + 1],
+                                             const double2 (*S)[PB + 1],
+                                             const InnerStep<PB> &prev, InnerStep<PB> &next,
+                                             uint2 te, double &cv, double &ct, double &cbig,
+                                             int *err) {
+    constexpr int NP = PB / 2;
+    static_assert(NP <= kEntryStride, "one lane per pair slot and entry kind");
+    // this lane's entry; for lanes k < NP, whether pair k is live (its
+    // (p,p) entry, formed by the lane itself, exists)
+    const bool mine = te.y != kNoEntry, live = mine;
+    double2 hv = cmk(0.0, 0.0), sv = cmk(0.0, 0.0);
+    if (mine) {
+        const double2 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0);
+        const int r0 = te.x & 0xff, r1 = (te.x >> 8) & 0xff;
+        const int c0 = (te.x >> 16) & 0xff, c1 = te.x >> 24;
+        const int ki = te.y & 0xff, ii = (te.y >> 8) & 0xff;
+        const int kj = (te.y >> 16) & 0xff, jj = te.y >> 24;
+        // every operand is read at once (one LDS round trip); the
+        // identity replaces an inactive slot's transformation by select
+        const int ai = prev.act[ki], aj = prev.act[kj];
+        const double2 za = prev.z[ki][2 * ii], zb = prev.z[ki][2 * ii + 1];
+        const double2 zc = prev.z[kj][2 * jj], zd = prev.z[kj][2 * jj + 1];
+        const double2 h00 = H[r0][c0], h01 = H[r0][c1], h10 = H[r1][c0], h11 = H[r1][c1];
+        const double2 s00 = S[r0][c0], s01 = S[r0][c1], s10 = S[r1][c0], s11 = S[r1][c1];
+        // column ii of Z'_ki, column jj of Z'_kj
+        const double2 ra = ai ? za : (ii ? zero : one), rb = ai ? zb : (ii ? one : zero);
+        const double2 ca = aj ? zc : (jj ? zero : one), cb = aj ? zd : (jj ? one : zero);
+        hv = macc2(ra, mac2(h00, ca, h01, cb), rb, mac2(h10, ca, h11, cb));
+        sv = macc2(ra, mac2(s00, ca, s01, cb), rb, mac2(s10, ca, s11, cb));
+    }
+    pivot_finish<PB, F32>(live, hv, sv, tol, crit, next, cv, ct, cbig, err);
 }
 
 // One inner sweep over the block pivot (H^, S^) in LDS, software-pipelined.
@@ -599,40 +592,56 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
     const int nsteps = ord.steps(), nsl = ord.slots();
     const int KC = A.kf + A.kg;
     const GPtr<double2> P(A.part + (size_t)bpi * KC * PB * PB);
-    for (int idx = tid; idx < PB * PB; idx += inner_threads<PB>()) {
-        const int i = idx % PB, j = idx / PB;
-        double2 h = cmk(0.0, 0.0), s = cmk(0.0, 0.0);
-        // partials summed in chunk order; unrolled so the loads issue together
-#pragma unroll 4
-        for (int k = 0; k < A.kf; ++k) h = cadd(h, P.ld((long)k * PB * PB + idx));
-#pragma unroll 4
-        for (int k = A.kf; k < KC; ++k) s = cadd(s, P.ld((long)k * PB * PB + idx));
-        H[0][i][j] = h;
-        S[0][i][j] = s;
-        Zs[i][j] = cmk(i == j ? 1.0 : 0.0, 0.0);
-    }
-    for (int idx = tid; idx < (nsteps - 1) * kEntryLanes; idx += inner_threads<PB>()) {
-        const int is = 1 + idx / kEntryLanes, l = idx % kEntryLanes;
-        tab[is][l] = lookahead_entry<PB>(ord, is, l, c);
-    }
-    __syncthreads();
     const double tol = (F32 ? 0x1p-23 : 0x1p-52) * sqrt((double)c);
     double cv = 0.0, ct = 0.0, cbig = 0.0;
-    // look-ahead operands of the next inner step, read one step ahead
-    uint2 te = make_uint2(0u, kNoEntry);
     if (tid < kWave) {
-        if (nsteps > 1 && tid < kEntryLanes) te = tab[1][tid];
-        inner_pivots<PB, F32, 0>(ord, 0, c, tol, crit, H[0], S[0], st[1], st[0], te, cv, ct,
-                                 cbig, &A.st->err);
+        // inner step 0 straight from the partial Grams, summed in the chunk
+        // order of the LDS fill below (so the entries are the same bits),
+        // while the other wavefronts fill LDS
+        const int k = tid % kEntryStride, e = tid / kEntryStride;
+        int pp = -1, qq = -1;
+        if (k < nsl) ord.pair(0, k, pp, qq);
+        const bool live = k < nsl && qq < c;
+        double2 hv = cmk(0.0, 0.0), sv = cmk(0.0, 0.0);
+        if (live && e < 3) {
+            const int i = (e == 1) ? qq : pp, j = (e == 0) ? pp : qq;
+            const long off = i + (long)PB * j;
+#pragma unroll 4
+            for (int kk = 0; kk < A.kf; ++kk) hv = cadd(hv, P.ld((long)kk * PB * PB + off));
+#pragma unroll 4
+            for (int kk = A.kf; kk < KC; ++kk) sv = cadd(sv, P.ld((long)kk * PB * PB + off));
+        }
+        pivot_finish<PB, F32>(live, hv, sv, tol, crit, st[0], cv, ct, cbig, &A.st->err);
+    } else {
+        const int t0 = tid - kWave, nt = inner_threads<PB>() - kWave;
+        for (int idx = t0; idx < PB * PB; idx += nt) {
+            const int i = idx % PB, j = idx / PB;
+            double2 h = cmk(0.0, 0.0), s = cmk(0.0, 0.0);
+            // partials summed in chunk order; unrolled so the loads issue together
+#pragma unroll 4
+            for (int k = 0; k < A.kf; ++k) h = cadd(h, P.ld((long)k * PB * PB + idx));
+#pragma unroll 4
+            for (int k = A.kf; k < KC; ++k) s = cadd(s, P.ld((long)k * PB * PB + idx));
+            H[0][i][j] = h;
+            S[0][i][j] = s;
+            Zs[i][j] = cmk(i == j ? 1.0 : 0.0, 0.0);
+        }
+        for (int idx = t0; idx < (nsteps - 1) * kEntryLanes; idx += nt) {
+            const int is = 1 + idx / kEntryLanes, l = idx % kEntryLanes;
+            tab[is][l] = lookahead_entry<PB>(ord, is, l, c);
+        }
     }
     __syncthreads();
+    // look-ahead operands of the next inner step, read one step ahead
+    uint2 te = make_uint2(0u, kNoEntry);
+    if (tid < kWave && nsteps > 1 && tid < kEntryLanes) te = tab[1][tid];
     for (int s = 0; s < nsteps; ++s) {
         const int cur = s & 1, nxt = cur ^ 1;
         const InnerStep<PB> &now = st[cur];
         if (tid < kWave) {
             if (s + 1 < nsteps) {
-                inner_pivots<PB, F32, 1>(ord, s + 1, c, tol, crit, H[cur], S[cur], now, st[nxt],
-                                         te, cv, ct, cbig, &A.st->err);
+                inner_pivots<PB, F32>(tol, crit, H[cur], S[cur], now, st[nxt], te, cv, ct, cbig,
+                                      &A.st->err);
                 te = (s + 2 < nsteps && tid < kEntryLanes) ? tab[s + 2][tid]
                                                             : make_uint2(0u, kNoEntry);
             }
