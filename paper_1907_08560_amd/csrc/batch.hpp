@@ -121,7 +121,24 @@ __device__ __forceinline__ int pencil_local(const int *pre, int pk, int blk) {
     return pk ? blk - pre[pk] : blk;
 }
 
+// The pencil is the last p with pre[p] <= blk (a pencil with no workgroups
+// in the launch has pre[p] == pre[p + 1]).  Up to kFindWide pencils, every
+// wavefront counts those p with one load per lane and chunk of 64 and a
+// ballot (one memory latency instead of a chain of dependent ones); larger
+// batches take the binary search.  Must be called by whole wavefronts.
+constexpr int kFindWide = 1024;
+
 __device__ __forceinline__ int find_pencil(const int *pre, int B, int blk) {
+    if (B <= 1) return 0;
+    if (B <= kFindWide) {
+        const int lane = threadIdx.x & (kWave - 1);
+        int cnt = 0;
+        for (int c = 0; c < B; c += kWave) {
+            const int p = c + lane;
+            cnt += __popcll(__ballot(p < B && pre[p] <= blk));
+        }
+        return cnt - 1;
+    }
     int lo = 0, hi = B - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;

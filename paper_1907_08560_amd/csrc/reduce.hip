@@ -26,6 +26,28 @@ constexpr int kOneNT = 1024;
 
 __device__ __forceinline__ double jsign(const int8_t *J, int r) { return (double)J[r]; }
 
+// Complex products with the FMA contraction spelled out: the register-
+// resident step forms below use these so that they round exactly as the
+// compiled streaming loops of the same step do (which product of a sum is
+// fused is otherwise the compiler's choice, and it differs between the two
+// forms).  fnorm2, fdot_*, fmul: the first product fused, the second rounded;
+// fdot_re2: the second fused (the streaming reflector J-product's form).
+__device__ __forceinline__ double fnorm2(double2 a) { return __builtin_fma(a.x, a.x, a.y * a.y); }
+// conj(a) * b, real and imaginary parts
+__device__ __forceinline__ double fdot_re(double2 a, double2 b) {
+    return __builtin_fma(a.x, b.x, a.y * b.y);
+}
+__device__ __forceinline__ double fdot_re2(double2 a, double2 b) {
+    return __builtin_fma(a.y, b.y, a.x * b.x);
+}
+__device__ __forceinline__ double fdot_im(double2 a, double2 b) {
+    return __builtin_fma(a.x, b.y, -(a.y * b.x));
+}
+// a * b
+__device__ __forceinline__ double2 fmul(double2 a, double2 b) {
+    return cmk(__builtin_fma(a.x, b.x, -(a.y * b.y)), __builtin_fma(a.x, b.y, a.y * b.x));
+}
+
 // Block-wide J-weighted dot conj(x)^T diag(J) y over rows r0..m-1.
 __device__ __forceinline__ double2 jdot_block(const double2 *x, const double2 *y, const int8_t *J,
                                               int r0, int m, double *red) {
@@ -64,7 +86,11 @@ __device__ __forceinline__ bool jqr_active(const JqrState &st, int n) {
 }
 
 // Batched launches over columns: workgroup -> (pencil, logical column j)
-// through the prefix sums of the column counts.  Columns never move: logical
+// through prefix sums of column counts.  A launch of step `it` covers only the
+// columns j >= jw of each pencil, jw = it rounded down to the window step
+// (k >= it for a pencil still in its factorization, so no live column lies
+// left of the window); the prefix sums of the window's column counts come
+// from a host-built table with one row per window.  Columns never move: logical
 // column l of the factorization is physical column perm[l] of Ft (the map
 // is P2), and a step's two swaps only change the map.  State, signature and
 // map are read from the copies of the step's parity `par`.
@@ -77,7 +103,7 @@ __device__ __forceinline__ bool jqr_active(const JqrState &st, int n) {
     const int m = P.m, n = P.n;                                   \
     const JqrState st = P.jst[par];                               \
     const int8_t *J = P.Jw + (size_t)par * m;                     \
-    const int j_local = pencil_local(pre, pk, blockIdx.x);        \
+    const int j_local = pencil_local(pre, pk, blockIdx.x) + jw;   \
     (void)J;                                                      \
     (void)j_local
 
@@ -104,7 +130,7 @@ __device__ __forceinline__ int jqr_diag_pivot(const double *hd, const int *cp, i
 
 // hd[c] = J-norm^2 of every column over rows 0..m-1 (before the first step).
 __global__ __launch_bounds__(kGridNT) void k_jqr_colnorms(const PencilDev *PD, const int *pre, int B,
-                                                          int par) {
+                                                          int par, int jw) {
     __shared__ double red[kGridNT / kWave];
     JQR_PENCIL_COL();
     if (!jqr_active(st, n)) return;
@@ -118,7 +144,7 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_colnorms(const PencilDev *PD, c
 // column j (rows k..m-1), stored at the position column j takes after the
 // swap k <-> bi.
 __global__ __launch_bounds__(kGridNT) void k_jqr_cross(const PencilDev *PD, const int *pre, int B,
-                                                       int par) {
+                                                       int par, int jw) {
     __shared__ double red[2 * kGridNT / kWave];
     __shared__ double rv[kGridNT / kWave];
     __shared__ int ri[kGridNT / kWave];
@@ -128,6 +154,7 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_cross(const PencilDev *PD, cons
     if (j < k || k == n - 1) return;
     const int *cp = P.perm;
     const int bi = jqr_diag_pivot(P.hd, cp, k, n, rv, ri);
+    if (j == k && threadIdx.x == 0) P.jdec->bi = bi;  // for the second kernel
     if (j == bi) return;
     const double2 d = jdot_block(jcol(A, lda, cp[bi]), jcol(A, lda, cp[j]), J, k, m, red);
     const int pos = (j == k) ? bi : j;
@@ -140,7 +167,7 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_cross(const PencilDev *PD, cons
 // the second test is needed, workgroup l computes |J-product| of the
 // candidate column ii with column l (post-swap positions).
 __global__ __launch_bounds__(kGridNT) void k_jqr_cross2(const PencilDev *PD, const int *pre, int B,
-                                                        int par) {
+                                                        int par, int jw) {
     __shared__ double red[2 * kGridNT / kWave];
     __shared__ double rv[kGridNT / kWave];
     __shared__ int ri[kGridNT / kWave];
@@ -149,7 +176,8 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_cross2(const PencilDev *PD, con
     const int k = st.k, j = j_local;
     if (j < k) return;
     const int *cp = P.perm;
-    const int bi = jqr_diag_pivot(P.hd, cp, k, n, rv, ri);
+    // the diagonal pivot, recorded by the first kernel (none at the last column)
+    const int bi = k == n - 1 ? k : P.jdec->bi;
     // candidate ii = argmax_{i > k} |h_ki| (hc holds post-swap positions)
     double cv = -1.0;
     int ci = k + 1;
@@ -222,20 +250,192 @@ __device__ __forceinline__ double2 sv_load(const double2 *x, const double2 *stas
 // in place and leaves its J-norm^2 over the rows still to reduce in hd.
 // The workgroup of column k writes the next state, map and signature, and
 // the pivot rows; the pivot columns themselves are not rewritten (the final
-// extraction takes their rows from rblk and zeros below them).
+// extraction takes their rows from rblk and zeros below them).  A final
+// state (factorization complete, or an error) goes to both parity copies, so
+// the later steps, which have no workgroup for a finished pencil, need not
+// carry it.
+template <int RC>
 __device__ __forceinline__ void qr_step_body(const PencilDev *PD, const int *pre, int B, int k,
-                                             int bid, double *red);
+                                             int bid, int jw, double *red);
 
-// Workgroups tot.. of the launch run column step qk of G's QR instead.
+// A 1x1 pivot step with the workgroup's rows in registers: thread tid holds
+// rows k + tid + i * kGridNT (i < RC) of the signature, the pivot column and
+// its own column, loaded together at the start (one memory latency), which
+// is the row assignment of the streaming loops below, so every sum rounds as
+// there.  The row swap k <-> b0 of the matching sign moves the three values
+// between the two owning threads through LDS.  Requires m - k <= RC * kGridNT.
+template <int RC, typename CP>
+__device__ __forceinline__ void jqr_step1_regs(const PencilDev &P, const JqrState &cur, int par,
+                                               int k, int j, const CP &cp2, double *red,
+                                               double *rv, int *ri, double2 *xch) {
+    const int m = P.m, n = P.n, tid = threadIdx.x;
+    const bool desig = j == k;
+    int8_t *Jc = P.Jw + (size_t)par * m;
+    int8_t *Jn = P.Jw + (size_t)(par ^ 1) * m;
+    const double2 *xa = jcol(P.Ft, P.ldft, cp2(k));
+    double2 *y = P.Ft + (size_t)cp2(j) * P.ldft;
+    const int jk = Jc[k];
+    const double2 xk = xa[k];
+    double2 xv[RC], yv[RC];
+    int js[RC];
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+        const int r = k + tid + i * kGridNT;
+        js[i] = 0;
+        xv[i] = yv[i] = cmk(0.0, 0.0);
+        if (r < m) {
+            js[i] = Jc[r];
+            xv[i] = xa[r];
+            if (!desig) yv[i] = y[r];
+        }
+    }
+    int status = 0;
+    double h0;
+    {
+        double v[1] = {0.0};
+#pragma unroll
+        for (int i = 0; i < RC; ++i)
+            if (k + tid + i * kGridNT < m) v[0] += (double)js[i] * fnorm2(xv[i]);
+        block_sum<1>(v, red);
+        h0 = v[0];
+    }
+    if (!isfinite(h0) || h0 == 0.0) status = isfinite(h0) ? GHSVD_ERANK : GHSVD_ENONFINITE;
+    const int sg0 = h0 > 0.0 ? 1 : -1;
+    int b0 = k;
+    if (status == 0 && jk != sg0) {
+        double bv = -1.0;
+        int bi = -1;
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            const int r = k + tid + i * kGridNT;
+            if (r < m && js[i] == sg0) {
+                const double v = fnorm2(xv[i]);
+                if (v > bv || (v == bv && (bi < 0 || r < bi))) {
+                    bv = v;
+                    bi = r;
+                }
+            }
+        }
+        if (bi < 0) bi = 0x7fffffff;
+        block_argmax(bv, bi, rv, ri);
+        if (bi < k || bi >= m) status = GHSVD_ERANK;
+        else b0 = bi;
+    }
+    if (status != 0) {
+        // every workgroup of the pencil reaches this branch (same pivot data)
+        if (desig) {
+            for (int r = tid; r < m; r += blockDim.x) Jn[r] = Jc[r];
+            if (tid == 0) {
+                JqrState t = cur;
+                t.status = status;
+                P.jst[par ^ 1] = t;
+                P.jst[par] = t;
+            }
+        }
+        return;
+    }
+    double2 f11 = xk;
+    if (b0 != k) {
+        // rows k and b0 trade places: J, the pivot column (as the reflector
+        // sees it) and the own column
+        if (tid == ((b0 - k) & (kGridNT - 1))) {
+#pragma unroll
+            for (int i = 0; i < RC; ++i)
+                if (k + tid + i * kGridNT == b0) {
+                    xch[0] = xv[i];
+                    xch[1] = yv[i];
+                }
+        }
+        if (tid == 0) xch[2] = yv[0];
+        __syncthreads();
+        f11 = xch[0];
+        if (tid == 0) {
+            yv[0] = xch[1];
+            js[0] = sg0;
+        }
+        if (tid == ((b0 - k) & (kGridNT - 1))) {
+            const double2 yk = xch[2];
+#pragma unroll
+            for (int i = 0; i < RC; ++i)
+                if (k + tid + i * kGridNT == b0) {
+                    xv[i] = xk;
+                    yv[i] = yk;
+                    js[i] = jk;
+                }
+        }
+    }
+    const double af = sqrt(fnorm2(f11));
+    const double2 e = af > 0.0 ? cmk(f11.x / af, f11.y / af) : cmk(1.0, 0.0);
+    const double rr = sqrt(fabs(h0));
+    const double2 s0k = cscale(e, af + rr);
+    const double2 r0k = cscale(e, -rr);
+    const double tau0 = -1.0 / (h0 + rr * af * (double)sg0);
+    if (desig) {
+        const bool fin = k + 1 >= n;
+        for (int l = tid; l < n; l += blockDim.x) P.perm[l] = cp2(l);
+        for (int r = tid; r < k; r += blockDim.x) Jn[r] = Jc[r];
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            const int r = k + tid + i * kGridNT;
+            if (r < m) {
+                Jn[r] = (int8_t)js[i];
+                if (fin) Jc[r] = (int8_t)js[i];
+            }
+        }
+        if (tid == 0) {
+            P.rblk[2 * k] = r0k;
+            P.rblk[2 * k + 1] = cmk(0.0, 0.0);
+            P.pblk[2 * k] = k;
+            P.pblk[2 * k + 1] = 1;
+            JqrState t = cur;
+            t.k = k + 1;
+            P.jst[par ^ 1] = t;
+            if (fin) P.jst[par] = t;
+        }
+        return;
+    }
+    // the reflector on the own column: the J-product, then the update and
+    // the column's J-norm^2 over the rows still to reduce
+    double v[2] = {0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+        const int r = k + tid + i * kGridNT;
+        if (r < m) {
+            const double s = (double)js[i];
+            const double2 a = r == k ? s0k : xv[i], b = yv[i];
+            v[0] += s * fdot_re2(a, b);
+            v[1] += s * fdot_im(a, b);
+        }
+    }
+    block_sum<2>(v, red);
+    const double2 tw = cscale(cmk(v[0], v[1]), tau0);
+    double h[1] = {0.0};
+#pragma unroll
+    for (int i = 0; i < RC; ++i) {
+        const int r = k + tid + i * kGridNT;
+        if (r < m) {
+            const double2 nv = cadd(yv[i], fmul(r == k ? s0k : xv[i], tw));
+            if (r > k) h[0] += (double)js[i] * fnorm2(nv);
+            y[r] = nv;
+        }
+    }
+    block_sum<1>(h, red);
+    if (tid == 0) P.hd[cp2(j)] = h[0];
+}
+
+// Workgroups tot.. of the launch run column step qk of G's QR instead.  RC:
+// rows per thread of the register-resident 1x1 step (and of G's column
+// step); longer columns, and 2x2 pivots, take the streaming loops.
+template <int RC>
 __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const int *pre, int B,
-                                                      int par, int tot, int qk) {
+                                                      int par, int tot, int qk, int jw) {
     extern __shared__ int8_t Jl[];  // signature with this step's row swaps
     __shared__ double red[4 * kGridNT / kWave];
     __shared__ double rv[kGridNT / kWave];
     __shared__ int ri[kGridNT / kWave];
     __shared__ double2 stash[4];
     if ((int)blockIdx.x >= tot) {
-        qr_step_body(PD, pre, B, qk, (int)blockIdx.x - tot, red);
+        qr_step_body<RC>(PD, pre, B, qk, (int)blockIdx.x - tot, jw, red);
         return;
     }
     const int pk = find_pencil(pre, B, blockIdx.x);
@@ -246,17 +446,11 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
     const int m = P.m, n = P.n;
     const JqrState cur = P.jst[par];
     JqrState *nxt = P.jst + (par ^ 1);
-    const int8_t *Jc = P.Jw + (size_t)par * m;
+    int8_t *Jc = P.Jw + (size_t)par * m;
     int8_t *Jn = P.Jw + (size_t)(par ^ 1) * m;
-    const int j = pencil_local(pre, pk, blockIdx.x);
+    const int j = pencil_local(pre, pk, blockIdx.x) + jw;
     const int tid = threadIdx.x;
-    if (!jqr_active(cur, n)) {
-        if (j == 0) {  // carry the state to the next parity
-            for (int r = tid; r < m; r += blockDim.x) Jn[r] = Jc[r];
-            if (tid == 0) *nxt = cur;
-        }
-        return;
-    }
+    if (!jqr_active(cur, n)) return;
     const int k = cur.k;
     if (j < k) return;
     const bool desig = j == k;
@@ -298,6 +492,10 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
         return cpb[q];
     };
     if (j > k && j < k + piv) return;  // the second column of a 2x2 pivot
+    if (piv == 1 && m - k <= RC * kGridNT) {
+        jqr_step1_regs<RC>(P, cur, par, k, j, cp2, red, rv, ri, stash);
+        return;
+    }
     for (int r = k + tid; r < m; r += blockDim.x) Jl[r] = Jc[r];
     __syncthreads();
     const double2 *xa = jcol(A, lda, cp2(k));
@@ -453,12 +651,14 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
         }
     }
     if (status != 0) {
+        // every workgroup of the pencil reaches this branch (same pivot data)
         if (desig) {
             for (int r = tid; r < m; r += blockDim.x) Jn[r] = Jc[r];
             if (tid == 0) {
                 JqrState t = cur;
                 t.status = status;
                 *nxt = t;
+                P.jst[par] = t;
             }
         }
         return;
@@ -469,9 +669,17 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
         return pb1(q);
     };
     if (desig) {
-        // next state, map, signature, pivot rows
+        // next state, map, signature, pivot rows; when the factorization ends
+        // here no other workgroup of the pencil is past its early return (a
+        // 2x2 pivot's second column is the last one), so the current copies
+        // may be overwritten too
+        const bool fin = k + piv >= n;
         for (int l = tid; l < n; l += blockDim.x) P.perm[l] = cp2(l);
-        for (int r = tid; r < m; r += blockDim.x) Jn[r] = r < k ? Jc[r] : Jl[r];
+        for (int r = tid; r < m; r += blockDim.x) {
+            const int8_t sg = r < k ? Jc[r] : Jl[r];
+            Jn[r] = sg;
+            if (fin) Jc[r] = sg;
+        }
         if (tid == 0) {
             if (piv == 1) {
                 P.rblk[2 * k] = r0k;
@@ -495,6 +703,7 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
             t.k = k + piv;
             t.n2x2 = cur.n2x2 + (piv == 2 ? 1 : 0);
             *nxt = t;
+            if (fin) P.jst[par] = t;
         }
         return;
     }
@@ -636,17 +845,67 @@ int jqr_extract(const PencilDev &P, double2 *dst, long ldd, const int *rowmap, h
 // (rows k..p-1; v = x + e^{i arg x_1} ||x|| e_1) from the column as stored,
 // which no workgroup rewrites during the step, and applies it to its own
 // column j > k; the workgroup of column k records R_kk = -e^{i arg x_1} ||x||.
+template <int RC>
 __device__ __forceinline__ void qr_step_body(const PencilDev *PD, const int *pre, int B, int k,
-                                             int bid, double *red) {
+                                             int bid, int jw, double *red) {
     const int pk = find_pencil(pre, B, bid);
     const PencilDev P = PD[pk];
     if (!P.reduce || k >= P.n) return;
-    const int j = pencil_local(pre, pk, bid);
+    const int j = pencil_local(pre, pk, bid) + jw;
     if (j < k) return;
     double2 *A = P.Gt;
     const long lda = P.ldgt;
     const int p = P.p;
     const double2 *x = A + (size_t)k * lda;
+    double2 *y = A + (size_t)j * lda;
+    if (p - k <= RC * kGridNT) {
+        // both columns in registers, loaded together (rows k + tid + i *
+        // kGridNT, the streaming loops' assignment)
+        double2 xv[RC], yv[RC];
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            const int r = k + (int)threadIdx.x + i * kGridNT;
+            xv[i] = yv[i] = cmk(0.0, 0.0);
+            if (r < p) {
+                xv[i] = x[r];
+                if (j != k) yv[i] = y[r];
+            }
+        }
+        const double2 x1 = x[k];
+        double s[1] = {0.0};
+#pragma unroll
+        for (int i = 0; i < RC; ++i)
+            if (k + (int)threadIdx.x + i * kGridNT < p) s[0] += fnorm2(xv[i]);
+        block_sum<1>(s, red);
+        const double nrm = sqrt(s[0]);
+        const double ax1 = sqrt(fnorm2(x1));
+        const double2 ph = ax1 > 0.0 ? cmk(x1.x / ax1, x1.y / ax1) : cmk(1.0, 0.0);
+        if (j == k) {
+            if (threadIdx.x == 0) P.qdiag[k] = nrm == 0.0 ? x1 : cscale(ph, -nrm);
+            return;
+        }
+        if (nrm == 0.0) return;
+        const double cf = 1.0 / (nrm * (nrm + ax1));
+        const double2 vk = cscale(ph, ax1 + nrm);
+        double w[2] = {0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            const int r = k + (int)threadIdx.x + i * kGridNT;
+            if (r < p) {
+                const double2 a = r == k ? vk : xv[i], b = yv[i];
+                w[0] += fdot_re(a, b);
+                w[1] += fdot_im(a, b);
+            }
+        }
+        block_sum<2>(w, red);
+        const double2 tw = cmk(w[0] * cf, w[1] * cf);
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            const int r = k + (int)threadIdx.x + i * kGridNT;
+            if (r < p) y[r] = csub(yv[i], fmul(r == k ? vk : xv[i], tw));
+        }
+        return;
+    }
     double s[1] = {0.0};
     for (int r = k + threadIdx.x; r < p; r += blockDim.x) s[0] += cnorm2(x[r]);
     block_sum<1>(s, red);
@@ -661,7 +920,6 @@ __device__ __forceinline__ void qr_step_body(const PencilDev *PD, const int *pre
     if (nrm == 0.0) return;
     const double cf = 1.0 / (nrm * (nrm + ax1));  // 2 / (v^* v)
     const double2 vk = cscale(ph, ax1 + nrm);
-    double2 *y = A + (size_t)j * lda;
     double w[2] = {0.0, 0.0};
     for (int r = k + threadIdx.x; r < p; r += blockDim.x) {
         const double2 a = r == k ? vk : x[r], b = y[r];
@@ -865,7 +1123,7 @@ static int qr_end(const BatchCtx &c, hipStream_t s) {
 // columns permuted by P2 afterwards (the caller gathers the columns of Gt by
 // the permutation).  That QR needs no pivot decision; its column step it
 // runs in the hyperbolic QR's step launch of iteration it.
-int run_reduction(const BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
+int run_reduction(BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
                   hipStream_t s) {
     const int B = c.B;
     status.assign(B, 0);
@@ -881,22 +1139,50 @@ int run_reduction(const BatchCtx &c, std::vector<int> &status, std::vector<int> 
         if ((rc = copy_cols(P.p, P.n, P.Gin, P.ldgin, P.Gt, P.ldgt, nullptr, s))) return rc;
         GHSVD_HIP(hipMemcpyAsync(P.Jw, P.Jin, (size_t)P.m, hipMemcpyDeviceToDevice, s));
     }
-    const int *pc = c.pre_of(BatchCtx::kCols);
-    const int tot = c.total(BatchCtx::kCols);
+    // column windows: row w covers columns j >= w * step of each pencil
+    const int step = (c.max_n + kWinRows - 1) / kWinRows;
+    const int rows = (c.max_n + step - 1) / step;
+    c.win.assign((size_t)rows * (B + 1), 0);
+    for (int w = 0; w < rows; ++w)
+        for (int k = 0; k < B; ++k) {
+            const PencilDev &P = c.host[k];
+            const int cols = P.reduce && P.n > w * step ? P.n - w * step : 0;
+            c.win[(size_t)w * (B + 1) + k + 1] = c.win[(size_t)w * (B + 1) + k] + cols;
+        }
+    GHSVD_HIP(hipMemcpyAsync(c.win_dev, c.win.data(), sizeof(int) * c.win.size(),
+                             hipMemcpyHostToDevice, s));
+    // rows per thread a window's step kernel keeps in registers: enough for
+    // the longest trailing column of F or G at the window's first step
+    std::vector<int> rows_cap(rows, 0);
+    for (int w = 0; w < rows; ++w)
+        for (const PencilDev &P : c.host) {
+            if (!P.reduce || P.n <= w * step) continue;
+            const int len = (P.m > P.p ? P.m : P.p) - w * step;
+            const int per = (len + kGridNT - 1) / kGridNT;
+            rows_cap[w] = per > rows_cap[w] ? per : rows_cap[w];
+        }
     int max_m = 0;
     for (const PencilDev &P : c.host) max_m = P.m > max_m ? P.m : max_m;
     const size_t jl_bytes = align_up((size_t)max_m, 16);
     hipLaunchKernelGGL(k_jqr_init, dim3(B), dim3(256), 0, s, c.dev);
-    hipLaunchKernelGGL(k_jqr_colnorms, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, 0);
-    // At most max_n steps (fewer when 2x2 pivots occur; extra ones only carry
-    // the state to the next parity).  Three launches per step; the third
+    hipLaunchKernelGGL(k_jqr_colnorms, dim3(c.win[B]), dim3(kGridNT), 0, s, c.dev, c.win_dev, B, 0,
+                       0);
+    // At most max_n steps (fewer when 2x2 pivots occur; a pencil that has
+    // finished has no workgroups left).  Three launches per step; the third
     // also carries G's column step it.
     for (int it = 0; it < c.max_n; ++it) {
         const int par = it & 1;
-        hipLaunchKernelGGL(k_jqr_cross, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, par);
-        hipLaunchKernelGGL(k_jqr_cross2, dim3(tot), dim3(kGridNT), 0, s, c.dev, pc, B, par);
-        hipLaunchKernelGGL(k_jqr_step, dim3(2 * tot), dim3(kGridNT), jl_bytes, s, c.dev, pc, B,
-                           par, tot, it);
+        const int w = it / step;
+        const int *pw = c.win_dev + (size_t)w * (B + 1);
+        const int tot = c.win[(size_t)w * (B + 1) + B];
+        const int jw = w * step;
+        if (tot == 0) continue;
+        hipLaunchKernelGGL(k_jqr_cross, dim3(tot), dim3(kGridNT), 0, s, c.dev, pw, B, par, jw);
+        hipLaunchKernelGGL(k_jqr_cross2, dim3(tot), dim3(kGridNT), 0, s, c.dev, pw, B, par, jw);
+        const int rc = rows_cap[w];
+        auto step_k = rc <= 4 ? k_jqr_step<4> : rc <= 8 ? k_jqr_step<8> : k_jqr_step<16>;
+        hipLaunchKernelGGL(step_k, dim3(2 * tot), dim3(kGridNT), jl_bytes, s, c.dev, pw, B, par,
+                           tot, it, jw);
     }
     hipLaunchKernelGGL(k_jqr_settle, dim3(B), dim3(256), 0, s, c.dev, c.max_n & 1);
     GHSVD_HIP(hipGetLastError());

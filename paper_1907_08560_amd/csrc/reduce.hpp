@@ -10,10 +10,11 @@
 namespace ghsvd {
 
 // Hyperbolic QR of every pencil's Ft (m x n) under Jw, in place, with P2 in
-// perm; then Gt = G P2 and its Householder QR (R_kk = -e^{i arg x_1} ||x||).
-// Pencils with reduce = 0 are skipped.  One launch per step covers all
-// pencils.  Synchronizes the stream; status[k] and n2x2[k] per pencil.
-int run_reduction(const BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
+// perm; and the Householder QR of Gt = G without pivoting (R_kk = -e^{i arg
+// x_1} ||x||; the caller permutes R's columns by P2).  Pencils with reduce =
+// 0 are skipped.  One launch per step covers all pencils.  Synchronizes the
+// stream; status[k] and n2x2[k] per pencil.
+int run_reduction(BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
                   hipStream_t s);
 
 // dst(:, j) = src(:, perm[j]) for rows 0..rows-1 (perm may be NULL = identity).
