@@ -1180,7 +1180,9 @@ int run_reduction(BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
         hipLaunchKernelGGL(k_jqr_cross, dim3(tot), dim3(kGridNT), 0, s, c.dev, pw, B, par, jw);
         hipLaunchKernelGGL(k_jqr_cross2, dim3(tot), dim3(kGridNT), 0, s, c.dev, pw, B, par, jw);
         const int rc = rows_cap[w];
-        auto step_k = rc <= 4 ? k_jqr_step<4> : rc <= 8 ? k_jqr_step<8> : k_jqr_step<16>;
+        // 8 rows per thread only when every column fits: its register
+        // count lowers the occupancy of the streaming paths
+        auto step_k = rc > 4 && rc <= 8 ? k_jqr_step<8> : k_jqr_step<4>;
         hipLaunchKernelGGL(step_k, dim3(2 * tot), dim3(kGridNT), jl_bytes, s, c.dev, pw, B, par,
                            tot, it, jw);
     }
