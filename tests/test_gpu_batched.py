@@ -80,3 +80,21 @@ def test_batched_square_and_tall_mixed(oracle):
     for k, P in enumerate(Ps):
         st, lam_o, _, _ = oracle.ghsvd(P.F, P.J, P.G, max_sweeps=80)
         assert rel_err(host(lams[k]), lam_o) <= 1e-10
+
+
+@pytest.mark.parametrize("count", [70, 1030])
+def test_batched_many_pencils(count):
+    """More pencils than one 64-lane lookup chunk (70), and more than the
+    ballot lookup covers (1030, binary search): every workgroup must find
+    its pencil, so each pencil's result equals its own single solve."""
+    sizes = [4 + (k * 7) % 9 for k in range(count)]
+    Ps = [synth.random_pencil(5000 + k, n, 2 * n, n + 1, 2 * n, 1e-2) for k, n in enumerate(sizes)]
+    dev = [to_dev(P) for P in Ps]
+    kw = dict(precision="fp64", variant="blocked", waves_per_pair=1, block_width=8)
+    lams, Xs, infos, rc = ghsvd.solve_batched([d[0] for d in dev], [d[1] for d in dev],
+                                              [d[2] for d in dev], **kw)
+    assert rc == 0
+    for k in sorted({0, 1, 63, 64, 65, count // 2, count - 1}):
+        assert infos[k]["status"] == 0, (k, infos[k])
+        lam1, X1, info1 = ghsvd.solve(*dev[k], **kw)
+        assert torch.equal(lam1, lams[k]) and torch.equal(X1, Xs[k]), k

@@ -62,3 +62,43 @@ def test_reduce_isotropic_2x2():
     H = F.conj().T @ (J[:, None] * F)
     pm = host(perm)
     assert np.abs(Fs.conj().T @ (host(Jsq)[:, None] * Fs) - H[np.ix_(pm, pm)]).max() < 1e-14
+
+
+@pytest.mark.parametrize("n,m,m_plus,p", [(300, 1300, 975, 2100), (600, 900, 675, 1200)])
+def test_reduce_register_and_streaming_columns(oracle, n, m, m_plus, p):
+    """Shapes whose trailing columns are longer than the register-resident
+    step holds (1024 or 2048 rows) at the first steps and fit later, so
+    both forms of the column step run in one factorization.
+
+    The pivot decisions must match exactly.  The hyperbolic factor's
+    elementwise bar is set by its own forward sensitivity: the oracle is run
+    again on F with relative noise of 1e-16 (a rounding-level change of the
+    input, with the same pivots), and the GPU factor, whose sums round in a
+    different order, may differ from the oracle's by 20 times that change
+    (at least 1e-10).  The J-Gram of the factor must reproduce P2^T F^* J F P2
+    to 1e-11 of its largest entry."""
+    P = synth.random_pencil(900 + n, n, m, m_plus, p, 1e-4)
+    F, J, G = to_dev(P)
+    Fsq, Jsq, Gsq, perm, n2 = ghsvd.reduce(F, J, G)
+    st, Fo, Jo, Go, perm_o, n2o = oracle.reduce(P.F, P.J, P.G)
+    assert st == 0
+    assert np.array_equal(host(perm), perm_o)
+    assert np.array_equal(host(Jsq), Jo)
+    assert n2 == n2o
+    colscale = np.linalg.norm(Fo, axis=0)
+    rng = np.random.default_rng(n)
+    Fn = P.F * (1.0 + 1e-16 * rng.standard_normal(P.F.shape))
+    st_n, Fo_n, _, _, perm_n, _ = oracle.reduce(Fn, P.J, P.G)
+    assert st_n == 0 and np.array_equal(perm_n, perm_o)
+    sens = np.max(np.abs(Fo_n - Fo) / colscale[None, :])
+    err = np.max(np.abs(host(Fsq) - Fo) / colscale[None, :])
+    assert err < max(1e-10, 20.0 * sens), (err, sens)
+    H = P.F.conj().T @ (P.J[:, None] * P.F)
+    Hp = H[np.ix_(perm_o, perm_o)]
+    Fs = host(Fsq)
+    assert np.abs(Fs.conj().T @ (host(Jsq)[:, None] * Fs) - Hp).max() < 1e-11 * np.abs(H).max()
+    st_g, Rg = oracle.qr(np.asfortranarray(P.G))
+    assert st_g == 0
+    B = Rg[:, perm_o]
+    err_g = np.max(np.abs(host(Gsq) - B) / np.linalg.norm(B, axis=0)[None, :])
+    assert err_g < 1e-10, err_g
