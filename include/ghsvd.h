@@ -238,6 +238,33 @@ int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, doub
                        int crit_literal, long long *counters, int *sweeps_done, void *stream);
 
 /*
+ * Full GHSVD from a finished sweep stage (Phase 4, Section 7, with the
+ * outputs of Section 6.1).  Inputs (device, column-major complex128 as
+ * interleaved re/im doubles, not modified): the swept F' (m x n, rows
+ * 0..n_plus-1 carry J = +1, the rest J = -1), G' (p x n) and the accumulated
+ * transformation Z' (n x n) that ghsvd_sweeps or ghsvd_block_sweeps leave in
+ * place.  Outputs (device): with h_j = f'_j^* J f'_j, s_j = g'_j^* g'_j and
+ * Sigma_j = (|h_j| + s_j)^{1/2},
+ *   sigma_f[j] = |h_j|^{1/2} / Sigma_j, sigma_g[j] = s_j^{1/2} / Sigma_j  (n doubles each),
+ *   U = F' diag(|h_j|^{-1/2})  (m x n, ldu >= m),
+ *   V = G' diag(s_j^{-1/2})    (p x n, ldv >= p),
+ *   X = Z^{-1}, Z = Z' diag(Sigma_j)^{-1}  (n x n, ldx >= n),
+ * the inverse by LU with complete pivoting (among entries of equal modulus
+ * the first in column-major order) and one pair of triangular solves per
+ * column.  Then F' Z'^{-1} = U diag(sigma_f) X, G' Z'^{-1} = V diag(sigma_g) X,
+ * sigma_f^2 + sigma_g^2 = 1, U^* J U = diag(sign h_j), V^* V = I at
+ * convergence, and the eigenvalues of the pencil are sign(h_j) (sigma_f[j] /
+ * sigma_g[j])^2.  Errors: GHSVD_EINVAL for sizes, leading dimensions, NULL
+ * pointers or n > 4096; GHSVD_ERANK when some h_j or s_j is zero or Z is
+ * singular (a zero pivot); GHSVD_ENONFINITE for NaN/Inf column norms.
+ * Allocates and frees its own workspace (n^2 complex128 + O(n)); synchronizes
+ * the stream.
+ */
+int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_plus, const double *G,
+               int ldg, const double *Z, int ldz, double *U, int ldu, double *V, int ldv,
+               double *sigma_f, double *sigma_g, double *X, int ldx, void *stream);
+
+/*
  * The round-robin ordering (host): N = n rounded up to even; step s pairs
  * slot N-1 with s and (s+k) mod (N-1) with (s-k) mod (N-1), k = 1..N/2-1;
  * each pair as p < q; a pair meeting index n (odd n) is a bye, p = q = -1.
