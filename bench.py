@@ -3,10 +3,10 @@
 A "step" is one complete ghsvd_solve of the n = 1024 pencil (F 1536 x 1024
 with J = diag(+1 x1152, -1 x384), G 2048 x 1024 = U diag(s) W^* with s
 log-uniform in [1e-8, 1], so cond(G^* G) = 1e16; complex128): input checks,
-one-time reduction (hyperbolic QR of F, QR of G P2), the sweep stages of the
-chosen path (default: Level-2 blocked FP64 sweeps, then the FP64 pointwise
-sweep that confirms convergence), and the outputs lambda, X.  Inputs are
-resident in HBM before the timed region.  Prints one JSON line.
+one-time reduction (hyperbolic QR of F, QR of G), the sweep stages of the
+chosen path (default: Level-2 blocked FP64 sweeps until a sweep has no big
+transformation), and the outputs lambda, X.  Inputs are resident in HBM
+before the timed region.  Prints one JSON line.
 
 Beside the timed path it reports:
   * per sweep-kernel kind, the mean launch time measured with HIP events on
@@ -14,10 +14,13 @@ Beside the timed path it reports:
   * the error of lambda against the stored oracle eigenvalues of this pencil;
   * the other paths on the same pencil (plain FP64 pointwise; mixed FP32 ->
     FP64), with their times and errors;
-  * the CPU oracle on a bounded sample (reduction + one sweep, extrapolated).
+  * the CPU oracle on a bounded sample (reduction + one sweep, extrapolated);
+  * the full GHSVD (Phase 4: U, V, Sigma_F, Sigma_G, X = Z^{-1}) of the swept
+    square factors, timed alone, with the relative errors (7.1).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
                     [--variant blocked|pointwise] [--no-compare] [--no-cpu-baseline]
+                    [--no-full]
 """
 import argparse
 import hashlib
@@ -156,6 +159,37 @@ def cpu_baseline(P, oracle_sweeps):
             "sample": (f"one pencil: reduction ({t_red:.1f} s) + 1 square sweep ({t_sw:.1f} s) "
                        f"measured single-threaded; total extrapolated to {oracle_sweeps} sweeps "
                        f"(the oracle's count on this pencil) = {total:.0f} s/pencil")}
+
+
+def full_leg(ghsvd, F, J, G, reps=3):
+    """The full GHSVD of the pencil (Phase 4): the reduction, the row split
+    by the signature, blocked FP64 sweeps in place on the square factors, then
+    ghsvd_full, timed alone (median of `reps` calls), with the relative errors
+    (7.1) of the decomposition of the square factors."""
+    import torch
+    Fsq, Jsq, Gsq, perm, n2 = ghsvd.reduce(F, J, G)
+    n = Fsq.shape[1]
+    order = torch.cat([torch.nonzero(Jsq > 0).flatten(), torch.nonzero(Jsq < 0).flatten()])
+    n_plus = int((Jsq > 0).sum().item())
+    # column-major copies: F0, G0 keep the square factors for the errors,
+    # Fw, Gw, Zw are swept in place
+    F0 = Fsq[order, :].t().contiguous().t()
+    G0 = Gsq.t().clone().t()
+    Fw = F0.t().clone().t()
+    Gw = G0.t().clone().t()
+    Zw = torch.eye(n, dtype=torch.complex128, device=F.device).t()
+    rc, done, cnt = ghsvd.block_sweeps(Fw, n_plus, Gw, Zw, 60, block_width=16)
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        U, V, sf, sg, X = ghsvd.full(Fw, n_plus, Gw, Zw)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    eF = (torch.linalg.norm(F0 - (U * sf[None, :]) @ X) / torch.linalg.norm(F0)).item()
+    eG = (torch.linalg.norm(G0 - (V * sg[None, :]) @ X) / torch.linalg.norm(G0)).item()
+    return {"ms": 1000.0 * sorted(ts)[len(ts) // 2], "sweeps": done, "sweep_status": rc,
+            "errors_7_1": {"F": eF, "G": eG}}
 
 
 def run_path(ghsvd, F, J, G, P, kw, steps, warmup, profile_every=0):
@@ -348,6 +382,8 @@ def main():
     ap.add_argument("--variant", default="blocked", choices=["pointwise", "blocked"])
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-full", action="store_true",
+                    help="skip the full-GHSVD leg (Phase 4 timing and the errors (7.1))")
     ap.add_argument("--profile-every", type=int, default=4)
     ap.add_argument("--max-sweeps", type=int, default=0)
     ap.add_argument("--block-width", type=int, default=0, choices=[0, 8, 16, 32],
@@ -460,6 +496,8 @@ def main():
                                      "status": cinf[-1]["status"],
                                      "lambda_rel_err_vs_oracle": {"max": emax, "median": emed}}
         rec["compare"] = comp
+    if not args.no_full:
+        rec["full_ghsvd"] = full_leg(ghsvd, F, J, G)
     if not args.no_cpu_baseline:
         with open(GOLDEN) as f:
             osw = json.load(f)["sweeps"]
