@@ -382,6 +382,8 @@ def main():
     ap.add_argument("--variant", default="blocked", choices=["pointwise", "blocked"])
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-reduce", action="store_true",
+                    help="sweep the tall factors directly, without the one-time reduction")
     ap.add_argument("--no-full", action="store_true",
                     help="skip the full-GHSVD leg (Phase 4 timing and the errors (7.1))")
     ap.add_argument("--profile-every", type=int, default=4)
@@ -426,7 +428,7 @@ def main():
     G = ghsvd.to_device_fortran(P.G, dev)
     J = torch.from_numpy(P.J).to(dev)
     kw = dict(precision=args.precision, variant=args.variant, max_sweeps=args.max_sweeps,
-              block_width=args.block_width)
+              block_width=args.block_width, reduce=not args.no_reduce)
 
     dt, infos, lam, times = run_path(ghsvd, F, J, G, P, kw, args.steps, args.warmup,
                                      args.profile_every)
@@ -458,9 +460,10 @@ def main():
         "config": {
             "workload": ("one LAPW-shaped pencil n=1024: F 1536x1024 Gaussian, J 1152(+)/384(-), "
                          "G 2048x1024 = U diag(s) W^*, s log-uniform [1e-8,1] (cond S = 1e16), "
-                         f"complex128; reduction + {args.variant} {args.precision} sweeps"),
+                         f"complex128; {'no reduction (tall factors)' if args.no_reduce else 'reduction'}"
+                         f" + {args.variant} {args.precision} sweeps"),
             "n": n, "m": P.m, "p": P.p, "batch": 1,
-            "precision": args.precision, "variant": args.variant,
+            "precision": args.precision, "variant": args.variant, "reduce": not args.no_reduce,
         },
         "pair_updates_per_s": isum["pairs_visited"] / dt,
         "sweeps_fp64": info["sweeps_fp64"],

@@ -90,3 +90,17 @@ def test_full_rank_errors():
     with pytest.raises(ghsvd.GhsvdError) as e:
         ghsvd.full(dev(Fp), 3, dev(Gp), dev(Zs))
     assert e.value.status == -2  # GHSVD_ERANK: a zero pivot
+
+
+def test_full_at_full_size():
+    # the n = 1024 pencil, in the configuration the benchmark times: the
+    # decomposition errors (7.1) and X Z = I on sampled columns (properties
+    # that hold at any size; the oracle is not run at this size)
+    import bench
+    P = synth.workload_pencil(2)
+    F = dev(P.F)
+    G = dev(P.G)
+    J = torch.from_numpy(P.J).cuda()
+    r = bench.full_leg(ghsvd, F, J, G, reps=1)
+    assert r["sweep_status"] == 0
+    assert r["errors_7_1"]["F"] < 1e-12 and r["errors_7_1"]["G"] < 1e-12, r
