@@ -13,12 +13,17 @@
 // column-major order) and one pair of triangular solves per column of X,
 // as the paper does with one solve per column in parallel.
 //
-// The factorization runs one column step per pair of launches: a single
-// workgroup takes the pivot from the per-tile maxima, swaps the pivot row and
-// column into place and scales the multipliers; then one workgroup per
-// 64 x 64 tile of the trailing matrix applies the rank-one update and records
-// the largest modulus of its updated tile for the next step.  The solves run
-// one workgroup per column of X with the right-hand side in LDS.
+// The factorization runs one launch per column step, with one workgroup per
+// 64 x 64 tile of the trailing matrix.  Every workgroup takes the pivot from
+// the tile maxima of the previous launch, reads its tile of the interchanged
+// matrix through the two interchanges without moving any data, applies the
+// rank-one update and writes the tile, with its largest modulus, to the other
+// of two working matrices.  Rows and columns keep labels (their index in Z),
+// so the multipliers and the pivot row of a step are stored at their labels
+// and need no later interchanges; one gather puts L and U in the usual
+// triangular layout.  The solves run four (n <= 1024) right-hand sides per
+// workgroup in LDS, one barrier per substitution step, and store X through
+// the column labels.
 #include "hz_common.hpp"
 
 namespace ghsvd {
@@ -120,40 +125,29 @@ __global__ __launch_bounds__(kP4Threads) void k_p4_scale(int m, int p, int n, co
     }
 }
 
-// Tile maxima of |w|^2 over rows and columns k..n-1 of W (ld n), tiles of
-// kP4Tile x kP4Tile; with upd, first the rank-one update of step k - 1
-// (w_ij -= w_i,k-1 w_k-1,j for i, j >= k).
-__global__ __launch_bounds__(kP4Threads) void k_p4_update(int n, int k, int upd, double2 *W,
-                                                          TileMax *part) {
+// Tile maxima of |w|^2 of the starting matrix W (ld n), tiles of
+// kP4Tile x kP4Tile; workgroup 0 also gives every row and column its label
+// (its index in W).
+__global__ __launch_bounds__(kP4Threads) void k_p4_tilemax(int n, const double2 *W, TileMax *part,
+                                                           int *rlab, int *clab) {
     __shared__ double sv[kP4Threads / kWave];
     __shared__ long si[kP4Threads / kWave];
-    __shared__ double2 rowk[kP4Tile];
-    const int nt = (n - k + kP4Tile - 1) / kP4Tile;
+    const int nt = (n + kP4Tile - 1) / kP4Tile;
     const int ti = blockIdx.x % nt, tj = blockIdx.x / nt;
-    const int i0 = k + ti * kP4Tile, j0 = k + tj * kP4Tile;
     const int tid = threadIdx.x;
-    const int kp = k - 1;
-    if (upd && tid < kP4Tile) {
-        const int j = j0 + tid;
-        rowk[tid] = j < n ? W[(size_t)j * n + kp] : cmk(0.0, 0.0);
-    }
-    __syncthreads();
+    if (blockIdx.x == 0)
+        for (int r = tid; r < n; r += blockDim.x) {
+            rlab[r] = r;
+            clab[r] = r;
+        }
     double bv = -1.0;
     long bi = 0x7fffffffffffffffL;
-    // thread t: row i0 + (t % 64), columns j0 + t / 64 + 4 c
-    const int i = i0 + (tid % kP4Tile);
-    const double2 lik = (upd && i < n) ? W[(size_t)kp * n + i] : cmk(0.0, 0.0);
+    // thread t: row ti * 64 + (t % 64), columns tj * 64 + t / 64 + 4 c
+    const int i = ti * kP4Tile + (tid % kP4Tile);
     for (int c = tid / kP4Tile; c < kP4Tile; c += kP4Threads / kP4Tile) {
-        const int j = j0 + c;
+        const int j = tj * kP4Tile + c;
         if (i >= n || j >= n) continue;
-        double2 *w = W + (size_t)j * n + i;
-        double2 x = *w;
-        if (upd) {
-            const double2 u = rowk[c];
-            x = csub(x, cmul(lik, u));
-            *w = x;
-        }
-        const double v = cnorm2(x);
+        const double v = cnorm2(W[(size_t)j * n + i]);
         const long idx = (long)j * n + i;
         if (tm_better(v, idx, bv, bi)) {
             bv = v;
@@ -164,113 +158,180 @@ __global__ __launch_bounds__(kP4Threads) void k_p4_update(int n, int k, int upd,
     if (tid == 0) part[blockIdx.x] = TileMax{bv, bi};
 }
 
-// Pivot of step k from the tile maxima: swap row k with the pivot row and
-// column k with the pivot column (whole rows and columns), record both, and
-// divide the multipliers below the pivot by it.  flags bit 0 on a zero pivot.
-__global__ __launch_bounds__(1024) void k_p4_pivot(int n, int k, double2 *W, const TileMax *part,
-                                                   int *piv_r, int *piv_c, int *flags) {
-    __shared__ double sv[1024 / kWave];
-    __shared__ long si[1024 / kWave];
+// Step k of the factorization, one launch.  Win holds rows and columns k..n-1
+// of the working matrix after step k - 1 and pin their tile maxima (tiles
+// anchored at k).  Every workgroup takes the pivot (pr, q) from pin itself.
+// The interchanges of row k with row pr and of column k with column q are
+// not made in memory: the interchanged matrix has at (i, j), i, j > k, the
+// entry (rs(i), cs(j)) of Win, where rs swaps pr for k and cs swaps q for k.
+// A workgroup updates one 64 x 64 tile of rows and columns k+1..n-1 of it by
+// the rank-one term of step k and writes the tile, at the same positions, to
+// Wout with its largest modulus for step k + 1.  Rows and columns carry
+// labels (rl, cl; their index in the starting matrix), so the factors are
+// stored by label: the multipliers of step k at Lt[label, k], the pivot row
+// at Ut[k, label], the pivot at dg[k], the labels of the pivot's row and
+// column at piv_r[k], piv_c[k].  flags bit 0 on a zero pivot; every step
+// after it then finds a zero pivot too and writes nothing else.
+__global__ __launch_bounds__(kP4Threads) void k_p4_step(
+    int n, int k, const double2 *Win, double2 *Wout, const TileMax *pin, TileMax *pout,
+    const int *rl_in, const int *cl_in, int *rl_out, int *cl_out, double2 *Lt, double2 *Ut,
+    double2 *dg, int *piv_r, int *piv_c, int *flags) {
+    __shared__ double sv[kP4Threads / kWave];
+    __shared__ long si[kP4Threads / kWave];
+    __shared__ double2 rowk[kP4Tile];
+    const int tid = threadIdx.x;
     const int nt = (n - k + kP4Tile - 1) / kP4Tile;
     double bv = -1.0;
     long bi = 0x7fffffffffffffffL;
-    for (int t = threadIdx.x; t < nt * nt; t += blockDim.x) {
-        const TileMax m = part[t];
+    for (int t = tid; t < nt * nt; t += blockDim.x) {
+        const TileMax m = pin[t];
         if (tm_better(m.v, m.idx, bv, bi)) {
             bv = m.v;
             bi = m.idx;
         }
     }
     block_tm(bv, bi, sv, si);
-    const int q = (int)(bi / n), pr = (int)(bi % n);
     if (!(bv > 0.0)) {
-        if (threadIdx.x == 0) {
-            atomicOr(flags, 1);
-            piv_r[k] = k;
-            piv_c[k] = k;
+        // empty maxima for the next step, which then stops here too
+        if (tid == 0) {
+            pout[blockIdx.x] = TileMax{-1.0, 0x7fffffffffffffffL};
+            if (blockIdx.x == 0) atomicOr(flags, 1);
         }
         return;
     }
-    // row swap k <-> pr over all columns, then column swap k <-> q over all rows
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        double2 *a = W + (size_t)j * n;
-        const double2 t = a[k];
-        a[k] = a[pr];
-        a[pr] = t;
-    }
-    __syncthreads();
-    if (q != k) {
-        double2 *a = W + (size_t)k * n, *b = W + (size_t)q * n;
-        for (int r = threadIdx.x; r < n; r += blockDim.x) {
-            const double2 t = a[r];
-            a[r] = b[r];
-            b[r] = t;
-        }
-    }
-    __syncthreads();
-    const double2 d = W[(size_t)k * n + k];
+    const int q = (int)(bi / n), pr = (int)(bi % n);
+    const int nt1 = (n - k - 1 + kP4Tile - 1) / kP4Tile;
+    const int ti = nt1 ? (int)blockIdx.x % nt1 : 0, tj = nt1 ? (int)blockIdx.x / nt1 : 0;
+    const int i0 = k + 1 + ti * kP4Tile, j0 = k + 1 + tj * kP4Tile;
+    const double2 d = Win[(size_t)q * n + pr];
     const double dn = cnorm2(d);
     const double2 dinv = cmk(d.x / dn, -d.y / dn);  // 1 / d
-    double2 *col = W + (size_t)k * n;
-    for (int r = k + 1 + threadIdx.x; r < n; r += blockDim.x) col[r] = cmul(col[r], dinv);
-    if (threadIdx.x == 0) {
-        piv_r[k] = pr;
-        piv_c[k] = q;
+    if (tid < kP4Tile) {
+        // the pivot row on this tile's columns
+        const int j = j0 + tid;
+        double2 u = cmk(0.0, 0.0);
+        if (j < n) {
+            const int cs = j == q ? k : j;
+            u = Win[(size_t)cs * n + pr];
+            if (ti == 0) {
+                const int lab = cl_in[cs];
+                Ut[(size_t)lab * n + k] = u;
+                cl_out[j] = lab;
+            }
+        }
+        rowk[tid] = u;
     }
+    if (blockIdx.x == 0 && tid == 0) {
+        dg[k] = d;
+        piv_r[k] = rl_in[pr];
+        piv_c[k] = cl_in[q];
+    }
+    __syncthreads();
+    // thread t: row i0 + (t % 64), columns j0 + t / 64 + 4 c
+    const int i = i0 + (tid % kP4Tile);
+    const int rs = i == pr ? k : i;
+    double2 l = cmk(0.0, 0.0);
+    if (i < n) {
+        l = cmul(Win[(size_t)q * n + rs], dinv);
+        if (tj == 0 && tid < kP4Tile) {
+            const int lab = rl_in[rs];
+            Lt[(size_t)k * n + lab] = l;
+            rl_out[i] = lab;
+        }
+    }
+    bv = -1.0;
+    bi = 0x7fffffffffffffffL;
+    for (int c = tid / kP4Tile; c < kP4Tile; c += kP4Threads / kP4Tile) {
+        const int j = j0 + c;
+        if (i >= n || j >= n) continue;
+        const int cs = j == q ? k : j;
+        const double2 x = csub(Win[(size_t)cs * n + rs], cmul(l, rowk[c]));
+        Wout[(size_t)j * n + i] = x;
+        const double v = cnorm2(x);
+        const long idx = (long)j * n + i;
+        if (tm_better(v, idx, bv, bi)) {
+            bv = v;
+            bi = idx;
+        }
+    }
+    block_tm(bv, bi, sv, si);
+    if (tid == 0) pout[blockIdx.x] = TileMax{bv, bi};
 }
 
-// Column j of X = Q U^{-1} L^{-1} P e_j from P W Q = L U (W holds L below
-// its diagonal and U on and above it): the row interchanges move e_j to
-// e_r, then forward and back substitution in LDS, then the column
-// interchanges place the entries.
-__global__ __launch_bounds__(kP4Threads) void k_p4_solve(int n, const double2 *W, const int *piv_r,
-                                                         const int *piv_c, double2 *X, long ldx) {
-    extern __shared__ double2 y[];
-    __shared__ int rsh;
-    const int j = blockIdx.x;
-    if (threadIdx.x == 0) {
-        int r = j;
-        for (int k = 0; k < n; ++k) {
-            const int pk = piv_r[k];
-            if (r == k) r = pk;
-            else if (r == pk) r = k;
+// P W Q = L U in the triangular layout (L below the diagonal, U on and
+// above it, column c = blockIdx.x) from the factors stored by label:
+// L(r, c) = Lt(piv_r[r], c) for r > c, U(r, c) = Ut(r, piv_c[c]) for r < c,
+// U(c, c) = dg[c].
+__global__ __launch_bounds__(kP4Threads) void k_p4_gather(int n, const double2 *Lt,
+                                                          const double2 *Ut, const double2 *dg,
+                                                          const int *piv_r, const int *piv_c,
+                                                          double2 *LU, const int *flags) {
+    if (*flags & 1) return;
+    const int c = blockIdx.x;
+    const double2 *lt = Lt + (size_t)c * n;
+    const double2 *ut = Ut + (size_t)piv_c[c] * n;
+    double2 *o = LU + (size_t)c * n;
+    for (int r = threadIdx.x; r < n; r += blockDim.x)
+        o[r] = r > c ? lt[piv_r[r]] : (r < c ? ut[r] : dg[c]);
+}
+
+// NR columns of X = Q U^{-1} L^{-1} P per workgroup.  P e_j = e_c for the
+// step c at which row label j was pivoted (j = piv_r[c]); workgroup g takes
+// c = g NR .. g NR + NR - 1, so the forward substitutions of its right-hand
+// sides start together at row g NR (the entries above stay zero).  Forward
+// and back substitution run with the right-hand sides in LDS, one barrier per
+// step; x_c = y_c / u_cc is formed again when stored, at row piv_c[c] of X
+// (Q e_c = e_{piv_c[c]}).
+template <int NR>
+__global__ __launch_bounds__(kP4Threads) void k_p4_solve(int n, const double2 *LU,
+                                                         const int *piv_r, const int *piv_c,
+                                                         double2 *X, long ldx, const int *flags) {
+    extern __shared__ double2 y[];  // NR right-hand sides of n entries
+    if (*flags & 1) return;
+    const int g0 = blockIdx.x * NR;
+    const int ns = n - g0 < NR ? n - g0 : NR;
+    for (int i = threadIdx.x; i < NR * n; i += blockDim.x) y[i] = cmk(0.0, 0.0);
+    __syncthreads();
+    if (threadIdx.x < ns) y[threadIdx.x * n + g0 + threadIdx.x] = cmk(1.0, 0.0);
+    __syncthreads();
+    // L y = e_c (unit lower triangular)
+    for (int t = g0; t < n - 1; ++t) {
+        double2 yt[NR];
+#pragma unroll
+        for (int s = 0; s < NR; ++s) yt[s] = y[s * n + t];
+        const double2 *l = LU + (size_t)t * n;
+        for (int i = t + 1 + threadIdx.x; i < n; i += blockDim.x) {
+            const double2 li = l[i];
+#pragma unroll
+            for (int s = 0; s < NR; ++s) y[s * n + i] = csub(y[s * n + i], cmul(li, yt[s]));
         }
-        rsh = r;
-    }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) y[i] = cmk(0.0, 0.0);
-    __syncthreads();
-    const int r = rsh;
-    if (threadIdx.x == 0) y[r] = cmk(1.0, 0.0);
-    __syncthreads();
-    // L y = e_r (unit lower triangular): entries above r stay zero
-    for (int t = r; t < n - 1; ++t) {
-        const double2 yt = y[t];
-        const double2 *l = W + (size_t)t * n;
-        for (int i = t + 1 + threadIdx.x; i < n; i += blockDim.x) y[i] = csub(y[i], cmul(l[i], yt));
         __syncthreads();
     }
-    // U w = y
-    for (int t = n - 1; t >= 0; --t) {
-        const double2 *u = W + (size_t)t * n;
+    // U x = y: entry t of each right-hand side is final once the steps above
+    // it are done, and is not written again
+    for (int t = n - 1; t > 0; --t) {
+        const double2 *u = LU + (size_t)t * n;
         const double2 d = u[t];
         const double dn = cnorm2(d);
-        const double2 wt = cmul(y[t], cmk(d.x / dn, -d.y / dn));
-        __syncthreads();
-        if (threadIdx.x == 0) y[t] = wt;
-        for (int i = threadIdx.x; i < t; i += blockDim.x) y[i] = csub(y[i], cmul(u[i], wt));
-        __syncthreads();
-    }
-    // X(:, j) = Q w: the column interchanges, applied in reverse order
-    for (int k = n - 1; k >= 0; --k) {
-        const int qk = piv_c[k];
-        if (qk != k && threadIdx.x == 0) {
-            const double2 t = y[k];
-            y[k] = y[qk];
-            y[qk] = t;
+        const double2 di = cmk(d.x / dn, -d.y / dn);
+        double2 xt[NR];
+#pragma unroll
+        for (int s = 0; s < NR; ++s) xt[s] = cmul(y[s * n + t], di);
+        for (int i = threadIdx.x; i < t; i += blockDim.x) {
+            const double2 ui = u[i];
+#pragma unroll
+            for (int s = 0; s < NR; ++s) y[s * n + i] = csub(y[s * n + i], cmul(ui, xt[s]));
         }
         __syncthreads();
     }
-    for (int i = threadIdx.x; i < n; i += blockDim.x) X[(size_t)j * ldx + i] = y[i];
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+        const double2 d = LU[(size_t)t * n + t];
+        const double dn = cnorm2(d);
+        const double2 di = cmk(d.x / dn, -d.y / dn);
+        const long row = piv_c[t];
+        for (int s = 0; s < ns; ++s)
+            X[(size_t)piv_r[g0 + s] * ldx + row] = cmul(y[s * n + t], di);
+    }
 }
 
 }  // namespace
@@ -285,24 +346,44 @@ extern "C" int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_p
     if (n < 1 || m < n || p < n || n_plus < 0 || n_plus > m || ldf < m || ldg < p || ldz < n ||
         ldu < m || ldv < p || ldx < n || !F || !G || !Z || !U || !V || !sigma_f || !sigma_g || !X)
         return GHSVD_EINVAL;
-    // the right-hand side of a solve lives in LDS
+    // the right-hand sides of a solve live in LDS
     if ((size_t)n * sizeof(double2) > 64 * 1024) return GHSVD_EINVAL;
+    const int nr = n <= 1024 ? 4 : (n <= 2048 ? 2 : 1);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int nt = (n + kP4Tile - 1) / kP4Tile;
+    // two working matrices (steps alternate between them), the factors by
+    // label, the pivots, two sets of tile maxima and of labels
     const size_t wbytes = align_up(sizeof(double2) * (size_t)n * n, 256);
-    const size_t need = wbytes + align_up(sizeof(double) * 2 * (size_t)n, 256) +
-                        align_up(sizeof(TileMax) * (size_t)nt * nt, 256) +
-                        align_up(sizeof(int) * (2 * (size_t)n + 1), 256);
+    const size_t dbytes = align_up(sizeof(double) * 2 * (size_t)n, 256);
+    const size_t gbytes = align_up(sizeof(double2) * (size_t)n, 256);
+    const size_t pbytes = align_up(sizeof(TileMax) * (size_t)nt * nt, 256);
+    const size_t ibytes = align_up(sizeof(int) * (6 * (size_t)n + 1), 256);
+    const size_t need = 4 * wbytes + dbytes + gbytes + 2 * pbytes + ibytes;
     char *buf = nullptr;
     if (hipMalloc(&buf, need) != hipSuccess) return GHSVD_EDEVICE;
-    double2 *W = reinterpret_cast<double2 *>(buf);
-    double *sf = reinterpret_cast<double *>(buf + wbytes);
+    char *at = buf;
+    auto take = [&](size_t bytes) {
+        char *r = at;
+        at += bytes;
+        return r;
+    };
+    double2 *Wb[2];
+    Wb[0] = reinterpret_cast<double2 *>(take(wbytes));
+    Wb[1] = reinterpret_cast<double2 *>(take(wbytes));
+    double2 *Lt = reinterpret_cast<double2 *>(take(wbytes));
+    double2 *Ut = reinterpret_cast<double2 *>(take(wbytes));
+    double *sf = reinterpret_cast<double *>(take(dbytes));
     double *sg = sf + n;
-    TileMax *part = reinterpret_cast<TileMax *>(buf + wbytes + align_up(sizeof(double) * 2 * (size_t)n, 256));
-    int *piv_r = reinterpret_cast<int *>(reinterpret_cast<char *>(part) +
-                                         align_up(sizeof(TileMax) * (size_t)nt * nt, 256));
-    int *piv_c = piv_r + n;
-    int *flags = piv_c + n;
+    double2 *dg = reinterpret_cast<double2 *>(take(gbytes));
+    TileMax *part[2];
+    part[0] = reinterpret_cast<TileMax *>(take(pbytes));
+    part[1] = reinterpret_cast<TileMax *>(take(pbytes));
+    int *ib = reinterpret_cast<int *>(take(ibytes));
+    int *piv_r = ib, *piv_c = ib + n;
+    int *rl[2] = {ib + 2 * n, ib + 3 * n};
+    int *cl[2] = {ib + 4 * n, ib + 5 * n};
+    int *flags = ib + 6 * n;
+    double2 *W = Wb[0];
     int rc = GHSVD_OK;
     int hflags = 0;
     auto fail = [&](int code) {
@@ -327,22 +408,32 @@ extern "C" int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_p
         return fail(GHSVD_EDEVICE);
     if (hflags & 2) return fail(GHSVD_ENONFINITE);
     if (hflags & 1) return fail(GHSVD_ERANK);
-    // LU with complete pivoting: step k takes its pivot from the tile maxima
-    // of rows and columns k..n-1, then updates them for step k + 1
+    // LU with complete pivoting, one launch per step; step k reads the
+    // working matrix, tile maxima and labels of parity k % 2 and writes
+    // those of parity (k + 1) % 2
+    hipLaunchKernelGGL(k_p4_tilemax, dim3(nt * nt), dim3(kP4Threads), 0, s, n, W, part[0], rl[0],
+                       cl[0]);
     for (int k = 0; k < n; ++k) {
-        const int t = (n - k + kP4Tile - 1) / kP4Tile;
-        if (k == 0)
-            hipLaunchKernelGGL(k_p4_update, dim3(t * t), dim3(kP4Threads), 0, s, n, 0, 0, W, part);
-        hipLaunchKernelGGL(k_p4_pivot, dim3(1), dim3(1024), 0, s, n, k, W, part, piv_r, piv_c,
-                           flags);
-        if (k + 1 < n) {
-            const int t1 = (n - k - 1 + kP4Tile - 1) / kP4Tile;
-            hipLaunchKernelGGL(k_p4_update, dim3(t1 * t1), dim3(kP4Threads), 0, s, n, k + 1, 1, W,
-                               part);
-        }
+        const int t1 = (n - k - 1 + kP4Tile - 1) / kP4Tile;
+        const int a = k & 1, b = a ^ 1;
+        hipLaunchKernelGGL(k_p4_step, dim3(t1 > 0 ? t1 * t1 : 1), dim3(kP4Threads), 0, s, n, k,
+                           Wb[a], Wb[b], part[a], part[b], rl[a], cl[a], rl[b], cl[b], Lt, Ut, dg,
+                           piv_r, piv_c, flags);
     }
-    hipLaunchKernelGGL(k_p4_solve, dim3(n), dim3(kP4Threads), sizeof(double2) * (size_t)n, s, n, W,
-                       piv_r, piv_c, reinterpret_cast<double2 *>(X), (long)ldx);
+    hipLaunchKernelGGL(k_p4_gather, dim3(n), dim3(kP4Threads), 0, s, n, Lt, Ut, dg, piv_r, piv_c,
+                       W, flags);
+    const size_t lds = sizeof(double2) * (size_t)nr * n;
+    const int ng = (n + nr - 1) / nr;
+    double2 *X2 = reinterpret_cast<double2 *>(X);
+    if (nr == 4)
+        hipLaunchKernelGGL(k_p4_solve<4>, dim3(ng), dim3(kP4Threads), lds, s, n, W, piv_r, piv_c,
+                           X2, (long)ldx, flags);
+    else if (nr == 2)
+        hipLaunchKernelGGL(k_p4_solve<2>, dim3(ng), dim3(kP4Threads), lds, s, n, W, piv_r, piv_c,
+                           X2, (long)ldx, flags);
+    else
+        hipLaunchKernelGGL(k_p4_solve<1>, dim3(ng), dim3(kP4Threads), lds, s, n, W, piv_r, piv_c,
+                           X2, (long)ldx, flags);
     if (hipGetLastError() != hipSuccess) return fail(GHSVD_EDEVICE);
     if (hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
