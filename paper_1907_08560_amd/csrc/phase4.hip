@@ -176,10 +176,24 @@ __global__ __launch_bounds__(kP4Threads) void k_p4_step(
     int n, int k, const double2 *Win, double2 *Wout, const TileMax *pin, TileMax *pout,
     const int *rl_in, const int *cl_in, int *rl_out, int *cl_out, double2 *Lt, double2 *Ut,
     double2 *dg, int *piv_r, int *piv_c, int *flags) {
+    constexpr int kCols = kP4Tile * kWave / kP4Threads;  // columns per thread
     __shared__ double sv[kP4Threads / kWave];
     __shared__ long si[kP4Threads / kWave];
-    __shared__ double2 rowk[kP4Tile];
     const int tid = threadIdx.x;
+    const int nt1 = (n - k - 1 + kP4Tile - 1) / kP4Tile;
+    const int ti = nt1 ? (int)blockIdx.x % nt1 : 0, tj = nt1 ? (int)blockIdx.x / nt1 : 0;
+    const int i0 = k + 1 + ti * kP4Tile, j0 = k + 1 + tj * kP4Tile;
+    // thread t: row i0 + (t % 64), columns j0 + t / 64 + 4 c.  The tile is
+    // loaded before the pivot is known; only an entry in the pivot's row or
+    // column is read again once it is.
+    const int i = i0 + (tid % kP4Tile);
+    const int jt = j0 + tid / kP4Tile;
+    double2 x[kCols];
+#pragma unroll
+    for (int c = 0; c < kCols; ++c) {
+        const int j = jt + 4 * c;
+        x[c] = (i < n && j < n) ? Win[(size_t)j * n + i] : cmk(0.0, 0.0);
+    }
     const int nt = (n - k + kP4Tile - 1) / kP4Tile;
     double bv = -1.0;
     long bi = 0x7fffffffffffffffL;
@@ -200,54 +214,48 @@ __global__ __launch_bounds__(kP4Threads) void k_p4_step(
         return;
     }
     const int q = (int)(bi / n), pr = (int)(bi % n);
-    const int nt1 = (n - k - 1 + kP4Tile - 1) / kP4Tile;
-    const int ti = nt1 ? (int)blockIdx.x % nt1 : 0, tj = nt1 ? (int)blockIdx.x / nt1 : 0;
-    const int i0 = k + 1 + ti * kP4Tile, j0 = k + 1 + tj * kP4Tile;
+    const int rs = i == pr ? k : i;
+    // the pivot, the multiplier of row i and the pivot row on this thread's
+    // columns, all read at once
     const double2 d = Win[(size_t)q * n + pr];
+    double2 l = i < n ? Win[(size_t)q * n + rs] : cmk(0.0, 0.0);
+    double2 u[kCols];
+#pragma unroll
+    for (int c = 0; c < kCols; ++c) {
+        const int j = jt + 4 * c;
+        const int cs = j == q ? k : j;
+        u[c] = j < n ? Win[(size_t)cs * n + pr] : cmk(0.0, 0.0);
+        if (i < n && j < n && (i == pr || j == q)) x[c] = Win[(size_t)cs * n + rs];
+    }
     const double dn = cnorm2(d);
     const double2 dinv = cmk(d.x / dn, -d.y / dn);  // 1 / d
-    if (tid < kP4Tile) {
-        // the pivot row on this tile's columns
+    l = cmul(l, dinv);
+    if (i < n && tj == 0 && tid < kP4Tile) {
+        const int lab = rl_in[rs];
+        Lt[(size_t)k * n + lab] = l;
+        rl_out[i] = lab;
+    }
+    if (ti == 0 && tid < kP4Tile && j0 + tid < n) {
         const int j = j0 + tid;
-        double2 u = cmk(0.0, 0.0);
-        if (j < n) {
-            const int cs = j == q ? k : j;
-            u = Win[(size_t)cs * n + pr];
-            if (ti == 0) {
-                const int lab = cl_in[cs];
-                Ut[(size_t)lab * n + k] = u;
-                cl_out[j] = lab;
-            }
-        }
-        rowk[tid] = u;
+        const int cs = j == q ? k : j;
+        const int lab = cl_in[cs];
+        Ut[(size_t)lab * n + k] = Win[(size_t)cs * n + pr];
+        cl_out[j] = lab;
     }
     if (blockIdx.x == 0 && tid == 0) {
         dg[k] = d;
         piv_r[k] = rl_in[pr];
         piv_c[k] = cl_in[q];
     }
-    __syncthreads();
-    // thread t: row i0 + (t % 64), columns j0 + t / 64 + 4 c
-    const int i = i0 + (tid % kP4Tile);
-    const int rs = i == pr ? k : i;
-    double2 l = cmk(0.0, 0.0);
-    if (i < n) {
-        l = cmul(Win[(size_t)q * n + rs], dinv);
-        if (tj == 0 && tid < kP4Tile) {
-            const int lab = rl_in[rs];
-            Lt[(size_t)k * n + lab] = l;
-            rl_out[i] = lab;
-        }
-    }
     bv = -1.0;
     bi = 0x7fffffffffffffffL;
-    for (int c = tid / kP4Tile; c < kP4Tile; c += kP4Threads / kP4Tile) {
-        const int j = j0 + c;
+#pragma unroll
+    for (int c = 0; c < kCols; ++c) {
+        const int j = jt + 4 * c;
         if (i >= n || j >= n) continue;
-        const int cs = j == q ? k : j;
-        const double2 x = csub(Win[(size_t)cs * n + rs], cmul(l, rowk[c]));
-        Wout[(size_t)j * n + i] = x;
-        const double v = cnorm2(x);
+        const double2 y = csub(x[c], cmul(l, u[c]));
+        Wout[(size_t)j * n + i] = y;
+        const double v = cnorm2(y);
         const long idx = (long)j * n + i;
         if (tm_better(v, idx, bv, bi)) {
             bv = v;
@@ -280,51 +288,88 @@ __global__ __launch_bounds__(kP4Threads) void k_p4_gather(int n, const double2 *
 // c = g NR .. g NR + NR - 1, so the forward substitutions of its right-hand
 // sides start together at row g NR (the entries above stay zero).  Forward
 // and back substitution run with the right-hand sides in LDS, one barrier per
-// step; x_c = y_c / u_cc is formed again when stored, at row piv_c[c] of X
+// step; a thread holds up to KPT entries of a column of L or U, and the
+// columns of UN = 16 / KPT steps are read together before the first of them.
+// x_c = y_c / u_cc is formed again when stored, at row piv_c[c] of X
 // (Q e_c = e_{piv_c[c]}).
-template <int NR>
+template <int NR, int KPT>
 __global__ __launch_bounds__(kP4Threads) void k_p4_solve(int n, const double2 *LU,
                                                          const int *piv_r, const int *piv_c,
                                                          double2 *X, long ldx, const int *flags) {
+    constexpr int UN = 16 / KPT;
     extern __shared__ double2 y[];  // NR right-hand sides of n entries
     if (*flags & 1) return;
+    const int tid = threadIdx.x;
     const int g0 = blockIdx.x * NR;
     const int ns = n - g0 < NR ? n - g0 : NR;
-    for (int i = threadIdx.x; i < NR * n; i += blockDim.x) y[i] = cmk(0.0, 0.0);
+    for (int i = tid; i < NR * n; i += blockDim.x) y[i] = cmk(0.0, 0.0);
     __syncthreads();
-    if (threadIdx.x < ns) y[threadIdx.x * n + g0 + threadIdx.x] = cmk(1.0, 0.0);
+    if (tid < ns) y[tid * n + g0 + tid] = cmk(1.0, 0.0);
     __syncthreads();
-    // L y = e_c (unit lower triangular)
-    for (int t = g0; t < n - 1; ++t) {
-        double2 yt[NR];
+    // L y = e_c (unit lower triangular): step t uses rows t+1..n-1 of column t
+    for (int t0 = g0; t0 < n - 1; t0 += UN) {
+        double2 lv[UN][KPT];
 #pragma unroll
-        for (int s = 0; s < NR; ++s) yt[s] = y[s * n + t];
-        const double2 *l = LU + (size_t)t * n;
-        for (int i = t + 1 + threadIdx.x; i < n; i += blockDim.x) {
-            const double2 li = l[i];
+        for (int u = 0; u < UN; ++u)
 #pragma unroll
-            for (int s = 0; s < NR; ++s) y[s * n + i] = csub(y[s * n + i], cmul(li, yt[s]));
+            for (int e = 0; e < KPT; ++e) {
+                const int t = t0 + u, i = t + 1 + tid + e * kP4Threads;
+                lv[u][e] = (t < n - 1 && i < n) ? LU[(size_t)t * n + i] : cmk(0.0, 0.0);
+            }
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const int t = t0 + u;
+            if (t >= n - 1) break;
+            double2 yt[NR];
+#pragma unroll
+            for (int s = 0; s < NR; ++s) yt[s] = y[s * n + t];
+#pragma unroll
+            for (int e = 0; e < KPT; ++e) {
+                const int i = t + 1 + tid + e * kP4Threads;
+                if (i < n)
+#pragma unroll
+                    for (int s = 0; s < NR; ++s)
+                        y[s * n + i] = csub(y[s * n + i], cmul(lv[u][e], yt[s]));
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
-    // U x = y: entry t of each right-hand side is final once the steps above
-    // it are done, and is not written again
-    for (int t = n - 1; t > 0; --t) {
-        const double2 *u = LU + (size_t)t * n;
-        const double2 d = u[t];
-        const double dn = cnorm2(d);
-        const double2 di = cmk(d.x / dn, -d.y / dn);
-        double2 xt[NR];
+    // U x = y: step t uses rows 0..t-1 of column t; entry t of each
+    // right-hand side is final once the steps after it are done
+    for (int t0 = n - 1; t0 > 0; t0 -= UN) {
+        double2 uv[UN][KPT];
+        double2 dv[UN];
 #pragma unroll
-        for (int s = 0; s < NR; ++s) xt[s] = cmul(y[s * n + t], di);
-        for (int i = threadIdx.x; i < t; i += blockDim.x) {
-            const double2 ui = u[i];
+        for (int u = 0; u < UN; ++u) {
+            const int t = t0 - u;
+            dv[u] = t > 0 ? LU[(size_t)t * n + t] : cmk(1.0, 0.0);
 #pragma unroll
-            for (int s = 0; s < NR; ++s) y[s * n + i] = csub(y[s * n + i], cmul(ui, xt[s]));
+            for (int e = 0; e < KPT; ++e) {
+                const int i = tid + e * kP4Threads;
+                uv[u][e] = (t > 0 && i < t) ? LU[(size_t)t * n + i] : cmk(0.0, 0.0);
+            }
         }
-        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const int t = t0 - u;
+            if (t <= 0) break;
+            const double dn = cnorm2(dv[u]);
+            const double2 di = cmk(dv[u].x / dn, -dv[u].y / dn);
+            double2 xt[NR];
+#pragma unroll
+            for (int s = 0; s < NR; ++s) xt[s] = cmul(y[s * n + t], di);
+#pragma unroll
+            for (int e = 0; e < KPT; ++e) {
+                const int i = tid + e * kP4Threads;
+                if (i < t)
+#pragma unroll
+                    for (int s = 0; s < NR; ++s)
+                        y[s * n + i] = csub(y[s * n + i], cmul(uv[u][e], xt[s]));
+            }
+            __syncthreads();
+        }
     }
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+    for (int t = tid; t < n; t += blockDim.x) {
         const double2 d = LU[(size_t)t * n + t];
         const double dn = cnorm2(d);
         const double2 di = cmk(d.x / dn, -d.y / dn);
@@ -426,14 +471,14 @@ extern "C" int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_p
     const int ng = (n + nr - 1) / nr;
     double2 *X2 = reinterpret_cast<double2 *>(X);
     if (nr == 4)
-        hipLaunchKernelGGL(k_p4_solve<4>, dim3(ng), dim3(kP4Threads), lds, s, n, W, piv_r, piv_c,
-                           X2, (long)ldx, flags);
+        hipLaunchKernelGGL((k_p4_solve<4, 4>), dim3(ng), dim3(kP4Threads), lds, s, n, W, piv_r,
+                           piv_c, X2, (long)ldx, flags);
     else if (nr == 2)
-        hipLaunchKernelGGL(k_p4_solve<2>, dim3(ng), dim3(kP4Threads), lds, s, n, W, piv_r, piv_c,
-                           X2, (long)ldx, flags);
+        hipLaunchKernelGGL((k_p4_solve<2, 8>), dim3(ng), dim3(kP4Threads), lds, s, n, W, piv_r,
+                           piv_c, X2, (long)ldx, flags);
     else
-        hipLaunchKernelGGL(k_p4_solve<1>, dim3(ng), dim3(kP4Threads), lds, s, n, W, piv_r, piv_c,
-                           X2, (long)ldx, flags);
+        hipLaunchKernelGGL((k_p4_solve<1, 16>), dim3(ng), dim3(kP4Threads), lds, s, n, W, piv_r,
+                           piv_c, X2, (long)ldx, flags);
     if (hipGetLastError() != hipSuccess) return fail(GHSVD_EDEVICE);
     if (hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
