@@ -257,8 +257,9 @@ int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, doub
  * sigma_g[j])^2.  Errors: GHSVD_EINVAL for sizes, leading dimensions, NULL
  * pointers or n > 4096; GHSVD_ERANK when some h_j or s_j is zero or Z is
  * singular (a zero pivot); GHSVD_ENONFINITE for NaN/Inf column norms.
- * Allocates and frees its own workspace (n^2 complex128 + O(n)); synchronizes
- * the stream.
+ * Allocates and frees its own workspace (4 n^2 complex128 + O(n^2 / 4096)
+ * + O(n): two working matrices, L and U stored by row and column label);
+ * synchronizes the stream.
  */
 int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_plus, const double *G,
                int ldg, const double *Z, int ldz, double *U, int ldu, double *V, int ldv,

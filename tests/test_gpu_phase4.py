@@ -104,3 +104,41 @@ def test_full_at_full_size():
     r = bench.full_leg(ghsvd, F, J, G, reps=1)
     assert r["sweep_status"] == 0
     assert r["errors_7_1"]["F"] < 1e-12 and r["errors_7_1"]["G"] < 1e-12, r
+
+
+@pytest.mark.parametrize("n", [1, 65, 1100, 2100, 4096])
+def test_full_inverse_at_every_solve_width(n):
+    # X = Z^{-1} for Z = Z' Sigma^{-1} at sizes that take each form of the
+    # solve (four, two and one right-hand sides per workgroup) and ragged
+    # tiles, up to the largest n the solve's LDS takes; the residual of
+    # X Z = I against the backward-stable bound of an LU-based inverse
+    rng = np.random.default_rng(100 + n)
+    Fp = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Gp = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Zp = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    n_plus = n // 2
+    U, V, sf, sg, X = ghsvd.full(dev(Fp), n_plus, dev(Gp), dev(Zp))
+    Jd = np.where(np.arange(n) < n_plus, 1.0, -1.0)
+    sig = np.sqrt(np.abs(np.sum(np.conj(Fp) * (Jd[:, None] * Fp), axis=0))
+                  + np.sum(np.abs(Gp) ** 2, axis=0))
+    Z = Zp / sig[None, :]
+    Xh = host(X)
+    R = Xh @ Z - np.eye(n)
+    bound = 8 * n * np.finfo(np.float64).eps * np.linalg.norm(Xh) * np.linalg.norm(Z)
+    assert np.linalg.norm(R) <= bound, (np.linalg.norm(R), bound)
+    # sigma_f: h_j = f'^* J f' cancels between the rows of either sign of J, so
+    # a change of summation order moves it by up to about n eps ||f'_j||^2
+    h = np.abs(np.sum(np.conj(Fp) * (Jd[:, None] * Fp), axis=0))
+    f2 = np.sum(np.abs(Fp) ** 2, axis=0)
+    sfo = np.sqrt(h) / sig
+    tol = 4 * n * np.finfo(np.float64).eps * f2 / (np.sqrt(h) * sig) + 1e-15
+    assert np.all(np.abs(host(sf) - sfo) <= tol)
+
+
+def test_full_rejects_n_beyond_solve_lds():
+    # one right-hand side of n complex entries must fit the solve's 64 KiB of LDS
+    n = 4097
+    A = dev(np.eye(n))
+    with pytest.raises(ghsvd.GhsvdError) as e:
+        ghsvd.full(A, 1, A, A)
+    assert e.value.status == -1  # GHSVD_EINVAL
