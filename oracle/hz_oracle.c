@@ -779,6 +779,12 @@ int ora_ghsvd(int m, int n, int p, const cplx *F, int ldf, const signed char *J,
  * inner sweeps applied no big transformation.  stats as ora_hz_run, counting
  * inner pivot pairs.  eps is the machine precision of (6.12) with n the
  * order of the block pivot (tol = eps sqrt(c)).
+ *
+ * inner_order 2 is the Full Block (FB) variant of Section 6.4.2: the inner
+ * level runs round-robin sweeps over the c pivot columns until one of them
+ * applies no big transformation (the stopping rule of Algorithm 2, read as
+ * the inner level's own), at most C_max = 30 of them; Z^ accumulates them
+ * all.  BO is the same with C_max = 1.
  */
 int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J,
                      cplx *G, int ldg, cplx *Z, int ldz, int w, int max_sweeps,
@@ -845,6 +851,7 @@ int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J
                     for (int i = 0; i < c; ++i) Zh[(size_t)j * c + i] = (i == j) ? 1.0 : 0.0;
                 int isteps, islots;
                 const int ca = (a * w + w <= n) ? w : (a * w < n ? n - a * w : 0);
+                const int cmax_inner = inner_order == 2 ? 30 : 1;
                 if (inner_order == 1 && s > 0 && ca == w && c == 2 * w) {
                     isteps = w;
                     islots = w;
@@ -859,18 +866,22 @@ int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J
                 }
                 const double tol = eps * sqrt((double)c);
                 long long itr = 0;
-                for (int is = 0; is < isteps; ++is)
-                    for (int ik = 0; ik < islots; ++ik) {
-                        const int pc = ip[is * islots + ik], qc = iq[is * islots + ik];
-                        if (pc < 0) continue;
-                        const int kind = hz_pair(c, c, c, Ft, c, Jw, Gt, c, Zh, c, pc, qc, tol,
-                                                 crit_literal);
-                        stats[1]++;
-                        if (kind == ORA_ERANK) continue; /* left to the finishing sweeps */
-                        if (kind < 0) { status = kind; goto done; }
-                        if (kind > 0) { tr++; itr++; }
-                        if (kind == 2) big++;
-                    }
+                for (int isw = 0; isw < cmax_inner; ++isw) {
+                    long long ibig = 0;
+                    for (int is = 0; is < isteps; ++is)
+                        for (int ik = 0; ik < islots; ++ik) {
+                            const int pc = ip[is * islots + ik], qc = iq[is * islots + ik];
+                            if (pc < 0) continue;
+                            const int kind = hz_pair(c, c, c, Ft, c, Jw, Gt, c, Zh, c, pc, qc, tol,
+                                                     crit_literal);
+                            stats[1]++;
+                            if (kind == ORA_ERANK) continue; /* left to the finishing sweeps */
+                            if (kind < 0) { status = kind; goto done; }
+                            if (kind > 0) { tr++; itr++; }
+                            if (kind == 2) { big++; ibig++; }
+                        }
+                    if (ibig == 0) break;
+                }
                 if (itr == 0) continue;
                 /* F_C <- F_C Z^, G_C <- G_C Z^, Z_C <- Z_C Z^ (Section 6.4.3) */
                 for (int j = 0; j < c; ++j)

@@ -108,8 +108,10 @@ class Oracle:
 
     def hz_block_run(self, F, J, G, Z=None, w=8, max_sweeps=30, eps=EPS64, crit_literal=0,
                      inner_order=0):
-        """Level-2 BO block sweeps in place on copies; returns (status, F, G, Z, stats).
-        inner_order 1: cross-block inner pairs after the first block step of a sweep."""
+        """Level-2 block sweeps in place on copies; returns (status, F, G, Z, stats).
+        inner_order 0: BO, one round-robin inner sweep per block pivot; 1: BO with
+        cross-block inner pairs after the first block step of a sweep; 2: FB, inner
+        sweeps until one applies no big transformation, at most 30."""
         F = np.array(F, dtype=np.complex128, order="F", copy=True)
         G = np.array(G, dtype=np.complex128, order="F", copy=True)
         m, n = F.shape

@@ -1,5 +1,6 @@
-"""Pins of the oracle's Level-2 blocked sweeps (Section 6.4, one inner sweep
-per block pivot) under both inner orderings.
+"""Pins of the oracle's Level-2 blocked sweeps (Section 6.4): BO (one inner
+sweep per block pivot) under both inner orderings, and FB (inner sweeps until
+one applies no big transformation, at most 30).
 
 Cross ordering: with full blocks, the first block step of a sweep visits all
 pairs inside every block and the other steps only the w x w pairs across the
@@ -29,7 +30,7 @@ def test_cross_visits_each_pair_once_per_sweep(oracle):
     assert stats[1] == (nb - 1) * (nb // 2) * (2 * w) * (2 * w - 1) // 2
 
 
-@pytest.mark.parametrize("inner", [0, 1])
+@pytest.mark.parametrize("inner", [0, 1, 2])
 def test_blocked_orderings_reach_pointwise_eigenvalues(oracle, inner):
     n, w = 48, 8
     P = _pencil(913, n, 1e-3)
@@ -40,3 +41,27 @@ def test_blocked_orderings_reach_pointwise_eigenvalues(oracle, inner):
     st, lam, X = oracle.hz_post(F, P.J, G, Z)
     assert st == 0
     assert np.max(np.abs(lam - lam_ref) / np.abs(lam_ref)) < 1e-11
+
+
+def test_fb_on_one_block_pair_is_a_full_solve(oracle):
+    # n = 2w: the only block pivot is the whole pencil, so FB's inner sweeps
+    # are the pointwise iteration itself.  The first block sweep runs them to
+    # convergence (a whole number of inner sweeps over the c(c-1)/2 pairs,
+    # more than one), the second applies no big transformation and stops the
+    # iteration, and the swept factors are J-orthogonal / orthogonal to the
+    # tolerance of (6.12).  BO on the same pencil needs many block sweeps.
+    n, w = 16, 8
+    P = _pencil(917, n, 1e-2)
+    st, F, G, Z, stats = oracle.hz_block_run(P.F, P.J, P.G, w=w, max_sweeps=1, inner_order=2)
+    pairs = n * (n - 1) // 2
+    assert stats[1] % pairs == 0 and stats[1] > pairs
+    st, F, G, Z, stats = oracle.hz_block_run(P.F, P.J, P.G, w=w, max_sweeps=60, inner_order=2)
+    assert st == 0 and stats[0] == 2
+    H = F.conj().T @ (P.J[:, None] * F)
+    S = G.conj().T @ G
+    dh = np.sqrt(np.abs(np.diag(H)))
+    ds = np.sqrt(np.abs(np.diag(S)))
+    off = lambda M, d: np.max(np.abs(M - np.diag(np.diag(M))) / np.outer(d, d))
+    assert off(H, dh) < 1e-13 and off(S, ds) < 1e-13
+    st, F, G, Z, stats = oracle.hz_block_run(P.F, P.J, P.G, w=w, max_sweeps=60, inner_order=0)
+    assert st == 0 and stats[0] > 2
