@@ -380,6 +380,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--variant", default="blocked", choices=["pointwise", "blocked"])
+    ap.add_argument("--inner", default="cross", choices=["cross", "full", "fb"],
+                    help="blocked inner level: one sweep per block pivot in the cross or full "
+                         "round-robin ordering (BO), or sweeps to convergence (FB, at most 30; "
+                         "the inner kernel's roofline counts one sweep per launch)")
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reduce", action="store_true",
@@ -428,7 +432,7 @@ def main():
     G = ghsvd.to_device_fortran(P.G, dev)
     J = torch.from_numpy(P.J).to(dev)
     kw = dict(precision=args.precision, variant=args.variant, max_sweeps=args.max_sweeps,
-              block_width=args.block_width, reduce=not args.no_reduce)
+              block_width=args.block_width, reduce=not args.no_reduce, inner_order=args.inner)
 
     dt, infos, lam, times = run_path(ghsvd, F, J, G, P, kw, args.steps, args.warmup,
                                      args.profile_every)
@@ -464,6 +468,7 @@ def main():
                          f" + {args.variant} {args.precision} sweeps"),
             "n": n, "m": P.m, "p": P.p, "batch": 1,
             "precision": args.precision, "variant": args.variant, "reduce": not args.no_reduce,
+            "inner": args.inner,
         },
         "pair_updates_per_s": isum["pairs_visited"] / dt,
         "sweeps_fp64": info["sweeps_fp64"],

@@ -68,16 +68,19 @@ typedef struct {
     int sort;           /* 1: ascending lambda, X's columns permuted alike; 0: unsorted   */
     int crit_literal;   /* 0: criterion (6.12) with sqrt(|h_pp||h_qq|); 1: the printed
                            product form max*eps*sqrt(n)*min                                */
-    int inner_order;    /* blocked variant, pairs of the one inner sweep per block pivot:
-                           GHSVD_INNER_FULL: all pairs of the 2w pivot columns in round-
-                           robin order (Section 6.4.2, BO); GHSVD_INNER_CROSS (default):
-                           the same at the first block step of a sweep, where every block
-                           appears once, and only the w x w pairs across the two blocks
-                           at the other steps, so each column pair is visited once per
-                           sweep                                                        */
+    int inner_order;    /* blocked variant, the inner level per block pivot:
+                           GHSVD_INNER_FULL: one sweep over all pairs of the 2w pivot
+                           columns in round-robin order (Section 6.4.2, BO);
+                           GHSVD_INNER_CROSS (default): the same at the first block step
+                           of a sweep, where every block appears once, and only the w x w
+                           pairs across the two blocks at the other steps, so each column
+                           pair is visited once per sweep; GHSVD_INNER_FB: the Full Block
+                           variant (Section 6.4.2), round-robin inner sweeps until one
+                           applies no big transformation, at most 30 (block_width 8 or
+                           16; 32 gives GHSVD_EINVAL)                                    */
 } ghsvd_options;
 
-enum { GHSVD_INNER_FULL = 0, GHSVD_INNER_CROSS = 1 };  /* ghsvd_options.inner_order */
+enum { GHSVD_INNER_FULL = 0, GHSVD_INNER_CROSS = 1, GHSVD_INNER_FB = 2 };  /* ghsvd_options.inner_order */
 
 typedef struct {
     int status;

@@ -458,18 +458,21 @@ __device__ __forceinline__ double lane_plus32(double v) {
     return __hiloint2double((int)b[1], (int)a[1]);
 }
 
+// Step `is` follows step `prev` of the ordering: prev = is - 1 inside an
+// inner sweep, prev = the last step when step 0 starts another inner sweep.
 template <int PB>
-__device__ __forceinline__ uint2 lookahead_entry(const InnerOrder &ord, int is, int l, int c) {
+__device__ __forceinline__ uint2 lookahead_entry(const InnerOrder &ord, int is, int prev, int l,
+                                                 int c) {
     const int k = l % kEntryStride, e = l / kEntryStride;
     int pp = -1, qq = -1;
     if (k < ord.slots()) ord.pair(is, k, pp, qq);
     if (!(k < ord.slots() && qq < c && e < 3)) return make_uint2(0u, kNoEntry);
     const int i = (e == 1) ? qq : pp, j = (e == 0) ? pp : qq;
     int ki, ii, kj, jj, r0, r1, c0, c1;
-    ord.where(is - 1, i, ki, ii);
-    ord.where(is - 1, j, kj, jj);
-    ord.pair(is - 1, ki, r0, r1);
-    ord.pair(is - 1, kj, c0, c1);
+    ord.where(prev, i, ki, ii);
+    ord.where(prev, j, kj, jj);
+    ord.pair(prev, ki, r0, r1);
+    ord.pair(prev, kj, c0, c1);
     return make_uint2((unsigned)r0 | (unsigned)r1 << 8 | (unsigned)c0 << 16 | (unsigned)c1 << 24,
                       (unsigned)ki | (unsigned)ii << 8 | (unsigned)kj << 16 | (unsigned)jj << 24);
 }
@@ -554,15 +557,23 @@ __device__ __forceinline__ void inner_pivots(double tol, int crit, const double2
 // block does Zs <- Zs Z_k' in place.  The pairs of a step are disjoint, so
 // the blocks are independent.  Pair slots whose second column is a bye or
 // padding (>= c) carry the identity; padding entries are zero and stay so.
-// cross_mode = 1: block steps after the first of a sweep visit only the w^2
-// pairs across the two blocks (InnerOrder cross); the first block step of a
-// sweep, where every block appears once, visits all pairs, so that each pair
-// of columns is visited once per sweep.
+// mode GHSVD_INNER_CROSS: block steps after the first of a sweep visit only
+// the w^2 pairs across the two blocks (InnerOrder cross); the first block
+// step of a sweep, where every block appears once, visits all pairs, so that
+// each pair of columns is visited once per sweep.  mode GHSVD_INNER_FB (the
+// Full Block variant of Section 6.4.2): round-robin inner sweeps follow one
+// another, the step after the last of a sweep being step 0 of the next, until
+// an inner sweep applies no big transformation or kFbSweeps have run.  The
+// pivot wavefront, which forms the pivots of the next step while the last
+// step of a sweep is applied, decides from the sweep's big count whether
+// there is a next sweep and posts the decision for the whole workgroup.
+constexpr int kFbSweeps = 30;  // C_max of the FB inner level
+
 template <int PB, int F32>
 __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilDev *PD,
                                                                    const int *pre, const int *flag,
                                                                    int B, int crit, int step,
-                                                                   int cross_mode) {
+                                                                   int mode) {
     constexpr int NP = PB / 2;   // pivot pair slots per inner step
     constexpr int NB = NP * NP;  // 2x2 blocks
     __shared__ double2 H[2][PB][PB + 1];
@@ -570,6 +581,7 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
     __shared__ double2 Zs[PB][PB + 1];
     __shared__ InnerStep<PB> st[2];
     __shared__ uint2 tab[PB][kEntryLanes];  // look-ahead operands per inner step and lane
+    __shared__ int more[2];                 // FB: another inner sweep follows (by parity)
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev A = PD[pk];
     if (step >= A.nb - 1 || flag[pk]) return;
@@ -586,10 +598,11 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
     // the latency-critical pivot wavefront issues first
     if (tid < kWave) __builtin_amdgcn_s_setprio(3);
     InnerOrder ord;
-    ord.cross = cross_mode && step > 0 && ca == NP && cb == NP;
+    ord.cross = mode == GHSVD_INNER_CROSS && step > 0 && ca == NP && cb == NP;
     ord.C = c + (c & 1);
     ord.w = NP;
     const int nsteps = ord.steps(), nsl = ord.slots();
+    const int max_isw = mode == GHSVD_INNER_FB ? kFbSweeps : 1;
     const int KC = A.kf + A.kg;
     const GPtr<double2> P(A.part + (size_t)bpi * KC * PB * PB);
     const double tol = (F32 ? 0x1p-23 : 0x1p-52) * sqrt((double)c);
@@ -628,22 +641,43 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
         }
         for (int idx = t0; idx < (nsteps - 1) * kEntryLanes; idx += nt) {
             const int is = 1 + idx / kEntryLanes, l = idx % kEntryLanes;
-            tab[is][l] = lookahead_entry<PB>(ord, is, l, c);
+            tab[is][l] = lookahead_entry<PB>(ord, is, is - 1, l, c);
         }
+        // FB: row 0 holds step 0 of a following inner sweep
+        if (max_isw > 1)
+            for (int l = t0; l < kEntryLanes; l += nt)
+                tab[0][l] = lookahead_entry<PB>(ord, 0, nsteps - 1, l, c);
     }
     __syncthreads();
     // look-ahead operands of the next inner step, read one step ahead
     uint2 te = make_uint2(0u, kNoEntry);
-    if (tid < kWave && nsteps > 1 && tid < kEntryLanes) te = tab[1][tid];
-    for (int s = 0; s < nsteps; ++s) {
-        const int cur = s & 1, nxt = cur ^ 1;
+    if (tid < kWave && tid < kEntryLanes) {
+        if (nsteps > 1) te = tab[1][tid];
+        else if (max_isw > 1) te = tab[0][tid];
+    }
+    double cmark = 0.0;  // cbig at the end of the previous inner sweep
+    int g = 0;           // inner steps so far (parity of the H, S and step buffers)
+    for (int isw = 0;; ++isw) {
+    for (int s = 0; s < nsteps; ++s, ++g) {
+        const int cur = g & 1, nxt = cur ^ 1;
         const InnerStep<PB> &now = st[cur];
         if (tid < kWave) {
-            if (s + 1 < nsteps) {
+            bool go = s + 1 < nsteps;
+            if (!go && isw + 1 < max_isw) {
+                // the pivots of this sweep's last step are in cbig: another
+                // sweep follows when the sweep applied a big transformation
+                const double sb = wave_sum(cbig - cmark);
+                cmark = cbig;
+                go = sb > 0.0;
+                if (tid == 0) more[isw & 1] = go;
+            }
+            if (go) {
                 inner_pivots<PB, F32>(tol, crit, H[cur], S[cur], now, st[nxt], te, cv, ct, cbig,
                                       &A.st->err);
-                te = (s + 2 < nsteps && tid < kEntryLanes) ? tab[s + 2][tid]
-                                                            : make_uint2(0u, kNoEntry);
+                const int s2 = (s + 2) % nsteps;
+                te = ((s + 2 < nsteps || max_isw > 1) && tid < kEntryLanes)
+                         ? tab[s2][tid]
+                         : make_uint2(0u, kNoEntry);
             }
         } else {
             const double2 one = cmk(1.0, 0.0), zero = cmk(0.0, 0.0);
@@ -710,6 +744,8 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
             }
         }
         __syncthreads();
+    }
+        if (isw + 1 >= max_isw || !more[isw & 1]) break;
     }
     const GPtr<double2> Z64(A.zh64 + (size_t)bpi * PB * PB);
     const GPtr<float2> Z32(F32 ? A.zh32 + (size_t)bpi * PB * PB : A.zh32);
@@ -832,7 +868,7 @@ __global__ __launch_bounds__(kI64Threads) void k_blk_inner64(const PencilDev *PD
     }
     if (tid < kWave) __builtin_amdgcn_s_setprio(3);
     InnerOrder ord;
-    ord.cross = cross_mode && step > 0 && ca == NP && cb == NP;
+    ord.cross = cross_mode == GHSVD_INNER_CROSS && step > 0 && ca == NP && cb == NP;
     ord.C = c + (c & 1);
     ord.w = NP;
     const int nsteps = ord.steps(), nsl = ord.slots();
@@ -1368,7 +1404,7 @@ struct BlockedArg {
     BlkInnerFn inner;
     int inner_nt;
     int crit;
-    int cross;
+    int mode;  // inner_order
 };
 
 static int blocked_step(const BatchCtx &c, const void *arg, int step, hipStream_t s) {
@@ -1384,7 +1420,7 @@ static int blocked_step(const BatchCtx &c, const void *arg, int step, hipStream_
     prof_after(kProfGram, s, e0, e1);
     prof_before(kProfInner, s, e0, e1);
     hipLaunchKernelGGL(a->inner, dim3(c.total(BatchCtx::kBp)), dim3(a->inner_nt), 0, s, c.dev,
-                       c.pre_of(BatchCtx::kBp), c.flag_dev, c.B, a->crit, step, a->cross);
+                       c.pre_of(BatchCtx::kBp), c.flag_dev, c.B, a->crit, step, a->mode);
     prof_after(kProfInner, s, e0, e1);
     prof_before(kProfUpdate, s, e0, e1);
     hipLaunchKernelGGL(a->upd, dim3(c.total(BatchCtx::kUpd)), dim3(256), 0, s, c.dev,
@@ -1409,8 +1445,9 @@ int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, int
     }
     BlockedArg a{};
     a.crit = crit;
-    a.cross = inner_order == GHSVD_INNER_CROSS;
+    a.mode = inner_order;
     if (w == 32) {
+        if (inner_order == GHSVD_INNER_FB) return GHSVD_EINVAL;
         a.gram = fp32 ? k_blk_gram64<float> : k_blk_gram64<double>;
         a.gsum = fp32 ? k_blk_gsum64<float> : k_blk_gsum64<double>;
         a.inner = fp32 ? k_blk_inner64<1> : k_blk_inner64<0>;

@@ -6,7 +6,8 @@ inner sweep one-sidedly; the GPU forms the block pivots with MFMA Grams and
 runs the same 2x2 steps two-sidedly.  Both are the same transformations in
 exact arithmetic, so one block sweep is compared element by element, for
 both inner orderings (all pivot pairs, Section 6.4.2; or cross-block pairs
-after the first block step of a sweep).
+after the first block step of a sweep) and for the Full Block variant (inner
+sweeps until one applies no big transformation, at most 30).
 """
 import math
 
@@ -26,7 +27,7 @@ def small(seed, n, s_lo, ratio_m=1.5, ratio_p=2.0, plus=0.75, j_identity=False):
     return synth.random_pencil(seed, n, m, int(round(plus * m)), p, s_lo, j_identity=j_identity)
 
 
-INNER = {"full": 0, "cross": 1}
+INNER = {"full": 0, "cross": 1, "fb": 2}
 
 
 @pytest.mark.parametrize("inner", ["full", "cross"])
@@ -48,7 +49,7 @@ def test_one_block_sweep_elementwise(oracle, n, w, s_lo, inner):
         assert err < 1e-9, err
 
 
-@pytest.mark.parametrize("inner", ["full", "cross"])
+@pytest.mark.parametrize("inner", ["full", "cross", "fb"])
 def test_block_sweeps_converge(oracle, inner):
     P = small(401, 64, 1e-3)
     F, J, G = to_dev(P)
@@ -121,3 +122,63 @@ def test_mixed_fp32_stage_stops_before_cap_indefinite():
     assert rel_err(host(lam), host(lam64)) <= 1e-10
     e_s, e_h, e_d = factor_invariants(P.F, P.J, P.G, host(lam), host(X))
     assert e_s < 1e-9 and e_h < 1e-9 and e_d < 1e-9
+
+
+@pytest.mark.parametrize("n,w,s_lo", [(96, 8, 1e-3), (96, 16, 1e-3), (70, 16, 1e-2), (41, 8, 1e-2)])
+def test_one_fb_block_sweep_elementwise(oracle, n, w, s_lo):
+    # FB: each block pivot's inner sweeps run until one applies no big
+    # transformation.  The two sides may end a block pivot's inner sweeps one
+    # sweep apart where a transformation sits at the big threshold, so the
+    # visited counts are compared loosely; the factors element by element.
+    P = small(300 + n + w, n, s_lo)
+    F, J, G = to_dev(P)
+    Z = ghsvd.to_device_fortran(np.eye(n, dtype=np.complex128))
+    rc, done, cnt = ghsvd.block_sweeps(F, P.m_plus, G, Z, 1, block_width=w, inner_order="fb")
+    st, Fo, Go, Zo, stats = oracle.hz_block_run(P.F, P.J, P.G, w=w, max_sweeps=1, inner_order=2)
+    st_bo, _, _, _, stats_bo = oracle.hz_block_run(P.F, P.J, P.G, w=w, max_sweeps=1, inner_order=0)
+    assert done == 1 and rc in (0, 1) and st in (0, 1)
+    assert stats[1] > stats_bo[1] and cnt[0, 0] > stats_bo[1]
+    assert abs(cnt[0, 0] - stats[1]) <= stats[1] // 10
+    for A, B in ((host(F), Fo), (host(G), Go), (host(Z), Zo)):
+        colscale = np.linalg.norm(B, axis=0)
+        err = np.max(np.abs(A - B) / colscale[None, :])
+        assert err < 1e-9, err
+
+
+def test_fb_one_block_pair_is_a_full_solve():
+    # n = 2w: FB's inner sweeps on the only block pivot are the whole
+    # iteration; the second block sweep applies no big transformation, and
+    # the swept factors are J-orthogonal / orthogonal to the tolerance of (6.12)
+    P = small(917, 16, 1e-2)
+    F, J, G = to_dev(P)
+    Z = ghsvd.to_device_fortran(np.eye(16, dtype=np.complex128))
+    rc, done, cnt = ghsvd.block_sweeps(F, P.m_plus, G, Z, 60, block_width=8, inner_order="fb")
+    assert rc == 0 and done == 2 and cnt[1, 2] == 0
+    Fh, Gh = host(F), host(G)
+    Jd = np.where(np.arange(Fh.shape[0]) < P.m_plus, 1.0, -1.0)
+    H = Fh.conj().T @ (Jd[:, None] * Fh)
+    S = Gh.conj().T @ Gh
+    for M in (H, S):
+        d = np.sqrt(np.abs(np.diag(M)))
+        assert np.max(np.abs(M - np.diag(np.diag(M))) / np.outer(d, d)) < 1e-13
+
+
+@pytest.mark.parametrize("w", [8, 16])
+def test_fb_solve_workload_one(oracle, w):
+    P = synth.workload_pencil(1)
+    F, J, G = to_dev(P)
+    lam, X, info = ghsvd.solve(F, J, G, variant="blocked", block_width=w, inner_order="fb")
+    st, lam_o, X_o, _ = oracle.ghsvd(P.F, P.J, P.G)
+    assert info["status"] == 0 and st == 0
+    lam = host(lam)
+    assert rel_err(lam, lam_o) <= 1e-12
+    e_s, e_h, e_d = factor_invariants(P.F, P.J, P.G, lam, host(X))
+    assert e_s < 1e-10 and e_h < 1e-10 and e_d < 1e-10
+
+
+def test_fb_rejects_width_32():
+    P = synth.workload_pencil(1)
+    F, J, G = to_dev(P)
+    with pytest.raises(ghsvd.GhsvdError) as e:
+        ghsvd.solve(F, J, G, variant="blocked", block_width=32, inner_order="fb")
+    assert e.value.status == -1
