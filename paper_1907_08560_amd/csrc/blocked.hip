@@ -569,7 +569,7 @@ __device__ __forceinline__ void inner_pivots(double tol, int crit, const double2
 // there is a next sweep and posts the decision for the whole workgroup.
 constexpr int kFbSweeps = 30;  // C_max of the FB inner level
 
-template <int PB, int F32>
+template <int PB, int F32, int FB>
 __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilDev *PD,
                                                                    const int *pre, const int *flag,
                                                                    int B, int crit, int step,
@@ -598,11 +598,11 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
     // the latency-critical pivot wavefront issues first
     if (tid < kWave) __builtin_amdgcn_s_setprio(3);
     InnerOrder ord;
-    ord.cross = mode == GHSVD_INNER_CROSS && step > 0 && ca == NP && cb == NP;
+    ord.cross = !FB && mode == GHSVD_INNER_CROSS && step > 0 && ca == NP && cb == NP;
     ord.C = c + (c & 1);
     ord.w = NP;
     const int nsteps = ord.steps(), nsl = ord.slots();
-    const int max_isw = mode == GHSVD_INNER_FB ? kFbSweeps : 1;
+    constexpr int max_isw = FB ? kFbSweeps : 1;  // FB: mode is GHSVD_INNER_FB
     const int KC = A.kf + A.kg;
     const GPtr<double2> P(A.part + (size_t)bpi * KC * PB * PB);
     const double tol = (F32 ? 0x1p-23 : 0x1p-52) * sqrt((double)c);
@@ -1446,8 +1446,9 @@ int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, int
     BlockedArg a{};
     a.crit = crit;
     a.mode = inner_order;
+    const bool fb = inner_order == GHSVD_INNER_FB;
     if (w == 32) {
-        if (inner_order == GHSVD_INNER_FB) return GHSVD_EINVAL;
+        if (fb) return GHSVD_EINVAL;
         a.gram = fp32 ? k_blk_gram64<float> : k_blk_gram64<double>;
         a.gsum = fp32 ? k_blk_gsum64<float> : k_blk_gsum64<double>;
         a.inner = fp32 ? k_blk_inner64<1> : k_blk_inner64<0>;
@@ -1455,12 +1456,14 @@ int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, int
         a.upd = fp32 ? k_blk_update<float, 64> : k_blk_update<double, 64>;
     } else if (w == 16) {
         a.gram = fp32 ? k_blk_gram<float, 32> : k_blk_gram<double, 32>;
-        a.inner = fp32 ? k_blk_inner<32, 1> : k_blk_inner<32, 0>;
+        a.inner = fb ? (fp32 ? k_blk_inner<32, 1, 1> : k_blk_inner<32, 0, 1>)
+                     : (fp32 ? k_blk_inner<32, 1, 0> : k_blk_inner<32, 0, 0>);
         a.inner_nt = inner_threads<32>();
         a.upd = fp32 ? k_blk_update<float, 32> : k_blk_update<double, 32>;
     } else if (w == 8) {
         a.gram = fp32 ? k_blk_gram<float, 16> : k_blk_gram<double, 16>;
-        a.inner = fp32 ? k_blk_inner<16, 1> : k_blk_inner<16, 0>;
+        a.inner = fb ? (fp32 ? k_blk_inner<16, 1, 1> : k_blk_inner<16, 0, 1>)
+                     : (fp32 ? k_blk_inner<16, 1, 0> : k_blk_inner<16, 0, 0>);
         a.inner_nt = inner_threads<16>();
         a.upd = fp32 ? k_blk_update<float, 16> : k_blk_update<double, 16>;
     } else {
