@@ -76,8 +76,7 @@ typedef struct {
                            pairs across the two blocks at the other steps, so each column
                            pair is visited once per sweep; GHSVD_INNER_FB: the Full Block
                            variant (Section 6.4.2), round-robin inner sweeps until one
-                           applies no big transformation, at most 30 (block_width 8 or
-                           16; 32 gives GHSVD_EINVAL)                                    */
+                           applies no big transformation, at most 30                     */
 } ghsvd_options;
 
 enum { GHSVD_INNER_FULL = 0, GHSVD_INNER_CROSS = 1, GHSVD_INNER_FB = 2 };  /* ghsvd_options.inner_order */

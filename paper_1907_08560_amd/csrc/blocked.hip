@@ -794,16 +794,17 @@ __device__ __forceinline__ double2 hget(const double2 *M, int i, int j) {
 }
 
 // Look-ahead operands of entry kind e ((p,p), (q,q), (p,q)) of pair slot k
-// at inner step is >= 1, packed as for lookahead_entry; bit 1 of the byte
-// of ii marks an entry formed transposed and conjugated after.
-__device__ __forceinline__ uint2 lookahead64(const InnerOrder &ord, int is, int k, int e, int c) {
+// at inner step is following step prev, packed as for lookahead_entry; bit
+// 1 of the byte of ii marks an entry formed transposed and conjugated after.
+__device__ __forceinline__ uint2 lookahead64(const InnerOrder &ord, int is, int prev, int k, int e,
+                                             int c) {
     int pp = -1, qq = -1;
     if (k < ord.slots()) ord.pair(is, k, pp, qq);
     if (!(k < ord.slots() && qq < c)) return make_uint2(0u, kNoEntry);
     int i = (e == 1) ? qq : pp, j = (e == 0) ? pp : qq;
     int ki, ii, kj, jj;
-    ord.where(is - 1, i, ki, ii);
-    ord.where(is - 1, j, kj, jj);
+    ord.where(prev, i, ki, ii);
+    ord.where(prev, j, kj, jj);
     int cj = 0;
     if (ki > kj) {
         int t = ki;
@@ -815,8 +816,8 @@ __device__ __forceinline__ uint2 lookahead64(const InnerOrder &ord, int is, int 
         cj = 1;
     }
     int r0, r1, c0, c1;
-    ord.pair(is - 1, ki, r0, r1);
-    ord.pair(is - 1, kj, c0, c1);
+    ord.pair(prev, ki, r0, r1);
+    ord.pair(prev, kj, c0, c1);
     return make_uint2((unsigned)r0 | (unsigned)r1 << 8 | (unsigned)c0 << 16 | (unsigned)c1 << 24,
                       (unsigned)ki | (unsigned)(ii | cj << 1) << 8 | (unsigned)kj << 16 |
                           (unsigned)jj << 24);
@@ -843,16 +844,18 @@ __device__ __forceinline__ double2 lookahead_value(const double2 *M, uint2 te,
     return (iib & 2) ? cconj(v) : v;
 }
 
-template <int F32>
+template <int F32, int FB>
 __global__ __launch_bounds__(kI64Threads) void k_blk_inner64(const PencilDev *PD, const int *pre,
                                                             const int *flag, int B, int crit,
                                                             int step, int cross_mode) {
     constexpr int PB = 64, NP = 32;
+    constexpr int max_isw = FB ? kFbSweeps : 1;  // FB: inner sweeps as in k_blk_inner
     __shared__ double2 H[kG64Packed];
     __shared__ double2 S[kG64Packed];
     __shared__ double2 Zs[PB][PB + 1];  // Zs[column][row]
     __shared__ InnerStep<PB> st[2];
-    __shared__ uint2 tab[2][3 * NP];     // look-ahead operands, by step parity
+    __shared__ uint2 tab[2][3 * NP];     // look-ahead operands, by the parity of the step
+    __shared__ int more[2];              // FB: another inner sweep follows (by parity)
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev A = PD[pk];
     if (step >= A.nb - 1 || flag[pk]) return;
@@ -868,7 +871,7 @@ __global__ __launch_bounds__(kI64Threads) void k_blk_inner64(const PencilDev *PD
     }
     if (tid < kWave) __builtin_amdgcn_s_setprio(3);
     InnerOrder ord;
-    ord.cross = cross_mode == GHSVD_INNER_CROSS && step > 0 && ca == NP && cb == NP;
+    ord.cross = !FB && cross_mode == GHSVD_INNER_CROSS && step > 0 && ca == NP && cb == NP;
     ord.C = c + (c & 1);
     ord.w = NP;
     const int nsteps = ord.steps(), nsl = ord.slots();
@@ -891,8 +894,10 @@ __global__ __launch_bounds__(kI64Threads) void k_blk_inner64(const PencilDev *PD
             const int col = idx / PB, row = idx % PB;
             Zs[col][row] = cmk(row == col ? 1.0 : 0.0, 0.0);
         }
-        if (nsteps > 1 && tid < 3 * NP)
-            tab[1][tid] = lookahead64(ord, 1, tid % NP, tid / NP, c);
+        if (tid < 3 * NP) {
+            if (nsteps > 1) tab[1][tid] = lookahead64(ord, 1, 0, tid % NP, tid / NP, c);
+            else if (FB) tab[1][tid] = lookahead64(ord, 0, 0, tid % NP, tid / NP, c);
+        }
     }
     __syncthreads();
     const double tol = (F32 ? 0x1p-23 : 0x1p-52) * sqrt((double)c);
@@ -921,8 +926,11 @@ __global__ __launch_bounds__(kI64Threads) void k_blk_inner64(const PencilDev *PD
         st[0].act[k] = kind > 0;
     }
     __syncthreads();
-    for (int s = 0; s < nsteps; ++s) {
-        const int cur = s & 1, nxt = cur ^ 1;
+    double cmark = 0.0;  // cbig at the end of the previous inner sweep
+    int g = 0;           // inner steps so far (parity of the step and table buffers)
+    for (int isw = 0;; ++isw) {
+    for (int s = 0; s < nsteps; ++s, ++g) {
+        const int cur = g & 1, nxt = cur ^ 1;
         const InnerStep<PB> &now = st[cur];
         // ---- phase 1: reads ----
         double2 hv0 = cmk(0.0, 0.0), sv0 = hv0, hv2 = hv0, sv2 = hv0;
@@ -930,16 +938,26 @@ __global__ __launch_bounds__(kI64Threads) void k_blk_inner64(const PencilDev *PD
         double2 bh[4], bs[4];
         int p1 = 0, q1 = 0, p2 = 0, q2 = 0;
         bool blk = false;
+        bool go = false;  // pivot wavefront: a next inner step follows
         if (tid < kWave) {
-            if (s + 1 < nsteps) {
-                const uint2 te0 = tab[(s + 1) & 1][tid];  // (p,p) for lanes < 32, (q,q) above
+            go = s + 1 < nsteps;
+            if (!go && isw + 1 < max_isw) {
+                // the pivots of this sweep's last step are in cbig: another
+                // sweep follows when the sweep applied a big transformation
+                const double sb = wave_sum(cbig - cmark);
+                cmark = cbig;
+                go = sb > 0.0;
+                if (tid == 0) more[isw & 1] = go;
+            }
+            if (go) {
+                const uint2 te0 = tab[nxt][tid];  // (p,p) for lanes < 32, (q,q) above
                 mine0 = te0.y != kNoEntry;
                 if (mine0) {
                     hv0 = lookahead_value(H, te0, now);
                     sv0 = lookahead_value(S, te0, now);
                 }
                 if (tid < NP) {
-                    const uint2 te2 = tab[(s + 1) & 1][2 * NP + tid];  // (p,q)
+                    const uint2 te2 = tab[nxt][2 * NP + tid];  // (p,q)
                     mine2 = te2.y != kNoEntry;
                     if (mine2) {
                         hv2 = lookahead_value(H, te2, now);
@@ -965,7 +983,7 @@ __global__ __launch_bounds__(kI64Threads) void k_blk_inner64(const PencilDev *PD
         __syncthreads();
         // ---- phase 2: writes ----
         if (tid < kWave) {
-            if (s + 1 < nsteps) {
+            if (go) {
                 // gather (q,q) of pair k from lane k + 32 (every lane takes part)
                 const double hqq = lane_plus32(hv0.x), sqq = lane_plus32(sv0.x);
                 if (tid < NP) {
@@ -1043,10 +1061,15 @@ __global__ __launch_bounds__(kI64Threads) void k_blk_inner64(const PencilDev *PD
                     Zs[qq][row] = mac2(w1, c12, w2, c22);
                 }
             }
-            if (s + 2 < nsteps && tz < 3 * NP)
-                tab[s & 1][tz] = lookahead64(ord, s + 2, tz % NP, tz / NP, c);
+            // operands of the step after next (in FB, across the end of a sweep)
+            if ((FB || s + 2 < nsteps) && tz < 3 * NP) {
+                const int t2 = (s + 2) % nsteps, t1 = (s + 1) % nsteps;
+                tab[cur][tz] = lookahead64(ord, t2, t1, tz % NP, tz / NP, c);
+            }
         }
         __syncthreads();
+    }
+        if (isw + 1 >= max_isw || !more[isw & 1]) break;
     }
     const GPtr<double2> Z64(A.zh64 + (size_t)bpi * PB * PB);
     const GPtr<float2> Z32(F32 ? A.zh32 + (size_t)bpi * PB * PB : A.zh32);
@@ -1448,10 +1471,10 @@ int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, int
     a.mode = inner_order;
     const bool fb = inner_order == GHSVD_INNER_FB;
     if (w == 32) {
-        if (fb) return GHSVD_EINVAL;
         a.gram = fp32 ? k_blk_gram64<float> : k_blk_gram64<double>;
         a.gsum = fp32 ? k_blk_gsum64<float> : k_blk_gsum64<double>;
-        a.inner = fp32 ? k_blk_inner64<1> : k_blk_inner64<0>;
+        a.inner = fb ? (fp32 ? k_blk_inner64<1, 1> : k_blk_inner64<0, 1>)
+                     : (fp32 ? k_blk_inner64<1, 0> : k_blk_inner64<0, 0>);
         a.inner_nt = kI64Threads;
         a.upd = fp32 ? k_blk_update<float, 64> : k_blk_update<double, 64>;
     } else if (w == 16) {

@@ -510,8 +510,7 @@ static bool valid_options(const ghsvd_options &o) {
             o.block_width == 32) &&
            o.waves_per_pair >= 0 && o.waves_per_pair <= 16 &&
            (o.inner_order == GHSVD_INNER_FULL || o.inner_order == GHSVD_INNER_CROSS ||
-            o.inner_order == GHSVD_INNER_FB) &&
-           !(o.inner_order == GHSVD_INNER_FB && o.block_width == 32);
+            o.inner_order == GHSVD_INNER_FB);
 }
 
 extern "C" size_t ghsvd_workspace_size(int m, int n, int p, const ghsvd_options *opt) {
@@ -719,7 +718,6 @@ extern "C" int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n
     if (inner_order != GHSVD_INNER_FULL && inner_order != GHSVD_INNER_CROSS &&
         inner_order != GHSVD_INNER_FB)
         return GHSVD_EINVAL;
-    if (inner_order == GHSVD_INNER_FB && block_width == 32) return GHSVD_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     OwnedBatch ob;
     int rc = make_inplace_batch(ob, m, n, p, F, ldf, G, ldg, Z, ldz, 1,

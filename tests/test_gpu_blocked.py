@@ -124,7 +124,8 @@ def test_mixed_fp32_stage_stops_before_cap_indefinite():
     assert e_s < 1e-9 and e_h < 1e-9 and e_d < 1e-9
 
 
-@pytest.mark.parametrize("n,w,s_lo", [(96, 8, 1e-3), (96, 16, 1e-3), (70, 16, 1e-2), (41, 8, 1e-2)])
+@pytest.mark.parametrize("n,w,s_lo", [(96, 8, 1e-3), (96, 16, 1e-3), (70, 16, 1e-2), (41, 8, 1e-2),
+                                       (192, 32, 1e-3), (150, 32, 1e-2)])
 def test_one_fb_block_sweep_elementwise(oracle, n, w, s_lo):
     # FB: each block pivot's inner sweeps run until one applies no big
     # transformation.  The two sides may end a block pivot's inner sweeps one
@@ -163,7 +164,7 @@ def test_fb_one_block_pair_is_a_full_solve():
         assert np.max(np.abs(M - np.diag(np.diag(M))) / np.outer(d, d)) < 1e-13
 
 
-@pytest.mark.parametrize("w", [8, 16])
+@pytest.mark.parametrize("w", [8, 16, 32])
 def test_fb_solve_workload_one(oracle, w):
     P = synth.workload_pencil(1)
     F, J, G = to_dev(P)
@@ -174,11 +175,3 @@ def test_fb_solve_workload_one(oracle, w):
     assert rel_err(lam, lam_o) <= 1e-12
     e_s, e_h, e_d = factor_invariants(P.F, P.J, P.G, lam, host(X))
     assert e_s < 1e-10 and e_h < 1e-10 and e_d < 1e-10
-
-
-def test_fb_rejects_width_32():
-    P = synth.workload_pencil(1)
-    F, J, G = to_dev(P)
-    with pytest.raises(ghsvd.GhsvdError) as e:
-        ghsvd.solve(F, J, G, variant="blocked", block_width=32, inner_order="fb")
-    assert e.value.status == -1
