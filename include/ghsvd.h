@@ -252,15 +252,15 @@ int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, doub
  *   V = G' diag(s_j^{-1/2})    (p x n, ldv >= p),
  *   X = Z^{-1}, Z = Z' diag(Sigma_j)^{-1}  (n x n, ldx >= n),
  * the inverse by LU with complete pivoting (among entries of equal modulus
- * the first in column-major order) and one pair of triangular solves per
- * column.  Then F' Z'^{-1} = U diag(sigma_f) X, G' Z'^{-1} = V diag(sigma_g) X,
+ * the first in column-major order) and blocked triangular solves.  Then F' Z'^{-1} = U diag(sigma_f) X, G' Z'^{-1} = V diag(sigma_g) X,
  * sigma_f^2 + sigma_g^2 = 1, U^* J U = diag(sign h_j), V^* V = I at
  * convergence, and the eigenvalues of the pencil are sign(h_j) (sigma_f[j] /
  * sigma_g[j])^2.  Errors: GHSVD_EINVAL for sizes, leading dimensions, NULL
- * pointers or n > 4096; GHSVD_ERANK when some h_j or s_j is zero or Z is
+ * pointers or n > 4096 (the largest order taken); GHSVD_ERANK when some h_j or s_j is zero or Z is
  * singular (a zero pivot); GHSVD_ENONFINITE for NaN/Inf column norms.
- * Allocates and frees its own workspace (4 n^2 complex128 + O(n^2 / 4096)
- * + O(n): two working matrices, L and U stored by row and column label);
+ * Allocates and frees its own workspace (4 n^2 complex128 + O(n): two
+ * working matrices, L and U stored by row and column label, which the solves
+ * reuse, plus the inverse diagonal blocks);
  * synchronizes the stream.
  */
 int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_plus, const double *G,

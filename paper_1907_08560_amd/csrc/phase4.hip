@@ -10,8 +10,9 @@
 //   Z = Z' Sigma^{-1}, X = Z^{-1},
 // the inverse by LU with complete pivoting (P Z Q = L U, L unit lower
 // triangular; among entries of equal modulus the pivot is the first in
-// column-major order) and one pair of triangular solves per column of X,
-// as the paper does with one solve per column in parallel.
+// column-major order) and triangular solves with the identity as
+// right-hand side (the paper solves the columns of X independently; here
+// they are solved together, blocked).
 //
 // The factorization runs one launch per column step, with one workgroup per
 // 64 x 64 tile of the trailing matrix.  Every workgroup takes the pivot from
@@ -21,9 +22,9 @@
 // of two working matrices.  Rows and columns keep labels (their index in Z),
 // so the multipliers and the pivot row of a step are stored at their labels
 // and need no later interchanges; one gather puts L and U in the usual
-// triangular layout.  The solves run four (n <= 1024) right-hand sides per
-// workgroup in LDS, one barrier per substitution step, and store X through
-// the column labels.
+// triangular layout.  The solves are blocked on 64 x 64 tiles (inverse
+// diagonal blocks, then one launch per panel whose products run on the FP64
+// MFMA) and store X through the row and column labels.
 #include "hz_common.hpp"
 
 namespace ghsvd {
@@ -283,99 +284,211 @@ __global__ __launch_bounds__(kP4Threads) void k_p4_gather(int n, const double2 *
         o[r] = r > c ? lt[piv_r[r]] : (r < c ? ut[r] : dg[c]);
 }
 
-// NR columns of X = Q U^{-1} L^{-1} P per workgroup.  P e_j = e_c for the
-// step c at which row label j was pivoted (j = piv_r[c]); workgroup g takes
-// c = g NR .. g NR + NR - 1, so the forward substitutions of its right-hand
-// sides start together at row g NR (the entries above stay zero).  Forward
-// and back substitution run with the right-hand sides in LDS, one barrier per
-// step; a thread holds up to KPT entries of a column of L or U, and the
-// columns of UN = 16 / KPT steps are read together before the first of them.
-// x_c = y_c / u_cc is formed again when stored, at row piv_c[c] of X
-// (Q e_c = e_{piv_c[c]}).
-template <int NR, int KPT>
-__global__ __launch_bounds__(kP4Threads) void k_p4_solve(int n, const double2 *LU,
-                                                         const int *piv_r, const int *piv_c,
-                                                         double2 *X, long ldx, const int *flags) {
-    constexpr int UN = 16 / KPT;
-    extern __shared__ double2 y[];  // NR right-hand sides of n entries
-    if (*flags & 1) return;
-    const int tid = threadIdx.x;
-    const int g0 = blockIdx.x * NR;
-    const int ns = n - g0 < NR ? n - g0 : NR;
-    for (int i = tid; i < NR * n; i += blockDim.x) y[i] = cmk(0.0, 0.0);
+// ---------------------------------------------------------------------------
+// X = Q U^{-1} L^{-1} P by blocked triangular solves on 64 x 64 tiles.
+// W1 = L^{-1} (lower triangular, the identity as right-hand side) and then
+// W = U^{-1} W1; the interchanges only relabel: X[piv_c[c], piv_r[c']] =
+// W[c, c'].  The diagonal blocks are inverted first (k_p4_dinv); panel k of
+// either pass is one launch in which a workgroup multiplies its column tile
+// of the panel's block row by the inverse diagonal block and, for a tile
+// below (forward) or above (backward) the panel, subtracts the product with
+// the panel's off-diagonal block of L or U.  The panel's block row is only
+// read in the launch; the forward pass writes its finished block row to a
+// second matrix, the backward pass straight into X.
+// ---------------------------------------------------------------------------
+constexpr int kTs = 64;  // tile order of the blocked solves
+
+typedef double p4v4d __attribute__((ext_vector_type(4)));
+
+// Inverse of diagonal block k of L (unit lower, blockIdx.y = 0) or of U
+// (blockIdx.y = 1) of the triangular layout LU (ld n), 64 x 64, column-major,
+// to D + (2 k + y) 64^2.  Past order n the block is the identity.  Thread t
+// holds column t / 4 of the inverse, rows t % 4 + 4 r: the four threads of a
+// column are adjacent lanes, so the substitution's pivot entry is a lane
+// shuffle and no barrier is needed.
+__global__ __launch_bounds__(256) void k_p4_dinv(int n, const double2 *LU, double2 *D) {
+    __shared__ double2 Bk[kTs][kTs];  // the diagonal block, Bk[column][row]
+    const int k = blockIdx.x, up = blockIdx.y;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int j = threadIdx.x >> 2, q = threadIdx.x & 3;
+    const int b0 = k * kTs;
+    const int nk = n - b0 < kTs ? n - b0 : kTs;
+    for (int e = threadIdx.x; e < kTs * kTs; e += blockDim.x) {
+        const int i = e % kTs, t = e / kTs;
+        Bk[t][i] = (i < nk && t < nk) ? LU[(size_t)(b0 + t) * n + b0 + i] : cmk(0.0, 0.0);
+    }
     __syncthreads();
-    if (tid < ns) y[tid * n + g0 + tid] = cmk(1.0, 0.0);
-    __syncthreads();
-    // L y = e_c (unit lower triangular): step t uses rows t+1..n-1 of column t
-    for (int t0 = g0; t0 < n - 1; t0 += UN) {
-        double2 lv[UN][KPT];
+    auto ent = [&](int i, int t) -> double2 { return Bk[t][i]; };
+    double2 x[kTs / 4];
 #pragma unroll
-        for (int u = 0; u < UN; ++u)
+    for (int r = 0; r < kTs / 4; ++r) x[r] = cmk(q + 4 * r == j ? 1.0 : 0.0, 0.0);
+    if (!up) {
+        // L y = e_j: rows below t take the finished entry t
+#pragma unroll 64
+        for (int t = 0; t < kTs; ++t) {
+            const double2 v = x[t >> 2];
+            const double2 xt = cmk(__shfl(v.x, (lane & ~3) | (t & 3), kWave),
+                                   __shfl(v.y, (lane & ~3) | (t & 3), kWave));
+            if (t < nk) {
 #pragma unroll
-            for (int e = 0; e < KPT; ++e) {
-                const int t = t0 + u, i = t + 1 + tid + e * kP4Threads;
-                lv[u][e] = (t < n - 1 && i < n) ? LU[(size_t)t * n + i] : cmk(0.0, 0.0);
+                for (int r = 0; r < kTs / 4; ++r) {
+                    const int i = q + 4 * r;
+                    if (i > t && i < nk) x[r] = csub(x[r], cmul(ent(i, t), xt));
+                }
             }
+        }
+    } else {
+        // U y = e_j: entry t is divided by u_tt, then rows above t take it
+#pragma unroll 64
+        for (int t = kTs - 1; t >= 0; --t) {
+            const double2 v = x[t >> 2];
+            double2 xt = cmk(__shfl(v.x, (lane & ~3) | (t & 3), kWave),
+                             __shfl(v.y, (lane & ~3) | (t & 3), kWave));
+            if (t < nk) {
+                const double2 d = Bk[t][t];
+                const double dn = cnorm2(d);
+                xt = cmul(xt, cmk(d.x / dn, -d.y / dn));
+                if (q == (t & 3)) x[t >> 2] = xt;
 #pragma unroll
-        for (int u = 0; u < UN; ++u) {
-            const int t = t0 + u;
-            if (t >= n - 1) break;
-            double2 yt[NR];
-#pragma unroll
-            for (int s = 0; s < NR; ++s) yt[s] = y[s * n + t];
-#pragma unroll
-            for (int e = 0; e < KPT; ++e) {
-                const int i = t + 1 + tid + e * kP4Threads;
-                if (i < n)
-#pragma unroll
-                    for (int s = 0; s < NR; ++s)
-                        y[s * n + i] = csub(y[s * n + i], cmul(lv[u][e], yt[s]));
+                for (int r = 0; r < kTs / 4; ++r) {
+                    const int i = q + 4 * r;
+                    if (i < t) x[r] = csub(x[r], cmul(ent(i, t), xt));
+                }
             }
-            __syncthreads();
         }
     }
-    // U x = y: step t uses rows 0..t-1 of column t; entry t of each
-    // right-hand side is final once the steps after it are done
-    for (int t0 = n - 1; t0 > 0; t0 -= UN) {
-        double2 uv[UN][KPT];
-        double2 dv[UN];
+    double2 *o = D + (size_t)(2 * k + up) * kTs * kTs + (size_t)j * kTs;
 #pragma unroll
-        for (int u = 0; u < UN; ++u) {
-            const int t = t0 - u;
-            dv[u] = t > 0 ? LU[(size_t)t * n + t] : cmk(1.0, 0.0);
+    for (int r = 0; r < kTs / 4; ++r) o[q + 4 * r] = x[r];
+}
+
+// acc += A B for the 32 x 32 quarter (wi, wj) of a 64 x 64 complex product,
+// a(i, k) and b(k, j) giving the operands (FP64 MFMA 16x16x4: A[i][k] from
+// lane i + 16 k, B[k][j] from lane j + 16 k; result r of lane l at row
+// l / 16 + 4 r, column l % 16 of its 16 x 16 tile).
+template <typename FA, typename FB>
+__device__ __forceinline__ void p4_mma64(FA a, FB b, int wi, int wj, int lane,
+                                         p4v4d (&re)[2][2], p4v4d (&im)[2][2]) {
+    const int i16 = lane & 15, kq = lane >> 4;
+#pragma unroll 4
+    for (int k0 = 0; k0 < kTs; k0 += 4) {
+        double2 av[2], bv[2];
 #pragma unroll
-            for (int e = 0; e < KPT; ++e) {
-                const int i = tid + e * kP4Threads;
-                uv[u][e] = (t > 0 && i < t) ? LU[(size_t)t * n + i] : cmk(0.0, 0.0);
-            }
+        for (int t = 0; t < 2; ++t) {
+            av[t] = a(wi * 32 + t * 16 + i16, k0 + kq);
+            bv[t] = b(k0 + kq, wj * 32 + t * 16 + i16);
         }
 #pragma unroll
-        for (int u = 0; u < UN; ++u) {
-            const int t = t0 - u;
-            if (t <= 0) break;
-            const double dn = cnorm2(dv[u]);
-            const double2 di = cmk(dv[u].x / dn, -dv[u].y / dn);
-            double2 xt[NR];
+        for (int ta = 0; ta < 2; ++ta)
 #pragma unroll
-            for (int s = 0; s < NR; ++s) xt[s] = cmul(y[s * n + t], di);
-#pragma unroll
-            for (int e = 0; e < KPT; ++e) {
-                const int i = tid + e * kP4Threads;
-                if (i < t)
-#pragma unroll
-                    for (int s = 0; s < NR; ++s)
-                        y[s * n + i] = csub(y[s * n + i], cmul(uv[u][e], xt[s]));
+            for (int tb = 0; tb < 2; ++tb) {
+                re[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ta].x, bv[tb].x, re[ta][tb], 0, 0, 0);
+                re[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av[ta].y, bv[tb].y, re[ta][tb], 0, 0, 0);
+                im[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ta].x, bv[tb].y, im[ta][tb], 0, 0, 0);
+                im[ta][tb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ta].y, bv[tb].x, im[ta][tb], 0, 0, 0);
             }
-            __syncthreads();
-        }
     }
-    for (int t = tid; t < n; t += blockDim.x) {
-        const double2 d = LU[(size_t)t * n + t];
-        const double dn = cnorm2(d);
-        const double2 di = cmk(d.x / dn, -d.y / dn);
-        const long row = piv_c[t];
-        for (int s = 0; s < ns; ++s)
-            X[(size_t)piv_r[g0 + s] * ldx + row] = cmul(y[s * n + t], di);
+}
+
+// One launch of panel k.  Forward (up = 0): workgroup (it, jt), it <
+// nb - k, jt <= k (the tiles right of the diagonal stay zero), forms V =
+// L_kk^{-1} Y(k, jt); it = 0 stores V as the finished Yf(k, jt), it > 0
+// subtracts L(k + it, k) V from Y(k + it, jt).  Backward (up = 1):
+// workgroup (it, jt), it <= k, forms V = U_kk^{-1} Yf(k, jt); it = 0 scatters
+// V into X, it > 0 subtracts U(k - it, k) V from Yf(k - it, jt).  Entries
+// past order n read as zero and are not written.
+__global__ __launch_bounds__(256) void k_p4_panel(int n, int nb, int k, int up, const double2 *LU,
+                                                  const double2 *D, double2 *Y, double2 *Yf,
+                                                  const int *piv_r, const int *piv_c, double2 *X,
+                                                  long ldx, const int *flags) {
+    // one 64 x 64 tile in LDS: the right-hand side, then V, then the update
+    __shared__ double2 Vs[kTs][kTs];  // [row][col]
+    if (up && (*flags & 1)) return;  // the pivots are incomplete after a zero pivot
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid >> 6;
+    const int wi = wv & 1, wj = wv >> 1;
+    const int rows_it = up ? k + 1 : nb - k;
+    const int it = blockIdx.x % rows_it, jt = blockIdx.x / rows_it;
+    const int b0 = k * kTs, c0 = jt * kTs;
+    const double2 *Dk = D + (size_t)(2 * k + up) * kTs * kTs;
+    const double2 *src = up ? Yf : Y;  // the panel's block row
+    // tile (row r0.., column c0..) of an n x n matrix to and from Vs, a column
+    // of 64 rows per wavefront pass (coalesced)
+    auto load_tile = [&](const double2 *M, int r0) {
+        for (int e = tid; e < kTs * kTs; e += blockDim.x) {
+            const int i = e % kTs, jj = e / kTs, r = r0 + i, c = c0 + jj;
+            Vs[i][jj] = (r < n && c < n) ? M[(size_t)c * n + r] : cmk(0.0, 0.0);
+        }
+    };
+    auto to_vs = [&](const p4v4d (&re)[2][2], const p4v4d (&im)[2][2]) {
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    Vs[wi * 32 + a * 16 + (lane >> 4) + 4 * r][wj * 32 + b * 16 + (lane & 15)] =
+                        cmk(re[a][b][r], im[a][b][r]);
+    };
+    auto dk = [&](int i, int kk) { return Dk[(size_t)kk * kTs + i]; };
+    auto vs = [&](int kk, int jj) { return Vs[kk][jj]; };
+    p4v4d re[2][2], im[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            re[a][b] = p4v4d{0, 0, 0, 0};
+            im[a][b] = p4v4d{0, 0, 0, 0};
+        }
+    load_tile(src, b0);
+    __syncthreads();
+    p4_mma64(dk, vs, wi, wj, lane, re, im);  // V = D_kk^{-1} (panel tile)
+    __syncthreads();
+    to_vs(re, im);
+    __syncthreads();
+    if (it == 0) {
+        for (int e = tid; e < kTs * kTs; e += blockDim.x) {
+            const int i = e % kTs, jj = e / kTs, row = b0 + i, col = c0 + jj;
+            if (row >= n || col >= n) continue;
+            if (!up) {
+                Yf[(size_t)col * n + row] = Vs[i][jj];
+            } else {
+                const int xr = piv_c[row], xc = piv_r[col];
+                if (xr >= 0 && xr < n && xc >= 0 && xc < n) X[(size_t)xc * ldx + xr] = Vs[i][jj];
+            }
+        }
+        return;
+    }
+    const int t0 = up ? (k - it) * kTs : (k + it) * kTs;  // the block row updated
+    auto off = [&](int i, int kk) {
+        const int r = t0 + i, c = b0 + kk;
+        return (r < n && c < n) ? LU[(size_t)c * n + r] : cmk(0.0, 0.0);
+    };
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            re[a][b] = p4v4d{0, 0, 0, 0};
+            im[a][b] = p4v4d{0, 0, 0, 0};
+        }
+    p4_mma64(off, vs, wi, wj, lane, re, im);  // (off-diagonal block) V
+    __syncthreads();
+    to_vs(re, im);
+    __syncthreads();
+    double2 *dst = up ? Yf : Y;
+    for (int e = tid; e < kTs * kTs; e += blockDim.x) {
+        const int i = e % kTs, jj = e / kTs, row = t0 + i, col = c0 + jj;
+        if (row >= n || col >= n) continue;
+        double2 *y = dst + (size_t)col * n + row;
+        *y = csub(*y, Vs[i][jj]);
+    }
+}
+
+// Y = I (ld n), Yf = 0
+__global__ void k_p4_eye(int n, double2 *Y, double2 *Yf) {
+    const int j = blockIdx.y;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
+        Y[(size_t)j * n + r] = cmk(r == j ? 1.0 : 0.0, 0.0);
+        Yf[(size_t)j * n + r] = cmk(0.0, 0.0);
     }
 }
 
@@ -391,9 +504,8 @@ extern "C" int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_p
     if (n < 1 || m < n || p < n || n_plus < 0 || n_plus > m || ldf < m || ldg < p || ldz < n ||
         ldu < m || ldv < p || ldx < n || !F || !G || !Z || !U || !V || !sigma_f || !sigma_g || !X)
         return GHSVD_EINVAL;
-    // the right-hand sides of a solve live in LDS
-    if ((size_t)n * sizeof(double2) > 64 * 1024) return GHSVD_EINVAL;
-    const int nr = n <= 1024 ? 4 : (n <= 2048 ? 2 : 1);
+    // the largest order this entry point takes
+    if (n > 4096) return GHSVD_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int nt = (n + kP4Tile - 1) / kP4Tile;
     // two working matrices (steps alternate between them), the factors by
@@ -403,7 +515,9 @@ extern "C" int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_p
     const size_t gbytes = align_up(sizeof(double2) * (size_t)n, 256);
     const size_t pbytes = align_up(sizeof(TileMax) * (size_t)nt * nt, 256);
     const size_t ibytes = align_up(sizeof(int) * (6 * (size_t)n + 1), 256);
-    const size_t need = 4 * wbytes + dbytes + gbytes + 2 * pbytes + ibytes;
+    const int nb = (n + kTs - 1) / kTs;  // tiles of the blocked solves
+    const size_t vbytes = align_up(sizeof(double2) * 2 * (size_t)nb * kTs * kTs, 256);
+    const size_t need = 4 * wbytes + dbytes + gbytes + 2 * pbytes + ibytes + vbytes;
     char *buf = nullptr;
     if (hipMalloc(&buf, need) != hipSuccess) return GHSVD_EDEVICE;
     char *at = buf;
@@ -428,6 +542,7 @@ extern "C" int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_p
     int *rl[2] = {ib + 2 * n, ib + 3 * n};
     int *cl[2] = {ib + 4 * n, ib + 5 * n};
     int *flags = ib + 6 * n;
+    double2 *Dinv = reinterpret_cast<double2 *>(take(vbytes));  // inverse diagonal blocks
     double2 *W = Wb[0];
     int rc = GHSVD_OK;
     int hflags = 0;
@@ -467,18 +582,22 @@ extern "C" int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_p
     }
     hipLaunchKernelGGL(k_p4_gather, dim3(n), dim3(kP4Threads), 0, s, n, Lt, Ut, dg, piv_r, piv_c,
                        W, flags);
-    const size_t lds = sizeof(double2) * (size_t)nr * n;
-    const int ng = (n + nr - 1) / nr;
+    // X = Q U^{-1} L^{-1} P: the diagonal blocks' inverses, then the panels of
+    // the forward pass into Yf (Lt, free after the gather) with the working
+    // right-hand side in the other working matrix, then the panels of the
+    // backward pass into X
+    double2 *Yw = Wb[1], *Yf = Lt;
+    hipLaunchKernelGGL(k_p4_dinv, dim3(nb, 2), dim3(256), 0, s, n, W, Dinv);
+    int ex = (n + 255) / 256;
+    if (ex > 16) ex = 16;
+    hipLaunchKernelGGL(k_p4_eye, dim3(ex, n), dim3(256), 0, s, n, Yw, Yf);
     double2 *X2 = reinterpret_cast<double2 *>(X);
-    if (nr == 4)
-        hipLaunchKernelGGL((k_p4_solve<4, 4>), dim3(ng), dim3(kP4Threads), lds, s, n, W, piv_r,
-                           piv_c, X2, (long)ldx, flags);
-    else if (nr == 2)
-        hipLaunchKernelGGL((k_p4_solve<2, 8>), dim3(ng), dim3(kP4Threads), lds, s, n, W, piv_r,
-                           piv_c, X2, (long)ldx, flags);
-    else
-        hipLaunchKernelGGL((k_p4_solve<1, 16>), dim3(ng), dim3(kP4Threads), lds, s, n, W, piv_r,
-                           piv_c, X2, (long)ldx, flags);
+    for (int k = 0; k < nb; ++k)
+        hipLaunchKernelGGL(k_p4_panel, dim3((nb - k) * (k + 1)), dim3(256), 0, s, n, nb, k, 0, W,
+                           Dinv, Yw, Yf, piv_r, piv_c, X2, (long)ldx, flags);
+    for (int k = nb - 1; k >= 0; --k)
+        hipLaunchKernelGGL(k_p4_panel, dim3((k + 1) * nb), dim3(256), 0, s, n, nb, k, 1, W, Dinv,
+                           Yw, Yf, piv_r, piv_c, X2, (long)ldx, flags);
     if (hipGetLastError() != hipSuccess) return fail(GHSVD_EDEVICE);
     if (hipMemcpyAsync(&hflags, flags, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)

@@ -107,11 +107,10 @@ def test_full_at_full_size():
 
 
 @pytest.mark.parametrize("n", [1, 65, 1100, 2100, 4096])
-def test_full_inverse_at_every_solve_width(n):
-    # X = Z^{-1} for Z = Z' Sigma^{-1} at sizes that take each form of the
-    # solve (four, two and one right-hand sides per workgroup) and ragged
-    # tiles, up to the largest n the solve's LDS takes; the residual of
-    # X Z = I against the backward-stable bound of an LU-based inverse
+def test_full_inverse_at_many_sizes(n):
+    # X = Z^{-1} for Z = Z' Sigma^{-1} at sizes with one tile, a ragged last
+    # tile of the blocked solves, and up to the largest n taken; the residual
+    # of X Z = I against the backward-stable bound of an LU-based inverse
     rng = np.random.default_rng(100 + n)
     Fp = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
     Gp = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
@@ -135,8 +134,7 @@ def test_full_inverse_at_every_solve_width(n):
     assert np.all(np.abs(host(sf) - sfo) <= tol)
 
 
-def test_full_rejects_n_beyond_solve_lds():
-    # one right-hand side of n complex entries must fit the solve's 64 KiB of LDS
+def test_full_rejects_n_beyond_largest_order():
     n = 4097
     A = dev(np.eye(n))
     with pytest.raises(ghsvd.GhsvdError) as e:
