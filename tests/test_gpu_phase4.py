@@ -106,7 +106,7 @@ def test_full_at_full_size():
     assert r["errors_7_1"]["F"] < 1e-12 and r["errors_7_1"]["G"] < 1e-12, r
 
 
-@pytest.mark.parametrize("n", [1, 65, 1100, 2100, 4096])
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 127, 1100, 2100, 4096])
 def test_full_inverse_at_many_sizes(n):
     # X = Z^{-1} for Z = Z' Sigma^{-1} at sizes with one tile, a ragged last
     # tile of the blocked solves, and up to the largest n taken; the residual
