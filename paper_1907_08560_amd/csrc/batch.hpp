@@ -80,6 +80,7 @@ struct PencilDev {
     JqrState *jst;    // [2] by step parity
     JqrDecision *jdec;
     double *hd;      // J-norm^2 of each physical column over the unreduced rows
+    double *hl;      // the same by logical column (position in the step's column order)
     double2 *hc;
     double *hi;
     int *cpb;        // column map after the diagonal-pivot swap of the current step

@@ -112,13 +112,13 @@ __device__ __forceinline__ const double2 *jcol(const double2 *A, long lda, int c
 }
 
 // Diagonal pivot of step k: the logical column i >= k with the largest
-// |J-norm^2| (the first one on ties), the same in every workgroup.
-__device__ __forceinline__ int jqr_diag_pivot(const double *hd, const int *cp, int k, int n,
-                                              double *rv, int *ri) {
+// |J-norm^2| (the first one on ties), the same in every workgroup.  hl holds
+// the J-norms by logical column, so no column map is read first.
+__device__ __forceinline__ int jqr_diag_pivot(const double *hl, int k, int n, double *rv, int *ri) {
     double bv = -1.0;
     int bi = k;
     for (int i = k + threadIdx.x; i < n; i += blockDim.x) {
-        const double v = fabs(hd[cp[i]]);
+        const double v = fabs(hl[i]);
         if (v > bv || (v == bv && i < bi)) {
             bv = v;
             bi = i;
@@ -128,7 +128,8 @@ __device__ __forceinline__ int jqr_diag_pivot(const double *hd, const int *cp, i
     return bi;
 }
 
-// hd[c] = J-norm^2 of every column over rows 0..m-1 (before the first step).
+// hd[c] = J-norm^2 of every column over rows 0..m-1 (before the first step),
+// and hl[j] for its logical column j.
 __global__ __launch_bounds__(kGridNT) void k_jqr_colnorms(const PencilDev *PD, const int *pre, int B,
                                                           int par, int jw) {
     __shared__ double red[kGridNT / kWave];
@@ -136,7 +137,10 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_colnorms(const PencilDev *PD, c
     if (!jqr_active(st, n)) return;
     const int c = P.perm[j_local];
     const double h = jnorm_block(jcol(A, lda, c), J, st.k, m, red);
-    if (threadIdx.x == 0) P.hd[c] = h;
+    if (threadIdx.x == 0) {
+        P.hd[c] = h;
+        P.hl[j_local] = h;
+    }
 }
 
 // Step, first kernel: every workgroup finds the diagonal pivot bi, and the
@@ -153,7 +157,7 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_cross(const PencilDev *PD, cons
     const int k = st.k, j = j_local;
     if (j < k || k == n - 1) return;
     const int *cp = P.perm;
-    const int bi = jqr_diag_pivot(P.hd, cp, k, n, rv, ri);
+    const int bi = jqr_diag_pivot(P.hl, k, n, rv, ri);
     if (j == k && threadIdx.x == 0) P.jdec->bi = bi;  // for the second kernel
     if (j == bi) return;
     const double2 d = jdot_block(jcol(A, lda, cp[bi]), jcol(A, lda, cp[j]), J, k, m, red);
@@ -420,7 +424,10 @@ __device__ __forceinline__ void jqr_step1_regs(const PencilDev &P, const JqrStat
         }
     }
     block_sum<1>(h, red);
-    if (tid == 0) P.hd[cp2(j)] = h[0];
+    if (tid == 0) {
+        P.hd[cp2(j)] = h[0];
+        P.hl[j] = h[0];
+    }
 }
 
 // Workgroups tot.. of the launch run column step qk of G's QR instead.  RC:
@@ -745,7 +752,10 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
             y[r] = nv;
         }
         block_sum<1>(v, red);
-        if (tid == 0) P.hd[cp2(j)] = v[0];
+        if (tid == 0) {
+            P.hd[cp2(j)] = v[0];
+            P.hl[j] = v[0];
+        }
         return;
     }
     double2 tw1;
@@ -774,7 +784,10 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
         y[r] = nv;
     }
     block_sum<1>(v, red);
-    if (tid == 0) P.hd[cp2(j)] = v[0];
+    if (tid == 0) {
+        P.hd[cp2(j)] = v[0];
+        P.hl[j] = v[0];
+    }
 }
 
 __global__ void k_jqr_init(const PencilDev *PD) {

@@ -62,6 +62,7 @@ void carve_pencil(Carver &c, const Plan &pl, PencilDev &d) {
         d.Gt = c.take<double2>((size_t)pl.ldgt * n);
         d.jdec = c.take<JqrDecision>(1);
         d.hd = c.take<double>(n);
+        d.hl = c.take<double>(n);
         d.hc = c.take<double2>(n);
         d.hi = c.take<double>(n);
         d.cpb = c.take<int>(n);
