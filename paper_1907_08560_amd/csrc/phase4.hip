@@ -173,32 +173,32 @@ __global__ __launch_bounds__(kP4Threads) void k_p4_tilemax(int n, const double2 
 // at Ut[k, label], the pivot at dg[k], the labels of the pivot's row and
 // column at piv_r[k], piv_c[k].  flags bit 0 on a zero pivot; every step
 // after it then finds a zero pivot too and writes nothing else.
-__global__ __launch_bounds__(kP4Threads) void k_p4_step(
-    int n, int k, const double2 *Win, double2 *Wout, const TileMax *pin, TileMax *pout,
-    const int *rl_in, const int *cl_in, int *rl_out, int *cl_out, double2 *Lt, double2 *Ut,
-    double2 *dg, int *piv_r, int *piv_c, int *flags) {
-    constexpr int kCols = kP4Tile * kWave / kP4Threads;  // columns per thread
-    __shared__ double sv[kP4Threads / kWave];
-    __shared__ long si[kP4Threads / kWave];
-    const int tid = threadIdx.x;
+constexpr int kP4Cols = kP4Tile * kWave / kP4Threads;  // tile columns per thread
+
+// Tile `tile` of rows and columns k+1..n-1 (tiles of kP4Tile, column-major
+// tile order): thread t holds row i0 + (t % 64), columns j0 + t / 64 + 4 c,
+// read at the positions of the working matrix before the interchanges.
+__device__ __forceinline__ void p4_load_tile(int n, int k, int tile, const double2 *Win,
+                                             double2 (&x)[kP4Cols]) {
     const int nt1 = (n - k - 1 + kP4Tile - 1) / kP4Tile;
-    const int ti = nt1 ? (int)blockIdx.x % nt1 : 0, tj = nt1 ? (int)blockIdx.x / nt1 : 0;
-    const int i0 = k + 1 + ti * kP4Tile, j0 = k + 1 + tj * kP4Tile;
-    // thread t: row i0 + (t % 64), columns j0 + t / 64 + 4 c.  The tile is
-    // loaded before the pivot is known; only an entry in the pivot's row or
-    // column is read again once it is.
-    const int i = i0 + (tid % kP4Tile);
-    const int jt = j0 + tid / kP4Tile;
-    double2 x[kCols];
+    const int ti = nt1 ? tile % nt1 : 0, tj = nt1 ? tile / nt1 : 0;
+    const int i = k + 1 + ti * kP4Tile + ((int)threadIdx.x % kP4Tile);
+    const int jt = k + 1 + tj * kP4Tile + (int)threadIdx.x / kP4Tile;
 #pragma unroll
-    for (int c = 0; c < kCols; ++c) {
+    for (int c = 0; c < kP4Cols; ++c) {
         const int j = jt + 4 * c;
         x[c] = (i < n && j < n) ? Win[(size_t)j * n + i] : cmk(0.0, 0.0);
     }
+}
+
+// The pivot of step k from the tile maxima pin (tiles anchored at k), the
+// same in every workgroup: its modulus squared bv and position bi.
+__device__ __forceinline__ void p4_find_pivot(int n, int k, const TileMax *pin, double *sv,
+                                              long *si, double &bv, long &bi) {
     const int nt = (n - k + kP4Tile - 1) / kP4Tile;
-    double bv = -1.0;
-    long bi = 0x7fffffffffffffffL;
-    for (int t = tid; t < nt * nt; t += blockDim.x) {
+    bv = -1.0;
+    bi = 0x7fffffffffffffffL;
+    for (int t = threadIdx.x; t < nt * nt; t += blockDim.x) {
         const TileMax m = pin[t];
         if (tm_better(m.v, m.idx, bv, bi)) {
             bv = m.v;
@@ -206,23 +206,44 @@ __global__ __launch_bounds__(kP4Threads) void k_p4_step(
         }
     }
     block_tm(bv, bi, sv, si);
+}
+
+// Step k on one tile, its entries x loaded by p4_load_tile and the pivot
+// (bv, bi) known: the interchanged matrix has at (i, j), i, j > k, the entry
+// (rs(i), cs(j)) of Win, rs swapping pr for k and cs swapping q for k, so
+// only an entry in the pivot's row or column is read again.  Writes the
+// updated tile to Wout and its largest modulus to *pout; the tiles of the
+// first tile row and column also store the multipliers (Lt[label, k]) and
+// the pivot row (Ut[k, label]) by label and the next labels, tile 0 the
+// pivot (dg[k]) and its row and column labels.  A zero pivot sets flags
+// bit 0 and leaves empty maxima, so that every later step finds one too.
+__device__ __forceinline__ void p4_tile_update(
+    int n, int k, int tile, double bv, long bi, double2 (&x)[kP4Cols], const double2 *Win,
+    double2 *Wout, TileMax *pout, const int *rl_in, const int *cl_in, int *rl_out, int *cl_out,
+    double2 *Lt, double2 *Ut, double2 *dg, int *piv_r, int *piv_c, int *flags, double *sv,
+    long *si) {
+    const int tid = threadIdx.x;
     if (!(bv > 0.0)) {
-        // empty maxima for the next step, which then stops here too
         if (tid == 0) {
-            pout[blockIdx.x] = TileMax{-1.0, 0x7fffffffffffffffL};
-            if (blockIdx.x == 0) atomicOr(flags, 1);
+            *pout = TileMax{-1.0, 0x7fffffffffffffffL};
+            if (tile == 0) atomicOr(flags, 1);
         }
         return;
     }
     const int q = (int)(bi / n), pr = (int)(bi % n);
+    const int nt1 = (n - k - 1 + kP4Tile - 1) / kP4Tile;
+    const int ti = nt1 ? tile % nt1 : 0, tj = nt1 ? tile / nt1 : 0;
+    const int i0 = k + 1 + ti * kP4Tile, j0 = k + 1 + tj * kP4Tile;
+    const int i = i0 + (tid % kP4Tile);
+    const int jt = j0 + tid / kP4Tile;
     const int rs = i == pr ? k : i;
     // the pivot, the multiplier of row i and the pivot row on this thread's
     // columns, all read at once
     const double2 d = Win[(size_t)q * n + pr];
     double2 l = i < n ? Win[(size_t)q * n + rs] : cmk(0.0, 0.0);
-    double2 u[kCols];
+    double2 u[kP4Cols];
 #pragma unroll
-    for (int c = 0; c < kCols; ++c) {
+    for (int c = 0; c < kP4Cols; ++c) {
         const int j = jt + 4 * c;
         const int cs = j == q ? k : j;
         u[c] = j < n ? Win[(size_t)cs * n + pr] : cmk(0.0, 0.0);
@@ -243,28 +264,47 @@ __global__ __launch_bounds__(kP4Threads) void k_p4_step(
         Ut[(size_t)lab * n + k] = Win[(size_t)cs * n + pr];
         cl_out[j] = lab;
     }
-    if (blockIdx.x == 0 && tid == 0) {
+    if (tile == 0 && tid == 0) {
         dg[k] = d;
         piv_r[k] = rl_in[pr];
         piv_c[k] = cl_in[q];
     }
-    bv = -1.0;
-    bi = 0x7fffffffffffffffL;
+    double tv = -1.0;
+    long tix = 0x7fffffffffffffffL;
 #pragma unroll
-    for (int c = 0; c < kCols; ++c) {
+    for (int c = 0; c < kP4Cols; ++c) {
         const int j = jt + 4 * c;
         if (i >= n || j >= n) continue;
         const double2 y = csub(x[c], cmul(l, u[c]));
         Wout[(size_t)j * n + i] = y;
         const double v = cnorm2(y);
         const long idx = (long)j * n + i;
-        if (tm_better(v, idx, bv, bi)) {
-            bv = v;
-            bi = idx;
+        if (tm_better(v, idx, tv, tix)) {
+            tv = v;
+            tix = idx;
         }
     }
-    block_tm(bv, bi, sv, si);
-    if (tid == 0) pout[blockIdx.x] = TileMax{bv, bi};
+    block_tm(tv, tix, sv, si);
+    if (tid == 0) *pout = TileMax{tv, tix};
+}
+
+// Step k of the factorization, one launch with a workgroup per tile; the
+// tile is read before the pivot is known.  (One cooperative launch for all
+// steps, with a grid-wide barrier between them, took 2.5 times as long: the
+// barrier across the chip costs more than the launch it saves.)
+__global__ __launch_bounds__(kP4Threads) void k_p4_step(
+    int n, int k, const double2 *Win, double2 *Wout, const TileMax *pin, TileMax *pout,
+    const int *rl_in, const int *cl_in, int *rl_out, int *cl_out, double2 *Lt, double2 *Ut,
+    double2 *dg, int *piv_r, int *piv_c, int *flags) {
+    __shared__ double sv[kP4Threads / kWave];
+    __shared__ long si[kP4Threads / kWave];
+    double2 x[kP4Cols];
+    p4_load_tile(n, k, blockIdx.x, Win, x);
+    double bv;
+    long bi;
+    p4_find_pivot(n, k, pin, sv, si, bv, bi);
+    p4_tile_update(n, k, blockIdx.x, bv, bi, x, Win, Wout, pout + blockIdx.x, rl_in, cl_in, rl_out,
+                   cl_out, Lt, Ut, dg, piv_r, piv_c, flags, sv, si);
 }
 
 // P W Q = L U in the triangular layout (L below the diagonal, U on and

@@ -140,3 +140,4 @@ def test_full_rejects_n_beyond_largest_order():
     with pytest.raises(ghsvd.GhsvdError) as e:
         ghsvd.full(A, 1, A, A)
     assert e.value.status == -1  # GHSVD_EINVAL
+
