@@ -194,8 +194,8 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_cross2(const PencilDev *PD, con
     }
     block_argmax(cv, ci, rv, ri);
     const double alpha = (1.0 + sqrt(17.0)) / 8.0;
-    const int cpk = cp[bi];  // physical column at position k after the swap
-    const int need2 = (k < n - 1) && !(fabs(P.hd[cpk]) >= alpha * cv);
+    // |J-norm^2| of the column at position k after the swap: hl[bi] = hd[cp[bi]]
+    const int need2 = (k < n - 1) && !(fabs(P.hl[bi]) >= alpha * cv);
     auto cp1 = [&](int l) { return l == k ? cp[bi] : (l == bi ? cp[k] : cp[l]); };
     if (j == k) {
         for (int l = threadIdx.x; l < n; l += blockDim.x) P.cpb[l] = cp1(l);
