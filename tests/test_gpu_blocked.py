@@ -175,3 +175,20 @@ def test_fb_solve_workload_one(oracle, w):
     assert rel_err(lam, lam_o) <= 1e-12
     e_s, e_h, e_d = factor_invariants(P.F, P.J, P.G, lam, host(X))
     assert e_s < 1e-10 and e_h < 1e-10 and e_d < 1e-10
+
+
+@pytest.mark.parametrize("w", [8, 16, 32])
+def test_fb_mixed_solve_workload_one(oracle, w):
+    # FB in the FP32 warm-up too (the FP32 inner kernels run their inner
+    # sweeps to convergence at the FP32 tolerance), then the FP64 finish
+    P = synth.workload_pencil(1)
+    F, J, G = to_dev(P)
+    lam, X, info = ghsvd.solve(F, J, G, precision="mixed", variant="blocked", block_width=w,
+                               inner_order="fb")
+    st, lam_o, X_o, _ = oracle.ghsvd(P.F, P.J, P.G)
+    assert info["status"] == 0 and st == 0
+    assert info["sweeps_fp32"] > 0 and info["sweeps_fp64"] >= 1, info
+    lam = host(lam)
+    assert rel_err(lam, lam_o) <= 1e-12
+    e_s, e_h, e_d = factor_invariants(P.F, P.J, P.G, lam, host(X))
+    assert e_s < 1e-10 and e_h < 1e-10 and e_d < 1e-10
