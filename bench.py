@@ -78,7 +78,7 @@ def kernel_rooflines(times, info_sum, mr, pr, n, w, nbp, fp32_blocked=False):
         elif kind in ("gram", "update"):
             bsz = 8 if fp32_blocked else 16
             if kind == "gram":
-                flops = 4.0 * c * c * (mr + pr) * nbp           # Hermitian Grams, SURVEY model
+                flops = 4.0 * c * c * (mr + pr) * nbp           # Hermitian Grams: 8 c^2 rows / 2
                 byts = c * bsz * (mr + pr) * nbp                # block columns read once
             else:
                 flops = 8.0 * c * c * (mr + pr + n) * nbp       # three complex GEMMs
@@ -401,8 +401,8 @@ def main():
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design note, not a built path.", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU only (asked for --gpus {args.gpus}); "
+              "sharding across GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
