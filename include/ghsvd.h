@@ -76,7 +76,8 @@ typedef struct {
                            pairs across the two blocks at the other steps, so each column
                            pair is visited once per sweep; GHSVD_INNER_FB: the Full Block
                            variant (Section 6.4.2), round-robin inner sweeps until one
-                           applies no big transformation, at most 30                     */
+                           applies no transformation, big or small (Section 6.1.7), at
+                           most 30                                                       */
 } ghsvd_options;
 
 enum { GHSVD_INNER_FULL = 0, GHSVD_INNER_CROSS = 1, GHSVD_INNER_FB = 2 };  /* ghsvd_options.inner_order */
@@ -258,14 +259,19 @@ int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, doub
  * sigma_g[j])^2.  Errors: GHSVD_EINVAL for sizes, leading dimensions, NULL
  * pointers or n > 4096 (the largest order taken); GHSVD_ERANK when some h_j or s_j is zero or Z is
  * singular (a zero pivot); GHSVD_ENONFINITE for NaN/Inf column norms.
- * Allocates and frees its own workspace (4 n^2 complex128 + O(n): two
+ * work (device, 256-byte aligned, owned by the caller) holds
+ * lwork >= ghsvd_full_workspace_size(n) bytes (4 n^2 complex128 + O(n): two
  * working matrices, L and U stored by row and column label, which the solves
- * reuse, plus the inverse diagonal blocks);
- * synchronizes the stream.
+ * reuse, plus the inverse diagonal blocks); a shorter lwork gives
+ * GHSVD_ENOMEM and a misaligned work GHSVD_EINVAL.  work = NULL makes the
+ * call allocate and free its own.  The library keeps no pointer after the
+ * call.  Synchronizes the stream (the zero-pivot test is read on the host).
  */
+size_t ghsvd_full_workspace_size(int n);  /* 0 for n < 1 or n > 4096 */
 int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_plus, const double *G,
                int ldg, const double *Z, int ldz, double *U, int ldu, double *V, int ldv,
-               double *sigma_f, double *sigma_g, double *X, int ldx, void *stream);
+               double *sigma_f, double *sigma_g, double *X, int ldx, void *work, size_t lwork,
+               void *stream);
 
 /*
  * The round-robin ordering (host): N = n rounded up to even; step s pairs

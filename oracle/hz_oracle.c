@@ -23,6 +23,9 @@
  *   R3  sigma = sgn(h) is taken as +1 at h = 0.
  *   R4  a sweep ends the iteration when it applied no "big" transformation
  *       (Section 6.1.7); stop_rule = 1 selects "no transformation at all".
+ *       The inner level of a blocked run (the Full Block variant) stops on
+ *       an inner sweep with no transformation at all, as Section 6.1.7 says
+ *       of inner levels.
  *   R5  the D0-prescaled pivot entries enter (6.4)-(6.12).
  *   R6  h_pq = s_pq = 0 skips the pair before (6.12) is evaluated.
  *   R7  G is taken as numerically rank deficient (error -2) when a pivot has
@@ -777,14 +780,17 @@ int ora_ghsvd(int m, int n, int p, const cplx *F, int ldf, const signed char *J,
  * it transformed anything, F_C, G_C and Z_C are multiplied by Z^
  * (Section 6.4.3).  After each block sweep the iteration stops when the
  * inner sweeps applied no big transformation.  stats as ora_hz_run, counting
- * inner pivot pairs.  eps is the machine precision of (6.12) with n the
- * order of the block pivot (tol = eps sqrt(c)).
+ * inner pivot pairs; stats[5] = the most inner sweeps any block pivot ran.
+ * eps is the machine precision of (6.12) with n the order of the block pivot
+ * (tol = eps sqrt(c)).
  *
  * inner_order 2 is the Full Block (FB) variant of Section 6.4.2: the inner
  * level runs round-robin sweeps over the c pivot columns until one of them
- * applies no big transformation (the stopping rule of Algorithm 2, read as
- * the inner level's own), at most C_max = 30 of them; Z^ accumulates them
- * all.  BO is the same with C_max = 1.
+ * applies no transformation at all, big or small (Section 6.1.7: the inner
+ * levels of a blocked algorithm count every transformation for stopping, as
+ * Algorithm 2's own test does), at most C_max = 30 of them; Z^ accumulates
+ * them all.  Only the outer level stops on the absence of big
+ * transformations.  BO is the same with C_max = 1.
  */
 int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J,
                      cplx *G, int ldg, cplx *Z, int ldz, int w, int max_sweeps,
@@ -792,7 +798,7 @@ int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J
 {
     if (m < 1 || n < 2 || p < 1 || ldf < m || ldg < p || ldz < n || w < 1 || max_sweeps < 1)
         return ORA_EINVAL;
-    for (int i = 0; i < 5; ++i) stats[i] = 0;
+    for (int i = 0; i < 6; ++i) stats[i] = 0;
     int nb = (n + w - 1) / w;
     if (nb % 2) nb += 1;
     int bsteps = 0;
@@ -867,7 +873,8 @@ int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J
                 const double tol = eps * sqrt((double)c);
                 long long itr = 0;
                 for (int isw = 0; isw < cmax_inner; ++isw) {
-                    long long ibig = 0;
+                    /* transformations (all, and big) of this inner sweep */
+                    long long iall = 0, ibig = 0;
                     for (int is = 0; is < isteps; ++is)
                         for (int ik = 0; ik < islots; ++ik) {
                             const int pc = ip[is * islots + ik], qc = iq[is * islots + ik];
@@ -877,10 +884,17 @@ int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J
                             stats[1]++;
                             if (kind == ORA_ERANK) continue; /* left to the finishing sweeps */
                             if (kind < 0) { status = kind; goto done; }
-                            if (kind > 0) { tr++; itr++; }
+                            if (kind > 0) { tr++; itr++; iall++; }
                             if (kind == 2) { big++; ibig++; }
                         }
+                    if (isw + 1 > stats[5]) stats[5] = isw + 1;
+#if ORA_MUTANT == 15
+                    (void)iall;
                     if (ibig == 0) break;
+#else
+                    (void)ibig;
+                    if (iall == 0) break;
+#endif
                 }
                 if (itr == 0) continue;
                 /* F_C <- F_C Z^, G_C <- G_C Z^, Z_C <- Z_C Z^ (Section 6.4.3) */

@@ -563,10 +563,12 @@ __device__ __forceinline__ void inner_pivots(double tol, int crit, const double2
 // each pair of columns is visited once per sweep.  mode GHSVD_INNER_FB (the
 // Full Block variant of Section 6.4.2): round-robin inner sweeps follow one
 // another, the step after the last of a sweep being step 0 of the next, until
-// an inner sweep applies no big transformation or kFbSweeps have run.  The
-// pivot wavefront, which forms the pivots of the next step while the last
-// step of a sweep is applied, decides from the sweep's big count whether
-// there is a next sweep and posts the decision for the whole workgroup.
+// an inner sweep applies no transformation at all (big or small: Section
+// 6.1.7 has inner levels count every transformation for stopping) or
+// kFbSweeps have run.  The pivot wavefront, which forms the pivots of the
+// next step while the last step of a sweep is applied, decides from the
+// sweep's transformation count whether there is a next sweep and posts the
+// decision for the whole workgroup.
 constexpr int kFbSweeps = 30;  // C_max of the FB inner level
 
 template <int PB, int F32, int FB>
@@ -655,7 +657,7 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
         if (nsteps > 1) te = tab[1][tid];
         else if (max_isw > 1) te = tab[0][tid];
     }
-    double cmark = 0.0;  // cbig at the end of the previous inner sweep
+    double cmark = 0.0;  // ct at the end of the previous inner sweep
     int g = 0;           // inner steps so far (parity of the H, S and step buffers)
     for (int isw = 0;; ++isw) {
     for (int s = 0; s < nsteps; ++s, ++g) {
@@ -664,11 +666,12 @@ __global__ __launch_bounds__(inner_threads<PB>()) void k_blk_inner(const PencilD
         if (tid < kWave) {
             bool go = s + 1 < nsteps;
             if (!go && isw + 1 < max_isw) {
-                // the pivots of this sweep's last step are in cbig: another
-                // sweep follows when the sweep applied a big transformation
-                const double sb = wave_sum(cbig - cmark);
-                cmark = cbig;
-                go = sb > 0.0;
+                // the pivots of this sweep's last step are in ct: another
+                // sweep follows when the sweep applied any transformation,
+                // big or small (inner levels count them all for stopping)
+                const double sa = wave_sum(ct - cmark);
+                cmark = ct;
+                go = sa > 0.0;
                 if (tid == 0) more[isw & 1] = go;
             }
             if (go) {
@@ -926,7 +929,7 @@ __global__ __launch_bounds__(kI64Threads) void k_blk_inner64(const PencilDev *PD
         st[0].act[k] = kind > 0;
     }
     __syncthreads();
-    double cmark = 0.0;  // cbig at the end of the previous inner sweep
+    double cmark = 0.0;  // ct at the end of the previous inner sweep
     int g = 0;           // inner steps so far (parity of the step and table buffers)
     for (int isw = 0;; ++isw) {
     for (int s = 0; s < nsteps; ++s, ++g) {
@@ -942,11 +945,11 @@ __global__ __launch_bounds__(kI64Threads) void k_blk_inner64(const PencilDev *PD
         if (tid < kWave) {
             go = s + 1 < nsteps;
             if (!go && isw + 1 < max_isw) {
-                // the pivots of this sweep's last step are in cbig: another
-                // sweep follows when the sweep applied a big transformation
-                const double sb = wave_sum(cbig - cmark);
-                cmark = cbig;
-                go = sb > 0.0;
+                // the pivots of this sweep's last step are in ct: another
+                // sweep follows when the sweep applied any transformation
+                const double sa = wave_sum(ct - cmark);
+                cmark = ct;
+                go = sa > 0.0;
                 if (tid == 0) more[isw & 1] = go;
             }
             if (go) {

@@ -538,34 +538,76 @@ __global__ void k_p4_eye(int n, double2 *Y, double2 *Yf) {
 
 using namespace ghsvd;
 
+namespace ghsvd {
+namespace {
+
+// Workspace of ghsvd_full: two working matrices (steps alternate between
+// them), the factors by label, the column statistics, the pivots, two sets
+// of tile maxima and of labels, the inverse diagonal blocks of the solves.
+struct FullLayout {
+    size_t wbytes, dbytes, gbytes, pbytes, ibytes, vbytes;
+    size_t total() const { return 4 * wbytes + dbytes + gbytes + 2 * pbytes + ibytes + vbytes; }
+};
+
+FullLayout full_layout(int n) {
+    const int nt = (n + kP4Tile - 1) / kP4Tile;
+    const int nb = (n + kTs - 1) / kTs;  // tiles of the blocked solves
+    FullLayout L;
+    L.wbytes = align_up(sizeof(double2) * (size_t)n * n, 256);
+    L.dbytes = align_up(sizeof(double) * 2 * (size_t)n, 256);
+    L.gbytes = align_up(sizeof(double2) * (size_t)n, 256);
+    L.pbytes = align_up(sizeof(TileMax) * (size_t)nt * nt, 256);
+    L.ibytes = align_up(sizeof(int) * (6 * (size_t)n + 1), 256);
+    L.vbytes = align_up(sizeof(double2) * 2 * (size_t)nb * kTs * kTs, 256);
+    return L;
+}
+
+__global__ void k_p4_zero_flag(int *flags) {
+    if (threadIdx.x == 0) flags[0] = 0;
+}
+
+}  // namespace
+}  // namespace ghsvd
+
+// the largest order ghsvd_full takes
+static constexpr int kFullMaxN = 4096;
+
+extern "C" size_t ghsvd_full_workspace_size(int n) {
+    if (n < 1 || n > kFullMaxN) return 0;
+    return full_layout(n).total();
+}
+
 extern "C" int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_plus, const double *G,
                           int ldg, const double *Z, int ldz, double *U, int ldu, double *V, int ldv,
-                          double *sigma_f, double *sigma_g, double *X, int ldx, void *stream) {
+                          double *sigma_f, double *sigma_g, double *X, int ldx, void *work,
+                          size_t lwork, void *stream) {
     if (n < 1 || m < n || p < n || n_plus < 0 || n_plus > m || ldf < m || ldg < p || ldz < n ||
         ldu < m || ldv < p || ldx < n || !F || !G || !Z || !U || !V || !sigma_f || !sigma_g || !X)
         return GHSVD_EINVAL;
-    // the largest order this entry point takes
-    if (n > 4096) return GHSVD_EINVAL;
+    if (n > kFullMaxN) return GHSVD_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     const int nt = (n + kP4Tile - 1) / kP4Tile;
-    // two working matrices (steps alternate between them), the factors by
-    // label, the pivots, two sets of tile maxima and of labels
-    const size_t wbytes = align_up(sizeof(double2) * (size_t)n * n, 256);
-    const size_t dbytes = align_up(sizeof(double) * 2 * (size_t)n, 256);
-    const size_t gbytes = align_up(sizeof(double2) * (size_t)n, 256);
-    const size_t pbytes = align_up(sizeof(TileMax) * (size_t)nt * nt, 256);
-    const size_t ibytes = align_up(sizeof(int) * (6 * (size_t)n + 1), 256);
-    const int nb = (n + kTs - 1) / kTs;  // tiles of the blocked solves
-    const size_t vbytes = align_up(sizeof(double2) * 2 * (size_t)nb * kTs * kTs, 256);
-    const size_t need = 4 * wbytes + dbytes + gbytes + 2 * pbytes + ibytes + vbytes;
+    const int nb = (n + kTs - 1) / kTs;
+    const FullLayout lay = full_layout(n);
+    const size_t need = lay.total();
     char *buf = nullptr;
-    if (hipMalloc(&buf, need) != hipSuccess) return GHSVD_EDEVICE;
+    bool owned = false;
+    if (work) {
+        if (lwork < need) return GHSVD_ENOMEM;
+        if (reinterpret_cast<uintptr_t>(work) % 256) return GHSVD_EINVAL;
+        buf = reinterpret_cast<char *>(work);
+    } else {
+        if (hipMalloc(&buf, need) != hipSuccess) return GHSVD_EDEVICE;
+        owned = true;
+    }
     char *at = buf;
     auto take = [&](size_t bytes) {
         char *r = at;
         at += bytes;
         return r;
     };
+    const size_t wbytes = lay.wbytes, dbytes = lay.dbytes, gbytes = lay.gbytes;
+    const size_t pbytes = lay.pbytes, ibytes = lay.ibytes, vbytes = lay.vbytes;
     double2 *Wb[2];
     Wb[0] = reinterpret_cast<double2 *>(take(wbytes));
     Wb[1] = reinterpret_cast<double2 *>(take(wbytes));
@@ -588,10 +630,10 @@ extern "C" int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_p
     int hflags = 0;
     auto fail = [&](int code) {
         (void)hipStreamSynchronize(s);
-        (void)hipFree(buf);
+        if (owned) (void)hipFree(buf);
         return code;
     };
-    if (hipMemsetAsync(flags, 0, sizeof(int), s) != hipSuccess) return fail(GHSVD_EDEVICE);
+    hipLaunchKernelGGL(k_p4_zero_flag, dim3(1), dim3(64), 0, s, flags);
     const double2 *F2 = reinterpret_cast<const double2 *>(F);
     const double2 *G2 = reinterpret_cast<const double2 *>(G);
     const double2 *Z2 = reinterpret_cast<const double2 *>(Z);
@@ -643,6 +685,6 @@ extern "C" int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_p
         hipStreamSynchronize(s) != hipSuccess)
         return fail(GHSVD_EDEVICE);
     rc = (hflags & 1) ? GHSVD_ERANK : GHSVD_OK;
-    (void)hipFree(buf);
+    if (owned) (void)hipFree(buf);
     return rc;
 }

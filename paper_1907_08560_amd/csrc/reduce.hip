@@ -1051,6 +1051,11 @@ int jsplit(int rows, int n, const double2 *src, long lds, const int8_t *J, doubl
     return GHSVD_OK;
 }
 
+// Input checks and ||G||_F^2.  Workgroup (x, j) writes its partial sum of
+// column j to gnorm2[1 + 8 j + x]; k_check_sum adds the partials in one
+// fixed order, so ||G||_F^2 does not depend on workgroup timing.
+constexpr int kCheckSplit = 8;  // workgroups per column, at most
+
 __global__ void k_check(int m, int n, int p, const double2 *F, long ldf, const int8_t *J,
                         const double2 *G, long ldg, int *flags, double *gnorm2) {
     __shared__ double red[256 / kWave];
@@ -1074,16 +1079,29 @@ __global__ void k_check(int m, int n, int p, const double2 *F, long ldf, const i
     }
     if (bad) atomicOr(flags, bad);
     block_sum<1>(g2, red);
-    if (threadIdx.x == 0) atomicAdd(gnorm2, g2[0]);
+    if (threadIdx.x == 0) gnorm2[1 + (size_t)kCheckSplit * j + blockIdx.x] = g2[0];
+}
+
+// gnorm2[0] = the sum of the nx partials of each of the n columns: thread t
+// adds columns t, t + 256, ... in order, then a fixed tree over the threads.
+__global__ void k_check_sum(int n, int nx, double *gnorm2) {
+    __shared__ double red[256 / kWave];
+    double v[1] = {0.0};
+    for (int j = threadIdx.x; j < n; j += blockDim.x)
+        for (int x = 0; x < nx; ++x) v[0] += gnorm2[1 + (size_t)kCheckSplit * j + x];
+    block_sum<1>(v, red);
+    if (threadIdx.x == 0) gnorm2[0] = v[0];
 }
 
 int check_inputs(int m, int n, int p, const double2 *F, long ldf, const int8_t *J,
                  const double2 *G, long ldg, int *flags, double *gnorm2, hipStream_t stream) {
     int rows = m > p ? m : p;
     int bx = (rows + 255) / 256;
-    if (bx > 8) bx = 8;
+    if (bx > kCheckSplit) bx = kCheckSplit;
     hipLaunchKernelGGL(k_check, dim3(bx, n), dim3(256), 0, stream, m, n, p, F, ldf, J, G, ldg,
                        flags, gnorm2);
+    GHSVD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_check_sum, dim3(1), dim3(256), 0, stream, n, bx, gnorm2);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }

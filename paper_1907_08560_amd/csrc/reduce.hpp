@@ -26,8 +26,10 @@ int copy_cols(int rows, int n, const double2 *src, long lds, double2 *dst, long 
 int jsplit(int rows, int n, const double2 *src, long lds, const int8_t *J, double2 *dst,
            long ldd, int *rowmap, int *nplus_dev, hipStream_t stream);
 
-// Checks the inputs: J entries in {+1, -1}, F and G finite; accumulates
-// ||G||_F^2 into gnorm2[0].  flags[0] |= 1 (bad J), 2 (non-finite).
+// Checks the inputs: J entries in {+1, -1}, F and G finite; writes
+// ||G||_F^2 into gnorm2[0], summed in a fixed order from per-workgroup
+// partials kept in gnorm2[1 .. 8 n] (the buffer holds 1 + 8 n doubles).
+// flags[0] |= 1 (bad J), 2 (non-finite).
 int check_inputs(int m, int n, int p, const double2 *F, long ldf, const int8_t *J,
                  const double2 *G, long ldg, int *flags, double *gnorm2, hipStream_t stream);
 

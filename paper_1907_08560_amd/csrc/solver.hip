@@ -82,7 +82,7 @@ void carve_pencil(Carver &c, const Plan &pl, PencilDev &d) {
     d.scale = c.take<double>(n);
     d.rank = c.take<int>(n);
     d.small = c.take<int>(8);
-    d.gnorm2 = c.take<double>(1);
+    d.gnorm2 = c.take<double>(1 + 8 * (size_t)n);  // ||G||_F^2 and its partials
     if (pl.mixed) {
         d.F32 = c.take<float2>((size_t)pl.ldf * n);
         d.G32 = c.take<float2>((size_t)pl.ldg * n);

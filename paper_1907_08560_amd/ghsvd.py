@@ -90,8 +90,10 @@ _lib.ghsvd_autotune.restype = _i
 _lib.ghsvd_autotune_clear.argtypes = []
 _lib.ghsvd_autotune_clear.restype = None
 _lib.ghsvd_full.argtypes = [_i, _i, _i, _p, _i, _i, _p, _i, _p, _i, _p, _i, _p, _i, _p, _p, _p, _i,
-                            _p]
+                            _p, _sz, _p]
 _lib.ghsvd_full.restype = _i
+_lib.ghsvd_full_workspace_size.argtypes = [_i]
+_lib.ghsvd_full_workspace_size.restype = _sz
 _lib.ghsvd_status_string.argtypes = [_i]
 _lib.ghsvd_status_string.restype = ctypes.c_char_p
 
@@ -99,7 +101,7 @@ EXPORTED = ["ghsvd_default_options", "ghsvd_workspace_size", "ghsvd_solve",
             "ghsvd_workspace_size_batched", "ghsvd_solve_batched", "ghsvd_reduce",
             "ghsvd_pair_params", "ghsvd_sweeps", "ghsvd_round_robin", "ghsvd_status_string",
             "ghsvd_profile_enable", "ghsvd_profile_read", "ghsvd_block_sweeps",
-            "ghsvd_autotune", "ghsvd_autotune_clear", "ghsvd_full"]
+            "ghsvd_autotune", "ghsvd_autotune_clear", "ghsvd_full", "ghsvd_full_workspace_size"]
 
 
 class GhsvdError(RuntimeError):
@@ -278,8 +280,14 @@ def block_sweeps(F, n_plus: int, G, Z, nsweeps: int, block_width=0, crit_literal
     return rc, done.value, cnt.reshape(nsweeps, 3)
 
 
-def full(F, n_plus: int, G, Z, stream=None):
-    """Full GHSVD from swept factors (ghsvd_full): (U, V, sigma_f, sigma_g, X)."""
+def full_workspace_size(n: int) -> int:
+    return int(_lib.ghsvd_full_workspace_size(int(n)))
+
+
+def full(F, n_plus: int, G, Z, work=None, stream=None):
+    """Full GHSVD from swept factors (ghsvd_full): (U, V, sigma_f, sigma_g, X).
+    work: a uint8 CUDA tensor of at least full_workspace_size(n) bytes (None:
+    one is allocated here, through torch)."""
     m, n = F.shape
     p = G.shape[0]
     U = fortran_empty(m, n, device=F.device)
@@ -287,10 +295,13 @@ def full(F, n_plus: int, G, Z, stream=None):
     X = fortran_empty(n, n, device=F.device)
     sf = torch.empty(n, dtype=torch.float64, device=F.device)
     sg = torch.empty(n, dtype=torch.float64, device=F.device)
+    if work is None:
+        nbytes = full_workspace_size(n)
+        work = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=F.device)
     rc = _lib.ghsvd_full(m, n, p, F.data_ptr(), _check_fortran(F, "F"), int(n_plus), G.data_ptr(),
                          _check_fortran(G, "G"), Z.data_ptr(), _check_fortran(Z, "Z"),
                          U.data_ptr(), m, V.data_ptr(), p, sf.data_ptr(), sg.data_ptr(),
-                         X.data_ptr(), n, _stream_ptr(stream))
+                         X.data_ptr(), n, work.data_ptr(), work.numel(), _stream_ptr(stream))
     if rc < 0:
         raise GhsvdError(rc, "ghsvd_full")
     return U, V, sf, sg, X

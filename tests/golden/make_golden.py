@@ -4,9 +4,12 @@ Calls only the CPU oracle (oracle/) on inputs from the seeded generator; no
 value here comes from the GPU path.  Each file records an input fingerprint
 so a test can confirm it sees the same inputs.
 
-    python tests/golden/make_golden.py workload2        # n = 1024, tall, ~25 min
+    python tests/golden/make_golden.py workload2        # n = 1024, tall, ~7 min
+    python tests/golden/make_golden.py workload4        # 64 pencils, a process pool
+    python tests/golden/make_golden.py samples          # downsized workloads 3 and 5
 """
 import json
+import multiprocessing as mp
 import os
 import sys
 import time
@@ -39,6 +42,35 @@ def run(name: str, P, reduce: bool):
     print(name, st, stats, f"{dt:.1f}s", flush=True)
 
 
+def _one(job):
+    """One pencil of a batch: (workload, k, n_override, j_identity) -> record.
+    The oracle reduces the tall factors (Section 5) and sweeps the square ones
+    in the round-robin order."""
+    number, k, n_override, j_identity = job
+    P = synth.workload_pencil(number, k, j_identity=j_identity, n_override=n_override)
+    o = O.Oracle()
+    t0 = time.process_time()
+    st, lam, X, stats = o.ghsvd(P.F, P.J, P.G, reduce=True, order=1, max_sweeps=80)
+    dt = time.process_time() - t0
+    print(f"workload {number} pencil {k} n={P.n} status {st} sweeps {stats[0]} {dt:.1f}s",
+          flush=True)
+    return {"k": k, "status": int(st), "n": P.n, "m": P.m, "p": P.p, "m_plus": P.m_plus,
+            "j_identity": j_identity, "sweeps": int(stats[0]), "oracle_cpu_seconds": dt,
+            "fingerprint": fingerprint(P), "lambda": [repr(float(v)) for v in lam]}
+
+
+def run_batch(name: str, jobs, desc: str):
+    # largest pencils first, so the pool's tail is short
+    order = sorted(jobs, key=lambda j: -(j[2] or synth.workload_sizes(j[0])[j[1]]))
+    with mp.Pool(os.cpu_count() or 1) as pool:
+        recs = pool.map(_one, order, chunksize=1)
+    recs.sort(key=lambda r: r["k"])
+    out = {"name": name, "description": desc, "reduce": True, "order": "round-robin",
+           "max_sweeps": 80, "pencils": recs}
+    with open(os.path.join(HERE, f"{name}_lambda.json"), "w") as f:
+        json.dump(out, f, indent=0)
+
+
 if __name__ == "__main__":
     O.build()
     which = sys.argv[1:] or ["workload2"]
@@ -47,5 +79,15 @@ if __name__ == "__main__":
             run("workload2", synth.workload_pencil(2), reduce=False)
         elif w == "workload1":
             run("workload1", synth.workload_pencil(1), reduce=False)
+        elif w == "workload4":
+            run_batch("workload4", [(4, k, None, False) for k in range(64)],
+                      "all 64 pencils of workload 4 at full size")
+        elif w == "samples":
+            run_batch("workload5_sample", [(5, 0, 1000, False), (5, 1, 640, False)],
+                      "pencils 0 and 1 of workload 5 (J 4:1, s in [1e-6, 1]) downsized "
+                      "to n = 1000 and 640")
+            run_batch("workload3_sample", [(3, 0, 1024, True), (3, 0, 768, False)],
+                      "the workload-3 pencil (s in [1e-5, 1]) downsized to n = 1024 under "
+                      "J = I, and to n = 768 with its 3:1 signature")
         else:
             raise SystemExit(f"unknown {w}")

@@ -7,7 +7,7 @@ runs the same 2x2 steps two-sidedly.  Both are the same transformations in
 exact arithmetic, so one block sweep is compared element by element, for
 both inner orderings (all pivot pairs, Section 6.4.2; or cross-block pairs
 after the first block step of a sweep) and for the Full Block variant (inner
-sweeps until one applies no big transformation, at most 30).
+sweeps until one applies no transformation, big or small, at most 30).
 """
 import math
 
@@ -127,10 +127,11 @@ def test_mixed_fp32_stage_stops_before_cap_indefinite():
 @pytest.mark.parametrize("n,w,s_lo", [(96, 8, 1e-3), (96, 16, 1e-3), (70, 16, 1e-2), (41, 8, 1e-2),
                                        (192, 32, 1e-3), (150, 32, 1e-2)])
 def test_one_fb_block_sweep_elementwise(oracle, n, w, s_lo):
-    # FB: each block pivot's inner sweeps run until one applies no big
-    # transformation.  The two sides may end a block pivot's inner sweeps one
-    # sweep apart where a transformation sits at the big threshold, so the
-    # visited counts are compared loosely; the factors element by element.
+    # FB: each block pivot's inner sweeps run until one applies no
+    # transformation, big or small.  The two sides may end a block pivot's
+    # inner sweeps one sweep apart where a pivot entry sits at the threshold
+    # of (6.12), so the visited counts are compared loosely; the factors
+    # element by element.
     P = small(300 + n + w, n, s_lo)
     F, J, G = to_dev(P)
     Z = ghsvd.to_device_fortran(np.eye(n, dtype=np.complex128))

@@ -141,3 +141,28 @@ def test_full_rejects_n_beyond_largest_order():
         ghsvd.full(A, 1, A, A)
     assert e.value.status == -1  # GHSVD_EINVAL
 
+
+
+def test_full_caller_workspace(oracle):
+    # a caller-owned workspace of exactly ghsvd_full_workspace_size(n) bytes
+    # gives the same bits as the call that allocates its own; one byte short
+    # is GHSVD_ENOMEM; the workspace is reused by a second, smaller call
+    P = synth.workload_pencil(4, n_override=97)
+    st, Fp, Gp, Zp, _ = oracle.hz_run(P.F, P.J, P.G, max_sweeps=60)
+    assert st == 0
+    F, G, Z = dev(Fp), dev(Gp), dev(Zp)
+    ref = ghsvd.full(F, P.m_plus, G, Z)
+    nbytes = ghsvd.full_workspace_size(P.n)
+    work = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    out = ghsvd.full(F, P.m_plus, G, Z, work=work)
+    for a, b in zip(ref, out):
+        assert torch.equal(a, b)
+    with pytest.raises(ghsvd.GhsvdError) as e:
+        ghsvd.full(F, P.m_plus, G, Z, work=work[: nbytes - 256])
+    assert e.value.status == -4  # GHSVD_ENOMEM
+    Q = synth.workload_pencil(1)
+    st, Fq, Gq, Zq, _ = oracle.hz_run(Q.F, Q.J, Q.G, max_sweeps=60)
+    ref = ghsvd.full(dev(Fq), Q.m_plus, dev(Gq), dev(Zq))
+    out = ghsvd.full(dev(Fq), Q.m_plus, dev(Gq), dev(Zq), work=work)
+    for a, b in zip(ref, out):
+        assert torch.equal(a, b)

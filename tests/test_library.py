@@ -61,3 +61,11 @@ def test_status_strings(lib):
     from paper_1907_08560_amd import ghsvd
     for s in (0, 1, -1, -2, -3, -4, -5):
         assert ghsvd._lib.ghsvd_status_string(s)
+
+
+def test_full_workspace_size(lib):
+    from paper_1907_08560_amd import ghsvd
+    assert ghsvd.full_workspace_size(1024) >= 4 * 1024 * 1024 * 16
+    assert ghsvd.full_workspace_size(64) < ghsvd.full_workspace_size(65)
+    assert ghsvd.full_workspace_size(0) == 0
+    assert ghsvd.full_workspace_size(4097) == 0

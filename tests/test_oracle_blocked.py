@@ -1,6 +1,7 @@
 """Pins of the oracle's Level-2 blocked sweeps (Section 6.4): BO (one inner
 sweep per block pivot) under both inner orderings, and FB (inner sweeps until
-one applies no big transformation, at most 30).
+one applies no transformation at all, big or small, at most 30: Section
+6.1.7 on the inner levels of a blocked algorithm).
 
 Cross ordering: with full blocks, the first block step of a sweep visits all
 pairs inside every block and the other steps only the w x w pairs across the
@@ -65,3 +66,48 @@ def test_fb_on_one_block_pair_is_a_full_solve(oracle):
     assert off(H, dh) < 1e-13 and off(S, ds) < 1e-13
     st, F, G, Z, stats = oracle.hz_block_run(P.F, P.J, P.G, w=w, max_sweeps=60, inner_order=0)
     assert st == 0 and stats[0] > 2
+
+
+def shortened_pivot(o, F, J, G):
+    """The (J)QR-shortened block pivot (Section 6.4.2) of the columns of (F, G),
+    with the columns put back in pivot order: (F~, J^, G~), F~^* J^ F~ = F^* J F,
+    G~^* G~ = G^* G."""
+    st, A, Jh, perm, _, _ = o.jqr(F, J)
+    assert st == 0
+    st, R = o.qr(np.asfortranarray(G[:, perm]))
+    assert st == 0
+    c = F.shape[1]
+    Ft = np.zeros((c, c), dtype=np.complex128)
+    Gt = np.zeros((c, c), dtype=np.complex128)
+    Ft[:, perm] = A
+    Gt[:, perm] = R
+    return np.asfortranarray(Ft), Jh, np.asfortranarray(Gt)
+
+
+@pytest.mark.parametrize("seed,n,s_lo", [(917, 16, 1e-2), (919, 24, 1e-4), (921, 32, 1e-3)])
+def test_fb_inner_level_is_algorithm_2(oracle, seed, n, s_lo):
+    # n = 2w: the only block pivot is the whole pencil, so the FB inner level
+    # of the first block sweep is Algorithm 2 itself, run on the shortened
+    # pivot with the round-robin ordering and Algorithm 2's own stopping test
+    # (a sweep with no transformation, big or small).  The visited pairs, the
+    # number of inner sweeps and the accumulated Z^ must be those of the
+    # pointwise iteration with that test; the "no big transformation" test
+    # of the outer level stops earlier on these pencils.
+    w = n // 2
+    P = _pencil(seed, n, s_lo)
+    st, F, G, Z, stats = oracle.hz_block_run(P.F, P.J, P.G, w=w, max_sweeps=1, inner_order=2)
+    assert st in (0, 1)
+    Ft, Jh, Gt = shortened_pivot(oracle, P.F, P.J, P.G)
+    st1, _, _, Zp, s1 = oracle.hz_run(Ft, Jh, Gt, order=1, max_sweeps=30, stop_rule=1)
+    st0, _, _, _, s0 = oracle.hz_run(Ft, Jh, Gt, order=1, max_sweeps=30, stop_rule=0)
+    assert st1 == 0 and s1[4] == 0
+    pairs = n * (n - 1) // 2
+    assert stats[1] == s1[1] == s1[0] * pairs
+    assert stats[5] == s1[0]
+    assert stats[2] == s1[2] and stats[3] == s1[3]
+    assert s0[0] < s1[0]  # the two stopping tests differ on this pencil
+    # F = F_in Z^, G = G_in Z^, Z = Z^ with Z^ the pointwise run's accumulation
+    for A, B in ((F, P.F @ Zp), (G, P.G @ Zp), (Z, Zp)):
+        err = np.max(np.abs(A - B)) / np.max(np.abs(B))
+        assert err < 1e-12, err
+

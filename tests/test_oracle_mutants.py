@@ -1,6 +1,6 @@
 """Planted mistakes in the oracle must be caught by its pins.
 
-hz_oracle.c carries compile-time switches ORA_MUTANT = 1..14, each a
+hz_oracle.c carries compile-time switches ORA_MUTANT = 1..15, each a
 plausible slip (a sign, a conjugate, a transposed operand, a dropped scaling,
 a wrong index, a skipped pivoting rule).  This test builds each variant on the
 CPU and runs a compact battery of the same independent checks the pin tests
@@ -16,7 +16,7 @@ from oracle import oracle as O
 from paper_1907_08560_amd import synth
 
 EPS = 2.0 ** -52
-MUTANTS = list(range(1, 15))
+MUTANTS = list(range(1, 16))
 
 
 def battery(o):
@@ -87,6 +87,20 @@ def battery(o):
         if np.abs(GX.conj().T @ GX - np.eye(P.n)).max() > 1e-9 or \
                 np.abs(np.real(np.diag(Hx)) - lam).max() > 1e-9 * np.abs(lam).max():
             fails.append(f"inv{int(reduce)}")
+    # Full Block inner level on a pencil of one block pair: Algorithm 2 with
+    # its own stopping test (no transformation) on the (J)QR-shortened pivot
+    Q = synth.random_pencil(103, 16, 24, 18, 32, 1e-2)
+    st, Fb, Gb, Zb, sb = o.hz_block_run(Q.F, Q.J, Q.G, w=8, max_sweeps=1, inner_order=2)
+    st_, A, Jh, perm, _, _ = o.jqr(Q.F, Q.J)
+    st2, R = o.qr(np.asfortranarray(Q.G[:, perm]))
+    Ft = np.zeros((16, 16), dtype=complex)
+    Gt = np.zeros((16, 16), dtype=complex)
+    Ft[:, perm] = A
+    Gt[:, perm] = R
+    st3, _, _, _, s3 = o.hz_run(np.asfortranarray(Ft), Jh, np.asfortranarray(Gt), order=1,
+                                max_sweeps=30, stop_rule=1)
+    if st < 0 or st3 != 0 or sb[1] != s3[1]:
+        fails.append("fb")
     return fails
 
 
