@@ -241,6 +241,36 @@ int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, doub
                        int crit_literal, long long *counters, int *sweeps_done, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (serving loops, harnesses
+ * that forbid hipMalloc): ghsvd_block_sweeps with the same arguments, results
+ * and errors, bit for bit, but without any allocation.  Its scratch
+ * (descriptor, done flags, sweep state, counters, partial Grams, block
+ * transforms) lives in a library-owned device array of
+ * GHSVD_NOALLOC_SCRATCH_BYTES, one copy per GPU, which the library holds
+ * until the process ends; the call uses the copy of the current device and
+ * looks its address up on the first call there.  F, G, Z are the caller's
+ * and swept in place, as in ghsvd_block_sweeps.  The call launches its rounds
+ * directly on `stream` (no captured graph, internal stream or timing events)
+ * and reads the done flags on the host after every round, so it cannot
+ * itself be captured into a graph.
+ * Limit: the scratch a call needs grows as (n / w) (m / c + p / c) (2 w)^2
+ * complex128 (c = 256 rows, 128 at w = 32) plus O(m + n); a pencil whose need
+ * exceeds GHSVD_NOALLOC_SCRATCH_BYTES is rejected with GHSVD_ENOMEM before
+ * any work is enqueued (square n = 1024 at every width fits, and n = 2048 at
+ * w = 8 and 16).
+ * Calls on one GPU share its array, which keeps the last call's contents (the
+ * call clears every counter and state it reads before using it): two calls
+ * that overlapped on one GPU would race, so within a process the library
+ * holds a per-device lock for the whole call and such calls run one after
+ * the other.
+ */
+#define GHSVD_NOALLOC_SCRATCH_BYTES (32u << 20)
+int ghsvd_block_sweeps_noalloc(int m, int n, int p, double *F, int ldf, int n_plus, double *G,
+                               int ldg, double *Z, int ldz, int block_width, int inner_order,
+                               int nsweeps, int crit_literal, long long *counters,
+                               int *sweeps_done, void *stream);
+
+/*
  * Full GHSVD from a finished sweep stage (Phase 4, Section 7, with the
  * outputs of Section 6.1).  Inputs (device, column-major complex128 as
  * interleaved re/im doubles, not modified): the swept F' (m x n, rows

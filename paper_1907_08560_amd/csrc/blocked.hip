@@ -1435,23 +1435,25 @@ struct BlockedArg {
 
 static int blocked_step(const BatchCtx &c, const void *arg, int step, hipStream_t s) {
     const BlockedArg *a = static_cast<const BlockedArg *>(arg);
-    hipEvent_t e0, e1;
-    prof_before(kProfGram, s, e0, e1);
+    // kernel timing events are taken unless the batch is plain (no events)
+    const bool tm = !c.plain;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (tm) prof_before(kProfGram, s, e0, e1);
     hipLaunchKernelGGL(a->gram, dim3(c.total(BatchCtx::kGram)),
                        dim3(a->gsum ? kWave * kG64Tiles : kWave * kGramWaves), 0, s, c.dev,
                        c.pre_of(BatchCtx::kGram), c.flag_dev, c.B, step);
     if (a->gsum)
         hipLaunchKernelGGL(a->gsum, dim3(c.total(BatchCtx::kBp), 2 * kG64Tiles), dim3(256), 0, s,
                            c.dev, c.pre_of(BatchCtx::kBp), c.flag_dev, c.B, step);
-    prof_after(kProfGram, s, e0, e1);
-    prof_before(kProfInner, s, e0, e1);
+    if (tm) prof_after(kProfGram, s, e0, e1);
+    if (tm) prof_before(kProfInner, s, e0, e1);
     hipLaunchKernelGGL(a->inner, dim3(c.total(BatchCtx::kBp)), dim3(a->inner_nt), 0, s, c.dev,
                        c.pre_of(BatchCtx::kBp), c.flag_dev, c.B, a->crit, step, a->mode);
-    prof_after(kProfInner, s, e0, e1);
-    prof_before(kProfUpdate, s, e0, e1);
+    if (tm) prof_after(kProfInner, s, e0, e1);
+    if (tm) prof_before(kProfUpdate, s, e0, e1);
     hipLaunchKernelGGL(a->upd, dim3(c.total(BatchCtx::kUpd)), dim3(256), 0, s, c.dev,
                        c.pre_of(BatchCtx::kUpd), c.flag_dev, c.B, step);
-    prof_after(kProfUpdate, s, e0, e1);
+    if (tm) prof_after(kProfUpdate, s, e0, e1);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }

@@ -407,7 +407,7 @@ int drive_stage(const BatchCtx &c, int max_sweeps, int noise_floor, int blocked,
     const int B = c.B;
     res.assign(B, SweepResult{GHSVD_OK, 0, 0, 0, 0, 0});
     RoundGraph rg;
-    if (!prof_active() && !std::getenv("GHSVD_NO_GRAPH") &&
+    if (!c.plain && !prof_active() && !std::getenv("GHSVD_NO_GRAPH") &&
         !capture_round(c, one_step, arg, steps_per_round, blocked, rg)) {
         (void)hipGetLastError();
         if (rg.exec) (void)hipGraphExecDestroy(rg.exec);
@@ -485,11 +485,11 @@ struct PointwiseArg {
 static int pointwise_step(const BatchCtx &c, const void *arg, int step, hipStream_t s) {
     const PointwiseArg *a = static_cast<const PointwiseArg *>(arg);
     const int kind = a->fp32 ? kProfPair32 : kProfPair64;
-    hipEvent_t e0, e1;
-    prof_before(kind, s, e0, e1);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (!c.plain) prof_before(kind, s, e0, e1);
     hipLaunchKernelGGL(a->fn, dim3(c.total(BatchCtx::kSlots)), dim3(a->g.nt), 0, s, c.dev,
                        c.pre_of(BatchCtx::kSlots), c.flag_dev, c.B, a->crit, step);
-    prof_after(kind, s, e0, e1);
+    if (!c.plain) prof_after(kind, s, e0, e1);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }

@@ -73,9 +73,11 @@ void carve_pencil(Carver &c, const Plan &pl, PencilDev &d) {
     d.Jw = c.take<int8_t>(2 * (size_t)pl.m);
     d.rowmap = c.take<int>(pl.m > n ? pl.m : n);
     d.perm = c.take<int>(n);
-    d.Fw = c.take<double2>((size_t)pl.ldf * n);
-    d.Gw = c.take<double2>((size_t)pl.ldg * n);
-    d.Zw = c.take<double2>((size_t)pl.ldz * n);
+    if (!pl.inplace) {
+        d.Fw = c.take<double2>((size_t)pl.ldf * n);
+        d.Gw = c.take<double2>((size_t)pl.ldg * n);
+        d.Zw = c.take<double2>((size_t)pl.ldz * n);
+    }
     d.st = c.take<SweepState>(1);
     d.slot_cnt = c.take<unsigned long long>(3 * (size_t)(pl.N / 2 + 1));
     d.lam_tmp = c.take<double>(n);
@@ -430,30 +432,50 @@ struct OwnedBatch {
     }
 };
 
-static int make_inplace_batch(OwnedBatch &ob, int m, int n, int p, double *F, int ldf, double *G,
-                              int ldg, double *Z, int ldz, int blocked, int w, hipStream_t s) {
+// Plan of a one-pencil batch swept in place on the caller's F, G, Z.
+static Plan inplace_plan(int m, int n, int p, int blocked, int w) {
     ghsvd_options o;
     fill_options(nullptr, o);
     o.reduce = 0;
     o.variant = blocked ? GHSVD_BLOCKED : GHSVD_POINTWISE;
     Plan pl = make_plan(m, n, p, o, w);
-    const size_t need = batch_bytes(1) + pencil_bytes(pl);
-    GHSVD_HIP(hipMalloc(&ob.buf, need));
-    Carver c{reinterpret_cast<char *>(ob.buf), 0, need};
-    carve_batch(c, ob.bc, 1);
-    ob.bc.B = 1;
-    ob.bc.host.resize(1);
-    PencilDev &d = ob.bc.host[0];
+    pl.inplace = 1;
+    return pl;
+}
+
+static size_t inplace_bytes(int m, int n, int p, int blocked, int w) {
+    return batch_bytes(1) + pencil_bytes(inplace_plan(m, n, p, blocked, w));
+}
+
+// Carves a one-pencil in-place batch from buf (cap bytes, 256-byte aligned)
+// and uploads its descriptor.
+static int inplace_batch_at(BatchCtx &bc, void *buf, size_t cap, int m, int n, int p, double *F,
+                            int ldf, double *G, int ldg, double *Z, int ldz, int blocked, int w,
+                            hipStream_t s) {
+    const Plan pl = inplace_plan(m, n, p, blocked, w);
+    Carver c{reinterpret_cast<char *>(buf), 0, cap};
+    carve_batch(c, bc, 1);
+    bc.B = 1;
+    bc.host.resize(1);
+    PencilDev &d = bc.host[0];
     d = PencilDev{};
     c.used = align_up(c.used, 256);
     carve_pencil(c, pl, d);
+    if (!c.ok()) return GHSVD_ENOMEM;
     d.Fw = reinterpret_cast<double2 *>(F);
     d.ldf = ldf;
     d.Gw = reinterpret_cast<double2 *>(G);
     d.ldg = ldg;
     d.Zw = reinterpret_cast<double2 *>(Z);
     d.ldz = ldz;
-    return upload_batch(ob.bc, s);
+    return upload_batch(bc, s);
+}
+
+static int make_inplace_batch(OwnedBatch &ob, int m, int n, int p, double *F, int ldf, double *G,
+                              int ldg, double *Z, int ldz, int blocked, int w, hipStream_t s) {
+    const size_t need = inplace_bytes(m, n, p, blocked, w);
+    GHSVD_HIP(hipMalloc(&ob.buf, need));
+    return inplace_batch_at(ob.bc, ob.buf, need, m, n, p, F, ldf, G, ldg, Z, ldz, blocked, w, s);
 }
 
 __global__ void k_set_nplus(const PencilDev *PD, int nplus) { PD[0].small[1] = nplus; }
@@ -707,29 +729,100 @@ extern "C" int ghsvd_sweeps(int m, int n, int p, double *F, int ldf, int n_plus,
     return res[0].status;
 }
 
+static int block_sweeps_args_ok(int m, int n, int p, const double *F, int ldf, int n_plus,
+                                const double *G, int ldg, const double *Z, int ldz,
+                                int block_width, int inner_order, int nsweeps) {
+    if (n < 4 || m < 1 || p < 1 || ldf < m || ldg < p || ldz < n || nsweeps < 1 ||
+        nsweeps > kMaxHist || n_plus < 0 || n_plus > m || !F || !G || !Z)
+        return 0;
+    if (block_width != 0 && block_width != 8 && block_width != 16 && block_width != 32) return 0;
+    return inner_order == GHSVD_INNER_FULL || inner_order == GHSVD_INNER_CROSS ||
+           inner_order == GHSVD_INNER_FB;
+}
+
+// The blocked stage on a prepared one-pencil in-place batch.
+static int block_sweeps_on(const BatchCtx &bc, int n_plus, int inner_order, int nsweeps,
+                           int crit_literal, long long *counters, int *sweeps_done,
+                           hipStream_t s) {
+    hipLaunchKernelGGL(k_set_nplus, dim3(1), dim3(1), 0, s, bc.dev, n_plus);
+    GHSVD_HIP(hipGetLastError());
+    std::vector<SweepResult> res;
+    int rc = run_blocked_stage(bc, 0, nsweeps, crit_literal, inner_order, s, res);
+    if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) return rc;
+    if ((rc = copy_counters(bc, nsweeps, counters, sweeps_done, s))) return rc;
+    return res[0].status;
+}
+
 extern "C" int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, double *G,
                                   int ldg, double *Z, int ldz, int block_width, int inner_order,
                                   int nsweeps, int crit_literal, long long *counters,
                                   int *sweeps_done, void *stream) {
-    if (n < 4 || m < 1 || p < 1 || ldf < m || ldg < p || ldz < n || nsweeps < 1 ||
-        nsweeps > kMaxHist || n_plus < 0 || n_plus > m || !F || !G || !Z)
-        return GHSVD_EINVAL;
-    if (block_width != 0 && block_width != 8 && block_width != 16 && block_width != 32)
-        return GHSVD_EINVAL;
-    if (inner_order != GHSVD_INNER_FULL && inner_order != GHSVD_INNER_CROSS &&
-        inner_order != GHSVD_INNER_FB)
+    if (!block_sweeps_args_ok(m, n, p, F, ldf, n_plus, G, ldg, Z, ldz, block_width, inner_order,
+                              nsweeps))
         return GHSVD_EINVAL;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     OwnedBatch ob;
     int rc = make_inplace_batch(ob, m, n, p, F, ldf, G, ldg, Z, ldz, 1,
                                 pick_block_width(n, block_width), s);
     if (rc) return rc;
-    hipLaunchKernelGGL(k_set_nplus, dim3(1), dim3(1), 0, s, ob.bc.dev, n_plus);
-    std::vector<SweepResult> res;
-    rc = run_blocked_stage(ob.bc, 0, nsweeps, crit_literal, inner_order, s, res);
-    if (rc < 0 && rc != GHSVD_ERANK && rc != GHSVD_ENONFINITE) return rc;
-    if ((rc = copy_counters(ob.bc, nsweeps, counters, sweeps_done, s))) return rc;
-    return res[0].status;
+    return block_sweeps_on(ob.bc, n_plus, inner_order, nsweeps, crit_literal, counters,
+                           sweeps_done, s);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free blocked sweeps.  All scratch of ghsvd_block_sweeps_noalloc
+// (descriptor, prefix sums, done flags, sweep state, counters, partial Grams,
+// block transforms) is carved from this library-owned device array: one copy
+// per GPU, held until the process ends.  In host code the array's name is a
+// host-side stand-in, not a device address; the address of the current
+// device's copy comes from hipGetSymbolAddress, once per device, and only
+// that address is passed to kernels and copies.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[GHSVD_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu[kMaxDevices];  // held for a whole call on that device
+void *g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of the current device's scratch copy (looked up on the
+// first call on each device).  The caller holds g_scratch_mu[dev].
+static int scratch_address(int dev, void **ptr) {
+    if (!g_scratch_ptr[dev]) {
+        void *a = nullptr;
+        if (hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)) != hipSuccess || !a)
+            return GHSVD_EDEVICE;
+        g_scratch_ptr[dev] = a;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return GHSVD_OK;
+}
+
+extern "C" int ghsvd_block_sweeps_noalloc(int m, int n, int p, double *F, int ldf, int n_plus,
+                                          double *G, int ldg, double *Z, int ldz, int block_width,
+                                          int inner_order, int nsweeps, int crit_literal,
+                                          long long *counters, int *sweeps_done, void *stream) {
+    if (!block_sweeps_args_ok(m, n, p, F, ldf, n_plus, G, ldg, Z, ldz, block_width, inner_order,
+                              nsweeps))
+        return GHSVD_EINVAL;
+    const int w = pick_block_width(n, block_width);
+    if (inplace_bytes(m, n, p, 1, w) > (size_t)GHSVD_NOALLOC_SCRATCH_BYTES) return GHSVD_ENOMEM;
+    int dev = -1;
+    GHSVD_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return GHSVD_EDEVICE;
+    std::lock_guard<std::mutex> lk(g_scratch_mu[dev]);
+    void *buf = nullptr;
+    int rc = scratch_address(dev, &buf);
+    if (rc) return rc;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    BatchCtx bc;
+    bc.plain = true;
+    if ((rc = inplace_batch_at(bc, buf, GHSVD_NOALLOC_SCRATCH_BYTES, m, n, p, F, ldf, G, ldg, Z,
+                               ldz, 1, w, s)))
+        return rc;
+    return block_sweeps_on(bc, n_plus, inner_order, nsweeps, crit_literal, counters, sweeps_done,
+                           s);
 }
 
 extern "C" int ghsvd_autotune(int batch, const int *m, const int *n, const int *p,

@@ -19,6 +19,7 @@ struct Plan {
     int mixed;         // FP32 warm-up stage
     int blocked;       // Level-2 blocked stage
     int w;             // block width (blocked or mixed)
+    int inplace;       // the sweep buffers F, G, Z are the caller's: carve no copies
 };
 
 Plan make_plan(int m, int n, int p, const ghsvd_options &o, int block_width);

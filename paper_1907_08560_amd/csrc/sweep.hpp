@@ -39,6 +39,8 @@ struct BatchCtx {
     int *done_dev = nullptr;        // device [2 (B + 1)] small per-pencil results for the host
     int *flag_dev = nullptr;        // device [B] 1: the pencil's sweep stage is done (read by
                                     // every sweep kernel, written at the end of each round)
+    bool plain = false;             // launch rounds directly on the caller's stream: no
+                                    // captured graph, internal stream or timing events
 };
 
 // Rows of the reduction's column-window table (see run_reduction).

@@ -77,6 +77,9 @@ _lib.ghsvd_sweeps.restype = _i
 _lib.ghsvd_block_sweeps.argtypes = [_i, _i, _i, _p, _i, _i, _p, _i, _p, _i, _i, _i, _i, _i, _p,
                                     ctypes.POINTER(_i), _p]
 _lib.ghsvd_block_sweeps.restype = _i
+_lib.ghsvd_block_sweeps_noalloc.argtypes = _lib.ghsvd_block_sweeps.argtypes
+_lib.ghsvd_block_sweeps_noalloc.restype = _i
+NOALLOC_SCRATCH_BYTES = 32 << 20  # GHSVD_NOALLOC_SCRATCH_BYTES
 _lib.ghsvd_round_robin.argtypes = [_i, _p, _p]
 _lib.ghsvd_round_robin.restype = _i
 _lib.ghsvd_profile_enable.argtypes = [_i]
@@ -101,7 +104,8 @@ EXPORTED = ["ghsvd_default_options", "ghsvd_workspace_size", "ghsvd_solve",
             "ghsvd_workspace_size_batched", "ghsvd_solve_batched", "ghsvd_reduce",
             "ghsvd_pair_params", "ghsvd_sweeps", "ghsvd_round_robin", "ghsvd_status_string",
             "ghsvd_profile_enable", "ghsvd_profile_read", "ghsvd_block_sweeps",
-            "ghsvd_autotune", "ghsvd_autotune_clear", "ghsvd_full", "ghsvd_full_workspace_size"]
+            "ghsvd_autotune", "ghsvd_autotune_clear", "ghsvd_full", "ghsvd_full_workspace_size",
+            "ghsvd_block_sweeps_noalloc"]
 
 
 class GhsvdError(RuntimeError):
@@ -265,18 +269,20 @@ def sweeps(F, n_plus: int, G, Z, nsweeps: int, waves_per_pair=0, crit_literal=0,
 
 
 def block_sweeps(F, n_plus: int, G, Z, nsweeps: int, block_width=0, crit_literal=0,
-                 inner_order="cross", stream=None):
-    """In-place Level-2 blocked FP64 sweeps; returns (status, sweeps_done, counters (nsweeps, 3))."""
+                 inner_order="cross", stream=None, noalloc=False):
+    """In-place Level-2 blocked FP64 sweeps; returns (status, sweeps_done, counters (nsweeps, 3)).
+    noalloc=True calls ghsvd_block_sweeps_noalloc (scratch in the library's static array)."""
     m, n = F.shape
     p = G.shape[0]
     cnt = np.zeros(3 * nsweeps, dtype=np.int64)
     done = ctypes.c_int(0)
-    rc = _lib.ghsvd_block_sweeps(m, n, p, F.data_ptr(), _check_fortran(F, "F"), int(n_plus),
-                                 G.data_ptr(), _check_fortran(G, "G"), Z.data_ptr(),
-                                 _check_fortran(Z, "Z"), int(block_width), INNER[inner_order],
-                                 int(nsweeps),
-                                 int(crit_literal), cnt.ctypes.data, ctypes.byref(done),
-                                 _stream_ptr(stream))
+    fn = _lib.ghsvd_block_sweeps_noalloc if noalloc else _lib.ghsvd_block_sweeps
+    rc = fn(m, n, p, F.data_ptr(), _check_fortran(F, "F"), int(n_plus),
+            G.data_ptr(), _check_fortran(G, "G"), Z.data_ptr(),
+            _check_fortran(Z, "Z"), int(block_width), INNER[inner_order],
+            int(nsweeps),
+            int(crit_literal), cnt.ctypes.data, ctypes.byref(done),
+            _stream_ptr(stream))
     return rc, done.value, cnt.reshape(nsweeps, 3)
 
 
