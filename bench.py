@@ -1,26 +1,33 @@
-"""Benchmark: whole-solve throughput of the HZ-GHSVD path on one MI355X.
+"""Benchmark: batched throughput of the HZ-GHSVD path on one MI355X.
 
-A "step" is one complete ghsvd_solve of the n = 1024 pencil (F 1536 x 1024
-with J = diag(+1 x1152, -1 x384), G 2048 x 1024 = U diag(s) W^* with s
-log-uniform in [1e-8, 1], so cond(G^* G) = 1e16; complex128): input checks,
-one-time reduction (hyperbolic QR of F, QR of G), the sweep stages of the
-chosen path (default: Level-2 blocked FP64 sweeps until a sweep has no big
-transformation), and the outputs lambda, X.  Inputs are resident in HBM
-before the timed region.  Prints one JSON line.
+Default (the headline): a "step" is one ghsvd_solve_batched call on 64
+k-point pencils of uneven order (n_k uniform in [300, 900]; F ceil(1.5 n_k) x
+n_k Gaussian with a 3:1 signature; G 2 n_k x n_k = U diag(s) W^* with s
+log-uniform in [1e-6, 1], so cond(G^* G) <= 1e12; complex128): input checks,
+one-time reduction of every pencil (hyperbolic QR of F, QR of G), complex
+FP32 blocked warm-up sweeps, the hand-off to FP64, FP64 blocked sweeps to
+convergence, and the outputs lambda, X.  Inputs are resident in HBM before
+the timed region.  `value` is pencils/s of that mixed-precision path.  Prints
+one JSON line.
 
-Beside the timed path it reports:
-  * per sweep-kernel kind, the mean launch time measured with HIP events on
-    the launch stream over the timed region, and its roofline;
-  * the error of lambda against the stored oracle eigenvalues of this pencil;
-  * the other paths on the same pencil (plain FP64 pointwise; mixed FP32 ->
-    FP64), with their times and errors;
-  * the CPU oracle on a bounded sample (reduction + one sweep, extrapolated);
-  * the full GHSVD (Phase 4: U, V, Sigma_F, Sigma_G, X = Z^{-1}) of the swept
-    square factors, timed alone, with the relative errors (7.1).
+Beside it the line reports:
+  * the plain FP64 blocked and FP64 pointwise paths on the same batch (ms per
+    batch, sweeps, the largest lambda difference from FP64 blocked);
+  * every path's lambda error against the stored oracle eigenvalues;
+  * per kernel kind (FP32 and FP64 Gram, inner sweep, update; the reduction's
+    column step), the mean launch time measured with HIP events on the launch
+    stream over the timed region, and its roofline; `roofline` is the
+    dominant kernel of the headline path;
+  * the CPU oracle on a bounded sample of the batch, in a process pool;
+  * the single n = 1024 pencil at cond(S) = 1e16 (FP64 and mixed blocked, and
+    the full GHSVD of its swept factors with the errors (7.1)).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp64|mixed]
-                    [--variant blocked|pointwise] [--no-compare] [--no-cpu-baseline]
-                    [--no-full]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 4|2|3|5]
+                    [--block-width 0|8|16|32] [--inner cross|full|fb]
+                    [--no-compare] [--no-cpu-baseline] [--no-workload2] [--no-full]
+
+--workload 2 times single solves of the n = 1024 pencil on one path
+(--precision, --variant); 3 and 5 time the large pencils on the blocked paths.
 """
 import argparse
 import hashlib
@@ -39,6 +46,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_MFMA_PEAK_TF = 78.6       # dense FP64 matrix
 FP32_MFMA_PEAK_TF = 157.3      # dense FP32 matrix
 FP64_VALU_PEAK_TF = 78.6       # FP64 vector
+FP32_VALU_PEAK_TF = 157.3      # FP32 vector
 GOLDEN = os.path.join(ROOT, "tests", "golden", "workload2_lambda.json")
 TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
 
@@ -57,61 +65,14 @@ def block_width_for(n):
     return 16 if n >= 512 else 8
 
 
-def kernel_rooflines(times, info_sum, mr, pr, n, w, nbp, fp32_blocked=False):
-    """Per-kind roofline over the timed region.  times[kind] = (ms, timed, launches)."""
-    out = {}
-    c = 2 * w
-    for kind, (ms, timed, launches) in times.items():
-        if timed == 0 or launches == 0:
-            continue
-        mean_s = ms / timed * 1e-3
-        rec = {"mean_us": mean_s * 1e6, "launches": launches, "timed_launches": timed,
-               "total_ms_est": mean_s * launches * 1e3}
-        if kind in ("pair64", "pair32"):
-            vis, tr = info_sum["pw_visited"], info_sum["pw_transformed"]
-            if kind == "pair32":  # FP32 pair stage counters are not separated; skip
-                continue
-            b = pair_bytes(vis, tr, mr, pr, n) / launches
-            rec.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
-                       achieved=b / mean_s / 1e9, units_per_launch=vis / launches,
-                       work_per_launch=b, work_unit="bytes")
-        elif kind in ("gram", "update"):
-            bsz = 8 if fp32_blocked else 16
-            if kind == "gram":
-                flops = 4.0 * c * c * (mr + pr) * nbp           # Hermitian Grams: 8 c^2 rows / 2
-                byts = c * bsz * (mr + pr) * nbp                # block columns read once
-            else:
-                flops = 8.0 * c * c * (mr + pr + n) * nbp       # three complex GEMMs
-                byts = 2.0 * c * bsz * (mr + pr + n) * nbp      # block columns read + written
-            peak_tf = FP32_MFMA_PEAK_TF if fp32_blocked else FP64_MFMA_PEAK_TF
-            t_mfma = flops / (peak_tf * 1e12)
-            t_hbm = byts / (HBM_PEAK_GBS * 1e9)
-            if t_hbm >= t_mfma:
-                rec.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
-                           achieved=byts / mean_s / 1e9, work_per_launch=byts, work_unit="bytes")
-            else:
-                rec.update(bound="mfma", unit="TFLOP/s", peak=peak_tf,
-                           achieved=flops / mean_s / 1e12, work_per_launch=flops,
-                           work_unit="flops")
-            rec["units_per_launch"] = nbp
-        elif kind == "inner":
-            # two-sided 2x2-block updates of H^ and S^ (128 flops each) and the
-            # accumulation into Z^ (64 flops), (c/2)^2 blocks per inner step,
-            # c - 1 inner steps per block pair
-            flops = 320.0 * (c * c / 4.0) * (c - 1) * nbp
-            rec.update(bound="alu", unit="TFLOP/s", peak=FP64_VALU_PEAK_TF,
-                       achieved=flops / mean_s / 1e12, work_per_launch=flops, work_unit="flops",
-                       units_per_launch=nbp, us_per_inner_step=mean_s * 1e6 / (c - 1))
-        rec["frac"] = rec["achieved"] / rec["peak"]
-        rec["traffic"] = stored_traffic(kind)
-        out[kind] = rec
-    return out
-
-
 KERNEL_NAMES = {"pair64": "k_pair<double> (pointwise FP64 pair kernel)",
-                "gram": "k_blk_gram (block-pivot Grams, MFMA)",
-                "inner": "k_blk_inner (inner 2x2 sweep of a block pivot, LDS)",
-                "update": "k_blk_update (block-column update, MFMA)"}
+                "gram": "k_blk_gram<double> (block-pivot Grams, MFMA)",
+                "inner": "k_blk_inner (inner 2x2 sweep of a block pivot, LDS; FP64 stage)",
+                "update": "k_blk_update<double> (block-column update, MFMA)",
+                "gram32": "k_blk_gram<float> (block-pivot Grams, FP32 MFMA)",
+                "inner32": "k_blk_inner (inner 2x2 sweep of a block pivot, LDS; FP32 stage)",
+                "update32": "k_blk_update<float> (block-column update, FP32 MFMA)",
+                "reduce": "one-time reduction column step (k_jqr_cross, k_jqr_cross2, k_jqr_step)"}
 
 
 def stored_traffic(kind):
@@ -222,55 +183,322 @@ def run_path(ghsvd, F, J, G, P, kw, steps, warmup, profile_every=0):
     return dt, infos, lam.cpu().numpy(), times
 
 
+GOLDEN4 = os.path.join(ROOT, "tests", "golden", "workload4_lambda.json")
+
+
+def golden_batch(path, Ps):
+    """Stored oracle eigenvalues of a batch, by pencil (None where the stored
+    input fingerprint does not match)."""
+    try:
+        with open(path) as f:
+            recs = {r["k"]: r for r in json.load(f)["pencils"]}
+    except (OSError, ValueError, KeyError):
+        return None, None
+    lams, sweeps = [], []
+    for k, P in enumerate(Ps):
+        r = recs.get(k)
+        ok = r is not None and r["n"] == P.n and abs(
+            r["fingerprint"][0] - float(np.abs(P.F).sum())) <= 1e-9 * r["fingerprint"][0]
+        if ok:
+            lam = np.asarray([float(v) for v in r["lambda"]])
+            kap = np.asarray(r.get("kappa_h", np.ones_like(lam)), dtype=np.float64)
+            # the parity tests' gate: 1e-10, plus the cancellation in h_j of an
+            # eigenvalue near zero (kappa_j = ||F x_j||^2 / |lambda_j|)
+            lams.append((lam, 1e-10 + 4.0 * np.sqrt(float(P.m) * P.n) * 2.0 ** -52 * kap))
+        else:
+            lams.append(None)
+        sweeps.append(r["sweeps"] if ok else None)
+    return lams, sweeps
+
+
+def batch_errors(lams, ref):
+    """max and median over all eigenvalues of all pencils of |lam - ref| / |ref|,
+    and the largest ratio of that error to the parity tests' per-eigenvalue gate."""
+    es, rs = [], []
+    for a, r in zip(lams, ref):
+        if r is None:
+            continue
+        e = np.abs(a - r[0]) / np.abs(r[0])
+        es.append(e)
+        rs.append(e / r[1])
+    if not es:
+        return None
+    e = np.concatenate(es)
+    return {"max": float(e.max()), "median": float(np.median(e)), "pencils": len(es),
+            "max_over_gate": float(np.concatenate(rs).max())}
+
+
+def block_schedule(n, w):
+    """Blocks (rounded up to even), block pairs per step and block steps per sweep."""
+    nb = -(-n // w)
+    nb += nb & 1
+    return nb, nb // 2, nb - 1
+
+
+def batch_rooflines(times, infos, w, inner_order, steps, fp32_blocked=True):
+    """Per-kind roofline of a batched path over the timed region (`steps`
+    solves).  The algorithmic work of a kind is counted from each pencil's
+    block schedule and its sweep counts (info): every block pair of every
+    block step of a sweep (the update kernel skips a pair only when its inner
+    sweep transformed nothing, which the sweep counters show to be rare), in
+    the precision of the stage.  Per launch it is that total over all launches
+    of the kind (pencils that have retired or have fewer block steps idle in a
+    launch), divided by the sampled mean launch time."""
+    c = 2 * w
+    tot = {}
+    for inf in infos:
+        n = inf["n"]
+        mr, pr = inf["m_r"], inf["p_r"]
+        nb, nbp, bsteps = block_schedule(n, w)
+        # sweeps_blocked counts the blocked sweeps of both stages
+        s32 = inf["sweeps_fp32"] if fp32_blocked else 0
+        for kind32, sweeps in ((True, s32), (False, inf["sweeps_blocked"] - s32)):
+            if sweeps <= 0:
+                continue
+            bsz = 8 if kind32 else 16
+            pairs = sweeps * bsteps * nbp
+            sfx = "32" if kind32 else ""
+            g = tot.setdefault("gram" + sfx, [0.0, 0.0])
+            g[0] += pairs * c * bsz * (mr + pr)                 # block columns read once
+            g[1] += pairs * 4.0 * c * c * (mr + pr)             # Hermitian Grams
+            u = tot.setdefault("update" + sfx, [0.0, 0.0])
+            u[0] += pairs * 2.0 * c * bsz * (mr + pr + n)       # block columns read + written
+            u[1] += pairs * 8.0 * c * c * (mr + pr + n)         # three complex GEMMs
+            # inner: two-sided 2x2-block updates of H^, S^ (128 flops each) and
+            # the accumulation into Z^ (64 flops) for (c/2)^2 blocks per inner
+            # step; 2w - 1 inner steps at block step 0 and w at the others in
+            # the cross ordering, 2w - 1 at every step in the full one
+            later = w if inner_order == "cross" else c - 1
+            isteps = sweeps * nbp * ((c - 1) + (bsteps - 1) * later)
+            i = tot.setdefault("inner" + sfx, [0.0, 0.0])
+            i[1] += isteps * 320.0 * (c * c / 4.0)
+        if inf.get("pw_visited"):
+            r = tot.setdefault("pair64", [0.0, 0.0])
+            r[0] += pair_bytes(inf["pw_visited"], inf["pw_transformed"], mr, pr, n)
+        if inf.get("reduced"):
+            m, p = inf["m"], inf["p"]
+            t = np.arange(n, dtype=np.float64)
+            r = tot.setdefault("reduce", [0.0, 0.0])
+            # one read and one write of the trailing columns of F and G per column step
+            r[0] += float(np.sum(32.0 * (m + p - 2 * t) * (n - t)))
+    out = {}
+    for kind, (ms, timed, launches) in times.items():
+        if timed == 0 or launches == 0 or kind not in tot:
+            continue
+        mean_s = ms / timed * 1e-3
+        byts, flops = (v * steps / launches for v in tot[kind])
+        rec = {"mean_us": mean_s * 1e6, "launches": launches, "timed_launches": timed,
+               "total_ms_est": mean_s * launches * 1e3}
+        fp32 = kind.endswith("32")
+        peak_tf = FP32_MFMA_PEAK_TF if fp32 else FP64_MFMA_PEAK_TF
+        if kind.startswith("inner"):
+            rec.update(bound="alu", unit="TFLOP/s", peak=FP32_VALU_PEAK_TF if fp32 else
+                       FP64_VALU_PEAK_TF, achieved=flops / mean_s / 1e12,
+                       work_per_launch=flops, work_unit="flops",
+                       note="latency-bound inner sweep; reported as time, ALU fraction for context")
+        elif kind == "reduce" or byts / (HBM_PEAK_GBS * 1e9) >= flops / (peak_tf * 1e12):
+            rec.update(bound="hbm", unit="GB/s", peak=HBM_PEAK_GBS,
+                       achieved=byts / mean_s / 1e9, work_per_launch=byts, work_unit="bytes")
+        else:
+            rec.update(bound="mfma", unit="TFLOP/s", peak=peak_tf,
+                       achieved=flops / mean_s / 1e12, work_per_launch=flops, work_unit="flops")
+        rec["frac"] = rec["achieved"] / rec["peak"]
+        rec["traffic"] = stored_traffic(kind)
+        out[kind] = rec
+    return out
+
+
+def time_batch(ghsvd, torch, Fs, Js, Gs, kw, steps, warmup, profile_every=0):
+    """Times `steps` batched solves after `warmup` untimed ones; returns (seconds,
+    infos of the last solve, lambdas of the last solve, per-kind kernel times)."""
+    for _ in range(warmup):
+        ghsvd.solve_batched(Fs, Js, Gs, **kw)
+    torch.cuda.synchronize()
+    if profile_every:
+        ghsvd.profile_enable(profile_every)
+        for k in ghsvd.PROF_KINDS:
+            ghsvd.profile_read(k)  # clear
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        lam, X, infos, rc = ghsvd.solve_batched(Fs, Js, Gs, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    times = {}
+    if profile_every:
+        times = {k: ghsvd.profile_read(k) for k in ghsvd.PROF_KINDS}
+        ghsvd.profile_enable(0)
+    lams = [l.cpu().numpy() for l in lam]
+    del X
+    return dt, infos, lams, times, rc
+
+
+def _oracle_sample(job):
+    """One pencil of the CPU baseline's sample: the oracle's reduction and one
+    round-robin sweep of the square factors, in CPU seconds."""
+    number, k = job
+    from oracle import oracle as O
+    from paper_1907_08560_amd import synth
+    P = synth.workload_pencil(number, k)
+    o = O.Oracle()
+    t0 = time.process_time()
+    st, Fsq, Jsq, Gsq, perm, n2 = o.reduce(P.F, P.J, P.G)
+    t_red = time.process_time() - t0
+    t0 = time.process_time()
+    o.hz_run(Fsq, Jsq, Gsq, order=1, max_sweeps=1)
+    t_sw = time.process_time() - t0
+    return k, P.n, t_red, t_sw
+
+
+def cpu_baseline_batched(sizes, oracle_sweeps, cores):
+    """The CPU oracle on a bounded sample of the batch, in a process pool of
+    `cores` workers (one serial oracle process per core): for each of the
+    first `cores` pencils, the reduction and one square sweep, each pencil's
+    time extrapolated to its own oracle sweep count; the batch's throughput
+    is the pool's, cores / mean per-pencil time (the sample's mean scaled by
+    the batch's mean n^3 over the sample's)."""
+    import multiprocessing as mp
+    jobs = [(4, k) for k in range(min(cores, len(sizes)))]
+    # one thread per worker (the workers' numpy draws the inputs; the oracle
+    # itself is serial), set before the workers start
+    for var in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+        os.environ[var] = "1"
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(len(jobs)) as pool:
+        res = pool.map(_oracle_sample, jobs, chunksize=1)
+    wall = time.perf_counter() - t0
+    per = []
+    for k, n, t_red, t_sw in res:
+        sw = oracle_sweeps[k] if oracle_sweeps and oracle_sweeps[k] else 28
+        per.append(t_red + sw * t_sw)
+    n3 = np.asarray(sizes, dtype=np.float64) ** 3
+    scale = n3.mean() / n3[: len(per)].mean()
+    mean_pencil = float(np.mean(per)) * scale
+    cpu_s = sum(r[2] + r[3] for r in res)
+    return {"value": cores / mean_pencil, "unit": "pencils/s", "cores": cores, "kind": "oracle",
+            "host_cpu_count": os.cpu_count(),
+            "sample": (f"{len(jobs)} of the {len(sizes)} pencils, one serial oracle process per "
+                       f"core: reduction + 1 round-robin sweep each ({cpu_s:.0f} CPU-s, {wall:.1f} s "
+                       f"wall), each pencil extrapolated to its own oracle sweep count "
+                       f"(mean {mean_pencil:.0f} CPU-s per pencil at the batch's mean n^3); "
+                       f"value = cores / that")}
+
+
+def workload2_leg(args, ghsvd, synth, torch, dev):
+    """The single n = 1024 pencil at cond(S) = 1e16: FP64 and mixed blocked
+    solves (3 each), errors against its stored oracle eigenvalues, and the
+    full GHSVD of its swept square factors."""
+    P = synth.workload_pencil(2)
+    F = ghsvd.to_device_fortran(P.F, dev)
+    G = ghsvd.to_device_fortran(P.G, dev)
+    J = torch.from_numpy(P.J).to(dev)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        kw = dict(precision=prec, variant="blocked", max_sweeps=args.max_sweeps)
+        dt, infos, lam, _ = run_path(ghsvd, F, J, G, P, kw, 3, 1)
+        emax, emed = lambda_errors(lam)
+        out[f"{prec}-blocked"] = {"ms_per_pencil": 1000.0 * dt / 3, "pencils_per_s": 3 / dt,
+                                  "sweeps_fp32": infos[-1]["sweeps_fp32"],
+                                  "sweeps_fp64": infos[-1]["sweeps_fp64"],
+                                  "status": infos[-1]["status"],
+                                  "lambda_rel_err_vs_oracle": {"max": emax, "median": emed}}
+        log(f"workload 2 {prec}-blocked: {out[f'{prec}-blocked']['ms_per_pencil']:.1f} ms")
+    if not args.no_full:
+        out["full_ghsvd"] = full_leg(ghsvd, F, J, G)
+    return out
+
+
 def batched_workload(args, ghsvd, synth, torch, dev):
-    """The batch of 64 k-point pencils (n_k uniform in [300, 900], F 1.5 n_k x n_k
-    with a 3:1 signature, G 2 n_k x n_k with s log-uniform in [1e-6, 1]) in one
-    ghsvd_solve_batched call per step, after an untimed launch-tuning call."""
+    """The headline: 64 k-point pencils (n_k uniform in [300, 900], F
+    ceil(1.5 n_k) x n_k with a 3:1 signature, G 2 n_k x n_k with s
+    log-uniform in [1e-6, 1]) in one ghsvd_solve_batched call per step.  The
+    timed path is mixed precision (FP32 blocked warm-up, FP64 blocked finish);
+    the plain FP64 blocked and FP64 pointwise paths are timed on the same
+    batch beside it, after an untimed launch-tuning call."""
     sizes = synth.workload_sizes(4)
     Ps = [synth.workload_pencil(4, k) for k in range(len(sizes))]
     Fs = [ghsvd.to_device_fortran(P.F, dev) for P in Ps]
     Gs = [ghsvd.to_device_fortran(P.G, dev) for P in Ps]
     Js = [torch.from_numpy(P.J).to(dev) for P in Ps]
-    tuned = {}
-    for var in ("blocked", "pointwise"):
-        w, wpp, trials = ghsvd.autotune(Fs, Js, Gs, variant=var)
-        tuned[var] = {"block_width": w, "waves_per_pair": wpp, "trial_ms": trials}
-    paths = {}
-    lams = {}
-    for prec, var in (("fp64", "blocked"), ("mixed", "blocked"), ("fp64", "pointwise")):
-        kw = dict(precision=prec, variant=var, max_sweeps=args.max_sweeps,
-                  block_width=args.block_width)
-        for _ in range(args.warmup):
-            ghsvd.solve_batched(Fs, Js, Gs, **kw)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            lam, X, infos, rc = ghsvd.solve_batched(Fs, Js, Gs, **kw)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        lams[f"{prec}-{var}"] = [l.cpu().numpy() for l in lam]
-        paths[f"{prec}-{var}"] = {
-            "pencils_per_s": len(Ps) * args.steps / dt, "ms_per_batch": 1000.0 * dt / args.steps,
-            "status": rc, "max_sweeps_fp64": max(i["sweeps_fp64"] for i in infos),
-            "max_sweeps_fp32": max(i["sweeps_fp32"] for i in infos),
-            "pair_updates_per_s": sum(i["pairs_visited"] for i in infos) * args.steps / dt}
-    ref = lams["fp64-blocked"]
-    for key in ("mixed-blocked", "fp64-pointwise"):
-        e = max(float(np.max(np.abs(a - b) / np.abs(b))) for a, b in zip(lams[key], ref))
-        paths[key]["max_rel_diff_vs_fp64_blocked"] = e
-    best = max(paths, key=lambda k: paths[k]["pencils_per_s"])
+    log(f"{len(Ps)} pencils built, n in [{min(sizes)}, {max(sizes)}]")
+    ref, oracle_sweeps = golden_batch(GOLDEN4, Ps)
+    w, wpp, trials = ghsvd.autotune(Fs, Js, Gs, variant="blocked")
+    if args.block_width:
+        w = args.block_width
+    tuned = {"block_width": w, "waves_per_pair": wpp, "trial_ms": trials}
+    log(f"tuned: w={w}, waves per pair {wpp}")
+    inner = args.inner
+    kw = dict(variant="blocked", max_sweeps=args.max_sweeps, block_width=w, waves_per_pair=wpp,
+              inner_order=inner)
+    prime(ghsvd, synth, torch, dev, dict(kw, precision="mixed"))
+    paths, kern, lams = {}, {}, {}
+    plan = [("mixed", "blocked", args.steps, args.warmup),
+            ("fp64", "blocked", max(3, args.steps // 4), 1)]
+    if not args.no_compare:
+        plan.append(("fp64", "pointwise", 2, 0))
+    for prec, var, steps, warm in plan:
+        pkw = dict(kw, precision=prec, variant=var)
+        log(f"timing {prec}-{var}: {steps} steps after {warm} warm-up")
+        dt, infos, lam, times, rc = time_batch(ghsvd, torch, Fs, Js, Gs, pkw, steps, warm,
+                                               args.profile_every if var == "blocked" else 0)
+        key = f"{prec}-{var}"
+        lams[key] = lam
+        for inf, P in zip(infos, Ps):
+            inf.update(n=P.n, m=P.m, p=P.p, reduced=P.m > P.n or P.p > P.n)
+        rec = {"pencils_per_s": len(Ps) * steps / dt, "ms_per_batch": 1000.0 * dt / steps,
+               "steps": steps, "warmup": warm, "status": rc,
+               "max_sweeps_fp32": max(i["sweeps_fp32"] for i in infos),
+               "max_sweeps_fp64": max(i["sweeps_fp64"] for i in infos),
+               "mean_sweeps_fp32": float(np.mean([i["sweeps_fp32"] for i in infos])),
+               "mean_sweeps_fp64": float(np.mean([i["sweeps_fp64"] for i in infos])),
+               "pair_updates_per_s": sum(i["pairs_visited"] for i in infos) * steps / dt}
+        if ref is not None:
+            rec["lambda_rel_err_vs_oracle"] = batch_errors(lam, ref)
+        paths[key] = rec
+        if times:
+            kern[key] = batch_rooflines(times, infos, w, inner, steps, fp32_blocked=var == "blocked")
+        log(f"{key}: {rec['ms_per_batch']:.1f} ms per batch, status {rc}")
+    for key in paths:
+        if key != "fp64-blocked":
+            paths[key]["max_rel_diff_vs_fp64_blocked"] = max(
+                float(np.max(np.abs(a - b) / np.abs(b))) for a, b in zip(lams[key],
+                                                                         lams["fp64-blocked"]))
+    head = paths["mixed-blocked"]
     rec = {
-        "metric": METRIC, "value": paths[best]["pencils_per_s"], "unit": "pencils/s",
+        "metric": METRIC, "value": head["pencils_per_s"], "unit": "pencils/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": paths[best]["ms_per_batch"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64" if best.startswith("fp64") else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": ("64 k-point pencils, n_k uniform in [300,900], F ceil(1.5 n_k) x n_k "
-                                "Gaussian, J 3:1, G 2 n_k x n_k = U diag(s) W^*, s log-uniform "
-                                f"[1e-6,1], complex128, one batched call; best path {best}"),
-                   "batch": len(Ps), "n_min": int(min(sizes)), "n_max": int(max(sizes))},
+        "ms_per_step": head["ms_per_batch"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": ("64 k-point pencils, n_k uniform in [300,900], F ceil(1.5 n_k) x "
+                                "n_k Gaussian, J 3:1, G 2 n_k x n_k = U diag(s) W^*, s "
+                                "log-uniform [1e-6,1] (cond S <= 1e12), complex128, one batched "
+                                "call per step: reduction + FP32 blocked warm-up + FP64 blocked "
+                                "finish + lambda, X"),
+                   "batch": len(Ps), "n_min": int(min(sizes)), "n_max": int(max(sizes)),
+                   "precision": "mixed", "variant": "blocked", "inner": inner,
+                   "block_width": w, "waves_per_pair": wpp},
+        "pair_updates_per_s": head["pair_updates_per_s"],
+        "lambda_rel_err_vs_oracle": head.get("lambda_rel_err_vs_oracle"),
+        "vs_fp64_blocked": head["pencils_per_s"] / paths["fp64-blocked"]["pencils_per_s"],
         "paths": paths, "tuned": tuned,
     }
+    km = kern.get("mixed-blocked", {})
+    if km:
+        dom = max(km, key=lambda k: km[k]["total_ms_est"])
+        d = km[dom]
+        rec["roofline"] = {
+            "bound": d["bound"], "kernel": KERNEL_NAMES.get(dom, dom),
+            "achieved": d["achieved"], "peak": d["peak"], "unit": d["unit"], "frac": d["frac"],
+            "traffic": d["traffic"], "mean_launch_us": d["mean_us"],
+            "work_per_launch": d["work_per_launch"], "work_unit": d["work_unit"],
+            "timed_launches": d["timed_launches"], "launches": d["launches"]}
+    rec["kernels"] = kern
+    if not args.no_workload2:
+        rec["workload2"] = workload2_leg(args, ghsvd, synth, torch, dev)
+    if not args.no_cpu_baseline:
+        log("cpu baseline")
+        rec["cpu_baseline"] = cpu_baseline_batched(sizes, oracle_sweeps,
+                                                   min(16, os.cpu_count() or 1))
     print(json.dumps(rec), flush=True)
 
 
@@ -394,9 +622,11 @@ def main():
     ap.add_argument("--max-sweeps", type=int, default=0)
     ap.add_argument("--block-width", type=int, default=0, choices=[0, 8, 16, 32],
                     help="blocked variant's block width (0: the library's choice)")
-    ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4, 5],
-                    help="2: the single n=1024 pencil (default); 3: one n=4096 pencil; "
-                         "4: the batch of 64 pencils; 5: the batch of 16 large pencils")
+    ap.add_argument("--workload", type=int, default=4, choices=[2, 3, 4, 5],
+                    help="4: the batch of 64 pencils (default, the headline); 2: the single "
+                         "n=1024 pencil; 3: one n=4096 pencil; 5: the batch of 16 large pencils")
+    ap.add_argument("--no-workload2", action="store_true",
+                    help="workload 4: skip the single-pencil n=1024 leg")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -439,12 +669,11 @@ def main():
     ms_per_step = 1000.0 * dt / args.steps
     info = infos[-1]
     isum = {k: sum(i[k] for i in infos) for k in ("pairs_visited", "pw_visited", "pw_transformed")}
-    mr, pr, n = info["m_r"], info["p_r"], P.n
+    n = P.n
     w = args.block_width or block_width_for(n)
-    nb = -(-n // w)
-    nb += nb & 1
-    kr = kernel_rooflines(times, isum, mr, pr, n, w, nb // 2,
-                          fp32_blocked=args.precision == "mixed")
+    info.update(n=n, m=P.m, p=P.p, reduced=not args.no_reduce and (P.m > n or P.p > n))
+    kr = batch_rooflines(times, [info], w, args.inner, args.steps,
+                         fp32_blocked=args.variant == "blocked")
     dom = max(kr, key=lambda k: kr[k]["total_ms_est"]) if kr else None
     err_max, err_med = lambda_errors(lam)
 

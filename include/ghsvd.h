@@ -29,7 +29,8 @@
  *    outputs undefined).  See ghsvd_status.
  *  - The library is thread-safe for calls with distinct workspaces; its only
  *    global state is a mutex-guarded cache of tuned launch parameters
- *    (ghsvd_autotune).
+ *    (ghsvd_autotune), the kernel-timing record (ghsvd_profile_enable) and
+ *    the scratch array of ghsvd_block_sweeps_noalloc (locked per device).
  */
 #ifndef GHSVD_H
 #define GHSVD_H
@@ -324,10 +325,14 @@ int ghsvd_round_robin(int n, int *p_out, int *q_out);
  * enabling, then clears that kind's record.  Kinds: GHSVD_PROF_PAIR64 (FP64
  * pointwise pair kernel), GHSVD_PROF_PAIR32 (its FP32 form),
  * GHSVD_PROF_GRAM, GHSVD_PROF_INNER, GHSVD_PROF_UPDATE (the three kernels
- * of a blocked step).  Returns GHSVD_EINVAL for an unknown kind.
+ * of an FP64 blocked step), GHSVD_PROF_GRAM32, GHSVD_PROF_INNER32,
+ * GHSVD_PROF_UPDATE32 (the same in the FP32 warm-up), GHSVD_PROF_REDUCE (the
+ * launches of one column step of the one-time reduction, bracketed
+ * together).  Returns GHSVD_EINVAL for an unknown kind.
  */
 enum { GHSVD_PROF_PAIR64 = 0, GHSVD_PROF_PAIR32 = 1, GHSVD_PROF_GRAM = 2, GHSVD_PROF_INNER = 3,
-       GHSVD_PROF_UPDATE = 4 };
+       GHSVD_PROF_UPDATE = 4, GHSVD_PROF_GRAM32 = 5, GHSVD_PROF_INNER32 = 6,
+       GHSVD_PROF_UPDATE32 = 7, GHSVD_PROF_REDUCE = 8 };
 void ghsvd_profile_enable(int every);
 int ghsvd_profile_read(int kind, double *ms, long long *timed, long long *launches);
 

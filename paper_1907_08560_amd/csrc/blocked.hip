@@ -78,10 +78,15 @@ __device__ __forceinline__ int blk_col(int w, int a, int b, int ca, int cc) {
 // of the Hermitian result are formed; the wavefronts' sums are added in LDS
 // in a fixed order, and the lower tile is written as the conjugate
 // transpose.  Padding columns (>= c) and rows past the end read as zero.
+// The cross-wavefront sum runs in two halves (wavefronts 4-7 park their
+// tiles, 0-3 add them to their own, then the four sums are added in order),
+// so the LDS buffer holds four wavefronts' tiles and two workgroups share a
+// CU.
 constexpr int kGramWaves = 8;
+constexpr int kGramHalf = kGramWaves / 2;
 
 template <typename T, int PB>
-__global__ __launch_bounds__(kWave * kGramWaves) void k_blk_gram(const PencilDev *PD,
+__global__ __launch_bounds__(kWave * kGramWaves, 2) void k_blk_gram(const PencilDev *PD,
                                                                  const int *pre, const int *flag,
                                                                  int B, int step) {
     using C2 = typename Mfma<T>::c2;
@@ -90,7 +95,7 @@ __global__ __launch_bounds__(kWave * kGramWaves) void k_blk_gram(const PencilDev
     constexpr int NTD = PB / 16;              // column tiles
     constexpr int NT = NTD * (NTD + 1) / 2;   // upper output tiles
     constexpr int RW = kGramChunk / kGramWaves;  // rows per wavefront
-    __shared__ double2 red[kGramWaves][NT][256];
+    __shared__ double2 red[kGramHalf][NT][256];
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev A = PD[pk];
     if (step >= A.nb - 1 || flag[pk]) return;
@@ -163,18 +168,31 @@ __global__ __launch_bounds__(kWave * kGramWaves) void k_blk_gram(const PencilDev
                 acc_im[q] = Mfma<T>::mma(-ai, br, acc_im[q]);
             }
     }
+    if (wv >= kGramHalf) {
 #pragma unroll
-    for (int q = 0; q < NT; ++q)
+        for (int q = 0; q < NT; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-            red[wv][q][r * 64 + lane] = cmk((double)acc_re[q][r], (double)acc_im[q][r]);
+            for (int r = 0; r < 4; ++r)
+                red[wv - kGramHalf][q][r * 64 + lane] =
+                    cmk((double)acc_re[q][r], (double)acc_im[q][r]);
+    }
+    __syncthreads();
+    if (wv < kGramHalf) {
+#pragma unroll
+        for (int q = 0; q < NT; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                double2 &slot = red[wv][q][r * 64 + lane];
+                slot = cadd(cmk((double)acc_re[q][r], (double)acc_im[q][r]), slot);
+            }
+    }
     __syncthreads();
     const GPtr<double2> P(A.part + ((size_t)bpi * KC + kc) * PB * PB);
     for (int e = tid; e < NT * 256; e += kWave * kGramWaves) {
         const int q = e / 256, rl = e % 256, r = rl / 64, ln = rl % 64;
         double2 sum = red[0][q][rl];
 #pragma unroll
-        for (int w2 = 1; w2 < kGramWaves; ++w2) sum = cadd(sum, red[w2][q][rl]);
+        for (int w2 = 1; w2 < kGramHalf; ++w2) sum = cadd(sum, red[w2][q][rl]);
         int ti = 0, tj = q;  // upper tile q -> (ti, tj)
         if (NTD == 2) {
             ti = q == 2 ? 1 : 0;
@@ -1431,29 +1449,32 @@ struct BlockedArg {
     int inner_nt;
     int crit;
     int mode;  // inner_order
+    int fp32;  // FP32 warm-up kernels (timed under their own kinds)
 };
 
 static int blocked_step(const BatchCtx &c, const void *arg, int step, hipStream_t s) {
     const BlockedArg *a = static_cast<const BlockedArg *>(arg);
     // kernel timing events are taken unless the batch is plain (no events)
     const bool tm = !c.plain;
+    const int kg = a->fp32 ? kProfGram32 : kProfGram, ki = a->fp32 ? kProfInner32 : kProfInner,
+              ku = a->fp32 ? kProfUpdate32 : kProfUpdate;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (tm) prof_before(kProfGram, s, e0, e1);
+    if (tm) prof_before(kg, s, e0, e1);
     hipLaunchKernelGGL(a->gram, dim3(c.total(BatchCtx::kGram)),
                        dim3(a->gsum ? kWave * kG64Tiles : kWave * kGramWaves), 0, s, c.dev,
                        c.pre_of(BatchCtx::kGram), c.flag_dev, c.B, step);
     if (a->gsum)
         hipLaunchKernelGGL(a->gsum, dim3(c.total(BatchCtx::kBp), 2 * kG64Tiles), dim3(256), 0, s,
                            c.dev, c.pre_of(BatchCtx::kBp), c.flag_dev, c.B, step);
-    if (tm) prof_after(kProfGram, s, e0, e1);
-    if (tm) prof_before(kProfInner, s, e0, e1);
+    if (tm) prof_after(kg, s, e0, e1);
+    if (tm) prof_before(ki, s, e0, e1);
     hipLaunchKernelGGL(a->inner, dim3(c.total(BatchCtx::kBp)), dim3(a->inner_nt), 0, s, c.dev,
                        c.pre_of(BatchCtx::kBp), c.flag_dev, c.B, a->crit, step, a->mode);
-    if (tm) prof_after(kProfInner, s, e0, e1);
-    if (tm) prof_before(kProfUpdate, s, e0, e1);
+    if (tm) prof_after(ki, s, e0, e1);
+    if (tm) prof_before(ku, s, e0, e1);
     hipLaunchKernelGGL(a->upd, dim3(c.total(BatchCtx::kUpd)), dim3(256), 0, s, c.dev,
                        c.pre_of(BatchCtx::kUpd), c.flag_dev, c.B, step);
-    if (tm) prof_after(kProfUpdate, s, e0, e1);
+    if (tm) prof_after(ku, s, e0, e1);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }
@@ -1474,6 +1495,7 @@ int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, int
     BlockedArg a{};
     a.crit = crit;
     a.mode = inner_order;
+    a.fp32 = fp32;
     const bool fb = inner_order == GHSVD_INNER_FB;
     if (w == 32) {
         a.gram = fp32 ? k_blk_gram64<float> : k_blk_gram64<double>;

@@ -1208,6 +1208,8 @@ int run_reduction(BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
         const int tot = c.win[(size_t)w * (B + 1) + B];
         const int jw = w * step;
         if (tot == 0) continue;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        prof_before(kProfReduce, s, e0, e1);
         hipLaunchKernelGGL(k_jqr_cross, dim3(tot), dim3(kGridNT), 0, s, c.dev, pw, B, par, jw);
         hipLaunchKernelGGL(k_jqr_cross2, dim3(tot), dim3(kGridNT), 0, s, c.dev, pw, B, par, jw);
         const int rc = rows_cap[w];
@@ -1216,6 +1218,7 @@ int run_reduction(BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
         auto step_k = rc > 4 && rc <= 8 ? k_jqr_step<8> : k_jqr_step<4>;
         hipLaunchKernelGGL(step_k, dim3(2 * tot), dim3(kGridNT), jl_bytes, s, c.dev, pw, B, par,
                            tot, it, jw);
+        prof_after(kProfReduce, s, e0, e1);
     }
     hipLaunchKernelGGL(k_jqr_settle, dim3(B), dim3(256), 0, s, c.dev, c.max_n & 1);
     GHSVD_HIP(hipGetLastError());

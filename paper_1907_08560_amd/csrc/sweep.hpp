@@ -69,7 +69,7 @@ void trace_stage(const char *name, int pencil, const SweepState &hs);
 
 // Sweep-kernel timing record (see ghsvd_profile_enable), per kernel kind.
 enum { kProfPair64 = 0, kProfPair32 = 1, kProfGram = 2, kProfInner = 3, kProfUpdate = 4,
-       kProfKinds = 5 };
+       kProfGram32 = 5, kProfInner32 = 6, kProfUpdate32 = 7, kProfReduce = 8, kProfKinds = 9 };
 void prof_before(int kind, hipStream_t s, hipEvent_t &e0, hipEvent_t &e1);
 void prof_after(int kind, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
 

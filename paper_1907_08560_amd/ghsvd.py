@@ -322,7 +322,8 @@ def round_robin(n: int):
     return steps, pp[: steps * slots].reshape(steps, slots), qq[: steps * slots].reshape(steps, slots)
 
 
-PROF_KINDS = {"pair64": 0, "pair32": 1, "gram": 2, "inner": 3, "update": 4}
+PROF_KINDS = {"pair64": 0, "pair32": 1, "gram": 2, "inner": 3, "update": 4, "gram32": 5,
+              "inner32": 6, "update32": 7, "reduce": 8}
 
 
 def profile_enable(every: int) -> None:
