@@ -7,6 +7,7 @@ so a test can confirm it sees the same inputs.
     python tests/golden/make_golden.py workload2        # n = 1024, tall, ~7 min
     python tests/golden/make_golden.py workload4        # 64 pencils, a process pool
     python tests/golden/make_golden.py samples          # downsized workloads 3 and 5
+    python tests/golden/make_golden.py parity           # uneven batch for the launch tests
 """
 import json
 import multiprocessing as mp
@@ -22,6 +23,10 @@ sys.path.insert(0, ROOT)
 
 from oracle import oracle as O  # noqa: E402
 from paper_1907_08560_amd import synth  # noqa: E402
+
+
+# orders of the uneven batch of the launch-configuration parity tests
+PARITY_SIZES = [513, 257, 300, 130, 77]
 
 
 def fingerprint(P) -> list:
@@ -54,9 +59,13 @@ def _one(job):
     dt = time.process_time() - t0
     print(f"workload {number} pencil {k} n={P.n} status {st} sweeps {stats[0]} {dt:.1f}s",
           flush=True)
+    # cancellation in h_j = f_j^* J f_j of each eigenvalue: kappa_j = ||F x_j||^2 / |lambda_j|
+    # (>= 1; large for an eigenvalue near zero of an indefinite pencil)
+    kap = np.sum(np.abs(P.F @ X) ** 2, axis=0) / np.abs(lam)
     return {"k": k, "status": int(st), "n": P.n, "m": P.m, "p": P.p, "m_plus": P.m_plus,
             "j_identity": j_identity, "sweeps": int(stats[0]), "oracle_cpu_seconds": dt,
-            "fingerprint": fingerprint(P), "lambda": [repr(float(v)) for v in lam]}
+            "fingerprint": fingerprint(P), "lambda": [repr(float(v)) for v in lam],
+            "kappa_h": [float(f"{v:.3g}") for v in kap]}
 
 
 def run_batch(name: str, jobs, desc: str):
@@ -89,5 +98,10 @@ if __name__ == "__main__":
             run_batch("workload3_sample", [(3, 0, 1024, True), (3, 0, 768, False)],
                       "the workload-3 pencil (s in [1e-5, 1]) downsized to n = 1024 under "
                       "J = I, and to n = 768 with its 3:1 signature")
+        elif w == "parity":
+            run_batch("batch_parity", [(4, k, n, False) for k, n in enumerate(PARITY_SIZES)],
+                      "pencils 0-4 of workload 4's recipe at n = " +
+                      ", ".join(map(str, PARITY_SIZES)) + " (uneven orders across the 256- and "
+                      "128-row Gram chunks, ragged last blocks and an empty padding block)")
         else:
             raise SystemExit(f"unknown {w}")

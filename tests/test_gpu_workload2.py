@@ -4,9 +4,10 @@ oracle's eigenvalues stored in tests/golden/ (written by make_golden.py, which
 calls only the CPU oracle: tall factors, row-cyclic Algorithm 2).
 
 Tolerance: at cond(S) = 1e16 (kappa(G) = 1e8) the per-eigenvalue error of the
-method itself is about eps * kappa(G) ~ 2e-8 in the worst case (the oracle
-against 40-digit brute force shows 1e-9 .. 1e-8 at this conditioning), so GPU
-and oracle may differ by twice that: 5e-8.  The median error is also reported.
+method itself is about 0.05 eps kappa(G) ~ 1e-9 (the oracle against 40-digit
+brute force at this conditioning shows 0.7e-9 .. 1.3e-9 as its worst), so GPU
+and oracle may differ by a few times that: the gate is 1e-8 (measured 2.7e-9
+on every path).  The median error is also reported.
 """
 import json
 import os
@@ -44,7 +45,7 @@ def test_workload2_full_size(pencil, precision, variant):
     print(f"{precision}/{variant}: max rel err {rel.max():.3e} median {np.median(rel):.3e} "
           f"sweeps fp32 {info['sweeps_fp32']} fp64 {info['sweeps_fp64']} "
           f"blocked {info['sweeps_blocked']}", flush=True)
-    assert rel.max() <= 5e-8
+    assert rel.max() <= 1e-8
     assert np.median(rel) <= 1e-11
     # same count of negative eigenvalues (the inertia of H)
     assert int((lam < 0).sum()) == int((lam_o < 0).sum())
