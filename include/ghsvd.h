@@ -81,7 +81,20 @@ typedef struct {
                            most 30                                                       */
 } ghsvd_options;
 
-enum { GHSVD_INNER_FULL = 0, GHSVD_INNER_CROSS = 1, GHSVD_INNER_FB = 2 };  /* ghsvd_options.inner_order */
+/* ghsvd_options.inner_order.  GHSVD_INNER_FULL_JQR and GHSVD_INNER_FB_JQR are
+ * GHSVD_INNER_FULL and GHSVD_INNER_FB with the block pivots shortened by
+ * (J)QR instead of formed as Grams (Section 6.4.2): in the FP64 blocked
+ * stage each block pair's c pivot columns F_C, G_C are reduced to square
+ * factors F~, G~ (the hyperbolic QR of F_C with the pivoting of Section
+ * 5.2.1, its columns put back in pivot-column order, and the QR of G_C), so
+ * that F~^* J~ F~ = F_C^* J F_C and G~^* G~ = G_C^* G_C, and the inner level
+ * runs the one-sided 2x2 steps of Section 6.1 on them, never squaring the
+ * block pivot's conditioning.  A pivot pair that looks numerically dependent
+ * is skipped there (left to later block sweeps).  Slower (each block step
+ * runs a batched reduction and pointwise sweep of all its block pairs); the
+ * FP32 warm-up keeps Gram-formed pivots. */
+enum { GHSVD_INNER_FULL = 0, GHSVD_INNER_CROSS = 1, GHSVD_INNER_FB = 2, GHSVD_INNER_FULL_JQR = 3,
+       GHSVD_INNER_FB_JQR = 4 };
 
 typedef struct {
     int status;
@@ -259,6 +272,8 @@ int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n_plus, doub
  * exceeds GHSVD_NOALLOC_SCRATCH_BYTES is rejected with GHSVD_ENOMEM before
  * any work is enqueued (square n = 1024 at every width fits, and n = 2048 at
  * w = 8 and 16).
+ * The shortened inner orders (GHSVD_INNER_FULL_JQR, GHSVD_INNER_FB_JQR) are
+ * rejected with GHSVD_EINVAL.
  * Calls on one GPU share its array, which keeps the last call's contents (the
  * call clears every counter and state it reads before using it): two calls
  * that overlapped on one GPU would race, so within a process the library

@@ -27,7 +27,8 @@ struct SweepState {
     int converged;   // 1: the last sweep had no big transformation
     int max_sweeps;  // cap of the stage
     int noise_floor; // 1: also stop at the noise floor (FP32 stage, see k_end_round)
-    int pad;
+    int stop_all;    // 1: stop after a sweep with no transformation at all, big or small
+                     // (the inner level of a blocked sweep, Section 6.1.7); else no big one
     unsigned int prev_big;  // big count of the previous sweep (noise-floor plateau)
     unsigned long long hist[3 * kMaxHist];  // (visited, transformed, big) per sweep
 };
@@ -62,7 +63,8 @@ struct PencilDev {
     int kf, kg;       // blocked: Gram chunks over F rows, over G rows
     int tf, tg, tz;   // blocked: 16-row update strips over F, G, Z
     int tu;           // blocked: update workgroups per block pair
-    int pad0;
+    int skip_rank;    // pointwise FP64: a pivot pair whose G columns look dependent is skipped
+                      // (left to later sweeps) instead of failing the pencil
     // caller buffers
     const double2 *Fin;
     long ldfin;
@@ -87,6 +89,7 @@ struct PencilDev {
     double2 *rblk;   // rows k, k+1 of each pivot column at the end of its step (2 n)
     int *pblk;       // first row and size of each column's pivot block (2 n)
     double2 *qdiag;  // R_kk of the QR of G P2 (n)
+    double *qnrm;    // ||x|| of the column each QR reflector of G is built from (n)
     int8_t *Jw;       // [2 m] by step parity during the reduction; J_sq in the first copy after
     int *rowmap;
     int *perm;        // column map P2 (logical column j is physical column perm[j] of Ft)

@@ -23,6 +23,13 @@
 #include <cmath>
 #include <cstdlib>
 
+// Floating-point contraction is decided by the source expressions (a * b + c
+// within one expression becomes one fused multiply-add), not by the code an
+// expression is inlined into: the inner kernels and the look-ahead of their
+// pivot wavefront evaluate the same expressions in different contexts and
+// must round them the same way.
+#pragma clang fp contract(on)
+
 #include "hz_step.hpp"
 #include "reduce.hpp"
 #include "solver.hpp"
@@ -1440,7 +1447,6 @@ size_t blocked_bytes(int mr, int n, int pr, int w, int mixed) {
     return c.used + 256;
 }
 
-using BlkFn = void (*)(const PencilDev *, const int *, const int *, int, int);
 using BlkInnerFn = void (*)(const PencilDev *, const int *, const int *, int, int, int, int);
 
 struct BlockedArg {
@@ -1479,9 +1485,24 @@ static int blocked_step(const BatchCtx &c, const void *arg, int step, hipStream_
     return GHSVD_OK;
 }
 
+BlkFn block_update_kernel(int w) {
+    if (w == 32) return k_blk_update<double, 64>;
+    if (w == 16) return k_blk_update<double, 32>;
+    if (w == 8) return k_blk_update<double, 16>;
+    return nullptr;
+}
+
 int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, int inner_order,
                       hipStream_t s,
                       std::vector<SweepResult> &res) {
+    if (inner_shortened(inner_order)) {
+        // (J)QR-shortened block pivots in the FP64 stage; the FP32 warm-up
+        // forms them as Grams with the same inner ordering
+        if (!fp32)
+            return run_blocked_shortened(c, max_sweeps, crit,
+                                         inner_order == GHSVD_INNER_FB_JQR, s, res);
+        inner_order = inner_order == GHSVD_INNER_FB_JQR ? GHSVD_INNER_FB : GHSVD_INNER_FULL;
+    }
     int w = 0, steps = 1;
     for (const PencilDev &P : c.host) {
         if (w == 0) w = P.w;

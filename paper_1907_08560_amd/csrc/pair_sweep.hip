@@ -114,8 +114,9 @@ __device__ __forceinline__ void pair_body(const PencilDev &P, int p, int q, int 
     Zp z;
     int kind = hz_step(v[0], v[1], cmk(v[2], v[3]), v[4], v[5], cmk(v[6], v[7]), tol, crit, z,
                        F32 ? 1 : 0);
-    // FP32 stage: a pair that looks dependent in FP32 is left to the FP64 sweeps.
-    if (F32 && kind == GHSVD_ERANK) kind = kSkip;
+    // FP32 stage: a pair that looks dependent in FP32 is left to the FP64 sweeps;
+    // the inner level of a shortened block pivot leaves it to later block sweeps.
+    if ((F32 || P.skip_rank) && kind == GHSVD_ERANK) kind = kSkip;
     if (tid == 0) {
         unsigned long long *c = P.slot_cnt + 3 * slot;
         c[0] += 1ull;
@@ -171,7 +172,7 @@ __global__ __launch_bounds__(NT) void k_pair(const PencilDev *PD, const int *pre
 }
 
 __global__ void k_reset_states(const PencilDev *PD, int *flag, const int *presolved, int B,
-                               int max_sweeps, int noise_floor, int blocked) {
+                               int max_sweeps, int noise_floor, int blocked, int stop_all) {
     const int k = blockIdx.x;
     if (k >= B) return;
     const PencilDev P = PD[k];
@@ -188,6 +189,7 @@ __global__ void k_reset_states(const PencilDev *PD, int *flag, const int *presol
         st->err = 0;
         st->max_sweeps = max_sweeps;
         st->noise_floor = noise_floor;
+        st->stop_all = stop_all;
         st->prev_big = 0xffffffffu;
     }
 }
@@ -229,7 +231,7 @@ __global__ __launch_bounds__(256) void k_end_round(const PencilDev *PD, int *fla
         st->sweeps = sw + 1;
         if (st->err != 0) {
             st->done = 1;
-        } else if (v[2] == 0.0) {
+        } else if (v[st->stop_all ? 1 : 2] == 0.0) {
             st->done = 1;
             st->converged = 1;
         } else if (st->noise_floor &&
@@ -429,7 +431,7 @@ int drive_stage(const BatchCtx &c, int max_sweeps, int noise_floor, int blocked,
         pre_dev = c.done_dev;
     }
     hipLaunchKernelGGL(k_reset_states, dim3(B), dim3(256), 0, ss, c.dev, c.flag_dev, pre_dev, B,
-                       max_sweeps, noise_floor, blocked);
+                       max_sweeps, noise_floor, blocked, c.stop_all);
     GHSVD_HIP(hipGetLastError());
     std::vector<int> done(B, 0);
     const bool trace = std::getenv("GHSVD_TRACE") != nullptr;

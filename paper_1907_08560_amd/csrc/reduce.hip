@@ -23,6 +23,11 @@ namespace ghsvd {
 
 constexpr int kGridNT = 256;
 constexpr int kOneNT = 1024;
+// Blocked QR of G: panel width, the longest column the trailing kernel
+// holds in registers, columns per trailing workgroup.
+constexpr int kQrPanel = 32;
+constexpr int kQrRegRows = 2048;
+constexpr int kQrTrailCols = 4;
 
 __device__ __forceinline__ double jsign(const int8_t *J, int r) { return (double)J[r]; }
 
@@ -261,6 +266,9 @@ __device__ __forceinline__ double2 sv_load(const double2 *x, const double2 *stas
 template <int RC>
 __device__ __forceinline__ void qr_step_body(const PencilDev *PD, const int *pre, int B, int k,
                                              int bid, int jw, double *red);
+template <int RC>
+__device__ __forceinline__ void qr_panel_body(const PencilDev *PD, int B, int k, int bid,
+                                              double *red);
 
 // A 1x1 pivot step with the workgroup's rows in registers: thread tid holds
 // rows k + tid + i * kGridNT (i < RC) of the signature, the pivot column and
@@ -435,14 +443,18 @@ __device__ __forceinline__ void jqr_step1_regs(const PencilDev &P, const JqrStat
 // step); longer columns, and 2x2 pivots, take the streaming loops.
 template <int RC>
 __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const int *pre, int B,
-                                                      int par, int tot, int qk, int jw) {
+                                                      int par, int tot, int qk, int jw,
+                                                      int qpanel) {
     extern __shared__ int8_t Jl[];  // signature with this step's row swaps
     __shared__ double red[4 * kGridNT / kWave];
     __shared__ double rv[kGridNT / kWave];
     __shared__ int ri[kGridNT / kWave];
     __shared__ double2 stash[4];
     if ((int)blockIdx.x >= tot) {
-        qr_step_body<RC>(PD, pre, B, qk, (int)blockIdx.x - tot, jw, red);
+        if (qpanel)
+            qr_panel_body<RC>(PD, B, qk, (int)blockIdx.x - tot, red);
+        else
+            qr_step_body<RC>(PD, pre, B, qk, (int)blockIdx.x - tot, jw, red);
         return;
     }
     const int pk = find_pencil(pre, B, blockIdx.x);
@@ -827,11 +839,11 @@ __global__ void k_jqr_settle(const PencilDev *PD, int par) {
 // it, and zero below; rowmap (may be NULL) moves row r to rowmap[r].
 __global__ void k_jqr_extract(int n, const double2 *Ft, long ldft, const int *perm,
                               const double2 *rblk, const int *pblk, const int *rowmap,
-                              double2 *dst, long ldd) {
+                              double2 *dst, long ldd, int scatter) {
     const int j = blockIdx.y;
     const double2 *s = Ft + (size_t)perm[j] * ldft;
     const int kb = pblk[2 * j], bs = pblk[2 * j + 1];
-    double2 *d = dst + (size_t)j * ldd;
+    double2 *d = dst + (size_t)(scatter ? perm[j] : j) * ldd;
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < n; r += gridDim.x * blockDim.x) {
         double2 v;
         if (r < kb) v = s[r];
@@ -841,11 +853,12 @@ __global__ void k_jqr_extract(int n, const double2 *Ft, long ldft, const int *pe
     }
 }
 
-int jqr_extract(const PencilDev &P, double2 *dst, long ldd, const int *rowmap, hipStream_t s) {
+int jqr_extract(const PencilDev &P, double2 *dst, long ldd, const int *rowmap, hipStream_t s,
+                int scatter) {
     int bx = (P.n + 255) / 256;
     if (bx > 16) bx = 16;
     hipLaunchKernelGGL(k_jqr_extract, dim3(bx, P.n), dim3(256), 0, s, P.n, P.Ft, P.ldft, P.perm,
-                       P.rblk, P.pblk, rowmap, dst, ldd);
+                       P.rblk, P.pblk, rowmap, dst, ldd, scatter);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }
@@ -859,6 +872,10 @@ int jqr_extract(const PencilDev &P, double2 *dst, long ldd, const int *rowmap, h
 // which no workgroup rewrites during the step, and applies it to its own
 // column j > k; the workgroup of column k records R_kk = -e^{i arg x_1} ||x||.
 template <int RC>
+__device__ __forceinline__ void qr_col_step(const PencilDev &P, int k, int j, double *red);
+
+// Column j of G's step k, workgroup bid of the window's column range.
+template <int RC>
 __device__ __forceinline__ void qr_step_body(const PencilDev *PD, const int *pre, int B, int k,
                                              int bid, int jw, double *red) {
     const int pk = find_pencil(pre, B, bid);
@@ -866,6 +883,27 @@ __device__ __forceinline__ void qr_step_body(const PencilDev *PD, const int *pre
     if (!P.reduce || k >= P.n) return;
     const int j = pencil_local(pre, pk, bid) + jw;
     if (j < k) return;
+    qr_col_step<RC>(P, k, j, red);
+}
+
+// Blocked form of G's QR (every pencil's p <= kQrRegRows): step k applies
+// its reflector only to the columns of k's panel of kQrPanel columns,
+// kQrPanel workgroups per pencil; k_qr_trail applies a finished panel's
+// reflectors to the columns right of it.
+template <int RC>
+__device__ __forceinline__ void qr_panel_body(const PencilDev *PD, int B, int k, int bid,
+                                              double *red) {
+    const int pk = bid / kQrPanel;
+    if (pk >= B) return;
+    const PencilDev P = PD[pk];
+    if (!P.reduce || k >= P.n) return;
+    const int j = k - k % kQrPanel + bid % kQrPanel;
+    if (j < k || j >= P.n) return;
+    qr_col_step<RC>(P, k, j, red);
+}
+
+template <int RC>
+__device__ __forceinline__ void qr_col_step(const PencilDev &P, int k, int j, double *red) {
     double2 *A = P.Gt;
     const long lda = P.ldgt;
     const int p = P.p;
@@ -894,7 +932,10 @@ __device__ __forceinline__ void qr_step_body(const PencilDev *PD, const int *pre
         const double ax1 = sqrt(fnorm2(x1));
         const double2 ph = ax1 > 0.0 ? cmk(x1.x / ax1, x1.y / ax1) : cmk(1.0, 0.0);
         if (j == k) {
-            if (threadIdx.x == 0) P.qdiag[k] = nrm == 0.0 ? x1 : cscale(ph, -nrm);
+            if (threadIdx.x == 0) {
+                P.qdiag[k] = nrm == 0.0 ? x1 : cscale(ph, -nrm);
+                P.qnrm[k] = nrm;
+            }
             return;
         }
         if (nrm == 0.0) return;
@@ -927,7 +968,10 @@ __device__ __forceinline__ void qr_step_body(const PencilDev *PD, const int *pre
     const double ax1 = sqrt(cnorm2(x1));
     const double2 ph = ax1 > 0.0 ? cmk(x1.x / ax1, x1.y / ax1) : cmk(1.0, 0.0);
     if (j == k) {
-        if (threadIdx.x == 0) P.qdiag[k] = nrm == 0.0 ? x1 : cscale(ph, -nrm);
+        if (threadIdx.x == 0) {
+            P.qdiag[k] = nrm == 0.0 ? x1 : cscale(ph, -nrm);
+            P.qnrm[k] = nrm;
+        }
         return;
     }
     if (nrm == 0.0) return;
@@ -945,6 +989,78 @@ __device__ __forceinline__ void qr_step_body(const PencilDev *PD, const int *pre
         const double2 a = r == k ? vk : x[r];
         y[r] = csub(y[r], cmul(a, tw));
     }
+}
+
+// A finished panel [ps, pe) of G's QR applied to the columns right of it:
+// workgroup (g, pencil) holds columns pe + g kQrTrailCols .. + kQrTrailCols - 1,
+// rows ps..p-1, in registers (row ps + tid + i kGridNT, p - ps <= kQrRegRows)
+// and applies the panel's reflectors H_ps, ..., H_{pe-1} in order, each
+// rebuilt from its stored column (rows > k), R's row k value x_1 and the
+// recorded ||x||, as the step kernel builds it: w = v^* y, y <- y - v w / (||x||
+// (||x|| + |x_1|)).  The columns are read and written once per panel instead
+// of once per step.
+__global__ __launch_bounds__(kGridNT) void k_qr_trail(const PencilDev *PD, int B, int ps, int pe) {
+    constexpr int RC = kQrRegRows / kGridNT;
+    constexpr int NC = kQrTrailCols;
+    __shared__ double red[2 * NC * kGridNT / kWave];
+    const int pk = blockIdx.y;
+    if (pk >= B) return;
+    const PencilDev P = PD[pk];
+    if (!P.reduce || pe >= P.n) return;
+    const int j0 = pe + (int)blockIdx.x * NC;
+    if (j0 >= P.n) return;
+    const int p = P.p;
+    const long lda = P.ldgt;
+    const GPtr<double2> A(P.Gt);
+    const int tid = threadIdx.x;
+    double2 y[NC][RC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            const int r = ps + tid + i * kGridNT;
+            y[c][i] = (r < p && j0 + c < P.n) ? A.ld(r + (long)(j0 + c) * lda) : cmk(0.0, 0.0);
+        }
+    const int ke = pe < P.n ? pe : P.n;
+    for (int k = ps; k < ke; ++k) {
+        const double nrm = P.qnrm[k];
+        if (nrm == 0.0) continue;
+        const double2 x1 = A.ld(k + (long)k * lda);
+        const double ax1 = sqrt(fnorm2(x1));
+        const double2 ph = ax1 > 0.0 ? cmk(x1.x / ax1, x1.y / ax1) : cmk(1.0, 0.0);
+        const double cf = 1.0 / (nrm * (nrm + ax1));
+        const double2 vk = cscale(ph, ax1 + nrm);
+        double2 v[RC];
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            const int r = ps + tid + i * kGridNT;
+            v[i] = r == k ? vk : ((r > k && r < p) ? A.ld(r + (long)k * lda) : cmk(0.0, 0.0));
+        }
+        double w[2 * NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            w[2 * c] = w[2 * c + 1] = 0.0;
+#pragma unroll
+            for (int i = 0; i < RC; ++i) {
+                w[2 * c] += fdot_re(v[i], y[c][i]);
+                w[2 * c + 1] += fdot_im(v[i], y[c][i]);
+            }
+        }
+        block_sum<2 * NC>(w, red);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double2 tw = cmk(w[2 * c] * cf, w[2 * c + 1] * cf);
+#pragma unroll
+            for (int i = 0; i < RC; ++i) y[c][i] = csub(y[c][i], fmul(v[i], tw));
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int i = 0; i < RC; ++i) {
+            const int r = ps + tid + i * kGridNT;
+            if (r < p && j0 + c < P.n) A.st(r + (long)(j0 + c) * lda, y[c][i]);
+        }
 }
 
 // After the last step: R's diagonal in place and zeros below it.
@@ -1192,8 +1308,14 @@ int run_reduction(BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
             const int per = (len + kGridNT - 1) / kGridNT;
             rows_cap[w] = per > rows_cap[w] ? per : rows_cap[w];
         }
-    int max_m = 0;
-    for (const PencilDev &P : c.host) max_m = P.m > max_m ? P.m : max_m;
+    int max_m = 0, max_p = 0;
+    for (const PencilDev &P : c.host) {
+        max_m = P.m > max_m ? P.m : max_m;
+        if (P.reduce) max_p = P.p > max_p ? P.p : max_p;
+    }
+    // G's QR in panels when every column of G fits the trailing kernel's
+    // registers (else one launch per column step over all trailing columns)
+    const int qpanel = max_p <= kQrRegRows;
     const size_t jl_bytes = align_up((size_t)max_m, 16);
     hipLaunchKernelGGL(k_jqr_init, dim3(B), dim3(256), 0, s, c.dev);
     hipLaunchKernelGGL(k_jqr_colnorms, dim3(c.win[B]), dim3(kGridNT), 0, s, c.dev, c.win_dev, B, 0,
@@ -1216,8 +1338,15 @@ int run_reduction(BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
         // 8 rows per thread only when every column fits: its register
         // count lowers the occupancy of the streaming paths
         auto step_k = rc > 4 && rc <= 8 ? k_jqr_step<8> : k_jqr_step<4>;
-        hipLaunchKernelGGL(step_k, dim3(2 * tot), dim3(kGridNT), jl_bytes, s, c.dev, pw, B, par,
-                           tot, it, jw);
+        const int gq = qpanel ? B * kQrPanel : tot;  // G's workgroups
+        hipLaunchKernelGGL(step_k, dim3(tot + gq), dim3(kGridNT), jl_bytes, s, c.dev, pw, B, par,
+                           tot, it, jw, qpanel);
+        if (qpanel && (it % kQrPanel == kQrPanel - 1 || it == c.max_n - 1)) {
+            const int ps = it - it % kQrPanel, pe = ps + kQrPanel;
+            if (pe < c.max_n)
+                hipLaunchKernelGGL(k_qr_trail, dim3((c.max_n - pe + kQrTrailCols - 1) / kQrTrailCols, B),
+                                   dim3(kGridNT), 0, s, c.dev, B, ps, pe);
+        }
         prof_after(kProfReduce, s, e0, e1);
     }
     hipLaunchKernelGGL(k_jqr_settle, dim3(B), dim3(256), 0, s, c.dev, c.max_n & 1);

@@ -37,8 +37,11 @@ int check_inputs(int m, int n, int p, const double2 *F, long ldf, const int8_t *
 int jsplit_map(int rows, const int8_t *J, int *rowmap, int *nplus_dev, hipStream_t stream);
 
 // F_sq (n x n, columns in the order of P2) of a reduced pencil from its
-// factored columns into dst (ld ldd), rows moved by rowmap (NULL: in place).
-int jqr_extract(const PencilDev &P, double2 *dst, long ldd, const int *rowmap, hipStream_t stream);
+// factored columns into dst (ld ldd), rows moved by rowmap (NULL: in place);
+// scatter = 1 puts column j of the factor at column perm[j] instead (the
+// input's column order).
+int jqr_extract(const PencilDev &P, double2 *dst, long ldd, const int *rowmap, hipStream_t stream,
+                int scatter = 0);
 
 // Identity matrix n x n (ld) of complex128 or complex64.
 int set_identity(int n, void *Z, long ldz, int fp32, hipStream_t stream);

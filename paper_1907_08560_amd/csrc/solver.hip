@@ -69,6 +69,7 @@ void carve_pencil(Carver &c, const Plan &pl, PencilDev &d) {
         d.rblk = c.take<double2>(2 * (size_t)n);
         d.pblk = c.take<int>(2 * (size_t)n);
         d.qdiag = c.take<double2>(n);
+        d.qnrm = c.take<double>(n);
     }
     d.Jw = c.take<int8_t>(2 * (size_t)pl.m);
     d.rowmap = c.take<int>(pl.m > n ? pl.m : n);
@@ -114,7 +115,7 @@ size_t batch_bytes(int B) {
            align_up(sizeof(int) * 2 * (B + 1), 256) + align_up(sizeof(int) * (B + 1), 256) + 256;
 }
 
-static void carve_batch(Carver &c, BatchCtx &bc, int B) {
+void carve_batch(Carver &c, BatchCtx &bc, int B) {
     bc.dev = c.take<PencilDev>(B);
     bc.pre_dev = c.take<int>(BatchCtx::kKinds * (B + 1));
     bc.win_dev = c.take<int>(kWinRows * (B + 1));
@@ -239,6 +240,16 @@ size_t solve_batch_bytes(const std::vector<PencilIO> &io, const ghsvd_options &o
         }
         total += need;
     }
+    if (o.variant == GHSVD_BLOCKED && inner_shortened(o.inner_order)) {
+        size_t need = 0;
+        for (int w : {8, 16, 32}) {
+            if (o.block_width != 0 && o.block_width != w) continue;
+            std::vector<Plan> pl;
+            for (const PencilIO &p : io) pl.push_back(make_plan(p.m, p.n, p.p, o, w));
+            need = std::max(need, short_stage_bytes(pl, w));
+        }
+        total += align_up(need, 256) + 256;
+    }
     return total;
 }
 
@@ -273,6 +284,12 @@ int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *w
         idx[k] = k;
         info[k].m_r = pl.mr;
         info[k].p_r = pl.pr;
+    }
+    if (o.variant == GHSVD_BLOCKED && inner_shortened(o.inner_order)) {
+        std::vector<Plan> pl;
+        for (const PencilIO &p : io) pl.push_back(make_plan(p.m, p.n, p.p, o, w));
+        bc.short_cap = short_stage_bytes(pl, w);
+        bc.short_buf = c.take<char>(bc.short_cap);
     }
     if (!c.ok()) return GHSVD_ENOMEM;
     int rc = upload_batch(bc, s);
@@ -447,6 +464,11 @@ static size_t inplace_bytes(int m, int n, int p, int blocked, int w) {
     return batch_bytes(1) + pencil_bytes(inplace_plan(m, n, p, blocked, w));
 }
 
+// The shortened blocked stage's region of a one-pencil in-place batch.
+static size_t inplace_short_bytes(int m, int n, int p, int w) {
+    return align_up(short_stage_bytes({inplace_plan(m, n, p, 1, w)}, w), 256) + 256;
+}
+
 // Carves a one-pencil in-place batch from buf (cap bytes, 256-byte aligned)
 // and uploads its descriptor.
 static int inplace_batch_at(BatchCtx &bc, void *buf, size_t cap, int m, int n, int p, double *F,
@@ -472,10 +494,18 @@ static int inplace_batch_at(BatchCtx &bc, void *buf, size_t cap, int m, int n, i
 }
 
 static int make_inplace_batch(OwnedBatch &ob, int m, int n, int p, double *F, int ldf, double *G,
-                              int ldg, double *Z, int ldz, int blocked, int w, hipStream_t s) {
-    const size_t need = inplace_bytes(m, n, p, blocked, w);
-    GHSVD_HIP(hipMalloc(&ob.buf, need));
-    return inplace_batch_at(ob.bc, ob.buf, need, m, n, p, F, ldf, G, ldg, Z, ldz, blocked, w, s);
+                              int ldg, double *Z, int ldz, int blocked, int w, hipStream_t s,
+                              int shortened = 0) {
+    const size_t base = align_up(inplace_bytes(m, n, p, blocked, w), 256);
+    const size_t extra = shortened ? inplace_short_bytes(m, n, p, w) : 0;
+    GHSVD_HIP(hipMalloc(&ob.buf, base + extra));
+    const int rc = inplace_batch_at(ob.bc, ob.buf, base, m, n, p, F, ldf, G, ldg, Z, ldz, blocked,
+                                    w, s);
+    if (shortened) {
+        ob.bc.short_buf = reinterpret_cast<char *>(ob.buf) + base;
+        ob.bc.short_cap = extra;
+    }
+    return rc;
 }
 
 __global__ void k_set_nplus(const PencilDev *PD, int nplus) { PD[0].small[1] = nplus; }
@@ -533,7 +563,7 @@ static bool valid_options(const ghsvd_options &o) {
             o.block_width == 32) &&
            o.waves_per_pair >= 0 && o.waves_per_pair <= 16 &&
            (o.inner_order == GHSVD_INNER_FULL || o.inner_order == GHSVD_INNER_CROSS ||
-            o.inner_order == GHSVD_INNER_FB);
+            o.inner_order == GHSVD_INNER_FB || inner_shortened(o.inner_order));
 }
 
 extern "C" size_t ghsvd_workspace_size(int m, int n, int p, const ghsvd_options *opt) {
@@ -737,7 +767,7 @@ static int block_sweeps_args_ok(int m, int n, int p, const double *F, int ldf, i
         return 0;
     if (block_width != 0 && block_width != 8 && block_width != 16 && block_width != 32) return 0;
     return inner_order == GHSVD_INNER_FULL || inner_order == GHSVD_INNER_CROSS ||
-           inner_order == GHSVD_INNER_FB;
+           inner_order == GHSVD_INNER_FB || inner_shortened(inner_order);
 }
 
 // The blocked stage on a prepared one-pencil in-place batch.
@@ -763,7 +793,7 @@ extern "C" int ghsvd_block_sweeps(int m, int n, int p, double *F, int ldf, int n
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     OwnedBatch ob;
     int rc = make_inplace_batch(ob, m, n, p, F, ldf, G, ldg, Z, ldz, 1,
-                                pick_block_width(n, block_width), s);
+                                pick_block_width(n, block_width), s, inner_shortened(inner_order));
     if (rc) return rc;
     return block_sweeps_on(ob.bc, n_plus, inner_order, nsweeps, crit_literal, counters,
                            sweeps_done, s);
@@ -804,7 +834,8 @@ extern "C" int ghsvd_block_sweeps_noalloc(int m, int n, int p, double *F, int ld
                                           int inner_order, int nsweeps, int crit_literal,
                                           long long *counters, int *sweeps_done, void *stream) {
     if (!block_sweeps_args_ok(m, n, p, F, ldf, n_plus, G, ldg, Z, ldz, block_width, inner_order,
-                              nsweeps))
+                              nsweeps) ||
+        inner_shortened(inner_order))
         return GHSVD_EINVAL;
     const int w = pick_block_width(n, block_width);
     if (inplace_bytes(m, n, p, 1, w) > (size_t)GHSVD_NOALLOC_SCRATCH_BYTES) return GHSVD_ENOMEM;

@@ -59,6 +59,24 @@ int solve_batch(const std::vector<PencilIO> &io, const ghsvd_options &o, void *w
                 std::vector<ghsvd_info> &info, hipStream_t s, StageClock *clk = nullptr);
 size_t solve_batch_bytes(const std::vector<PencilIO> &io, const ghsvd_options &o);
 
+// Device bytes shared by a batch of B pencils, carved from c.
+void carve_batch(Carver &c, BatchCtx &bc, int B);
+
+// Block-column update kernel (FP64) of block width w (blocked.hip), for the
+// shortened stage.
+using BlkFn = void (*)(const PencilDev *, const int *, const int *, int, int);
+BlkFn block_update_kernel(int w);
+
+// Blocked FP64 stage with (J)QR-shortened block pivots (shorten.hip): fb = 1
+// runs the Full Block inner level.  Needs c.short_buf of short_stage_bytes.
+int run_blocked_shortened(const BatchCtx &c, int max_sweeps, int crit, int fb, hipStream_t s,
+                          std::vector<SweepResult> &res);
+size_t short_stage_bytes(const std::vector<Plan> &outer, int w);
+constexpr int kShortFbSweeps = 30;  // C_max of the FB inner level
+inline bool inner_shortened(int inner_order) {
+    return inner_order == GHSVD_INNER_FULL_JQR || inner_order == GHSVD_INNER_FB_JQR;
+}
+
 // Blocked and FP32 stages (blocked.hip).
 void set_block_geometry(PencilDev &d, int w);
 size_t blocked_bytes(int mr, int n, int pr, int w, int mixed);

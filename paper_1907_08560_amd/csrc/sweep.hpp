@@ -41,6 +41,10 @@ struct BatchCtx {
                                     // every sweep kernel, written at the end of each round)
     bool plain = false;             // launch rounds directly on the caller's stream: no
                                     // captured graph, internal stream or timing events
+    int stop_all = 0;               // the stage stops a pencil after a sweep with no
+                                    // transformation at all (else: no big one)
+    char *short_buf = nullptr;      // workspace region of the (J)QR-shortened blocked stage
+    size_t short_cap = 0;
 };
 
 // Rows of the reduction's column-window table (see run_reduction).

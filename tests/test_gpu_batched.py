@@ -98,3 +98,24 @@ def test_batched_many_pencils(count):
         assert infos[k]["status"] == 0, (k, infos[k])
         lam1, X1, info1 = ghsvd.solve(*dev[k], **kw)
         assert torch.equal(lam1, lams[k]) and torch.equal(X1, Xs[k]), k
+
+
+@pytest.mark.parametrize("precision,inner", [("fp64", "cross"), ("mixed", "cross"),
+                                             ("fp64", "full"), ("fp64", "fb")])
+def test_large_batch_every_inner_order(oracle_lams, precision, inner):
+    # 112 pencils (14 copies of the batch, 532 block pairs per launch at w = 8)
+    # in every inner ordering: each pencil matches the oracle and equals its
+    # own single solve bit for bit
+    Ps = pencils()
+    dev = [to_dev(P) for P in Ps] * 14
+    kw = dict(precision=precision, variant="blocked", waves_per_pair=4, block_width=8,
+              inner_order=inner)
+    lams, Xs, infos, rc = ghsvd.solve_batched([d[0] for d in dev], [d[1] for d in dev],
+                                              [d[2] for d in dev], **kw)
+    assert rc == 0, infos
+    for k in range(len(Ps)):
+        assert rel_err(host(lams[k]), oracle_lams[k]) <= 1e-10
+    for k in (0, 4, len(Ps) * 13 + 1):
+        lam1, X1, info1 = ghsvd.solve(*dev[k], **kw)
+        assert torch.equal(lam1, lams[k]) and torch.equal(X1, Xs[k]), k
+        assert info1["sweeps_fp64"] == infos[k]["sweeps_fp64"]

@@ -193,3 +193,65 @@ def test_fb_mixed_solve_workload_one(oracle, w):
     assert rel_err(lam, lam_o) <= 1e-12
     e_s, e_h, e_d = factor_invariants(P.F, P.J, P.G, lam, host(X))
     assert e_s < 1e-10 and e_h < 1e-10 and e_d < 1e-10
+
+
+# (J)QR-shortened block pivots (Section 6.4.2): both sides shorten each block
+# pair's columns by the hyperbolic QR with pivoting and the QR of G, and run
+# the inner level one-sidedly on the square factors, so the pivots of the
+# shortening must agree exactly and the factors after one block sweep closely.
+@pytest.mark.parametrize("inner", ["full", "fb"])
+@pytest.mark.parametrize("n,w,s_lo", [(96, 8, 1e-3), (70, 16, 1e-2), (41, 8, 1e-2),
+                                       (150, 32, 1e-2)])
+def test_one_shortened_block_sweep_elementwise(oracle, n, w, s_lo, inner):
+    P = small(700 + n + w, n, s_lo)
+    F, J, G = to_dev(P)
+    Z = ghsvd.to_device_fortran(np.eye(n, dtype=np.complex128))
+    rc, done, cnt = ghsvd.block_sweeps(F, P.m_plus, G, Z, 1, block_width=w,
+                                       inner_order=inner + "_jqr")
+    st, Fo, Go, Zo, stats = oracle.hz_block_run(P.F, P.J, P.G, w=w, max_sweeps=1,
+                                                inner_order=INNER[inner])
+    assert done == 1 and rc in (0, 1) and st in (0, 1)
+    if inner == "full":
+        assert cnt[0, 0] == stats[1]
+        assert abs(cnt[0, 1] - stats[2]) <= max(2, stats[2] // 100)
+    else:
+        assert abs(cnt[0, 0] - stats[1]) <= stats[1] // 10
+    # the bar of the Gram-formed pivots' one-sweep test: G~ is the triangular
+    # factor of G_C here and of G_C P on the oracle's side (same Gram), so the
+    # inner level's sums round differently
+    for A, B in ((host(F), Fo), (host(G), Go), (host(Z), Zo)):
+        colscale = np.linalg.norm(B, axis=0)
+        err = np.max(np.abs(A - B) / colscale[None, :])
+        print(f"shortened n={n} w={w} {inner}: {err:.2e}", flush=True)
+        assert err < 1e-9, err
+
+
+@pytest.mark.parametrize("inner", ["full_jqr", "fb_jqr"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_shortened_solve_workload_one(oracle, inner, precision):
+    P = synth.workload_pencil(1)
+    F, J, G = to_dev(P)
+    lam, X, info = ghsvd.solve(F, J, G, precision=precision, variant="blocked", block_width=8,
+                               inner_order=inner)
+    st, lam_o, X_o, _ = oracle.ghsvd(P.F, P.J, P.G)
+    assert info["status"] == 0 and st == 0, info
+    assert info["sweeps_blocked"] > 0
+    lam = host(lam)
+    assert rel_err(lam, lam_o) <= 1e-12
+    e_s, e_h, e_d = factor_invariants(P.F, P.J, P.G, lam, host(X))
+    assert e_s < 1e-10 and e_h < 1e-10 and e_d < 1e-10
+
+
+def test_shortened_batch_matches_single(oracle):
+    # uneven pencils in one batched call: each equals its own single solve
+    Ps = [small(800 + n, n, 1e-3) for n in (40, 70, 33)]
+    dev = [to_dev(P) for P in Ps]
+    kw = dict(variant="blocked", block_width=8, inner_order="full_jqr")
+    lams, Xs, infos, rc = ghsvd.solve_batched([d[0] for d in dev], [d[1] for d in dev],
+                                              [d[2] for d in dev], **kw)
+    assert rc == 0, infos
+    for k, P in enumerate(Ps):
+        st, lam_o, _, _ = oracle.ghsvd(P.F, P.J, P.G, reduce=True, order=1, max_sweeps=80)
+        assert rel_err(host(lams[k]), lam_o) <= 1e-12
+        lam1, X1, _ = ghsvd.solve(*dev[k], **kw)
+        assert torch.equal(lam1, lams[k]) and torch.equal(X1, Xs[k]), k
