@@ -1465,22 +1465,28 @@ static int blocked_step(const BatchCtx &c, const void *arg, int step, hipStream_
     const int kg = a->fp32 ? kProfGram32 : kProfGram, ki = a->fp32 ? kProfInner32 : kProfInner,
               ku = a->fp32 ? kProfUpdate32 : kProfUpdate;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (tm) prof_before(kg, s, e0, e1);
-    hipLaunchKernelGGL(a->gram, dim3(c.total(BatchCtx::kGram)),
-                       dim3(a->gsum ? kWave * kG64Tiles : kWave * kGramWaves), 0, s, c.dev,
-                       c.pre_of(BatchCtx::kGram), c.flag_dev, c.B, step);
-    if (a->gsum)
-        hipLaunchKernelGGL(a->gsum, dim3(c.total(BatchCtx::kBp), 2 * kG64Tiles), dim3(256), 0, s,
-                           c.dev, c.pre_of(BatchCtx::kBp), c.flag_dev, c.B, step);
-    if (tm) prof_after(kg, s, e0, e1);
-    if (tm) prof_before(ki, s, e0, e1);
-    hipLaunchKernelGGL(a->inner, dim3(c.total(BatchCtx::kBp)), dim3(a->inner_nt), 0, s, c.dev,
-                       c.pre_of(BatchCtx::kBp), c.flag_dev, c.B, a->crit, step, a->mode);
-    if (tm) prof_after(ki, s, e0, e1);
-    if (tm) prof_before(ku, s, e0, e1);
-    hipLaunchKernelGGL(a->upd, dim3(c.total(BatchCtx::kUpd)), dim3(256), 0, s, c.dev,
-                       c.pre_of(BatchCtx::kUpd), c.flag_dev, c.B, step);
-    if (tm) prof_after(ku, s, e0, e1);
+    if (tm) prof_take(kg, e0, e1);
+    const dim3 gb(a->gsum ? kWave * kG64Tiles : kWave * kGramWaves);
+    if (a->gsum) {
+        launch_ev(a->gram, dim3(c.total(BatchCtx::kGram)), gb, 0, s, e0, nullptr, c.dev,
+                  c.pre_of(BatchCtx::kGram), c.flag_dev, c.B, step);
+        launch_ev(a->gsum, dim3(c.total(BatchCtx::kBp), 2 * kG64Tiles), dim3(256), 0, s, nullptr,
+                  e1, c.dev, c.pre_of(BatchCtx::kBp), c.flag_dev, c.B, step);
+    } else {
+        launch_ev(a->gram, dim3(c.total(BatchCtx::kGram)), gb, 0, s, e0, e1, c.dev,
+                  c.pre_of(BatchCtx::kGram), c.flag_dev, c.B, step);
+    }
+    prof_done(kg, e0, e1);
+    e0 = e1 = nullptr;
+    if (tm) prof_take(ki, e0, e1);
+    launch_ev(a->inner, dim3(c.total(BatchCtx::kBp)), dim3(a->inner_nt), 0, s, e0, e1, c.dev,
+              c.pre_of(BatchCtx::kBp), c.flag_dev, c.B, a->crit, step, a->mode);
+    prof_done(ki, e0, e1);
+    e0 = e1 = nullptr;
+    if (tm) prof_take(ku, e0, e1);
+    launch_ev(a->upd, dim3(c.total(BatchCtx::kUpd)), dim3(256), 0, s, e0, e1, c.dev,
+              c.pre_of(BatchCtx::kUpd), c.flag_dev, c.B, step);
+    prof_done(ku, e0, e1);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }

@@ -341,21 +341,20 @@ static hipEvent_t take_event() {
 }
 }  // namespace prof
 
-void prof_before(int kind, hipStream_t s, hipEvent_t &e0, hipEvent_t &e1) {
+void prof_take(int kind, hipEvent_t &e0, hipEvent_t &e1) {
     e0 = e1 = nullptr;
     std::lock_guard<std::mutex> lk(prof::mu);
     if (prof::every <= 0) return;
     if (prof::launches[kind] % prof::every == 0) {
         e0 = prof::take_event();
         e1 = prof::take_event();
-        if (e0 && e1) (void)hipEventRecord(e0, s);
+        if (!e0 || !e1) e0 = e1 = nullptr;
     }
     prof::launches[kind]++;
 }
 
-void prof_after(int kind, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+void prof_done(int kind, hipEvent_t e0, hipEvent_t e1) {
     if (!e0 || !e1) return;
-    (void)hipEventRecord(e1, s);
     std::lock_guard<std::mutex> lk(prof::mu);
     prof::pending[kind].emplace_back(e0, e1);
 }
@@ -488,10 +487,10 @@ static int pointwise_step(const BatchCtx &c, const void *arg, int step, hipStrea
     const PointwiseArg *a = static_cast<const PointwiseArg *>(arg);
     const int kind = a->fp32 ? kProfPair32 : kProfPair64;
     hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (!c.plain) prof_before(kind, s, e0, e1);
-    hipLaunchKernelGGL(a->fn, dim3(c.total(BatchCtx::kSlots)), dim3(a->g.nt), 0, s, c.dev,
-                       c.pre_of(BatchCtx::kSlots), c.flag_dev, c.B, a->crit, step);
-    if (!c.plain) prof_after(kind, s, e0, e1);
+    if (!c.plain) prof_take(kind, e0, e1);
+    launch_ev(a->fn, dim3(c.total(BatchCtx::kSlots)), dim3(a->g.nt), 0, s, e0, e1, c.dev,
+              c.pre_of(BatchCtx::kSlots), c.flag_dev, c.B, a->crit, step);
+    prof_done(kind, e0, e1);
     GHSVD_HIP(hipGetLastError());
     return GHSVD_OK;
 }

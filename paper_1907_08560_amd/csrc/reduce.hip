@@ -1330,24 +1330,26 @@ int run_reduction(BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
         const int tot = c.win[(size_t)w * (B + 1) + B];
         const int jw = w * step;
         if (tot == 0) continue;
+        // timed as one bracket: start of the first launch, end of the last
         hipEvent_t e0 = nullptr, e1 = nullptr;
-        prof_before(kProfReduce, s, e0, e1);
-        hipLaunchKernelGGL(k_jqr_cross, dim3(tot), dim3(kGridNT), 0, s, c.dev, pw, B, par, jw);
+        prof_take(kProfReduce, e0, e1);
+        launch_ev(k_jqr_cross, dim3(tot), dim3(kGridNT), 0, s, e0, nullptr, c.dev, pw, B, par, jw);
         hipLaunchKernelGGL(k_jqr_cross2, dim3(tot), dim3(kGridNT), 0, s, c.dev, pw, B, par, jw);
         const int rc = rows_cap[w];
         // 8 rows per thread only when every column fits: its register
         // count lowers the occupancy of the streaming paths
         auto step_k = rc > 4 && rc <= 8 ? k_jqr_step<8> : k_jqr_step<4>;
         const int gq = qpanel ? B * kQrPanel : tot;  // G's workgroups
-        hipLaunchKernelGGL(step_k, dim3(tot + gq), dim3(kGridNT), jl_bytes, s, c.dev, pw, B, par,
-                           tot, it, jw, qpanel);
-        if (qpanel && (it % kQrPanel == kQrPanel - 1 || it == c.max_n - 1)) {
+        const bool trail = qpanel && (it % kQrPanel == kQrPanel - 1 || it == c.max_n - 1) &&
+                           it - it % kQrPanel + kQrPanel < c.max_n;
+        launch_ev(step_k, dim3(tot + gq), dim3(kGridNT), (uint32_t)jl_bytes, s, nullptr,
+                  trail ? nullptr : e1, c.dev, pw, B, par, tot, it, jw, qpanel);
+        if (trail) {
             const int ps = it - it % kQrPanel, pe = ps + kQrPanel;
-            if (pe < c.max_n)
-                hipLaunchKernelGGL(k_qr_trail, dim3((c.max_n - pe + kQrTrailCols - 1) / kQrTrailCols, B),
-                                   dim3(kGridNT), 0, s, c.dev, B, ps, pe);
+            launch_ev(k_qr_trail, dim3((c.max_n - pe + kQrTrailCols - 1) / kQrTrailCols, B),
+                      dim3(kGridNT), 0, s, nullptr, e1, c.dev, B, ps, pe);
         }
-        prof_after(kProfReduce, s, e0, e1);
+        prof_done(kProfReduce, e0, e1);
     }
     hipLaunchKernelGGL(k_jqr_settle, dim3(B), dim3(256), 0, s, c.dev, c.max_n & 1);
     GHSVD_HIP(hipGetLastError());

@@ -5,12 +5,17 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <tuple>
 #include <vector>
 
 #include "reduce.hpp"
 #include "solver.hpp"
 #include "sweep.hpp"
+
+#ifndef GHSVD_SPLIT_GROUPS
+#define GHSVD_SPLIT_GROUPS 2
+#endif
 
 namespace ghsvd {
 
@@ -575,6 +580,8 @@ extern "C" size_t ghsvd_workspace_size(int m, int n, int p, const ghsvd_options 
     return solve_batch_bytes(io, o);
 }
 
+static size_t batch_need(const std::vector<PencilIO> &io, const ghsvd_options &o);
+
 extern "C" size_t ghsvd_workspace_size_batched(int batch, const int *m, const int *n, const int *p,
                                                const ghsvd_options *opt) {
     if (batch < 1 || !m || !n || !p) return 0;
@@ -585,12 +592,112 @@ extern "C" size_t ghsvd_workspace_size_batched(int batch, const int *m, const in
         if (!valid_sizes(m[k], n[k], p[k])) return 0;
         io[k] = PencilIO{m[k], n[k], p[k], nullptr, m[k], nullptr, nullptr, p[k], nullptr, nullptr, n[k]};
     }
-    return solve_batch_bytes(io, o);
+    return batch_need(io, o);
+}
+
+// A batch of at least kSplitPencils pencils runs as kSplitGroups groups of
+// about equal work (n^3, longest first), each on its own stream driven by
+// its own host thread: the groups' kernels then overlap on the GPU, one
+// group's latency-bound launches (reduction column steps, inner sweeps)
+// beside another's bandwidth-bound ones.  No computation crosses pencils,
+// so every pencil's result is the same as in a single solve.
+constexpr int kSplitPencils = 16;
+constexpr int kSplitGroups = GHSVD_SPLIT_GROUPS;
+
+static bool split_batch(const std::vector<PencilIO> &io, std::vector<std::vector<int>> &g) {
+    g.clear();
+    if ((int)io.size() < kSplitPencils || kSplitGroups < 2) return false;
+    std::vector<int> ord(io.size());
+    for (size_t k = 0; k < io.size(); ++k) ord[k] = (int)k;
+    auto work = [&](int k) { return (double)io[k].n * io[k].n * io[k].n; };
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return work(a) > work(b); });
+    g.assign(kSplitGroups, {});
+    std::vector<double> w(kSplitGroups, 0.0);
+    for (int k : ord) {
+        int best = 0;
+        for (int i = 1; i < kSplitGroups; ++i)
+            if (w[i] < w[best]) best = i;
+        g[best].push_back(k);
+        w[best] += work(k);
+    }
+    for (auto &x : g) std::sort(x.begin(), x.end());
+    return true;
+}
+
+static std::vector<PencilIO> pick(const std::vector<PencilIO> &io, const std::vector<int> &g) {
+    std::vector<PencilIO> r;
+    for (int k : g) r.push_back(io[k]);
+    return r;
+}
+
+// Workspace of a batch as run_with_workspace runs it.
+static size_t batch_need(const std::vector<PencilIO> &io, const ghsvd_options &o) {
+    std::vector<std::vector<int>> g;
+    if (!split_batch(io, g)) return solve_batch_bytes(io, o);
+    size_t total = 0;
+    for (const auto &x : g) total += align_up(solve_batch_bytes(pick(io, x), o), 256);
+    return total;
+}
+
+// The groups of a split batch, each on its own stream and host thread.
+static int solve_split(const std::vector<PencilIO> &io, const std::vector<std::vector<int>> &g,
+                       const ghsvd_options &o, void *work, std::vector<ghsvd_info> &info,
+                       hipStream_t s) {
+    const int G = (int)g.size();
+    std::vector<std::vector<PencilIO>> iog(G);
+    std::vector<size_t> off(G + 1, 0);
+    for (int i = 0; i < G; ++i) {
+        iog[i] = pick(io, g[i]);
+        off[i + 1] = off[i] + align_up(solve_batch_bytes(iog[i], o), 256);
+    }
+    std::vector<hipStream_t> st(G, nullptr);
+    std::vector<hipEvent_t> ev(G + 1, nullptr);
+    struct Guard {
+        std::vector<hipStream_t> &st;
+        std::vector<hipEvent_t> &ev;
+        ~Guard() {
+            for (hipStream_t x : st)
+                if (x) (void)hipStreamDestroy(x);
+            for (hipEvent_t x : ev)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } guard{st, ev};
+    for (int i = 0; i < G; ++i) GHSVD_HIP(hipStreamCreateWithFlags(&st[i], hipStreamNonBlocking));
+    for (int i = 0; i <= G; ++i) GHSVD_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+    // every group starts after the caller's prior work on s
+    GHSVD_HIP(hipEventRecord(ev[G], s));
+    for (int i = 0; i < G; ++i) GHSVD_HIP(hipStreamWaitEvent(st[i], ev[G], 0));
+    std::vector<std::vector<ghsvd_info>> inf(G);
+    std::vector<int> rc(G, GHSVD_OK);
+    char *w = reinterpret_cast<char *>(work);
+    std::vector<std::thread> th;
+    for (int i = 1; i < G; ++i)
+        th.emplace_back([&, i] {
+            rc[i] = solve_batch(iog[i], o, w + off[i], off[i + 1] - off[i], inf[i], st[i]);
+        });
+    rc[0] = solve_batch(iog[0], o, w, off[1], inf[0], st[0]);
+    for (auto &t : th) t.join();
+    // s continues after every group
+    for (int i = 0; i < G; ++i) {
+        GHSVD_HIP(hipEventRecord(ev[i], st[i]));
+        GHSVD_HIP(hipStreamWaitEvent(s, ev[i], 0));
+    }
+    GHSVD_HIP(hipStreamSynchronize(s));
+    info.assign(io.size(), ghsvd_info{});
+    int worst = GHSVD_OK;
+    for (int i = 0; i < G; ++i) {
+        for (size_t k = 0; k < g[i].size(); ++k) {
+            if (k < inf[i].size()) info[g[i][k]] = inf[i][k];
+            else info[g[i][k]].status = rc[i] < 0 ? rc[i] : GHSVD_EDEVICE;
+        }
+        worst = worst_of(worst, rc[i]);
+    }
+    return worst;
 }
 
 static int run_with_workspace(const std::vector<PencilIO> &io, const ghsvd_options &o, void *work,
                               size_t lwork, std::vector<ghsvd_info> &info, hipStream_t s) {
-    const size_t need = solve_batch_bytes(io, o);
+    const size_t need = batch_need(io, o);
     void *own = nullptr;
     if (!work) {
         if (hipMalloc(&own, need) != hipSuccess) return GHSVD_EDEVICE;
@@ -603,7 +710,9 @@ static int run_with_workspace(const std::vector<PencilIO> &io, const ghsvd_optio
         info.assign(io.size(), ghsvd_info{});
         for (auto &i : info) i.status = rc;
     } else {
-        rc = solve_batch(io, o, work, lwork, info, s);
+        std::vector<std::vector<int>> g;
+        rc = split_batch(io, g) ? solve_split(io, g, o, work, info, s)
+                                : solve_batch(io, o, work, lwork, info, s);
         if (rc == GHSVD_EDEVICE || rc == GHSVD_ENOMEM)
             for (auto &i : info)
                 if (i.status >= 0) i.status = rc;

@@ -1,6 +1,8 @@
 // sweep.hpp -- sweep stages over a batch of pencils.
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include <vector>
 
 #include "batch.hpp"
@@ -74,8 +76,21 @@ void trace_stage(const char *name, int pencil, const SweepState &hs);
 // Sweep-kernel timing record (see ghsvd_profile_enable), per kernel kind.
 enum { kProfPair64 = 0, kProfPair32 = 1, kProfGram = 2, kProfInner = 3, kProfUpdate = 4,
        kProfGram32 = 5, kProfInner32 = 6, kProfUpdate32 = 7, kProfReduce = 8, kProfKinds = 9 };
-void prof_before(int kind, hipStream_t s, hipEvent_t &e0, hipEvent_t &e1);
-void prof_after(int kind, hipStream_t s, hipEvent_t e0, hipEvent_t e1);
+// prof_take decides whether this launch of `kind` is sampled and, if so,
+// hands out two events (else nullptr) for the launch itself to record at the
+// kernel's start and end (launch_ev); prof_done files the pair.
+void prof_take(int kind, hipEvent_t &e0, hipEvent_t &e1);
+void prof_done(int kind, hipEvent_t e0, hipEvent_t e1);
+
+// A kernel launch that records e0 as the kernel starts and e1 as it ends
+// (hipExtLaunchKernelGGL), so a sampled duration is the kernel's own; with
+// no events it is a plain launch (also under graph capture).
+template <typename F, typename... Args>
+inline void launch_ev(F k, dim3 g, dim3 b, uint32_t shm, hipStream_t s, hipEvent_t e0,
+                      hipEvent_t e1, Args... args) {
+    if (e0 || e1) hipExtLaunchKernelGGL(k, g, b, shm, s, e0, e1, 0, args...);
+    else hipLaunchKernelGGL(k, g, b, shm, s, args...);
+}
 
 // Shared host loop of the stages: resets the per-pencil states (blocked = 1
 // retires pencils too small for blocking at once), then runs rounds until
