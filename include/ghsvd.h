@@ -320,6 +320,63 @@ int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_plus, const 
                void *stream);
 
 /*
+ * Phase 1 (Section 4): the simultaneous factorizations of the atom blocks.
+ *
+ * ghsvd_hebpj_batched: ZHEBPJ (Sections 4.2, 4.3) of n_atoms Hermitian
+ * matrices T_a of order r (1 <= r <= 512), one workgroup per atom:
+ * T_a = Mt_a^* diag(Jt_a) Mt_a by the Hermitian indefinite factorization with
+ * Bunch-Parlett complete pivoting (pivot of order 1 when the largest diagonal
+ * modulus is at least alpha = (1 + sqrt 17) / 8 times the largest modulus of
+ * the Schur complement, else the largest off-diagonal entry as a pivot of
+ * order 2; moduli compared squared; ties to the first entry in column-major
+ * order), its order-2 pivots diagonalized by a Jacobi rotation and every
+ * pivot's rows scaled to signs +-1, the columns put back in the original
+ * order (M^ = M P) and the rows permuted stably so that the positive signs
+ * come first, then the negative ones.  A Schur complement that is exactly
+ * zero ends the factorization: the rest of Mt_a is zero and its signs 0
+ * (placed last).
+ *   T     device, r x r x n_atoms complex128 (interleaved re/im), T_a
+ *         column-major with leading dimension r, atom stride r^2; only the
+ *         upper triangle and the real part of the diagonal are read.
+ *   Mt    device output, r x r x n_atoms complex128, same layout.
+ *   Jt    device output, r x n_atoms int8 (+1, -1, 0).
+ *   piv   device output, r x n_atoms int: the index of T_a eliminated at
+ *         pivoted position k, stored as -(index + 1) for both positions of an
+ *         order-2 pivot.
+ *   stats device output, 2 ints per atom: the number of order-2 pivots (or
+ *         GHSVD_ENONFINITE when T_a holds a NaN or Inf; Mt_a and Jt_a are
+ *         then zero) and the number of zero signs.
+ *   work  device, 256-byte aligned, lwork >= ghsvd_hebpj_workspace_size
+ *         (2 r^2 n_atoms complex128: the working triangles and the factor rows
+ *         in pivot order), owned by the caller.
+ * Asynchronous on `stream`; errors returned are only GHSVD_EINVAL (sizes,
+ * NULL pointers, misaligned work) and GHSVD_ENOMEM (short workspace).
+ *
+ * ghsvd_phase1: the per-atom loop of Section 4.4 for n_atoms atoms of
+ * 2 nl x n blocks (eq. (4.1), (4.2)): T_a = Mt_a^* Jt_a Mt_a as above,
+ * F~_a = Mt_a H_a (FP64 matrix cores), G~_a = [A_a; U_a B_a], stacked by atom.
+ *   H     device, m x n complex128, m = 2 nl n_atoms, ldh >= m; rows
+ *         2 nl a .. 2 nl a + 2 nl - 1 are H_a = [A_a; B_a].
+ *   U     device, nl x n_atoms doubles: column a is the diagonal of U_a.
+ *   F, G  device outputs, m x n complex128 (ldf, ldg >= m): F~ and G~.
+ *   J     device output, m int8: J~ (per atom: +1 first, then -1, then 0).
+ *   stats device output, 2 ints per atom as for ghsvd_hebpj_batched.
+ *   work  lwork >= ghsvd_phase1_workspace_size(n_atoms, nl) bytes (the
+ *         factorization workspace plus Mt and piv).
+ * Then H = F~^* J~ F~ = sum_a H_a^* T_a H_a and S = G~^* G~ = sum_a S_a^* S_a;
+ * rows with J~ = 0 are zero rows of F~ and may be dropped before a solve.
+ * Asynchronous; errors as above, plus GHSVD_EINVAL for n < 1 or a leading
+ * dimension below m.
+ */
+size_t ghsvd_hebpj_workspace_size(int n_atoms, int r);  /* 0 for bad sizes */
+int ghsvd_hebpj_batched(int n_atoms, int r, const double *T, double *Mt, signed char *Jt,
+                        int *piv, int *stats, void *work, size_t lwork, void *stream);
+size_t ghsvd_phase1_workspace_size(int n_atoms, int nl);  /* 0 for bad sizes */
+int ghsvd_phase1(int n_atoms, int nl, int n, const double *T, const double *H, int ldh,
+                 const double *U, double *F, int ldf, signed char *J, double *G, int ldg,
+                 int *stats, void *work, size_t lwork, void *stream);
+
+/*
  * The round-robin ordering (host): N = n rounded up to even; step s pairs
  * slot N-1 with s and (s+k) mod (N-1) with (s-k) mod (N-1), k = 1..N/2-1;
  * each pair as p < q; a pair meeting index n (odd n) is a bye, p = q = -1.

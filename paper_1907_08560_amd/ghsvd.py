@@ -97,6 +97,14 @@ _lib.ghsvd_full.argtypes = [_i, _i, _i, _p, _i, _i, _p, _i, _p, _i, _p, _i, _p, 
 _lib.ghsvd_full.restype = _i
 _lib.ghsvd_full_workspace_size.argtypes = [_i]
 _lib.ghsvd_full_workspace_size.restype = _sz
+_lib.ghsvd_hebpj_workspace_size.argtypes = [_i, _i]
+_lib.ghsvd_hebpj_workspace_size.restype = _sz
+_lib.ghsvd_hebpj_batched.argtypes = [_i, _i, _p, _p, _p, _p, _p, _p, _sz, _p]
+_lib.ghsvd_hebpj_batched.restype = _i
+_lib.ghsvd_phase1_workspace_size.argtypes = [_i, _i]
+_lib.ghsvd_phase1_workspace_size.restype = _sz
+_lib.ghsvd_phase1.argtypes = [_i, _i, _i, _p, _p, _i, _p, _p, _i, _p, _p, _i, _p, _p, _sz, _p]
+_lib.ghsvd_phase1.restype = _i
 _lib.ghsvd_status_string.argtypes = [_i]
 _lib.ghsvd_status_string.restype = ctypes.c_char_p
 
@@ -105,7 +113,8 @@ EXPORTED = ["ghsvd_default_options", "ghsvd_workspace_size", "ghsvd_solve",
             "ghsvd_pair_params", "ghsvd_sweeps", "ghsvd_round_robin", "ghsvd_status_string",
             "ghsvd_profile_enable", "ghsvd_profile_read", "ghsvd_block_sweeps",
             "ghsvd_autotune", "ghsvd_autotune_clear", "ghsvd_full", "ghsvd_full_workspace_size",
-            "ghsvd_block_sweeps_noalloc"]
+            "ghsvd_block_sweeps_noalloc", "ghsvd_hebpj_workspace_size", "ghsvd_hebpj_batched",
+            "ghsvd_phase1_workspace_size", "ghsvd_phase1"]
 
 
 class GhsvdError(RuntimeError):
@@ -311,6 +320,60 @@ def full(F, n_plus: int, G, Z, work=None, stream=None):
     if rc < 0:
         raise GhsvdError(rc, "ghsvd_full")
     return U, V, sf, sg, X
+
+
+def hebpj_batched(T, work=None, stream=None):
+    """ZHEBPJ of every atom block (ghsvd_hebpj_batched).  T: complex128 CUDA
+    tensor of shape (n_atoms, r, r) whose [a] is T_a transposed in memory, i.e.
+    T_a column-major (`atoms_to_device` builds it).  Returns (Mt, Jt, piv,
+    stats) with Mt of the same layout, Jt (n_atoms, r) int8, piv (n_atoms, r)
+    int32, stats (n_atoms, 2) int32."""
+    na, r, r2 = T.shape
+    if r != r2 or T.dtype != torch.complex128 or not T.is_cuda or not T.is_contiguous():
+        raise ValueError("T must be a contiguous complex128 CUDA tensor (n_atoms, r, r)")
+    Mt = torch.empty_like(T)
+    Jt = torch.empty((na, r), dtype=torch.int8, device=T.device)
+    piv = torch.empty((na, r), dtype=torch.int32, device=T.device)
+    stats = torch.empty((na, 2), dtype=torch.int32, device=T.device)
+    if work is None:
+        work = torch.empty(max(int(_lib.ghsvd_hebpj_workspace_size(na, r)), 1),
+                           dtype=torch.uint8, device=T.device)
+    rc = _lib.ghsvd_hebpj_batched(na, r, T.data_ptr(), Mt.data_ptr(), Jt.data_ptr(),
+                                  piv.data_ptr(), stats.data_ptr(), work.data_ptr(),
+                                  work.numel(), _stream_ptr(stream))
+    if rc < 0:
+        raise GhsvdError(rc, "ghsvd_hebpj_batched")
+    return Mt, Jt, piv, stats
+
+
+def atoms_to_device(T: np.ndarray, device="cuda") -> torch.Tensor:
+    """(r, r, n_atoms) column-major numpy blocks -> (n_atoms, r, r) tensor whose
+    [a] holds T_a column-major (memory order i + r j + r^2 a)."""
+    return torch.from_numpy(np.ascontiguousarray(np.transpose(T, (2, 1, 0)))).to(device)
+
+
+def phase1(T, H, U, work=None, stream=None):
+    """Phase 1 (ghsvd_phase1): (F, J, G, stats).  T as for `hebpj_batched`,
+    H a column-major complex128 CUDA tensor (2 nl n_atoms, n), U a float64
+    CUDA tensor (n_atoms, nl) (row a = the diagonal of U_a)."""
+    na, r, _ = T.shape
+    nl = r // 2
+    m, n = H.shape
+    if U.dtype != torch.float64 or tuple(U.shape) != (na, nl) or not U.is_contiguous():
+        raise ValueError("U must be a contiguous float64 tensor (n_atoms, nl)")
+    F = fortran_empty(m, n, device=H.device)
+    G = fortran_empty(m, n, device=H.device)
+    J = torch.empty(m, dtype=torch.int8, device=H.device)
+    stats = torch.empty((na, 2), dtype=torch.int32, device=H.device)
+    if work is None:
+        work = torch.empty(max(int(_lib.ghsvd_phase1_workspace_size(na, nl)), 1),
+                           dtype=torch.uint8, device=H.device)
+    rc = _lib.ghsvd_phase1(na, nl, n, T.data_ptr(), H.data_ptr(), _check_fortran(H, "H"),
+                           U.data_ptr(), F.data_ptr(), m, J.data_ptr(), G.data_ptr(), m,
+                           stats.data_ptr(), work.data_ptr(), work.numel(), _stream_ptr(stream))
+    if rc < 0:
+        raise GhsvdError(rc, "ghsvd_phase1")
+    return F, J, G, stats
 
 
 def round_robin(n: int):

@@ -202,3 +202,57 @@ def random_pairs(seed: int, count: int) -> dict:
     c = scale_h * np.sqrt(sa * sb) * (rng.standard_normal(count)
                                        + 1j * rng.standard_normal(count))
     return dict(a=a, b=b, c=c, sa=sa, sb=sb, sc=sc)
+
+
+# ----------------------------------------------------------------------------
+# Phase 1 inputs (Section 4.1): atom blocks T_a, H_a = [A_a; B_a], U_a.
+#
+# Recipe for atom a of a set (seed, kind, N_L, n), all from the generator
+# pencil_rng(seed, N_A, a), in this order:
+#   * T_a = Q diag(l) Q^*, r = 2 N_L, Q an r x r Haar unitary, |l_i| =
+#     10**Uniform(-2, 0) i.i.d.; kind "A": 3 positive and r - 3 negative l_i
+#     (the sign pattern the paper reports for its datasets A), kind "B": atoms
+#     of even index positive definite, odd index negative definite (datasets
+#     B); the signs are then shuffled, so the pivoting has work to do.
+#   * H_a: r x n, entries i.i.d. (N(0,1) + i N(0,1)) / sqrt(2).
+#   * u_a: N_L doubles, Uniform(0.5, 2) (the diagonal of U_a).
+# The paper's shapes: A1 (N_L = 121, N_A = 108, n = 3275) and B1 (N_L = 49,
+# N_A = 512, n = 2256).
+# ----------------------------------------------------------------------------
+PHASE1_SETS = {
+    "A1": dict(kind="A", nl=121, atoms=108, n=3275, seed=2001),
+    "B1": dict(kind="B", nl=49, atoms=512, n=2256, seed=2002),
+}
+
+
+def phase1_atom(seed: int, atoms: int, a: int, kind: str, nl: int, n: int):
+    """(T_a, H_a, u_a) of atom a: T_a r x r and H_a r x n complex128 (Fortran
+    order), u_a N_L doubles."""
+    rng = pencil_rng(seed, atoms, a)
+    r = 2 * nl
+    Q = haar_frame(rng, r, r)
+    mag = 10.0 ** rng.uniform(-2.0, 0.0, size=r)
+    if kind == "A":
+        sign = np.where(np.arange(r) < min(3, r), 1.0, -1.0)
+    else:
+        sign = np.full(r, 1.0 if a % 2 == 0 else -1.0)
+    sign = sign[rng.permutation(r)]
+    T = (Q * (sign * mag)[None, :]) @ Q.conj().T
+    T = 0.5 * (T + T.conj().T)
+    H = _gauss(rng, r, n)
+    u = rng.uniform(0.5, 2.0, size=nl)
+    return np.asfortranarray(T), np.asfortranarray(H), u
+
+
+def phase1_set(seed: int, atoms: int, kind: str, nl: int, n: int):
+    """All atoms: T (r, r, N_A) Fortran, H (r N_A, n) Fortran, U (N_L, N_A)."""
+    r = 2 * nl
+    T = np.zeros((r, r, atoms), dtype=np.complex128, order="F")
+    H = np.zeros((r * atoms, n), dtype=np.complex128, order="F")
+    U = np.zeros((nl, atoms), order="F")
+    for a in range(atoms):
+        Ta, Ha, ua = phase1_atom(seed, atoms, a, kind, nl, n)
+        T[:, :, a] = Ta
+        H[a * r:(a + 1) * r, :] = Ha
+        U[:, a] = ua
+    return T, H, U
