@@ -20,11 +20,14 @@ Beside it the line reports:
     dominant kernel of the headline path;
   * the CPU oracle on a bounded sample of the batch, in a process pool;
   * the single n = 1024 pencil at cond(S) = 1e16 (FP64 and mixed blocked, and
-    the full GHSVD of its swept factors with the errors (7.1)).
+    the full GHSVD of its swept factors with the errors (7.1));
+  * Phase 1 (ZHEBPJ of the atom blocks and the assembly of F~, J~, G~) on the
+    A1- and B1-shaped atom sets, with the product kernel's MFMA roofline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 4|2|3|5]
                     [--block-width 0|8|16|32] [--inner cross|full|fb]
                     [--no-compare] [--no-cpu-baseline] [--no-workload2] [--no-full]
+                    [--no-phase1]
 
 --workload 2 times single solves of the n = 1024 pencil on one path
 (--precision, --variant); 3 and 5 time the large pencils on the blocked paths.
@@ -408,6 +411,63 @@ def workload2_leg(args, ghsvd, synth, torch, dev):
     return out
 
 
+def phase1_leg(ghsvd, synth, torch, dev, reps=3):
+    """Phase 1 (Section 4) on the A1- and B1-shaped atom sets: the whole
+    ghsvd_phase1 call and ZHEBPJ alone (median of `reps` after one warm-up,
+    HIP events on the launch stream), the product kernel's FP64 MFMA
+    roofline (8 r^2 n flops per atom, r = 2 N_L), and eq. (4.2) checked on
+    the first and last atom: F~_a^* J~_a F~_a = H_a^* T_a H_a."""
+    out = {}
+    for name, cfg in synth.PHASE1_SETS.items():
+        T, H, U = synth.phase1_set(cfg["seed"], cfg["atoms"], cfg["kind"], cfg["nl"], cfg["n"])
+        r, na, n = 2 * cfg["nl"], cfg["atoms"], cfg["n"]
+        Td = ghsvd.atoms_to_device(T, dev)
+        Hd = ghsvd.to_device_fortran(H, dev)
+        Ud = torch.from_numpy(np.ascontiguousarray(U.T)).to(dev)
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                res = fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            return float(np.median(ts)), res
+
+        t_all, (F, J, G, stats) = timed(lambda: ghsvd.phase1(Td, Hd, Ud))
+        t_bpj, _ = timed(lambda: ghsvd.hebpj_batched(Td))
+        t_apply = max(t_all - t_bpj, 1e-6)
+        flops = 8.0 * r * r * n * na
+        errs = []
+        for a in (0, na - 1):
+            Ha = H[a * r:(a + 1) * r]
+            ref = Ha.conj().T @ (T[:, :, a] @ Ha)
+            Fa = F[a * r:(a + 1) * r].cpu().numpy()
+            Ja = J[a * r:(a + 1) * r].cpu().numpy().astype(np.float64)
+            got = Fa.conj().T @ (Ja[:, None] * Fa)
+            errs.append(float(np.abs(got - ref).max() / np.abs(ref).max()))
+        out[name] = {
+            "atoms": na, "n_l": cfg["nl"], "n": n, "m": r * na,
+            "ms": t_all, "ms_hebpj": t_bpj, "ms_product_and_g": t_apply,
+            "atoms_per_s": na / (t_all / 1000.0),
+            "product_roofline": {"bound": "mfma", "achieved": flops / (t_apply * 1e-3) / 1e12,
+                                 "peak": 78.6, "unit": "TFLOP/s",
+                                 "frac": flops / (t_apply * 1e-3) / 1e12 / 78.6,
+                                 "hbm_bytes": 3.0 * r * na * n * 16,
+                                 "note": "time = whole call minus ZHEBPJ alone"},
+            "status_ok": bool((stats[:, 0] >= 0).all().item()),
+            "eq_4_2_rel_err_sampled": max(errs)}
+        log(f"phase 1 {name}: {t_all:.2f} ms (ZHEBPJ {t_bpj:.2f} ms)")
+        del T, H, Td, Hd, F, G
+        torch.cuda.empty_cache()
+    return out
+
+
 def batched_workload(args, ghsvd, synth, torch, dev):
     """The headline: 64 k-point pencils (n_k uniform in [300, 900], F
     ceil(1.5 n_k) x n_k with a 3:1 signature, G 2 n_k x n_k with s
@@ -495,6 +555,8 @@ def batched_workload(args, ghsvd, synth, torch, dev):
     rec["kernels"] = kern
     if not args.no_workload2:
         rec["workload2"] = workload2_leg(args, ghsvd, synth, torch, dev)
+    if not args.no_phase1:
+        rec["phase1"] = phase1_leg(ghsvd, synth, torch, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         rec["cpu_baseline"] = cpu_baseline_batched(sizes, oracle_sweeps,
@@ -627,6 +689,10 @@ def main():
                          "n=1024 pencil; 3: one n=4096 pencil; 5: the batch of 16 large pencils")
     ap.add_argument("--no-workload2", action="store_true",
                     help="workload 4: skip the single-pencil n=1024 leg")
+    ap.add_argument("--no-phase1", action="store_true",
+                    help="workload 4: skip the Phase 1 leg (A1- and B1-shaped atom sets)")
+    ap.add_argument("--phase1-only", action="store_true",
+                    help="only run the Phase 1 leg and print its record")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -651,6 +717,9 @@ def main():
     from paper_1907_08560_amd import ghsvd, synth
 
     dev = torch.device("cuda:0")
+    if args.phase1_only:
+        print(json.dumps({"phase1": phase1_leg(ghsvd, synth, torch, dev)}), flush=True)
+        return
     if args.workload == 4:
         batched_workload(args, ghsvd, synth, torch, dev)
         return

@@ -320,6 +320,54 @@ int ghsvd_full(int m, int n, int p, const double *F, int ldf, int n_plus, const 
                void *stream);
 
 /*
+ * The explicit-formation alternative (Section 4.5): H = F^* J F and
+ * S = G^* G are formed (FP64 matrix cores) and solved by a Cholesky-based
+ * generalized Hermitian eigensolver: S = R^* R, C = R^{-*} H R^{-1},
+ * C = V diag(lambda) V^* by blocked two-sided Jacobi (block columns of 16;
+ * a 2x2 rotation is applied while |c_pq| exceeds eps sqrt(n) times both
+ * sqrt(|c_pp c_qq|) and ||C||_F; the sweeps stop after one without a
+ * rotation, at most max_sweeps (0 -> 60)), X = R^{-1} V, lambda ascending.
+ * Outputs as ghsvd_solve: H X = S X diag(lambda), X^* S X = I (eq. (3.2)).
+ * Forming S squares the conditioning of G, so the eigenvalues carry a
+ * relative error of order eps cond(S); the route is taken only when the
+ * Cholesky factorization succeeds (every pivot positive and finite) and
+ * (max r_ii / min r_ii)^2 <= cond_max, a lower estimate of cond(S).
+ * Otherwise, with fallback != NULL, the call runs ghsvd_solve with those
+ * options (the implicit HZ path) on the same buffers and returns its status;
+ * with fallback == NULL it returns GHSVD_ERANK.
+ *   m, n, p, F, ldf, J, G, ldg, lambda, X, ldx as for ghsvd_solve (p >= n;
+ *   J entries must be +1 or -1: the fast route reads J > 0 as +1 and does
+ *   not check them; the fallback does).
+ *   work   device, 256-byte aligned, lwork >= ghsvd_fast_workspace_size(m, n,
+ *          p, fallback) (4 n^2 complex128 + O(n^2 / 64), or the fallback's
+ *          size if larger); owned by the caller.
+ *   info   (host, may be NULL) status, path (GHSVD_PATH_FAST or
+ *          GHSVD_PATH_HZ), Jacobi sweeps and rotations, the condition
+ *          estimate (0 when the factorization failed) and the fallback's
+ *          ghsvd_info.
+ * Synchronizes the stream (the factorization's outcome and each sweep's
+ * rotation count are read on the host).  Returns GHSVD_OK,
+ * GHSVD_NOT_CONVERGED (sweep cap), GHSVD_EINVAL (sizes, NULL pointers,
+ * misaligned work), GHSVD_ENOMEM, GHSVD_ERANK (see above) or the fallback's
+ * status.
+ */
+enum { GHSVD_PATH_FAST = 0, GHSVD_PATH_HZ = 1 };
+typedef struct {
+    int status;
+    int path;            /* GHSVD_PATH_FAST or GHSVD_PATH_HZ (the fallback ran) */
+    int sweeps;          /* Jacobi sweeps of the fast route                     */
+    int pad;
+    double cond_est;     /* (max r_ii / min r_ii)^2 of the Cholesky factor      */
+    long long rotations; /* 2x2 rotations applied by the fast route             */
+    ghsvd_info hz;       /* the fallback's counters when path == GHSVD_PATH_HZ  */
+} ghsvd_fast_info;
+size_t ghsvd_fast_workspace_size(int m, int n, int p, const ghsvd_options *fallback);
+int ghsvd_solve_fast(int m, int n, int p, const double *F, int ldf, const signed char *J,
+                     const double *G, int ldg, double *lambda, double *X, int ldx, double cond_max,
+                     int max_sweeps, void *work, size_t lwork, const ghsvd_options *fallback,
+                     ghsvd_fast_info *info, void *stream);
+
+/*
  * Phase 1 (Section 4): the simultaneous factorizations of the atom blocks.
  *
  * ghsvd_hebpj_batched: ZHEBPJ (Sections 4.2, 4.3) of n_atoms Hermitian

@@ -50,6 +50,18 @@ class Info(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class FastInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("path", ctypes.c_int), ("sweeps", ctypes.c_int),
+                ("pad", ctypes.c_int), ("cond_est", ctypes.c_double),
+                ("rotations", ctypes.c_longlong), ("hz", Info)]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("pad", "hz")}
+        d["path"] = "fast" if self.path == 0 else "hz"
+        d["hz"] = self.hz.as_dict()
+        return d
+
+
 _p = ctypes.c_void_p
 _i = ctypes.c_int
 _sz = ctypes.c_size_t
@@ -97,6 +109,11 @@ _lib.ghsvd_full.argtypes = [_i, _i, _i, _p, _i, _i, _p, _i, _p, _i, _p, _i, _p, 
 _lib.ghsvd_full.restype = _i
 _lib.ghsvd_full_workspace_size.argtypes = [_i]
 _lib.ghsvd_full_workspace_size.restype = _sz
+_lib.ghsvd_fast_workspace_size.argtypes = [_i, _i, _i, ctypes.POINTER(Options)]
+_lib.ghsvd_fast_workspace_size.restype = _sz
+_lib.ghsvd_solve_fast.argtypes = [_i, _i, _i, _p, _i, _p, _p, _i, _p, _p, _i, ctypes.c_double, _i,
+                                  _p, _sz, ctypes.POINTER(Options), ctypes.POINTER(FastInfo), _p]
+_lib.ghsvd_solve_fast.restype = _i
 _lib.ghsvd_hebpj_workspace_size.argtypes = [_i, _i]
 _lib.ghsvd_hebpj_workspace_size.restype = _sz
 _lib.ghsvd_hebpj_batched.argtypes = [_i, _i, _p, _p, _p, _p, _p, _p, _sz, _p]
@@ -114,7 +131,8 @@ EXPORTED = ["ghsvd_default_options", "ghsvd_workspace_size", "ghsvd_solve",
             "ghsvd_profile_enable", "ghsvd_profile_read", "ghsvd_block_sweeps",
             "ghsvd_autotune", "ghsvd_autotune_clear", "ghsvd_full", "ghsvd_full_workspace_size",
             "ghsvd_block_sweeps_noalloc", "ghsvd_hebpj_workspace_size", "ghsvd_hebpj_batched",
-            "ghsvd_phase1_workspace_size", "ghsvd_phase1"]
+            "ghsvd_phase1_workspace_size", "ghsvd_phase1", "ghsvd_fast_workspace_size",
+            "ghsvd_solve_fast"]
 
 
 class GhsvdError(RuntimeError):
@@ -197,6 +215,35 @@ def solve(F: torch.Tensor, J: torch.Tensor, G: torch.Tensor, *, work: torch.Tens
                           work.numel(), ctypes.byref(opt), ctypes.byref(info), _stream_ptr(stream))
     if check and rc < 0:
         raise GhsvdError(rc, "ghsvd_solve")
+    return lam, X, info.as_dict()
+
+
+def solve_fast(F: torch.Tensor, J: torch.Tensor, G: torch.Tensor, *, cond_max: float = 1e4,
+               max_sweeps: int = 0, fallback: dict | None = None, work=None, stream=None,
+               check=True):
+    """The explicit-formation route (ghsvd_solve_fast): lambda, X, info dict.
+    fallback: ghsvd_solve options (keyword dict) for the implicit HZ path
+    taken when S is too ill-conditioned, or None to get GHSVD_ERANK instead."""
+    m, n = F.shape
+    p = G.shape[0]
+    ldf = _check_fortran(F, "F")
+    ldg = _check_fortran(G, "G")
+    if J.dtype != torch.int8 or not J.is_cuda or J.numel() != m:
+        raise TypeError("J must be an int8 CUDA tensor with m entries")
+    fb = options(**fallback) if fallback is not None else None
+    fbp = ctypes.byref(fb) if fb is not None else None
+    lam = torch.empty(n, dtype=torch.float64, device=F.device)
+    X = fortran_empty(n, n, device=F.device)
+    if work is None:
+        need = int(_lib.ghsvd_fast_workspace_size(m, n, p, fbp))
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=F.device)
+    info = FastInfo()
+    rc = _lib.ghsvd_solve_fast(m, n, p, F.data_ptr(), ldf, J.data_ptr(), G.data_ptr(), ldg,
+                               lam.data_ptr(), X.data_ptr(), n, float(cond_max), int(max_sweeps),
+                               work.data_ptr(), work.numel(), fbp, ctypes.byref(info),
+                               _stream_ptr(stream))
+    if check and rc < 0:
+        raise GhsvdError(rc, "ghsvd_solve_fast")
     return lam, X, info.as_dict()
 
 
