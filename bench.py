@@ -22,12 +22,14 @@ Beside it the line reports:
   * the single n = 1024 pencil at cond(S) = 1e16 (FP64 and mixed blocked, and
     the full GHSVD of its swept factors with the errors (7.1));
   * Phase 1 (ZHEBPJ of the atom blocks and the assembly of F~, J~, G~) on the
-    A1- and B1-shaped atom sets, with the product kernel's MFMA roofline.
+    A1- and B1-shaped atom sets, with the product kernel's MFMA roofline;
+  * the explicit-formation route (Section 4.5) against the HZ solve on
+    well-conditioned pencils of order 1024 and 2048.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload 4|2|3|5]
                     [--block-width 0|8|16|32] [--inner cross|full|fb]
                     [--no-compare] [--no-cpu-baseline] [--no-workload2] [--no-full]
-                    [--no-phase1]
+                    [--no-phase1] [--no-fast]
 
 --workload 2 times single solves of the n = 1024 pencil on one path
 (--precision, --variant); 3 and 5 time the large pencils on the blocked paths.
@@ -468,6 +470,49 @@ def phase1_leg(ghsvd, synth, torch, dev, reps=3):
     return out
 
 
+def fast_leg(ghsvd, synth, torch, dev, reps=3):
+    """The explicit-formation route (Section 4.5) against the implicit HZ
+    solve on well-conditioned pencils of the workload-2 shape (F 1.5n x n,
+    J 3:1, G 2n x n, s log-uniform in [0.1, 1], so cond(S) <= 1e2), n = 1024
+    and 2048: median wall time of `reps` calls each (inputs resident), the
+    route's Jacobi sweeps, and the largest relative lambda difference."""
+    out = {}
+    for n in (1024, 2048):
+        m = synth.rows_for(n, 1.5)
+        P = synth.random_pencil(3000 + n, n, m, int(round(0.75 * m)), 2 * n, 0.1)
+        F = ghsvd.to_device_fortran(P.F, dev)
+        G = ghsvd.to_device_fortran(P.G, dev)
+        J = torch.from_numpy(P.J).to(dev)
+
+        def timed(fn):
+            res = fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                res = fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            return 1000.0 * float(np.median(ts)), res
+
+        t_fast, (lf, _, inf) = timed(lambda: ghsvd.solve_fast(F, J, G, cond_max=1e4))
+        rec = {"n": n, "m": P.m, "p": P.p, "fast_ms": t_fast, "fast_path": inf["path"],
+               "fast_sweeps": inf["sweeps"], "cond_est": inf["cond_est"]}
+        for prec in ("fp64", "mixed"):
+            t_hz, (lh, _, ih) = timed(lambda: ghsvd.solve(F, J, G, precision=prec,
+                                                          variant="blocked"))
+            rec[f"hz_{prec}_ms"] = t_hz
+            rec[f"hz_{prec}_sweeps"] = ih["sweeps_fp64"] + ih["sweeps_fp32"]
+            if prec == "fp64":
+                a, b = lf.cpu().numpy(), lh.cpu().numpy()
+                rec["max_rel_diff_fast_vs_hz"] = float(np.max(np.abs(a - b) / np.abs(b)))
+        rec["speedup_vs_hz_fp64"] = rec["hz_fp64_ms"] / t_fast
+        out[f"n{n}"] = rec
+        log(f"fast route n={n}: {t_fast:.1f} ms ({inf['sweeps']} sweeps) vs HZ "
+            f"{rec['hz_fp64_ms']:.1f} ms")
+    return out
+
+
 def batched_workload(args, ghsvd, synth, torch, dev):
     """The headline: 64 k-point pencils (n_k uniform in [300, 900], F
     ceil(1.5 n_k) x n_k with a 3:1 signature, G 2 n_k x n_k with s
@@ -557,6 +602,8 @@ def batched_workload(args, ghsvd, synth, torch, dev):
         rec["workload2"] = workload2_leg(args, ghsvd, synth, torch, dev)
     if not args.no_phase1:
         rec["phase1"] = phase1_leg(ghsvd, synth, torch, dev)
+    if not args.no_fast:
+        rec["explicit_formation"] = fast_leg(ghsvd, synth, torch, dev)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         rec["cpu_baseline"] = cpu_baseline_batched(sizes, oracle_sweeps,
@@ -693,6 +740,10 @@ def main():
                     help="workload 4: skip the Phase 1 leg (A1- and B1-shaped atom sets)")
     ap.add_argument("--phase1-only", action="store_true",
                     help="only run the Phase 1 leg and print its record")
+    ap.add_argument("--no-fast", action="store_true",
+                    help="workload 4: skip the explicit-formation leg")
+    ap.add_argument("--fast-only", action="store_true",
+                    help="only run the explicit-formation leg and print its record")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only run a plain device copy of this many bytes (counter calibration)")
     args = ap.parse_args()
@@ -719,6 +770,9 @@ def main():
     dev = torch.device("cuda:0")
     if args.phase1_only:
         print(json.dumps({"phase1": phase1_leg(ghsvd, synth, torch, dev)}), flush=True)
+        return
+    if args.fast_only:
+        print(json.dumps({"explicit_formation": fast_leg(ghsvd, synth, torch, dev)}), flush=True)
         return
     if args.workload == 4:
         batched_workload(args, ghsvd, synth, torch, dev)
