@@ -29,7 +29,6 @@ struct SweepState {
     int noise_floor; // 1: also stop at the noise floor (FP32 stage, see k_end_round)
     int stop_all;    // 1: stop after a sweep with no transformation at all, big or small
                      // (the inner level of a blocked sweep, Section 6.1.7); else no big one
-    unsigned int prev_big;  // big count of the previous sweep (noise-floor plateau)
     unsigned long long hist[3 * kMaxHist];  // (visited, transformed, big) per sweep
 };
 

@@ -190,19 +190,18 @@ __global__ void k_reset_states(const PencilDev *PD, int *flag, const int *presol
         st->max_sweeps = max_sweeps;
         st->noise_floor = noise_floor;
         st->stop_all = stop_all;
-        st->prev_big = 0xffffffffu;
     }
 }
 
 // End of a round, one workgroup per pencil still running: sums the per-slot
 // counters of the sweep just finished in a fixed order, clears them, records
 // them, and applies the stopping rules (Section 6.1.7: no big transformation
-// in the sweep; Algorithm 2: the sweep cap).  The FP32 stage also stops at its
-// noise floor: a sweep with at most one big transformation per 1024 visits,
-// or a plateau -- at most one per 64 visits and no fewer than 3/4 of the
-// previous sweep's.  An indefinite J amplifies FP32 rounding in the J-Grams
-// beyond the criterion's threshold, and the big count then settles at a level
-// that further FP32 sweeps do not lower.
+// in the sweep; Algorithm 2: the sweep cap).  The FP32 stage also stops at
+// the point where its sweeps stop paying: a sweep with at most one big
+// transformation per 8 visited pairs.  Later FP32 sweeps barely shorten the
+// FP64 finish (an indefinite J amplifies FP32 rounding in the J-Grams beyond
+// the criterion's threshold, so the FP32 big count settles well above zero),
+// while each costs about two thirds of an FP64 sweep.
 __global__ __launch_bounds__(256) void k_end_round(const PencilDev *PD, int *flag, int B,
                                                    int blocked) {
     __shared__ double red[3 * 256 / kWave];
@@ -234,14 +233,11 @@ __global__ __launch_bounds__(256) void k_end_round(const PencilDev *PD, int *fla
         } else if (v[st->stop_all ? 1 : 2] == 0.0) {
             st->done = 1;
             st->converged = 1;
-        } else if (st->noise_floor &&
-                   (v[2] * 1024.0 <= v[0] ||
-                    (v[2] * 64.0 <= v[0] && v[2] >= 0.75 * (double)st->prev_big))) {
+        } else if (st->noise_floor && v[2] * 8.0 <= v[0]) {
             st->done = 1;
         } else if (sw + 1 >= st->max_sweeps) {
             st->done = 1;
         }
-        st->prev_big = v[2] < 4294967295.0 ? (unsigned int)v[2] : 0xffffffffu;
         flag[blockIdx.x] = st->done;
     }
 }
