@@ -717,7 +717,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--variant", default="blocked", choices=["pointwise", "blocked"])
-    ap.add_argument("--inner", default="cross", choices=["cross", "full", "fb"],
+    ap.add_argument("--inner", default="cross",
+                    choices=["cross", "full", "fb", "full_jqr", "fb_jqr", "ml_bo", "ml_fb"],
                     help="blocked inner level: one sweep per block pivot in the cross or full "
                          "round-robin ordering (BO), or sweeps to convergence (FB, at most 30; "
                          "the inner kernel's roofline counts one sweep per launch)")

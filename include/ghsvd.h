@@ -94,7 +94,16 @@ typedef struct {
  * runs a batched reduction and pointwise sweep of all its block pairs); the
  * FP32 warm-up keeps Gram-formed pivots. */
 enum { GHSVD_INNER_FULL = 0, GHSVD_INNER_CROSS = 1, GHSVD_INNER_FB = 2, GHSVD_INNER_FULL_JQR = 3,
-       GHSVD_INNER_FB_JQR = 4 };
+       GHSVD_INNER_FB_JQR = 4, GHSVD_INNER_ML_BO = 5, GHSVD_INNER_ML_FB = 6 };
+/* GHSVD_INNER_ML_BO and GHSVD_INNER_ML_FB apply the blocking principle once
+ * more (Section 6.4 notes it can be applied recursively): each block pair's
+ * pivot columns are shortened by (J)QR as for *_JQR, and the shortened
+ * pivot (F~, J^, G~) of order 2w is swept by the Level-2 blocked algorithm
+ * of block width 8 (block pivots formed as Grams, one full round-robin inner
+ * sweep each): one blocked sweep (ML_BO) or blocked sweeps until one applies
+ * no big transformation, at most 30 (ML_FB; the nested level re-forms its
+ * block pivots every sweep, so it stops like an outer level).  FP64 stage
+ * only; the FP32 warm-up uses Gram-formed BO or FB pivots. */
 
 typedef struct {
     int status;

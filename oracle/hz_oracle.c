@@ -791,10 +791,50 @@ int ora_ghsvd(int m, int n, int p, const cplx *F, int ldf, const signed char *J,
  * Algorithm 2's own test does), at most C_max = 30 of them; Z^ accumulates
  * them all.  Only the outer level stops on the absence of big
  * transformations.  BO is the same with C_max = 1.
+ *
+ * inner_order 3 and 4 apply the blocking principle once more (Section 6.4:
+ * the Level-2 principle applied recursively): the shortened block pivot
+ * (F~, J^, G~), of order c, is itself swept by this Level-2 blocked run with
+ * block width ORA_ML_WIDTH and its own BO inner level (inner_order 0), one
+ * blocked sweep (3) or blocked sweeps until one applies no big
+ * transformation, at most C_max = 30 (4); Z^ accumulates them.  The nested
+ * run re-forms its own block pivots every sweep, so rounding keeps small
+ * transformations coming and the "no transformation at all" test of a
+ * pointwise inner level (Section 6.1.7) need not be met: it stops like an
+ * outer level.  stats count the innermost pivot pairs; stats[5] = the most
+ * nested blocked sweeps any block pivot ran.
  */
+#define ORA_ML_WIDTH 8
+
+static int block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J, cplx *G,
+                     int ldg, cplx *Z, int ldz, int w, int max_sweeps, double eps,
+                     int crit_literal, int inner_order, int stop_all, long long *stats);
+
 int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J,
                      cplx *G, int ldg, cplx *Z, int ldz, int w, int max_sweeps,
                      double eps, int crit_literal, int inner_order, long long *stats)
+{
+    if (inner_order < 0 || inner_order > 4) return ORA_EINVAL;
+    return block_run(m, n, p, F, ldf, J, G, ldg, Z, ldz, w, max_sweeps, eps, crit_literal,
+                     inner_order, 0, stats);
+}
+
+/* The same with the stopping test chosen: stop_all = 1 stops after a blocked
+ * sweep with no transformation at all (the test of an inner level, Section
+ * 6.1.7), 0 after one with no big transformation. */
+int ora_hz_block_run_ex(int m, int n, int p, cplx *F, int ldf, const signed char *J,
+                        cplx *G, int ldg, cplx *Z, int ldz, int w, int max_sweeps,
+                        double eps, int crit_literal, int inner_order, int stop_all,
+                        long long *stats)
+{
+    if (inner_order < 0 || inner_order > 4) return ORA_EINVAL;
+    return block_run(m, n, p, F, ldf, J, G, ldg, Z, ldz, w, max_sweeps, eps, crit_literal,
+                     inner_order, stop_all != 0, stats);
+}
+
+static int block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J, cplx *G,
+                     int ldg, cplx *Z, int ldz, int w, int max_sweeps, double eps,
+                     int crit_literal, int inner_order, int stop_all, long long *stats)
 {
     if (m < 1 || n < 2 || p < 1 || ldf < m || ldg < p || ldz < n || w < 1 || max_sweeps < 1)
         return ORA_EINVAL;
@@ -806,7 +846,8 @@ int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J
     bsteps = ora_round_robin(nb, bp, bq);
     const int bslots = nb / 2;
     const int cmax = 2 * w;
-    if (m < cmax || p < cmax) { free(bp); free(bq); return ORA_EINVAL; }
+    const int cneed = cmax < n ? cmax : n;  /* a block pivot's columns: m, p must cover them */
+    if (m < cneed || p < cneed) { free(bp); free(bq); return ORA_EINVAL; }
     int *cols = malloc(sizeof(int) * (size_t)cmax);
     cplx *FC = malloc(sizeof(cplx) * (size_t)m * cmax);
     cplx *GC = malloc(sizeof(cplx) * (size_t)p * cmax);
@@ -855,6 +896,25 @@ int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J
                  * pair of columns is visited once per sweep. */
                 for (int j = 0; j < c; ++j)
                     for (int i = 0; i < c; ++i) Zh[(size_t)j * c + i] = (i == j) ? 1.0 : 0.0;
+                if (inner_order >= 3) {
+                    /* the shortened pivot swept by the Level-2 blocked run */
+                    long long st2[6];
+#if ORA_MUTANT == 16
+                    const int wml = w;
+#else
+                    const int wml = ORA_ML_WIDTH;
+#endif
+                    const int rs = block_run(c, c, c, Ft, c, Jw, Gt, c, Zh, c, wml,
+                                             inner_order == 4 ? 30 : 1, eps, crit_literal, 0, 0,
+                                             st2);
+                    if (rs < 0) { status = rs; goto done; }
+                    stats[1] += st2[1];
+                    tr += st2[2];
+                    big += st2[3];
+                    if (st2[0] > stats[5]) stats[5] = st2[0];
+                    if (st2[2] == 0) continue;
+                    goto update;
+                }
                 int isteps, islots;
                 const int ca = (a * w + w <= n) ? w : (a * w < n ? n - a * w : 0);
                 const int cmax_inner = inner_order == 2 ? 30 : 1;
@@ -897,6 +957,7 @@ int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J
 #endif
                 }
                 if (itr == 0) continue;
+            update:
                 /* F_C <- F_C Z^, G_C <- G_C Z^, Z_C <- Z_C Z^ (Section 6.4.3) */
                 for (int j = 0; j < c; ++j)
                     for (int i = 0; i < m; ++i) {
@@ -924,7 +985,7 @@ int ora_hz_block_run(int m, int n, int p, cplx *F, int ldf, const signed char *J
         stats[2] += tr;
         stats[3] += big;
         stats[4] = big;
-        if (big == 0) { status = ORA_OK; break; }
+        if ((stop_all ? tr : big) == 0) { status = ORA_OK; break; }
     }
 done:
     free(bp); free(bq); free(cols); free(FC); free(GC); free(Ft); free(Gt); free(Zh); free(tmp);

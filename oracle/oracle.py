@@ -65,6 +65,8 @@ class Oracle:
         L.ora_hz_block_run.argtypes = [_c_int, _c_int, _c_int, _p, _c_int, _p, _p, _c_int, _p,
                                        _c_int, _c_int, _c_int, _c_dbl, _c_int, _c_int, _p]
         L.ora_hz_block_run.restype = _c_int
+        L.ora_hz_block_run_ex.argtypes = L.ora_hz_block_run.argtypes[:-1] + [_c_int, _p]
+        L.ora_hz_block_run_ex.restype = _c_int
 
     # -- 2x2 step -------------------------------------------------------------
     def pair_params(self, a, b, c, sa, sb, sc, tol, crit_literal=0):
@@ -107,11 +109,15 @@ class Oracle:
         return st, F, G, Z, stats
 
     def hz_block_run(self, F, J, G, Z=None, w=8, max_sweeps=30, eps=EPS64, crit_literal=0,
-                     inner_order=0):
+                     inner_order=0, stop_all=None):
         """Level-2 block sweeps in place on copies; returns (status, F, G, Z, stats).
         inner_order 0: BO, one round-robin inner sweep per block pivot; 1: BO with
         cross-block inner pairs after the first block step of a sweep; 2: FB, inner
-        sweeps until one applies no big transformation, at most 30."""
+        sweeps until one applies no transformation, at most 30; 3, 4: the shortened
+        pivot swept by a nested Level-2 run of width 8 (one blocked sweep, or
+        blocked sweeps until one applies no transformation, at most 30).
+        stop_all: the run's own stopping test (None or False: a sweep with no big
+        transformation; True: one with no transformation at all)."""
         F = np.array(F, dtype=np.complex128, order="F", copy=True)
         G = np.array(G, dtype=np.complex128, order="F", copy=True)
         m, n = F.shape
@@ -120,9 +126,11 @@ class Oracle:
              else np.array(Z, dtype=np.complex128, order="F", copy=True))
         J8 = np.ascontiguousarray(J, dtype=np.int8)
         stats = np.zeros(6, dtype=np.int64)
-        st = self.lib.ora_hz_block_run(m, n, p, F.ctypes.data, m, J8.ctypes.data, G.ctypes.data,
-                                       p, Z.ctypes.data, n, int(w), int(max_sweeps), float(eps),
-                                       int(crit_literal), int(inner_order), stats.ctypes.data)
+        st = self.lib.ora_hz_block_run_ex(m, n, p, F.ctypes.data, m, J8.ctypes.data,
+                                          G.ctypes.data, p, Z.ctypes.data, n, int(w),
+                                          int(max_sweeps), float(eps), int(crit_literal),
+                                          int(inner_order), int(bool(stop_all)),
+                                          stats.ctypes.data)
         return st, F, G, Z, stats
 
     def hz_post(self, F, J, G, Z, sort=1):

@@ -1499,15 +1499,16 @@ BlkFn block_update_kernel(int w) {
 }
 
 int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, int inner_order,
-                      hipStream_t s,
-                      std::vector<SweepResult> &res) {
+                      hipStream_t s, std::vector<SweepResult> &res,
+                      const std::vector<int> *presolved) {
     if (inner_shortened(inner_order)) {
         // (J)QR-shortened block pivots in the FP64 stage; the FP32 warm-up
         // forms them as Grams with the same inner ordering
+        const bool fbo = inner_order == GHSVD_INNER_FB_JQR || inner_order == GHSVD_INNER_ML_FB;
         if (!fp32)
-            return run_blocked_shortened(c, max_sweeps, crit,
-                                         inner_order == GHSVD_INNER_FB_JQR, s, res);
-        inner_order = inner_order == GHSVD_INNER_FB_JQR ? GHSVD_INNER_FB : GHSVD_INNER_FULL;
+            return run_blocked_shortened(c, max_sweeps, crit, fbo, inner_multilevel(inner_order),
+                                         s, res);
+        inner_order = fbo ? GHSVD_INNER_FB : GHSVD_INNER_FULL;
     }
     int w = 0, steps = 1;
     for (const PencilDev &P : c.host) {
@@ -1547,7 +1548,7 @@ int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, int
         return GHSVD_EINVAL;
     }
     return drive_stage(c, max_sweeps, fp32, 1, blocked_step, &a, steps,
-                       fp32 ? "blocked-fp32" : "blocked-fp64", s, res);
+                       fp32 ? "blocked-fp32" : "blocked-fp64", s, res, presolved);
 }
 
 int to_fp32(const BatchCtx &c, hipStream_t s) {

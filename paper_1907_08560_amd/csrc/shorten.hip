@@ -20,6 +20,11 @@
 // batched one-time reduction and pointwise sweep of the whole path in one
 // sub-batch.  A block step therefore takes about 3 c + c launches instead of
 // three; the stage runs its rounds directly (no captured graph).
+//
+// With three levels (GHSVD_INNER_ML_BO, GHSVD_INNER_ML_FB) the small pencils
+// are swept by the Level-2 blocked stage itself, block width kMlWidth, its
+// block pivots formed as Grams and swept once each in the full round-robin
+// order: the blocking principle applied once more (Section 6.4).
 #include <algorithm>
 #include <vector>
 
@@ -109,9 +114,12 @@ __global__ void k_short_collect(const PencilDev *PD, const PencilDev *SD, const 
 }
 
 // Plan of one block pair's small pencil: F_C (m_r x c) and G_C (p_r x c),
-// always reduced (also when square), swept pointwise in FP64.
+// always reduced (also when square), swept in FP64 pointwise or by the
+// Level-2 blocked stage of width kMlWidth (its scratch is always carved).
 static Plan short_plan(int mr, int c, int pr) {
     Plan pl{};
+    pl.blocked = 1;
+    pl.w = kMlWidth;
     pl.m = mr;
     pl.n = c;
     pl.p = pr;
@@ -151,7 +159,7 @@ size_t short_stage_bytes(const std::vector<Plan> &outer, int w) {
 struct ShortArg {
     BlkFn upd;        // block-column update kernel of the width
     int upd_nt;
-    int crit, fb, PB;
+    int crit, fb, ml, PB;
     char *buf;        // the stage's region of the workspace
     size_t cap;
     int8_t **jsig;    // host copy of the per-pencil signature pointers
@@ -186,7 +194,10 @@ static int short_step(const BatchCtx &c, const void *argp, int step, hipStream_t
         ShortMap *map_dev = cv.take<ShortMap>(S);
         sub.B = S;
         sub.plain = true;
-        sub.stop_all = a->fb;
+        // a pointwise FB inner level stops on a sweep with no transformation
+        // (Section 6.1.7); a nested blocked level re-forms its block pivots
+        // every sweep, so it stops like an outer level, on no big one
+        sub.stop_all = a->fb && !a->ml;
         sub.host.resize(S);
         for (int i = 0; i < S; ++i) {
             const PencilDev &P = c.host[maps[i].pk];
@@ -203,7 +214,6 @@ static int short_step(const BatchCtx &c, const void *argp, int step, hipStream_t
             d.ldgin = pad_ld(P.pr);
             d.Jin = a->jsig[maps[i].pk];
             d.skip_rank = 1;
-            d.w = P.w;
         }
         if (!cv.ok()) return GHSVD_ENOMEM;
         int rc = upload_batch(sub, s);
@@ -235,10 +245,17 @@ static int short_step(const BatchCtx &c, const void *argp, int step, hipStream_t
             if ((rc = jqr_extract(Q, Q.Fw, Q.ldf, Q.rowmap, s, 1))) return rc;
             if ((rc = copy_cols(Q.n, Q.n, Q.Gt, Q.ldgt, Q.Gw, Q.ldg, nullptr, s))) return rc;
         }
-        // the inner level: pointwise FP64 sweeps of the small pencils
+        // the inner level: pointwise FP64 sweeps of the small pencils, or the
+        // Level-2 blocked stage on them (its own inner level one full
+        // round-robin sweep per block pivot), one blocked sweep or sweeps
+        // until one applies no big transformation
         std::vector<SweepResult> res;
-        rc = run_pointwise_stage(sub, 0, a->fb ? kShortFbSweeps : 1, a->crit,
-                                 choose_pair_geom(a->PB, 0), s, res, &failed);
+        if (a->ml)
+            rc = run_blocked_stage(sub, 0, a->fb ? kShortFbSweeps : 1, a->crit, GHSVD_INNER_FULL,
+                                   s, res, &failed);
+        else
+            rc = run_pointwise_stage(sub, 0, a->fb ? kShortFbSweeps : 1, a->crit,
+                                     choose_pair_geom(a->PB, 0), s, res, &failed);
         if (rc < 0 && rc != GHSVD_ENONFINITE) return rc;
         for (int i = 0; i < S; ++i)
             if (res[i].status < 0)
@@ -254,8 +271,8 @@ static int short_step(const BatchCtx &c, const void *argp, int step, hipStream_t
     return GHSVD_OK;
 }
 
-int run_blocked_shortened(const BatchCtx &c, int max_sweeps, int crit, int fb, hipStream_t s,
-                          std::vector<SweepResult> &res) {
+int run_blocked_shortened(const BatchCtx &c, int max_sweeps, int crit, int fb, int ml,
+                          hipStream_t s, std::vector<SweepResult> &res) {
     int w = 0, steps = 1;
     for (const PencilDev &P : c.host) {
         if (w == 0) w = P.w;
@@ -286,6 +303,7 @@ int run_blocked_shortened(const BatchCtx &c, int max_sweeps, int crit, int fb, h
     a.upd_nt = 256;
     a.crit = crit;
     a.fb = fb;
+    a.ml = ml;
     a.PB = 2 * w;
     cv.used = align_up(cv.used, 256);
     a.buf = c.short_buf + cv.used;

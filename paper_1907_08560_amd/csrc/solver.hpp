@@ -68,13 +68,20 @@ using BlkFn = void (*)(const PencilDev *, const int *, const int *, int, int);
 BlkFn block_update_kernel(int w);
 
 // Blocked FP64 stage with (J)QR-shortened block pivots (shorten.hip): fb = 1
-// runs the Full Block inner level.  Needs c.short_buf of short_stage_bytes.
-int run_blocked_shortened(const BatchCtx &c, int max_sweeps, int crit, int fb, hipStream_t s,
-                          std::vector<SweepResult> &res);
+// runs the Full Block inner level; ml = 1 sweeps each shortened pivot with
+// the Level-2 blocked stage of width kMlWidth instead of pointwise sweeps
+// (three levels).  Needs c.short_buf of short_stage_bytes (which covers both).
+int run_blocked_shortened(const BatchCtx &c, int max_sweeps, int crit, int fb, int ml,
+                          hipStream_t s, std::vector<SweepResult> &res);
 size_t short_stage_bytes(const std::vector<Plan> &outer, int w);
 constexpr int kShortFbSweeps = 30;  // C_max of the FB inner level
+constexpr int kMlWidth = 8;         // block width of the nested Level-2 stage
+inline bool inner_multilevel(int inner_order) {
+    return inner_order == GHSVD_INNER_ML_BO || inner_order == GHSVD_INNER_ML_FB;
+}
 inline bool inner_shortened(int inner_order) {
-    return inner_order == GHSVD_INNER_FULL_JQR || inner_order == GHSVD_INNER_FB_JQR;
+    return inner_order == GHSVD_INNER_FULL_JQR || inner_order == GHSVD_INNER_FB_JQR ||
+           inner_multilevel(inner_order);
 }
 
 // Blocked and FP32 stages (blocked.hip).

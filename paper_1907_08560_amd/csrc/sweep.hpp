@@ -65,9 +65,10 @@ int run_pointwise_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, P
                         const std::vector<int> *presolved = nullptr);
 
 // Level-2 blocked sweeps (Section 6.4) for every pencil with n >= 4.
+// presolved as for run_pointwise_stage.
 int run_blocked_stage(const BatchCtx &c, int fp32, int max_sweeps, int crit, int inner_order,
-                      hipStream_t s,
-                      std::vector<SweepResult> &res);
+                      hipStream_t s, std::vector<SweepResult> &res,
+                      const std::vector<int> *presolved = nullptr);
 
 // When the environment variable GHSVD_TRACE is set, prints the per-sweep
 // counters of a finished stage to stderr (one line per sweep).

@@ -166,7 +166,7 @@ def _stream_ptr(stream) -> int:
     return s.cuda_stream
 
 
-INNER = {"full": 0, "cross": 1, "fb": 2, "full_jqr": 3, "fb_jqr": 4}
+INNER = {"full": 0, "cross": 1, "fb": 2, "full_jqr": 3, "fb_jqr": 4, "ml_bo": 5, "ml_fb": 6}
 
 
 def options(precision="fp64", variant="pointwise", reduce=True, block_width=0,

@@ -255,3 +255,57 @@ def test_shortened_batch_matches_single(oracle):
         assert rel_err(host(lams[k]), lam_o) <= 1e-12
         lam1, X1, _ = ghsvd.solve(*dev[k], **kw)
         assert torch.equal(lam1, lams[k]) and torch.equal(X1, Xs[k]), k
+
+
+# Three levels (the blocking principle applied once more, Section 6.4): each
+# shortened block pivot is swept by the Level-2 blocked algorithm of width 8.
+# The GPU forms the nested block pivots as Grams and the oracle shortens them
+# again (R12's difference, one level down), so the factors after one outer
+# block sweep agree to the bar of the shortened test.
+@pytest.mark.parametrize("inner", ["ml_bo", "ml_fb"])
+@pytest.mark.parametrize("n,w,s_lo", [(70, 16, 1e-2), (96, 16, 1e-3), (41, 8, 1e-2),
+                                       (150, 32, 1e-2)])
+def test_one_three_level_block_sweep_elementwise(oracle, n, w, s_lo, inner):
+    P = small(900 + n + w, n, s_lo)
+    F, J, G = to_dev(P)
+    Z = ghsvd.to_device_fortran(np.eye(n, dtype=np.complex128))
+    rc, done, cnt = ghsvd.block_sweeps(F, P.m_plus, G, Z, 1, block_width=w, inner_order=inner)
+    st, Fo, Go, Zo, stats = oracle.hz_block_run(P.F, P.J, P.G, w=w, max_sweeps=1,
+                                                inner_order=3 if inner == "ml_bo" else 4)
+    assert done == 1 and rc in (0, 1) and st in (0, 1)
+    assert abs(cnt[0, 0] - stats[1]) <= max(2, stats[1] // 10), (cnt[0], stats)
+    for A, B in ((host(F), Fo), (host(G), Go), (host(Z), Zo)):
+        colscale = np.linalg.norm(B, axis=0)
+        err = np.max(np.abs(A - B) / colscale[None, :])
+        print(f"three-level n={n} w={w} {inner}: {err:.2e}", flush=True)
+        assert err < 1e-9, err
+
+
+@pytest.mark.parametrize("inner", ["ml_bo", "ml_fb"])
+@pytest.mark.parametrize("w", [8, 16])
+def test_three_level_solve_workload_one(oracle, inner, w):
+    P = synth.workload_pencil(1)
+    F, J, G = to_dev(P)
+    lam, X, info = ghsvd.solve(F, J, G, precision="fp64", variant="blocked", block_width=w,
+                               inner_order=inner)
+    st, lam_o, X_o, _ = oracle.ghsvd(P.F, P.J, P.G)
+    assert info["status"] == 0 and st == 0, info
+    assert info["sweeps_blocked"] > 0
+    lam = host(lam)
+    assert rel_err(lam, lam_o) <= 1e-12
+    e_s, e_h, e_d = factor_invariants(P.F, P.J, P.G, lam, host(X))
+    assert e_s < 1e-10 and e_h < 1e-10 and e_d < 1e-10
+
+
+def test_three_level_batch_matches_single(oracle):
+    Ps = [small(950 + n, n, 1e-3) for n in (40, 70, 33)]
+    dev = [to_dev(P) for P in Ps]
+    kw = dict(variant="blocked", block_width=16, inner_order="ml_fb")
+    lams, Xs, infos, rc = ghsvd.solve_batched([d[0] for d in dev], [d[1] for d in dev],
+                                              [d[2] for d in dev], **kw)
+    assert rc == 0, infos
+    for k, P in enumerate(Ps):
+        st, lam_o, _, _ = oracle.ghsvd(P.F, P.J, P.G, reduce=True, order=1, max_sweeps=80)
+        assert rel_err(host(lams[k]), lam_o) <= 1e-12
+        lam1, X1, _ = ghsvd.solve(*dev[k], **kw)
+        assert torch.equal(lam1, lams[k]) and torch.equal(X1, Xs[k]), k

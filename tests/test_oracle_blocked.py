@@ -111,3 +111,45 @@ def test_fb_inner_level_is_algorithm_2(oracle, seed, n, s_lo):
         err = np.max(np.abs(A - B)) / np.max(np.abs(B))
         assert err < 1e-12, err
 
+
+
+@pytest.mark.parametrize("inner", [3, 4])
+def test_three_level_runs_reach_pointwise_eigenvalues(oracle, inner):
+    n, w = 48, 16
+    P = _pencil(923, n, 1e-3)
+    st, lam_ref, _, _ = oracle.ghsvd(P.F, P.J, P.G, max_sweeps=60)
+    assert st == 0
+    st, F, G, Z, stats = oracle.hz_block_run(P.F, P.J, P.G, w=w, max_sweeps=60, inner_order=inner)
+    assert st == 0
+    st, lam, X = oracle.hz_post(F, P.J, G, Z)
+    assert st == 0
+    assert np.max(np.abs(lam - lam_ref) / np.abs(lam_ref)) < 1e-11
+
+
+def test_three_level_bo_visits_one_nested_sweep(oracle):
+    # n = 2w = 32: one block pivot, shortened to 32 x 32 and swept once by a
+    # Level-2 run of width 8: 4 blocks, 3 block steps of 2 block pivots of 16
+    # columns, each visited once in the full round-robin order (120 pairs)
+    P = _pencil(925, 32, 1e-2)
+    st, F, G, Z, stats = oracle.hz_block_run(P.F, P.J, P.G, w=16, max_sweeps=1, inner_order=3)
+    assert st in (0, 1)
+    assert stats[1] == 3 * 2 * (16 * 15 // 2) and stats[5] == 1
+
+
+@pytest.mark.parametrize("seed,n,s_lo", [(927, 32, 1e-2), (929, 32, 1e-4)])
+def test_three_level_fb_inner_level_is_a_converged_level2_run(oracle, seed, n, s_lo):
+    # n = 2w: the inner level of the first block sweep is the Level-2 blocked
+    # run (width 8, BO inner) on the shortened pivot, run until a blocked
+    # sweep applies no big transformation; a single nested sweep (BO) differs
+    w = n // 2
+    P = _pencil(seed, n, s_lo)
+    st, F, G, Z, stats = oracle.hz_block_run(P.F, P.J, P.G, w=w, max_sweeps=1, inner_order=4)
+    assert st in (0, 1)
+    Ft, Jh, Gt = shortened_pivot(oracle, P.F, P.J, P.G)
+    st1, _, _, Zp, s1 = oracle.hz_block_run(Ft, Jh, Gt, w=8, max_sweeps=30, inner_order=0)
+    assert st1 == 0 and s1[0] > 1
+    assert stats[1] == s1[1] and stats[5] == s1[0]
+    assert stats[2] == s1[2] and stats[3] == s1[3]
+    for A, B in ((F, P.F @ Zp), (G, P.G @ Zp), (Z, Zp)):
+        err = np.max(np.abs(A - B)) / np.max(np.abs(B))
+        assert err < 1e-12, err

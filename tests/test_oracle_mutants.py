@@ -1,6 +1,6 @@
 """Planted mistakes in the oracle must be caught by its pins.
 
-hz_oracle.c carries compile-time switches ORA_MUTANT = 1..15, each a
+hz_oracle.c carries compile-time switches ORA_MUTANT = 1..16, each a
 plausible slip (a sign, a conjugate, a transposed operand, a dropped scaling,
 a wrong index, a skipped pivoting rule).  This test builds each variant on the
 CPU and runs a compact battery of the same independent checks the pin tests
@@ -16,7 +16,7 @@ from oracle import oracle as O
 from paper_1907_08560_amd import synth
 
 EPS = 2.0 ** -52
-MUTANTS = list(range(1, 16))
+MUTANTS = list(range(1, 17))
 
 
 def battery(o):
@@ -101,6 +101,13 @@ def battery(o):
                                 max_sweeps=30, stop_rule=1)
     if st < 0 or st3 != 0 or sb[1] != s3[1]:
         fails.append("fb")
+    # three-level BO on a pencil of one block pair (n = 32, w = 16): one nested
+    # blocked sweep of width 8 over the shortened pivot, 3 block steps of 2
+    # block pivots of 16 columns (120 pairs each)
+    Q = synth.random_pencil(105, 32, 48, 36, 64, 1e-2)
+    st, Fb, Gb, Zb, sb = o.hz_block_run(Q.F, Q.J, Q.G, w=16, max_sweeps=1, inner_order=3)
+    if st < 0 or sb[1] != 3 * 2 * 120:
+        fails.append("ml")
     return fails
 
 
