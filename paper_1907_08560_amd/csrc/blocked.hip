@@ -1177,8 +1177,10 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
     constexpr int NTD = PB / 16;  // output column tiles
     constexpr int KS = PB / 4;    // k-steps
     constexpr int NS = upd_strips(PB / 2);  // strips per wavefront
-    // 64 columns: Z^ is staged in LDS (its operands do not fit in registers)
-    constexpr bool ZL = PB > 32;
+    // 32 and 64 columns: Z^ is staged in LDS (in registers it would hold 64
+    // VGPRs of the 32-column kernel for all strips and cut its occupancy to
+    // two wavefronts per SIMD)
+    constexpr bool ZL = PB >= 32;
     __shared__ C2 Zl[ZL ? PB : 1][ZL ? PB + 1 : 1];
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev A = PD[pk];
@@ -1202,8 +1204,8 @@ __global__ __launch_bounds__(256) void k_blk_update(const PencilDev *PD, const i
         cofs[ks] = cc < c ? (long)blk_col(A.w, a, b, ca, cc) : -1;
     }
     // the A operands Z^[4 ks + kq][16 ti + j] (Z^ column-major, PB x PB):
-    // read straight into registers, where they stay for all strips (32
-    // columns), or staged once in LDS (64 columns)
+    // staged once in LDS (32 and 64 columns), or read straight into
+    // registers, where they stay for all strips (16 columns)
     C2 za[ZL ? 1 : KS][NTD];
     if constexpr (ZL) {
         for (int idx = tid; idx < PB * PB; idx += 256) {
