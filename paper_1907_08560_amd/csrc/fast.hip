@@ -12,8 +12,9 @@
 // pair's 32 x 32 principal submatrix is diagonalized in LDS by one cyclic
 // sweep of 2x2 rotations -- the full round-robin at the first block step of
 // a sweep, only the pairs across the two blocks at the others -- and the
-// accumulated rotation is applied to the block columns of C and V and the
-// block rows of C on MFMA), and X = R^{-1} V, eigenvalues ascending.
+// accumulated rotations are applied two-sidedly to C, block by block on
+// MFMA, and to the block columns of V), and X = R^{-1} V, eigenvalues
+// ascending.
 //
 // A 2x2 rotation is applied when |c_pq| exceeds both eps sqrt(n)
 // sqrt(|c_pp c_qq|) (the relative test of (6.12) with S = I) and eps sqrt(n)
@@ -529,110 +530,95 @@ __global__ __launch_bounds__(256) void k_fx_jinner(int n, int nb, int s, const d
     }
 }
 
-// Column update of C and V: X[:, I] <- X[:, I] Zh for the pair's 32 columns,
-// one workgroup per (pair, 64-row chunk): chunks 0 .. nc - 1 of C, then nc ..
-// 2 nc - 1 of V, nc = ceil(n / 64).
-__global__ __launch_bounds__(256) void k_fx_jcol(int n, int nb, int s, double2 *C, double2 *V,
-                                                 const double2 *Zh, const int *pflag,
-                                                 const int *flag) {
-    __shared__ double2 Xs[64][kJp + 1];
-    __shared__ double2 Zs[kJp][kJp + 1];
-    __shared__ int col[kJp];
-    if (*flag) return;
-    const int npair = nb / 2, k = blockIdx.x % npair, chunk = blockIdx.x / npair;
-    if (!pflag[k]) return;
-    int a, b;
-    rr_pair(nb, s, k, a, b);
-    const int tid = threadIdx.x;
-    if (tid < kJp) col[tid] = jcol(n, a, b, tid);
-    const int nc = (n + 63) / 64;
-    double2 *X = chunk < nc ? C : V;
-    const int r0 = (chunk < nc ? chunk : chunk - nc) * 64;
-    for (int e = tid; e < kJp * kJp; e += blockDim.x) Zs[e & 31][e >> 5] = Zh[(size_t)k * kJp * kJp + e];
-    __syncthreads();
-    for (int e = tid; e < 64 * kJp; e += blockDim.x) {
-        const int i = e & 63, t = e >> 6, c = col[t];
-        Xs[i][t] = (c >= 0 && r0 + i < n) ? X[(size_t)c * n + r0 + i] : cmk(0.0, 0.0);
-    }
-    __syncthreads();
-    // D (64 x 32) = Xs Zs: wavefront w takes rows 16 w .. 16 w + 15, two 16-column tiles
-    const int lane = tid & (kWave - 1), wv = tid >> 6, i16 = lane & 15, kq = lane >> 4;
-    fxv4d re[2], im[2];
-#pragma unroll
-    for (int y = 0; y < 2; ++y) { re[y] = fxv4d{0, 0, 0, 0}; im[y] = fxv4d{0, 0, 0, 0}; }
+// 32 x 32 complex product D = op(A) B on FP64 MFMA, operands and result in
+// LDS: wavefront w forms the 16 x 16 tile (w & 1, w >> 1) of D; op(A) = A
+// (conj_a = 0) or A^* (conj_a = 1).
+__device__ __forceinline__ void mma32(const double2 (*A)[kJp + 1], const double2 (*Bm)[kJp + 1],
+                                      double2 (*D)[kJp + 1], int conj_a) {
+    const int lane = threadIdx.x & (kWave - 1), wv = threadIdx.x >> 6;
+    const int ti = wv & 1, tj = wv >> 1, i16 = lane & 15, kq = lane >> 4;
+    fxv4d re = fxv4d{0, 0, 0, 0}, im = fxv4d{0, 0, 0, 0};
 #pragma unroll
     for (int k0 = 0; k0 < kJp; k0 += 4) {
-        const double2 av = Xs[wv * 16 + i16][k0 + kq];
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-            const double2 bv = Zs[k0 + kq][y * 16 + i16];
-            re[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, re[y], 0, 0, 0);
-            re[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv.y, re[y], 0, 0, 0);
-            im[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, im[y], 0, 0, 0);
-            im[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, im[y], 0, 0, 0);
-        }
+        const double2 av = conj_a ? cconj(A[k0 + kq][ti * 16 + i16]) : A[ti * 16 + i16][k0 + kq];
+        const double2 bv = Bm[k0 + kq][tj * 16 + i16];
+        re = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, re, 0, 0, 0);
+        re = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv.y, re, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, im, 0, 0, 0);
+        im = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, im, 0, 0, 0);
     }
-    __syncthreads();
 #pragma unroll
-    for (int y = 0; y < 2; ++y)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Xs[wv * 16 + kq + 4 * q][y * 16 + i16] = cmk(re[y][q], im[y][q]);
-    __syncthreads();
-    for (int e = tid; e < 64 * kJp; e += blockDim.x) {
-        const int i = e & 63, t = e >> 6, c = col[t];
-        if (c >= 0 && r0 + i < n) X[(size_t)c * n + r0 + i] = Xs[i][t];
-    }
+    for (int q = 0; q < 4; ++q) D[ti * 16 + kq + 4 * q][tj * 16 + i16] = cmk(re[q], im[q]);
 }
 
-// Row update of C: C[I, :] <- Zh^* C[I, :], one workgroup per (pair,
-// 64-column chunk).
-__global__ __launch_bounds__(256) void k_fx_jrow(int n, int nb, int s, double2 *C,
-                                                 const double2 *Zh, const int *pflag,
-                                                 const int *flag) {
-    __shared__ double2 Xs[kJp][64 + 1];
-    __shared__ double2 Zs[kJp][kJp + 1];
-    __shared__ int col[kJp];
+// The two-sided update of one block step in one pass: workgroups 0 ..
+// npair^2 - 1 take the 32 x 32 block (pair u rows, pair v columns) of C to
+// Zh_u^* C Zh_v (a side whose pair applied no rotation keeps the identity;
+// a block neither side touches is skipped), so every entry of C is read and
+// written once; the next npair * ceil(n / 32) workgroups take V's 32-row
+// chunk r and pair v's columns to V Zh_v.  The pairs of a step are disjoint,
+// so the blocks are independent.
+__global__ __launch_bounds__(256) void k_fx_j2s(int n, int nb, int s, double2 *C, double2 *V,
+                                                const double2 *Zh, const int *pflag,
+                                                const int *flag) {
+    __shared__ double2 X[kJp][kJp + 1];
+    __shared__ double2 T[kJp][kJp + 1];
+    __shared__ double2 Zu[kJp][kJp + 1];
+    __shared__ double2 Zv[kJp][kJp + 1];
+    __shared__ int colu[kJp], colv[kJp];
     if (*flag) return;
-    const int npair = nb / 2, k = blockIdx.x % npair, chunk = blockIdx.x / npair;
-    if (!pflag[k]) return;
-    int a, b;
-    rr_pair(nb, s, k, a, b);
-    const int tid = threadIdx.x;
-    if (tid < kJp) col[tid] = jcol(n, a, b, tid);
-    const int c0 = chunk * 64;
-    for (int e = tid; e < kJp * kJp; e += blockDim.x) Zs[e & 31][e >> 5] = Zh[(size_t)k * kJp * kJp + e];
-    __syncthreads();
-    for (int e = tid; e < kJp * 64; e += blockDim.x) {
-        const int t = e & 31, j = e >> 5, r = col[t];
-        Xs[t][j] = (r >= 0 && c0 + j < n) ? C[(size_t)(c0 + j) * n + r] : cmk(0.0, 0.0);
+    const int npair = nb / 2, tid = threadIdx.x;
+    const int nc = npair * npair;
+    const bool isC = (int)blockIdx.x < nc;
+    int u, v, r0 = 0;
+    if (isC) {
+        u = blockIdx.x % npair;
+        v = blockIdx.x / npair;
+    } else {
+        const int e = blockIdx.x - nc;
+        u = -1;
+        v = e % npair;
+        r0 = (e / npair) * kJp;
     }
-    __syncthreads();
-    // D (32 x 64) = Zs^* Xs: wavefront w takes columns 16 w .. 16 w + 15, two 16-row tiles
-    const int lane = tid & (kWave - 1), wv = tid >> 6, i16 = lane & 15, kq = lane >> 4;
-    fxv4d re[2], im[2];
-#pragma unroll
-    for (int x = 0; x < 2; ++x) { re[x] = fxv4d{0, 0, 0, 0}; im[x] = fxv4d{0, 0, 0, 0}; }
-#pragma unroll
-    for (int k0 = 0; k0 < kJp; k0 += 4) {
-        const double2 bv = Xs[k0 + kq][wv * 16 + i16];
-#pragma unroll
-        for (int x = 0; x < 2; ++x) {
-            const double2 av = cconj(Zs[k0 + kq][x * 16 + i16]);  // (Zh^*)[i][k] = conj(Zh[k][i])
-            re[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.x, re[x], 0, 0, 0);
-            re[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(-av.y, bv.y, re[x], 0, 0, 0);
-            im[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.x, bv.y, im[x], 0, 0, 0);
-            im[x] = __builtin_amdgcn_mfma_f64_16x16x4f64(av.y, bv.x, im[x], 0, 0, 0);
+    const int fu = u >= 0 ? pflag[u] : 0, fv = pflag[v];
+    if (!fu && !fv) return;
+    if (tid < kJp) {
+        int a, b;
+        rr_pair(nb, s, v, a, b);
+        colv[tid] = jcol(n, a, b, tid);
+        if (isC) {
+            rr_pair(nb, s, u, a, b);
+            colu[tid] = jcol(n, a, b, tid);
+        } else {
+            colu[tid] = r0 + tid < n ? r0 + tid : -1;  // plain rows of V
         }
     }
     __syncthreads();
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) Xs[x * 16 + kq + 4 * q][wv * 16 + i16] = cmk(re[x][q], im[x][q]);
+    double2 *M = isC ? C : V;
+    for (int e = tid; e < kJp * kJp; e += blockDim.x) {
+        const int i = e & 31, j = e >> 5;
+        const int ri = colu[i], cj = colv[j];
+        X[i][j] = (ri >= 0 && cj >= 0) ? M[(size_t)cj * n + ri] : cmk(0.0, 0.0);
+        if (fv) Zv[i][j] = Zh[(size_t)v * kJp * kJp + e];
+        if (fu) Zu[i][j] = Zh[(size_t)u * kJp * kJp + e];
+    }
     __syncthreads();
-    for (int e = tid; e < kJp * 64; e += blockDim.x) {
-        const int t = e & 31, j = e >> 5, r = col[t];
-        if (r >= 0 && c0 + j < n) C[(size_t)(c0 + j) * n + r] = Xs[t][j];
+    double2(*R)[kJp + 1] = X;  // the current result
+    if (fv) {
+        mma32(X, Zv, T, 0);  // X Zh_v
+        __syncthreads();
+        R = T;
+    }
+    if (fu) {
+        double2(*D)[kJp + 1] = R == X ? T : X;
+        mma32(Zu, R, D, 1);  // Zh_u^* R
+        __syncthreads();
+        R = D;
+    }
+    for (int e = tid; e < kJp * kJp; e += blockDim.x) {
+        const int i = e & 31, j = e >> 5;
+        const int ri = colu[i], cj = colv[j];
+        if (ri >= 0 && cj >= 0) M[(size_t)cj * n + ri] = R[i][j];
     }
 }
 
@@ -779,7 +765,7 @@ extern "C" int ghsvd_solve_fast(int m, int n, int p, const double *F, int ldf,
                        n, w.V);
     GHSVD_HIP(hipGetLastError());
     // Jacobi sweeps
-    const int npair = nb / 2, colch = (n + 63) / 64, rows2 = 2 * colch;
+    const int npair = nb / 2, vch = (n + kJp - 1) / kJp;
     int sweeps = 0, converged = 0;
     long long rot = 0;
     while (sweeps < cap) {
@@ -787,10 +773,8 @@ extern "C" int ghsvd_solve_fast(int m, int n, int p, const double *F, int ldf,
         for (int s = 0; s < nb - 1; ++s) {
             hipLaunchKernelGGL(k_fx_jinner, dim3(npair), dim3(256), 0, st, n, nb, s, w.C, w.Zh,
                                w.pflag, w.cnt, w.nu, w.flag);
-            hipLaunchKernelGGL(k_fx_jcol, dim3(npair * rows2), dim3(256), 0, st, n, nb, s, w.C,
-                               w.V, w.Zh, w.pflag, w.flag);
-            hipLaunchKernelGGL(k_fx_jrow, dim3(npair * colch), dim3(256), 0, st, n, nb, s, w.C,
-                               w.Zh, w.pflag, w.flag);
+            hipLaunchKernelGGL(k_fx_j2s, dim3(npair * npair + npair * vch), dim3(256), 0, st, n,
+                               nb, s, w.C, w.V, w.Zh, w.pflag, w.flag);
         }
         GHSVD_HIP(hipGetLastError());
         int hc = 0;
