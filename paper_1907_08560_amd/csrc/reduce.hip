@@ -99,8 +99,10 @@ __device__ __forceinline__ bool jqr_active(const JqrState &st, int n) {
 // column l of the factorization is physical column perm[l] of Ft (the map
 // is P2), and a step's two swaps only change the map.  State, signature and
 // map are read from the copies of the step's parity `par`.
-#define JQR_PENCIL_COL()                                          \
-    const int pk = find_pencil(pre, B, blockIdx.x);                \
+#define JQR_PENCIL_COL() JQR_PENCIL_COL_AT((int)blockIdx.x)
+#define JQR_PENCIL_COL_AT(BLK)                                    \
+    const int blk_ = (BLK);                                       \
+    const int pk = find_pencil(pre, B, blk_);                     \
     const PencilDev P = PD[pk];                                  \
     if (!P.reduce) return;                                        \
     const double2 *A = P.Ft;                                      \
@@ -108,7 +110,7 @@ __device__ __forceinline__ bool jqr_active(const JqrState &st, int n) {
     const int m = P.m, n = P.n;                                   \
     const JqrState st = P.jst[par];                               \
     const int8_t *J = P.Jw + (size_t)par * m;                     \
-    const int j_local = pencil_local(pre, pk, blockIdx.x) + jw;   \
+    const int j_local = pencil_local(pre, pk, blk_) + jw;         \
     (void)J;                                                      \
     (void)j_local
 
@@ -151,13 +153,17 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_colnorms(const PencilDev *PD, c
 // Step, first kernel: every workgroup finds the diagonal pivot bi, and the
 // workgroup of logical column j computes the J-product of column bi with
 // column j (rows k..m-1), stored at the position column j takes after the
-// swap k <-> bi.
+// swap k <-> bi.  Workgroups take the columns in the reverse of the step
+// kernel's order: workgroups start roughly in index order, so the columns the
+// previous step kernel wrote last, the ones most likely still held in the
+// memory-side cache, are read first (and the next step kernel starts on the
+// columns this kernel read last).
 __global__ __launch_bounds__(kGridNT) void k_jqr_cross(const PencilDev *PD, const int *pre, int B,
                                                        int par, int jw) {
     __shared__ double red[2 * kGridNT / kWave];
     __shared__ double rv[kGridNT / kWave];
     __shared__ int ri[kGridNT / kWave];
-    JQR_PENCIL_COL();
+    JQR_PENCIL_COL_AT((int)(gridDim.x - 1 - blockIdx.x));
     if (!jqr_active(st, n)) return;
     const int k = st.k, j = j_local;
     if (j < k || k == n - 1) return;
