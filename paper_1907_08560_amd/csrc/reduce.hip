@@ -23,6 +23,9 @@ namespace ghsvd {
 
 constexpr int kGridNT = 256;
 constexpr int kOneNT = 1024;
+// Trailing columns per workgroup of the step kernel: the pivot's reflector is
+// formed once for all of them.
+constexpr int kStepCols = 2;
 // Blocked QR of G: panel width, the longest column the trailing kernel
 // holds in registers, columns per trailing workgroup.
 constexpr int kQrPanel = 32;
@@ -278,33 +281,52 @@ __device__ __forceinline__ void qr_panel_body(const PencilDev *PD, int B, int k,
 
 // A 1x1 pivot step with the workgroup's rows in registers: thread tid holds
 // rows k + tid + i * kGridNT (i < RC) of the signature, the pivot column and
-// its own column, loaded together at the start (one memory latency), which
-// is the row assignment of the streaming loops below, so every sum rounds as
-// there.  The row swap k <-> b0 of the matching sign moves the three values
-// between the two owning threads through LDS.  Requires m - k <= RC * kGridNT.
+// the workgroup's own columns j0, j0 + 1, ... (those right of k), loaded
+// together at the start (one memory latency), which is the row assignment of
+// the streaming loops below, so every sum rounds as there.  The pivot's
+// J-norm, row search and reflector are formed once for all the workgroup's
+// columns, and their J-products and J-norms share each workgroup reduction
+// (every component is summed in the same order as alone).  The row swap
+// k <-> b0 of the matching sign moves the values between the two owning
+// threads through LDS.  Requires m - k <= RC * kGridNT.
 template <int RC, typename CP>
 __device__ __forceinline__ void jqr_step1_regs(const PencilDev &P, const JqrState &cur, int par,
-                                               int k, int j, const CP &cp2, double *red,
+                                               int k, int j0, const CP &cp2, double *red,
                                                double *rv, int *ri, double2 *xch) {
+    constexpr int NC = kStepCols;
     const int m = P.m, n = P.n, tid = threadIdx.x;
-    const bool desig = j == k;
+    bool tr[NC];  // column j0 + c is a trailing column of this step
+    bool desig = false, any = false;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const int j = j0 + c;
+        tr[c] = j > k && j < n;
+        desig |= j == k;
+        any |= tr[c];
+    }
     int8_t *Jc = P.Jw + (size_t)par * m;
     int8_t *Jn = P.Jw + (size_t)(par ^ 1) * m;
     const double2 *xa = jcol(P.Ft, P.ldft, cp2(k));
-    double2 *y = P.Ft + (size_t)cp2(j) * P.ldft;
+    double2 *y[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) y[c] = tr[c] ? P.Ft + (size_t)cp2(j0 + c) * P.ldft : P.Ft;
     const int jk = Jc[k];
     const double2 xk = xa[k];
-    double2 xv[RC], yv[RC];
+    double2 xv[RC], yv[NC][RC];
     int js[RC];
 #pragma unroll
     for (int i = 0; i < RC; ++i) {
         const int r = k + tid + i * kGridNT;
         js[i] = 0;
-        xv[i] = yv[i] = cmk(0.0, 0.0);
+        xv[i] = cmk(0.0, 0.0);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) yv[c][i] = cmk(0.0, 0.0);
         if (r < m) {
             js[i] = Jc[r];
             xv[i] = xa[r];
-            if (!desig) yv[i] = y[r];
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (tr[c]) yv[c][i] = y[c][r];
         }
     }
     int status = 0;
@@ -355,29 +377,36 @@ __device__ __forceinline__ void jqr_step1_regs(const PencilDev &P, const JqrStat
     double2 f11 = xk;
     if (b0 != k) {
         // rows k and b0 trade places: J, the pivot column (as the reflector
-        // sees it) and the own column
-        if (tid == ((b0 - k) & (kGridNT - 1))) {
+        // sees it) and the own columns (xch: the pivot's and the columns'
+        // rows b0, then the columns' rows k)
+        const int ow = (b0 - k) & (kGridNT - 1);
+        if (tid == ow) {
 #pragma unroll
             for (int i = 0; i < RC; ++i)
                 if (k + tid + i * kGridNT == b0) {
                     xch[0] = xv[i];
-                    xch[1] = yv[i];
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) xch[1 + c] = yv[c][i];
                 }
         }
-        if (tid == 0) xch[2] = yv[0];
+        if (tid == 0) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) xch[1 + NC + c] = yv[c][0];
+        }
         __syncthreads();
         f11 = xch[0];
         if (tid == 0) {
-            yv[0] = xch[1];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) yv[c][0] = xch[1 + c];
             js[0] = sg0;
         }
-        if (tid == ((b0 - k) & (kGridNT - 1))) {
-            const double2 yk = xch[2];
+        if (tid == ow) {
 #pragma unroll
             for (int i = 0; i < RC; ++i)
                 if (k + tid + i * kGridNT == b0) {
                     xv[i] = xk;
-                    yv[i] = yk;
+#pragma unroll
+                    for (int c = 0; c < NC; ++c) yv[c][i] = xch[1 + NC + c];
                     js[i] = jk;
                 }
         }
@@ -410,60 +439,81 @@ __device__ __forceinline__ void jqr_step1_regs(const PencilDev &P, const JqrStat
             P.jst[par ^ 1] = t;
             if (fin) P.jst[par] = t;
         }
-        return;
     }
-    // the reflector on the own column: the J-product, then the update and
-    // the column's J-norm^2 over the rows still to reduce
-    double v[2] = {0.0, 0.0};
+    if (!any) return;
+    // the reflector on the own columns: the J-products, then the update and
+    // each column's J-norm^2 over the rows still to reduce
+    double v[2 * NC];
+#pragma unroll
+    for (int q = 0; q < 2 * NC; ++q) v[q] = 0.0;
 #pragma unroll
     for (int i = 0; i < RC; ++i) {
         const int r = k + tid + i * kGridNT;
         if (r < m) {
             const double s = (double)js[i];
-            const double2 a = r == k ? s0k : xv[i], b = yv[i];
-            v[0] += s * fdot_re2(a, b);
-            v[1] += s * fdot_im(a, b);
+            const double2 a = r == k ? s0k : xv[i];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                v[2 * c] += s * fdot_re2(a, yv[c][i]);
+                v[2 * c + 1] += s * fdot_im(a, yv[c][i]);
+            }
         }
     }
-    block_sum<2>(v, red);
-    const double2 tw = cscale(cmk(v[0], v[1]), tau0);
-    double h[1] = {0.0};
+    block_sum<2 * NC>(v, red);
+    double2 tw[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) tw[c] = cscale(cmk(v[2 * c], v[2 * c + 1]), tau0);
+    double h[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) h[c] = 0.0;
 #pragma unroll
     for (int i = 0; i < RC; ++i) {
         const int r = k + tid + i * kGridNT;
         if (r < m) {
-            const double2 nv = cadd(yv[i], fmul(r == k ? s0k : xv[i], tw));
-            if (r > k) h[0] += (double)js[i] * fnorm2(nv);
-            y[r] = nv;
+            const double2 a = r == k ? s0k : xv[i];
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+                if (tr[c]) {
+                    const double2 nv = cadd(yv[c][i], fmul(a, tw[c]));
+                    if (r > k) h[c] += (double)js[i] * fnorm2(nv);
+                    y[c][r] = nv;
+                }
         }
     }
-    block_sum<1>(h, red);
+    block_sum<NC>(h, red);
     if (tid == 0) {
-        P.hd[cp2(j)] = h[0];
-        P.hl[j] = h[0];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (tr[c]) {
+                P.hd[cp2(j0 + c)] = h[c];
+                P.hl[j0 + c] = h[c];
+            }
     }
 }
 
-// Workgroups tot.. of the launch run column step qk of G's QR instead.  RC:
-// rows per thread of the register-resident 1x1 step (and of G's column
-// step); longer columns, and 2x2 pivots, take the streaming loops.
-template <int RC>
-__global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const int *pre, int B,
-                                                      int par, int tot, int qk, int jw,
-                                                      int qpanel) {
+// Workgroup g < tot of the launch takes the window's columns jw + kStepCols
+// g' .. + kStepCols - 1 of its pencil (g' its index within the pencil, from
+// the prefix sums pre2 of the pencils' column pairs); workgroups tot.. run
+// column step qk of G's QR instead (pre: the prefix sums of columns).  RC,
+// RCG: rows per thread of the register-resident 1x1 step of F and of G's
+// column step; longer columns, and 2x2 pivots, take the streaming loops.
+template <int RC, int RCG>
+__global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const int *pre,
+                                                      const int *pre2, int B, int par, int tot,
+                                                      int qk, int jw, int qpanel) {
     extern __shared__ int8_t Jl[];  // signature with this step's row swaps
     __shared__ double red[4 * kGridNT / kWave];
     __shared__ double rv[kGridNT / kWave];
     __shared__ int ri[kGridNT / kWave];
-    __shared__ double2 stash[4];
+    __shared__ double2 stash[2 + 2 * kStepCols];
     if ((int)blockIdx.x >= tot) {
         if (qpanel)
-            qr_panel_body<RC>(PD, B, qk, (int)blockIdx.x - tot, red);
+            qr_panel_body<RCG>(PD, B, qk, (int)blockIdx.x - tot, red);
         else
-            qr_step_body<RC>(PD, pre, B, qk, (int)blockIdx.x - tot, jw, red);
+            qr_step_body<RCG>(PD, pre, B, qk, (int)blockIdx.x - tot, jw, red);
         return;
     }
-    const int pk = find_pencil(pre, B, blockIdx.x);
+    const int pk = find_pencil(pre2, B, blockIdx.x);
     const PencilDev P = PD[pk];
     if (!P.reduce) return;
     double2 *A = P.Ft;
@@ -473,12 +523,12 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
     JqrState *nxt = P.jst + (par ^ 1);
     int8_t *Jc = P.Jw + (size_t)par * m;
     int8_t *Jn = P.Jw + (size_t)(par ^ 1) * m;
-    const int j = pencil_local(pre, pk, blockIdx.x) + jw;
+    const int j0 = kStepCols * pencil_local(pre2, pk, blockIdx.x) + jw;
     const int tid = threadIdx.x;
     if (!jqr_active(cur, n)) return;
     const int k = cur.k;
-    if (j < k) return;
-    const bool desig = j == k;
+    if (j0 + kStepCols <= k) return;  // every column of the workgroup is left of k
+    const bool desig = j0 <= k && k < j0 + kStepCols;
     const JqrDecision dec = *P.jdec;
     const int *cpb = P.cpb;
     // second Bunch-Kaufman test
@@ -516,11 +566,14 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
         }
         return cpb[q];
     };
-    if (j > k && j < k + piv) return;  // the second column of a 2x2 pivot
     if (piv == 1 && m - k <= RC * kGridNT) {
-        jqr_step1_regs<RC>(P, cur, par, k, j, cp2, red, rv, ri, stash);
+        jqr_step1_regs<RC>(P, cur, par, k, j0, cp2, red, rv, ri, stash);
         return;
     }
+    // the workgroup's columns this step rewrites: right of the pivot block
+    bool any = false;
+    for (int c = 0; c < kStepCols; ++c) any |= j0 + c >= k + piv && j0 + c < n;
+    if (!desig && !any) return;  // the second column of a 2x2 pivot only
     for (int r = k + tid; r < m; r += blockDim.x) Jl[r] = Jc[r];
     __syncthreads();
     const double2 *xa = jcol(A, lda, cp2(k));
@@ -730,43 +783,79 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
             *nxt = t;
             if (fin) P.jst[par] = t;
         }
-        return;
     }
-    // ---- a trailing column: apply the reflector(s) in place ----
-    double2 *y = A + (size_t)cp2(j) * lda;
-    if (tid == 0) {
-        stash[0] = y[sw.a0];
-        stash[1] = y[sw.b0];
-        stash[2] = y[sw.a1];
-        stash[3] = y[sw.b1];
-    }
-    __syncthreads();
-    // y0 at stored row q through the stash (rows named by a swap)
-    auto y0 = [&](int q) { return sv_load(y, stash, sw, q); };
-    // Jl holds both row swaps; the first reflector's dot takes J with the
-    // first swap only (undo the second one, rows k+1 <-> b1)
-    auto j0 = [&](int r) {
-        const int q = (r == sw.b1) ? sw.a1 : (r == sw.a1 ? sw.b1 : r);
-        return (double)Jl[q];
-    };
-    double2 tw0;
-    {
-        double v[2] = {0.0, 0.0};
-        for (int r = k + tid; r < m; r += blockDim.x) {
-            const double s = j0(r);
-            const double2 a = s0(r), b = y0(sw.src0(r));
-            v[0] += s * (a.x * b.x + a.y * b.y);
-            v[1] += s * (a.x * b.y - a.y * b.x);
+    // ---- the trailing columns: apply the reflector(s) in place ----
+    for (int c = 0; c < kStepCols; ++c) {
+        const int j = j0 + c;
+        if (j < k + piv || j >= n) continue;  // uniform over the workgroup
+        // (the previous column's reads of the stash all precede the
+        // barriers of its final reduction)
+        double2 *y = A + (size_t)cp2(j) * lda;
+        if (tid == 0) {
+            stash[0] = y[sw.a0];
+            stash[1] = y[sw.b0];
+            stash[2] = y[sw.a1];
+            stash[3] = y[sw.b1];
         }
-        block_sum<2>(v, red);
-        tw0 = cscale(cmk(v[0], v[1]), tau0);
-    }
-    auto y1 = [&](int r) { return cadd(y0(sw.src0(r)), cmul(s0(r), tw0)); };  // r >= k
-    if (piv == 1) {
+        __syncthreads();
+        // y0 at stored row q through the stash (rows named by a swap)
+        auto y0 = [&](int q) { return sv_load(y, stash, sw, q); };
+        // Jl holds both row swaps; the first reflector's dot takes J with the
+        // first swap only (undo the second one, rows k+1 <-> b1)
+        auto jf = [&](int r) {
+            const int q = (r == sw.b1) ? sw.a1 : (r == sw.a1 ? sw.b1 : r);
+            return (double)Jl[q];
+        };
+        double2 tw0;
+        {
+            double v[2] = {0.0, 0.0};
+            for (int r = k + tid; r < m; r += blockDim.x) {
+                const double s = jf(r);
+                const double2 a = s0(r), b = y0(sw.src0(r));
+                v[0] += s * (a.x * b.x + a.y * b.y);
+                v[1] += s * (a.x * b.y - a.y * b.x);
+            }
+            block_sum<2>(v, red);
+            tw0 = cscale(cmk(v[0], v[1]), tau0);
+        }
+        auto y1 = [&](int r) { return cadd(y0(sw.src0(r)), cmul(s0(r), tw0)); };  // r >= k
+        if (piv == 1) {
+            double v[1] = {0.0};
+            for (int r = k + tid; r < m; r += blockDim.x) {
+                const double2 nv = y1(r);
+                if (r > k) v[0] += (double)Jl[r] * cnorm2(nv);
+                y[r] = nv;
+            }
+            block_sum<1>(v, red);
+            if (tid == 0) {
+                P.hd[cp2(j)] = v[0];
+                P.hl[j] = v[0];
+            }
+            continue;
+        }
+        double2 tw1;
+        {
+            double v[2] = {0.0, 0.0};
+            for (int r = k + 1 + tid; r < m; r += blockDim.x) {
+                const double s = (double)Jl[r];
+                const int q = (r == sw.b1) ? k + 1 : (r == k + 1 ? sw.b1 : r);
+                const double2 a = s1(r), b = y1(q);
+                v[0] += s * (a.x * b.x + a.y * b.y);
+                v[1] += s * (a.x * b.y - a.y * b.x);
+            }
+            block_sum<2>(v, red);
+            tw1 = cscale(cmk(v[0], v[1]), tau1);
+        }
         double v[1] = {0.0};
         for (int r = k + tid; r < m; r += blockDim.x) {
-            const double2 nv = y1(r);
-            if (r > k) v[0] += (double)Jl[r] * cnorm2(nv);
+            double2 nv;
+            if (r == k) {
+                nv = y1(k);
+            } else {
+                const int q = (r == sw.b1) ? k + 1 : (r == k + 1 ? sw.b1 : r);
+                nv = cadd(y1(q), cmul(s1(r), tw1));
+                if (r > k + 1) v[0] += (double)Jl[r] * cnorm2(nv);
+            }
             y[r] = nv;
         }
         block_sum<1>(v, red);
@@ -774,37 +863,6 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
             P.hd[cp2(j)] = v[0];
             P.hl[j] = v[0];
         }
-        return;
-    }
-    double2 tw1;
-    {
-        double v[2] = {0.0, 0.0};
-        for (int r = k + 1 + tid; r < m; r += blockDim.x) {
-            const double s = (double)Jl[r];
-            const int q = (r == sw.b1) ? k + 1 : (r == k + 1 ? sw.b1 : r);
-            const double2 a = s1(r), b = y1(q);
-            v[0] += s * (a.x * b.x + a.y * b.y);
-            v[1] += s * (a.x * b.y - a.y * b.x);
-        }
-        block_sum<2>(v, red);
-        tw1 = cscale(cmk(v[0], v[1]), tau1);
-    }
-    double v[1] = {0.0};
-    for (int r = k + tid; r < m; r += blockDim.x) {
-        double2 nv;
-        if (r == k) {
-            nv = y1(k);
-        } else {
-            const int q = (r == sw.b1) ? k + 1 : (r == k + 1 ? sw.b1 : r);
-            nv = cadd(y1(q), cmul(s1(r), tw1));
-            if (r > k + 1) v[0] += (double)Jl[r] * cnorm2(nv);
-        }
-        y[r] = nv;
-    }
-    block_sum<1>(v, red);
-    if (tid == 0) {
-        P.hd[cp2(j)] = v[0];
-        P.hl[j] = v[0];
     }
 }
 
@@ -1292,27 +1350,34 @@ int run_reduction(BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
         if ((rc = copy_cols(P.p, P.n, P.Gin, P.ldgin, P.Gt, P.ldgt, nullptr, s))) return rc;
         GHSVD_HIP(hipMemcpyAsync(P.Jw, P.Jin, (size_t)P.m, hipMemcpyDeviceToDevice, s));
     }
-    // column windows: row w covers columns j >= w * step of each pencil
+    // column windows: row w covers columns j >= w * step of each pencil; the
+    // second table (from row kWinRows on) counts the step kernel's
+    // workgroups, kStepCols columns each
     const int step = (c.max_n + kWinRows - 1) / kWinRows;
     const int rows = (c.max_n + step - 1) / step;
-    c.win.assign((size_t)rows * (B + 1), 0);
+    const size_t pairs = (size_t)kWinRows * (B + 1);
+    c.win.assign(2 * pairs, 0);
     for (int w = 0; w < rows; ++w)
         for (int k = 0; k < B; ++k) {
             const PencilDev &P = c.host[k];
             const int cols = P.reduce && P.n > w * step ? P.n - w * step : 0;
-            c.win[(size_t)w * (B + 1) + k + 1] = c.win[(size_t)w * (B + 1) + k] + cols;
+            const size_t e = (size_t)w * (B + 1) + k;
+            c.win[e + 1] = c.win[e] + cols;
+            c.win[pairs + e + 1] = c.win[pairs + e] + (cols + kStepCols - 1) / kStepCols;
         }
     GHSVD_HIP(hipMemcpyAsync(c.win_dev, c.win.data(), sizeof(int) * c.win.size(),
                              hipMemcpyHostToDevice, s));
     // rows per thread a window's step kernel keeps in registers: enough for
-    // the longest trailing column of F or G at the window's first step
-    std::vector<int> rows_cap(rows, 0);
+    // the longest trailing column of F (and, separately, of G) at the
+    // window's first step
+    std::vector<int> rows_f(rows, 0), rows_g(rows, 0);
     for (int w = 0; w < rows; ++w)
         for (const PencilDev &P : c.host) {
             if (!P.reduce || P.n <= w * step) continue;
-            const int len = (P.m > P.p ? P.m : P.p) - w * step;
-            const int per = (len + kGridNT - 1) / kGridNT;
-            rows_cap[w] = per > rows_cap[w] ? per : rows_cap[w];
+            const int pf = (P.m - w * step + kGridNT - 1) / kGridNT;
+            const int pg = (P.p - w * step + kGridNT - 1) / kGridNT;
+            rows_f[w] = pf > rows_f[w] ? pf : rows_f[w];
+            rows_g[w] = pg > rows_g[w] ? pg : rows_g[w];
         }
     int max_m = 0, max_p = 0;
     for (const PencilDev &P : c.host) {
@@ -1334,6 +1399,7 @@ int run_reduction(BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
         const int w = it / step;
         const int *pw = c.win_dev + (size_t)w * (B + 1);
         const int tot = c.win[(size_t)w * (B + 1) + B];
+        const int tot2 = c.win[pairs + (size_t)w * (B + 1) + B];
         const int jw = w * step;
         if (tot == 0) continue;
         // timed as one bracket: start of the first launch, end of the last
@@ -1341,15 +1407,20 @@ int run_reduction(BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
         prof_take(kProfReduce, e0, e1);
         launch_ev(k_jqr_cross, dim3(tot), dim3(kGridNT), 0, s, e0, nullptr, c.dev, pw, B, par, jw);
         hipLaunchKernelGGL(k_jqr_cross2, dim3(tot), dim3(kGridNT), 0, s, c.dev, pw, B, par, jw);
-        const int rc = rows_cap[w];
-        // 8 rows per thread only when every column fits: its register
-        // count lowers the occupancy of the streaming paths
-        auto step_k = rc > 4 && rc <= 8 ? k_jqr_step<8> : k_jqr_step<4>;
+        // 6 or 8 rows per thread only when every column fits: their register
+        // counts lower the occupancy of the streaming paths
+        const int rf = rows_f[w], rg = rows_g[w];
+        const int cf = rf > 4 && rf <= 6 ? 1 : (rf > 6 && rf <= 8 ? 2 : 0);
+        const int cg = rg > 4 && rg <= 8 ? 1 : 0;
+        decltype(&k_jqr_step<4, 4>) const kinds[3][2] = {{k_jqr_step<4, 4>, k_jqr_step<4, 8>},
+                                                          {k_jqr_step<6, 4>, k_jqr_step<6, 8>},
+                                                          {k_jqr_step<8, 4>, k_jqr_step<8, 8>}};
+        auto step_k = kinds[cf][cg];
         const int gq = qpanel ? B * kQrPanel : tot;  // G's workgroups
         const bool trail = qpanel && (it % kQrPanel == kQrPanel - 1 || it == c.max_n - 1) &&
                            it - it % kQrPanel + kQrPanel < c.max_n;
-        launch_ev(step_k, dim3(tot + gq), dim3(kGridNT), (uint32_t)jl_bytes, s, nullptr,
-                  trail ? nullptr : e1, c.dev, pw, B, par, tot, it, jw, qpanel);
+        launch_ev(step_k, dim3(tot2 + gq), dim3(kGridNT), (uint32_t)jl_bytes, s, nullptr,
+                  trail ? nullptr : e1, c.dev, pw, pw + pairs, B, par, tot2, it, jw, qpanel);
         if (trail) {
             const int ps = it - it % kQrPanel, pe = ps + kQrPanel;
             launch_ev(k_qr_trail, dim3((c.max_n - pe + kQrTrailCols - 1) / kQrTrailCols, B),

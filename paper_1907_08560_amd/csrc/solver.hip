@@ -116,14 +116,14 @@ size_t pencil_bytes(const Plan &pl) {
 size_t batch_bytes(int B) {
     return align_up(sizeof(PencilDev) * B, 256) +
            align_up(sizeof(int) * BatchCtx::kKinds * (B + 1), 256) +
-           align_up(sizeof(int) * kWinRows * (B + 1), 256) +
+           align_up(sizeof(int) * 2 * kWinRows * (B + 1), 256) +
            align_up(sizeof(int) * 2 * (B + 1), 256) + align_up(sizeof(int) * (B + 1), 256) + 256;
 }
 
 void carve_batch(Carver &c, BatchCtx &bc, int B) {
     bc.dev = c.take<PencilDev>(B);
     bc.pre_dev = c.take<int>(BatchCtx::kKinds * (B + 1));
-    bc.win_dev = c.take<int>(kWinRows * (B + 1));
+    bc.win_dev = c.take<int>(2 * kWinRows * (B + 1));
     bc.done_dev = c.take<int>(2 * (B + 1));
     bc.flag_dev = c.take<int>(B + 1);
 }

@@ -36,7 +36,7 @@ struct BatchCtx {
     const int *pre_of(int kind) const { return pre_dev + kind * (B + 1); }
     int total(int kind) const { return pre[kind * (B + 1) + B]; }
     int max_n = 0, max_rows = 0;
-    int *win_dev = nullptr;         // device: reduction column windows, kWinRows blocks of B + 1
+    int *win_dev = nullptr;         // device: reduction column windows, 2 kWinRows blocks of B + 1
     std::vector<int> win;           // host copy (built by the reduction)
     int *done_dev = nullptr;        // device [2 (B + 1)] small per-pencil results for the host
     int *flag_dev = nullptr;        // device [B] 1: the pencil's sweep stage is done (read by
