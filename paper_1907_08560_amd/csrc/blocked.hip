@@ -22,6 +22,7 @@
 // transformation (Section 6.1.7).
 #include <cmath>
 #include <cstdlib>
+#include <type_traits>
 
 // Floating-point contraction is decided by the source expressions (a * b + c
 // within one expression becomes one fused multiply-add), not by the code an
@@ -88,7 +89,10 @@ __device__ __forceinline__ int blk_col(int w, int a, int b, int ca, int cc) {
 // The cross-wavefront sum runs in two halves (wavefronts 4-7 park their
 // tiles, 0-3 add them to their own, then the four sums are added in order),
 // so the LDS buffer holds four wavefronts' tiles and two workgroups share a
-// CU.
+// CU.  In the FP32 warm-up the parked tiles and the first additions stay in
+// FP32, the precision of the matrix-core sums themselves (24 KB instead of
+// 48 KB of LDS, so two Gram workgroups fit beside an inner-sweep workgroup);
+// the four half sums are added in FP64 as in the FP64 kernel.
 constexpr int kGramWaves = 8;
 constexpr int kGramHalf = kGramWaves / 2;
 
@@ -102,7 +106,8 @@ __global__ __launch_bounds__(kWave * kGramWaves, 2) void k_blk_gram(const Pencil
     constexpr int NTD = PB / 16;              // column tiles
     constexpr int NT = NTD * (NTD + 1) / 2;   // upper output tiles
     constexpr int RW = kGramChunk / kGramWaves;  // rows per wavefront
-    __shared__ double2 red[kGramHalf][NT][256];
+    using RC2 = typename std::conditional<F32, float2, double2>::type;  // LDS partials
+    __shared__ RC2 red[kGramHalf][NT][256];
     const int pk = find_pencil(pre, B, blockIdx.x);
     const PencilDev A = PD[pk];
     if (step >= A.nb - 1 || flag[pk]) return;
@@ -179,9 +184,12 @@ __global__ __launch_bounds__(kWave * kGramWaves, 2) void k_blk_gram(const Pencil
 #pragma unroll
         for (int q = 0; q < NT; ++q)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                red[wv - kGramHalf][q][r * 64 + lane] =
-                    cmk((double)acc_re[q][r], (double)acc_im[q][r]);
+            for (int r = 0; r < 4; ++r) {
+                RC2 t;
+                t.x = acc_re[q][r];
+                t.y = acc_im[q][r];
+                red[wv - kGramHalf][q][r * 64 + lane] = t;
+            }
     }
     __syncthreads();
     if (wv < kGramHalf) {
@@ -189,17 +197,19 @@ __global__ __launch_bounds__(kWave * kGramWaves, 2) void k_blk_gram(const Pencil
         for (int q = 0; q < NT; ++q)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                double2 &slot = red[wv][q][r * 64 + lane];
-                slot = cadd(cmk((double)acc_re[q][r], (double)acc_im[q][r]), slot);
+                RC2 &slot = red[wv][q][r * 64 + lane];
+                slot.x = acc_re[q][r] + slot.x;
+                slot.y = acc_im[q][r] + slot.y;
             }
     }
     __syncthreads();
     const GPtr<double2> P(A.part + ((size_t)bpi * KC + kc) * PB * PB);
     for (int e = tid; e < NT * 256; e += kWave * kGramWaves) {
         const int q = e / 256, rl = e % 256, r = rl / 64, ln = rl % 64;
-        double2 sum = red[0][q][rl];
+        double2 sum = cmk((double)red[0][q][rl].x, (double)red[0][q][rl].y);
 #pragma unroll
-        for (int w2 = 1; w2 < kGramHalf; ++w2) sum = cadd(sum, red[w2][q][rl]);
+        for (int w2 = 1; w2 < kGramHalf; ++w2)
+            sum = cadd(sum, cmk((double)red[w2][q][rl].x, (double)red[w2][q][rl].y));
         int ti = 0, tj = q;  // upper tile q -> (ti, tj)
         if (NTD == 2) {
             ti = q == 2 ? 1 : 0;
