@@ -23,8 +23,9 @@ namespace ghsvd {
 
 constexpr int kGridNT = 256;
 constexpr int kOneNT = 1024;
-// Trailing columns per workgroup of the step kernel: the pivot's reflector is
-// formed once for all of them.
+// Trailing columns per workgroup of the step kernel where F's columns fit the
+// register-resident step at up to 6 rows per thread (the pivot's reflector is
+// formed once for all of them); other windows keep one column per workgroup.
 constexpr int kStepCols = 2;
 // Blocked QR of G: panel width, the longest column the trailing kernel
 // holds in registers, columns per trailing workgroup.
@@ -289,11 +290,10 @@ __device__ __forceinline__ void qr_panel_body(const PencilDev *PD, int B, int k,
 // (every component is summed in the same order as alone).  The row swap
 // k <-> b0 of the matching sign moves the values between the two owning
 // threads through LDS.  Requires m - k <= RC * kGridNT.
-template <int RC, typename CP>
+template <int RC, int NC, typename CP>
 __device__ __forceinline__ void jqr_step1_regs(const PencilDev &P, const JqrState &cur, int par,
                                                int k, int j0, const CP &cp2, double *red,
                                                double *rv, int *ri, double2 *xch) {
-    constexpr int NC = kStepCols;
     const int m = P.m, n = P.n, tid = threadIdx.x;
     bool tr[NC];  // column j0 + c is a trailing column of this step
     bool desig = false, any = false;
@@ -491,13 +491,13 @@ __device__ __forceinline__ void jqr_step1_regs(const PencilDev &P, const JqrStat
     }
 }
 
-// Workgroup g < tot of the launch takes the window's columns jw + kStepCols
-// g' .. + kStepCols - 1 of its pencil (g' its index within the pencil, from
-// the prefix sums pre2 of the pencils' column pairs); workgroups tot.. run
+// Workgroup g < tot of the launch takes the window's columns jw + NC g' ..
+// + NC - 1 of its pencil (g' its index within the pencil, from the prefix
+// sums pre2 of the pencils' groups of NC columns); workgroups tot.. run
 // column step qk of G's QR instead (pre: the prefix sums of columns).  RC,
 // RCG: rows per thread of the register-resident 1x1 step of F and of G's
 // column step; longer columns, and 2x2 pivots, take the streaming loops.
-template <int RC, int RCG>
+template <int RC, int RCG, int NC>
 __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const int *pre,
                                                       const int *pre2, int B, int par, int tot,
                                                       int qk, int jw, int qpanel) {
@@ -505,7 +505,7 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
     __shared__ double red[4 * kGridNT / kWave];
     __shared__ double rv[kGridNT / kWave];
     __shared__ int ri[kGridNT / kWave];
-    __shared__ double2 stash[2 + 2 * kStepCols];
+    __shared__ double2 stash[2 + 2 * NC];
     if ((int)blockIdx.x >= tot) {
         if (qpanel)
             qr_panel_body<RCG>(PD, B, qk, (int)blockIdx.x - tot, red);
@@ -523,12 +523,12 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
     JqrState *nxt = P.jst + (par ^ 1);
     int8_t *Jc = P.Jw + (size_t)par * m;
     int8_t *Jn = P.Jw + (size_t)(par ^ 1) * m;
-    const int j0 = kStepCols * pencil_local(pre2, pk, blockIdx.x) + jw;
+    const int j0 = NC * pencil_local(pre2, pk, blockIdx.x) + jw;
     const int tid = threadIdx.x;
     if (!jqr_active(cur, n)) return;
     const int k = cur.k;
-    if (j0 + kStepCols <= k) return;  // every column of the workgroup is left of k
-    const bool desig = j0 <= k && k < j0 + kStepCols;
+    if (j0 + NC <= k) return;  // every column of the workgroup is left of k
+    const bool desig = j0 <= k && k < j0 + NC;
     const JqrDecision dec = *P.jdec;
     const int *cpb = P.cpb;
     // second Bunch-Kaufman test
@@ -567,12 +567,12 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
         return cpb[q];
     };
     if (piv == 1 && m - k <= RC * kGridNT) {
-        jqr_step1_regs<RC>(P, cur, par, k, j0, cp2, red, rv, ri, stash);
+        jqr_step1_regs<RC, NC>(P, cur, par, k, j0, cp2, red, rv, ri, stash);
         return;
     }
     // the workgroup's columns this step rewrites: right of the pivot block
     bool any = false;
-    for (int c = 0; c < kStepCols; ++c) any |= j0 + c >= k + piv && j0 + c < n;
+    for (int c = 0; c < NC; ++c) any |= j0 + c >= k + piv && j0 + c < n;
     if (!desig && !any) return;  // the second column of a 2x2 pivot only
     for (int r = k + tid; r < m; r += blockDim.x) Jl[r] = Jc[r];
     __syncthreads();
@@ -785,7 +785,7 @@ __global__ __launch_bounds__(kGridNT) void k_jqr_step(const PencilDev *PD, const
         }
     }
     // ---- the trailing columns: apply the reflector(s) in place ----
-    for (int c = 0; c < kStepCols; ++c) {
+    for (int c = 0; c < NC; ++c) {
         const int j = j0 + c;
         if (j < k + piv || j >= n) continue;  // uniform over the workgroup
         // (the previous column's reads of the stash all precede the
@@ -1408,19 +1408,28 @@ int run_reduction(BatchCtx &c, std::vector<int> &status, std::vector<int> &n2x2,
         launch_ev(k_jqr_cross, dim3(tot), dim3(kGridNT), 0, s, e0, nullptr, c.dev, pw, B, par, jw);
         hipLaunchKernelGGL(k_jqr_cross2, dim3(tot), dim3(kGridNT), 0, s, c.dev, pw, B, par, jw);
         // 6 or 8 rows per thread only when every column fits: their register
-        // counts lower the occupancy of the streaming paths
+        // counts lower the occupancy of the streaming paths.  Two F columns
+        // per workgroup when F's columns fit 6 rows per thread (158 VGPRs,
+        // three wavefronts per SIMD), else one (two columns at 8 rows would
+        // leave two wavefronts per SIMD, and the streaming loops gain
+        // nothing from sharing the pivot).
         const int rf = rows_f[w], rg = rows_g[w];
-        const int cf = rf > 4 && rf <= 6 ? 1 : (rf > 6 && rf <= 8 ? 2 : 0);
+        const int cf = rf > 4 && rf <= 6 ? 1 : (rf > 6 && rf <= 8 ? 2 : (rf > 8 ? 3 : 0));
         const int cg = rg > 4 && rg <= 8 ? 1 : 0;
-        decltype(&k_jqr_step<4, 4>) const kinds[3][2] = {{k_jqr_step<4, 4>, k_jqr_step<4, 8>},
-                                                          {k_jqr_step<6, 4>, k_jqr_step<6, 8>},
-                                                          {k_jqr_step<8, 4>, k_jqr_step<8, 8>}};
+        decltype(&k_jqr_step<4, 4, 1>) const kinds[4][2] = {
+            {k_jqr_step<4, 4, kStepCols>, k_jqr_step<4, 8, kStepCols>},
+            {k_jqr_step<6, 4, kStepCols>, k_jqr_step<6, 8, kStepCols>},
+            {k_jqr_step<8, 4, 1>, k_jqr_step<8, 8, 1>},
+            {k_jqr_step<4, 4, 1>, k_jqr_step<4, 8, 1>}};
         auto step_k = kinds[cf][cg];
+        const bool grouped = cf < 2;
+        const int *pre_f = grouped ? pw + pairs : pw;
+        const int tot_f = grouped ? tot2 : tot;
         const int gq = qpanel ? B * kQrPanel : tot;  // G's workgroups
         const bool trail = qpanel && (it % kQrPanel == kQrPanel - 1 || it == c.max_n - 1) &&
                            it - it % kQrPanel + kQrPanel < c.max_n;
-        launch_ev(step_k, dim3(tot2 + gq), dim3(kGridNT), (uint32_t)jl_bytes, s, nullptr,
-                  trail ? nullptr : e1, c.dev, pw, pw + pairs, B, par, tot2, it, jw, qpanel);
+        launch_ev(step_k, dim3(tot_f + gq), dim3(kGridNT), (uint32_t)jl_bytes, s, nullptr,
+                  trail ? nullptr : e1, c.dev, pw, pre_f, B, par, tot_f, it, jw, qpanel);
         if (trail) {
             const int ps = it - it % kQrPanel, pe = ps + kQrPanel;
             launch_ev(k_qr_trail, dim3((c.max_n - pe + kQrTrailCols - 1) / kQrTrailCols, B),
