@@ -64,11 +64,16 @@ def test_reduce_isotropic_2x2():
     assert np.abs(Fs.conj().T @ (host(Jsq)[:, None] * Fs) - H[np.ix_(pm, pm)]).max() < 1e-14
 
 
-@pytest.mark.parametrize("n,m,m_plus,p", [(300, 1300, 975, 2100), (600, 900, 675, 1200)])
+@pytest.mark.parametrize("n,m,m_plus,p", [(300, 1300, 975, 2100), (600, 900, 675, 1200),
+                                           (301, 1900, 1425, 1500), (257, 2300, 1725, 600)])
 def test_reduce_register_and_streaming_columns(oracle, n, m, m_plus, p):
     """Shapes whose trailing columns are longer than the register-resident
     step holds (1024 or 2048 rows) at the first steps and fit later, so
-    both forms of the column step run in one factorization.
+    both forms of the column step run in one factorization.  The last two
+    take F's columns through 8 rows per thread (one column per step
+    workgroup) and, for m = 2300, from the streaming loops through 8, 6 and
+    4 rows per thread, where the step workgroups switch to two columns each
+    (odd column counts included).
 
     The pivot decisions must match exactly.  The hyperbolic factor's
     elementwise bar is set by its own forward sensitivity: the oracle is run
