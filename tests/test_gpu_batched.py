@@ -119,3 +119,22 @@ def test_large_batch_every_inner_order(oracle_lams, precision, inner):
         lam1, X1, info1 = ghsvd.solve(*dev[k], **kw)
         assert torch.equal(lam1, lams[k]) and torch.equal(X1, Xs[k]), k
         assert info1["sweeps_fp64"] == infos[k]["sweeps_fp64"]
+
+
+def test_batched_reduction_windows_match_single_solves():
+    # one pencil whose F columns need the streaming loops at first beside
+    # small ones: in the batch every pencil's column steps run one column per
+    # step workgroup in those windows, in its single solve two; the
+    # arithmetic per column is the same, so the results are bitwise equal
+    shapes = [(150, 2200, 1650, 300), (120, 400, 300, 240), (91, 300, 225, 182),
+              (64, 1700, 1275, 128)]
+    Ps = [synth.random_pencil(950 + k, n, m, mp, p, 1e-3) for k, (n, m, mp, p) in enumerate(shapes)]
+    devs = [to_dev(P) for P in Ps]
+    kw = dict(precision="fp64", variant="blocked", block_width=16)
+    lam, X, infos, rc = ghsvd.solve_batched([d[0] for d in devs], [d[1] for d in devs],
+                                            [d[2] for d in devs], **kw)
+    assert rc == 0
+    for k, (F, J, G) in enumerate(devs):
+        l1, X1, info1 = ghsvd.solve(F, J, G, **kw)
+        assert info1["status"] == 0
+        assert torch.equal(lam[k], l1) and torch.equal(X[k], X1), k
